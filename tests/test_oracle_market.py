@@ -1,0 +1,235 @@
+"""Pins of the oracle's full solve (Alg. 2 with the Sec. 5 enhancements)
+against what fixes the answer independently of the algorithm: hand-worked
+equilibria (tests/golden), brute-force support enumeration, closed forms,
+invariants of the equilibrium (Sec. 3 Fact 1, Sec. 5 preprocessing), an
+independent algorithm (proportional response) and the Eisenberg-Gale
+duality gap."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from brute import dense_to_csr, eg_duality_gap, equilibria_by_support, proportional_response
+from paper_2506_06258_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def solve_dense(U, w, tol=1e-12, **kw):
+    rp, col, u = dense_to_csr(U)
+    n, m = np.asarray(U).shape
+    return oracle.solve(n, m, rp, col, u, w, tol=tol, max_iter=400000, **kw)
+
+
+def rel_err(p, q):
+    return np.max(np.abs(p - q)) / np.max(np.abs(q))
+
+
+@pytest.mark.parametrize("case", json.load(open(os.path.join(GOLDEN, "fisher_tiny.json")))["cases"],
+                         ids=lambda c: c["name"])
+def test_golden_tiny_markets(case):
+    sol = solve_dense(case["U"], case["w"])
+    assert sol.status == oracle.OK
+    assert rel_err(sol.p, np.array(case["p"], float)) < 1e-8
+
+
+@pytest.mark.parametrize("case", json.load(open(os.path.join(GOLDEN, "fisher_tiny.json")))["cases"],
+                         ids=lambda c: c["name"])
+def test_brute_force_reproduces_golden(case):
+    found = equilibria_by_support(np.array(case["U"], float), np.array(case["w"], float))
+    assert len(found) == 1
+    assert rel_err(found[0], np.array(case["p"], float)) < 1e-12
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_tiny_markets_match_support_enumeration(seed):
+    rng = np.random.default_rng(seed)
+    n, m = int(rng.integers(1, 4)), int(rng.integers(1, 4))
+    while True:
+        U = rng.uniform(0.05, 1.0, (n, m)) * (rng.random((n, m)) < 0.75)
+        if (U > 0).any(axis=1).all() and (U > 0).any(axis=0).all():
+            break
+    w = rng.uniform(0.2, 2.0, n)
+    found = equilibria_by_support(U, w)
+    assert len(found) == 1, "equilibrium prices are unique (Sec. 3 Fact 1)"
+    sol = solve_dense(U, w)
+    assert sol.status == oracle.OK
+    assert rel_err(sol.p, found[0]) < 1e-7
+
+
+def test_single_good_closed_form():
+    """m = 1: the good costs sum(w) and buyer i gets w_i/sum(w) of it."""
+    w = np.array([0.3, 1.2, 0.5, 2.0])
+    sol = solve_dense([[0.4], [1.0], [0.2], [0.7]], w)
+    assert sol.p[0] == pytest.approx(w.sum(), rel=1e-9)
+    assert np.allclose(sol.x, w / w.sum(), rtol=1e-7)
+
+
+def test_diagonal_closed_form():
+    """Each buyer likes only its own good: p_j = w_j."""
+    w = np.array([0.3, 1.2, 0.5, 2.0, 0.9])
+    sol = solve_dense(np.diag([0.5, 1.0, 0.2, 0.8, 0.3]), w)
+    assert rel_err(sol.p, w) < 1e-9
+
+
+def test_rank_one_closed_form_at_scale():
+    """Dense U = a v^T: p = v sum(w)/sum(v) at the small-market size."""
+    rng = np.random.default_rng(5)
+    n, m = 300, 120
+    a, v = rng.uniform(0.2, 1.0, n), rng.uniform(0.1, 1.0, m)
+    w = rng.uniform(0.5, 1.5, n)
+    sol = solve_dense(np.outer(a, v), w, tol=1e-10)
+    assert sol.status == oracle.OK
+    assert rel_err(sol.p, v * w.sum() / v.sum()) < 1e-7
+
+
+@pytest.fixture(scope="module")
+def small_market():
+    return synth.bernoulli_market(200, 80, 0.1, 11, w_mode="uniform")
+
+
+@pytest.fixture(scope="module")
+def small_solution(small_market):
+    mk = small_market
+    return oracle.solve(mk.n, mk.m, mk.row_ptr, mk.col, mk.u, mk.w, tol=1e-11, max_iter=400000)
+
+
+def test_prices_sum_to_budgets(small_market, small_solution):
+    """Sec. 3 Fact 1 / eq. sum-pj: sum_j p_j = sum_i w_i."""
+    assert small_solution.status == oracle.OK
+    assert small_solution.p.sum() == pytest.approx(small_market.w.sum(), rel=1e-9)
+
+
+def test_equilibrium_certificate(small_market, small_solution):
+    mk, s = small_market, small_solution
+    rows = mk.rows()
+    # market clearing and budget exhaustion
+    c = np.bincount(mk.col, weights=s.x, minlength=mk.m)
+    assert np.max(np.abs(c - 1)) < 1e-8
+    spend = np.bincount(rows, weights=s.p[mk.col] * s.x, minlength=mk.n)
+    assert np.max(np.abs(spend - mk.w) / mk.w) < 1e-8
+    # spending only on maximum bang-per-buck goods
+    bpb = mk.u / s.p[mk.col]
+    best = np.zeros(mk.n)
+    np.maximum.at(best, rows, bpb)
+    active = s.x > 1e-9
+    assert np.all(bpb[active] >= best[rows[active]] * (1 - 1e-6))
+    # t is returned in the caller's units
+    t = np.bincount(rows, weights=mk.u * s.x, minlength=mk.n)
+    assert np.allclose(s.t, t, rtol=1e-12)
+
+
+def test_duality_gap_vanishes(small_market, small_solution):
+    mk, s = small_market, small_solution
+    gap = eg_duality_gap(mk.row_ptr, mk.col, mk.u, mk.w, s.x, s.p)
+    assert -1e-9 <= gap < 1e-7
+    # and is clearly positive at a poor point
+    x0 = 1.0 / np.bincount(mk.col, minlength=mk.m)[mk.col]
+    p0 = np.full(mk.m, mk.w.sum() / mk.m)
+    assert eg_duality_gap(mk.row_ptr, mk.col, mk.u, mk.w, x0, p0) > 1e-2
+
+
+def test_proportional_response_agrees(small_market, small_solution):
+    mk = small_market
+    p_pr = proportional_response((mk.row_ptr, mk.col, mk.u), mk.w, iters=30000)
+    assert rel_err(small_solution.p, p_pr) < 1e-6
+
+
+def test_row_scaling_invariance(small_market, small_solution):
+    """Scaling a buyer's utilities does not change prices (Sec. 5)."""
+    mk = small_market
+    rng = np.random.default_rng(3)
+    scale = rng.uniform(0.1, 10.0, mk.n)
+    u2 = mk.u * scale[mk.rows()]
+    s2 = oracle.solve(mk.n, mk.m, mk.row_ptr, mk.col, u2, mk.w, tol=1e-11, max_iter=400000)
+    assert rel_err(s2.p, small_solution.p) < 1e-7
+
+
+def test_budget_homogeneity(small_market, small_solution):
+    mk = small_market
+    s2 = oracle.solve(mk.n, mk.m, mk.row_ptr, mk.col, mk.u, 3.5 * mk.w, tol=1e-11,
+                      max_iter=400000)
+    assert rel_err(s2.p, 3.5 * small_solution.p) < 1e-7
+
+
+def test_permutation_equivariance(small_market, small_solution):
+    mk = small_market
+    rng = np.random.default_rng(4)
+    pr, pc = rng.permutation(mk.n), rng.permutation(mk.m)
+    inv_c = np.argsort(pc)  # new column of old column j is inv_c[j]
+    U = np.zeros((mk.n, mk.m))
+    U[mk.rows(), mk.col] = mk.u
+    U2 = U[pr][:, pc]
+    rp, col, u = dense_to_csr(U2)
+    s2 = oracle.solve(mk.n, mk.m, rp, col, u, mk.w[pr], tol=1e-11, max_iter=400000)
+    assert rel_err(s2.p[inv_c], small_solution.p) < 1e-7
+
+
+def test_buyer_split_invariance(small_market, small_solution):
+    """Two copies of a buyer with half the budget each leave prices unchanged."""
+    mk = small_market
+    U = np.zeros((mk.n, mk.m))
+    U[mk.rows(), mk.col] = mk.u
+    U2 = np.vstack([U, U[:10]])
+    w2 = np.concatenate([mk.w, mk.w[:10] / 2])
+    w2[:10] /= 2
+    rp, col, u = dense_to_csr(U2)
+    s2 = oracle.solve(U2.shape[0], mk.m, rp, col, u, w2, tol=1e-11, max_iter=400000)
+    assert rel_err(s2.p, small_solution.p) < 1e-7
+
+
+def test_kkt_metric_zero_at_closed_form_equilibrium():
+    """The relative KKT error (Sec. 5 Criteria) vanishes at an exact
+    equilibrium and is positive away from it."""
+    U = np.diag([1.0, 0.5, 0.25])
+    w = np.array([1.0, 2.0, 3.0])
+    rp, col, u = dense_to_csr(U)
+    x = np.ones(3)
+    r, parts = oracle.kkt(3, 3, rp, col, u / u, w, x, w)  # normalised rows
+    assert r <= 1e-15
+    r2, parts2 = oracle.kkt(3, 3, rp, col, u / u, w, x, w * 1.1)
+    assert r2 > 1e-3
+
+
+def test_kkt_metric_hand_example():
+    """One buyer, two goods, u = (1, 0.5), w = 1, x = (0.5, 0.5),
+    p = (0.6, 0.3): column sums 0.5 -> r_primal = 0.5/2; t = 0.75,
+    y = 4/3, M = (4/3, 2/3) -> r_dual = (4/3 - 0.6)/(1 + 4/3); every
+    p_j - u_j y <= 0 -> r_gap = 0."""
+    rp = np.array([0, 2])
+    col = np.array([0, 1], np.int32)
+    r, parts = oracle.kkt(1, 2, rp, col, np.array([1.0, 0.5]), np.array([1.0]),
+                          np.array([0.5, 0.5]), np.array([0.6, 0.3]))
+    assert parts[0] == pytest.approx(0.25, rel=1e-14)
+    assert parts[1] == pytest.approx((4 / 3 - 0.6) / (1 + 4 / 3), rel=1e-14)
+    assert parts[2] == 0.0
+    assert r == pytest.approx(parts[1])
+
+
+def test_validation_codes():
+    rp = np.array([0, 1, 2])
+    col = np.array([0, 0], np.int32)
+    assert oracle.validate(2, 1, rp, col, [1.0, 1.0], [1.0, 1.0]) == oracle.OK
+    assert oracle.validate(2, 2, rp, col, [1.0, 1.0], [1.0, 1.0]) == oracle.ERR_ASSUMPTION
+    assert oracle.validate(2, 1, rp, col, [1.0, 0.0], [1.0, 1.0]) == oracle.ERR_ASSUMPTION
+    assert oracle.validate(2, 1, rp, col, [1.0, -1.0], [1.0, 1.0]) == oracle.ERR_ARG
+    assert oracle.validate(2, 1, rp, col, [1.0, 1.0], [1.0, 0.0]) == oracle.ERR_ARG
+    assert oracle.validate(2, 1, rp, np.array([0, 1], np.int32), [1.0, 1.0], [1, 1]) == oracle.ERR_ARG
+    assert oracle.validate(1, 2, np.array([0, 2]), np.array([1, 0], np.int32), [1, 1], [1]) == oracle.ERR_ARG
+
+
+def test_step_modes_and_searches_reach_same_prices(small_market, small_solution):
+    mk = small_market
+    for kw in (dict(step_mode=0), dict(prox=1), dict(prox=2, sections=32), dict(restart=0)):
+        s = oracle.solve(mk.n, mk.m, mk.row_ptr, mk.col, mk.u, mk.w, tol=1e-10,
+                         max_iter=800000, **kw)
+        assert s.status == oracle.OK, kw
+        assert rel_err(s.p, small_solution.p) < 1e-6, kw
+
+
+def test_max_iter_status(small_market):
+    mk = small_market
+    s = oracle.solve(mk.n, mk.m, mk.row_ptr, mk.col, mk.u, mk.w, tol=1e-14, max_iter=10)
+    assert s.status == oracle.MAX_ITER and s.iters == 10

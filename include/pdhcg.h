@@ -1,0 +1,215 @@
+/*
+ * pdhcg.h -- C ABI of the MI355X (gfx950) PDHCG solver for linear Fisher
+ * markets and the Arrow-Debreu fixed point built on it.
+ *
+ * Method: Liu, Huang, Li, Ge, Ye, "PDHCG: A Scalable First-Order Method for
+ * Large-Scale Competitive Market Equilibrium Computation" (arXiv 2506.06258).
+ *
+ * Problem (Sec. 1, Eisenberg-Gale program): n buyers with budgets w_i > 0,
+ * m goods of unit supply, linear utilities u_ij >= 0 on a sparse pattern:
+ *     max_x  sum_i w_i log(sum_j u_ij x_ij)  s.t.  sum_i x_ij = 1, x >= 0.
+ * The optimal duals p of the supply constraints are the unique equilibrium
+ * prices (Sec. 3, Fact 1); x is an equilibrium allocation.
+ *
+ * Conventions shared by every call:
+ *  - Pointers named "device" are HIP device pointers; the caller owns them.
+ *    Calls only read inputs; outputs are written in place.
+ *  - CSR: row_ptr[n+1] (int32, row_ptr[0] = 0, non-decreasing), col[nnz]
+ *    (int32, strictly increasing inside every row, values in [0, m)).  All
+ *    per-edge arrays (u, x) are aligned with col.
+ *  - Values are float32.  Internal global reductions (column sums, KKT and
+ *    restart norms) accumulate in float64.
+ *  - Every call returns a pdhcg_status (int).  Nothing throws across the
+ *    ABI.  pdhcg_last_error() returns a description of the last failure on
+ *    the calling thread.
+ *  - A market handle owns its device copies and workspace and is bound to
+ *    the device and stream given at creation.  Handles are not thread-safe;
+ *    different handles may be used from different threads.
+ *  - Synchronisation: pdhcg_market_create, pdhcg_solve, pdhcg_kkt and
+ *    pdhcg_arrow_debreu return after their device work on the handle's
+ *    stream has finished.  pdhcg_row_prox only enqueues.
+ */
+#ifndef PDHCG_H
+#define PDHCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PDHCG_ABI_VERSION 1
+
+typedef struct pdhcg_market_s *pdhcg_market;
+
+typedef enum {
+  PDHCG_OK = 0,
+  PDHCG_MAX_ITER = 1,         /* not fatal: outputs hold the last candidate */
+  PDHCG_ERR_ARG = -1,         /* bad size, pointer, CSR shape or value */
+  PDHCG_ERR_ASSUMPTION = -2,  /* a buyer or good with no positive utility
+                                 (Assumption 1, Sec. 2) */
+  PDHCG_ERR_NUMERIC = -3,     /* non-finite iterate or no positive row root */
+  PDHCG_ERR_OOM = -4,         /* device or host allocation failed */
+  PDHCG_ERR_HIP = -5,         /* a HIP runtime call failed */
+  PDHCG_ERR_UNSUPPORTED = -6  /* shape outside the built kernel variants */
+} pdhcg_status;
+
+/* Root search for the row subproblem (Sec. 2.2). */
+enum {
+  /* Bracketing search of Alg. 3 whose trial points are the roots of the
+   * quadratic that holds on the active set of the previous trial; each
+   * such root is a lower bound on s* and is exact once the active set
+   * settles.  Default on gfx950. */
+  PDHCG_SEARCH_ACTIVESET = 0,
+  /* k-section search of Sec. 2.2.1 (sections = k, 32 in the paper). */
+  PDHCG_SEARCH_KSECTION = 1
+};
+
+enum { PDHCG_STEP_FIXED = 0, PDHCG_STEP_ADAPTIVE = 1 };
+enum { PDHCG_RESTART_NONE = 0, PDHCG_RESTART_ADAPTIVE = 1 };
+enum { PDHCG_OUTPUT_CANDIDATE = 0, PDHCG_OUTPUT_CURRENT = 1, PDHCG_OUTPUT_AVERAGE = 2 };
+
+/* Solver parameters.  pdhcg_default_params() fills the values given in
+ * Sec. 5 ("Algorithmic Enhancements", "Criteria") and the readings of the
+ * passages the paper leaves open (documented with the defaults). */
+typedef struct pdhcg_params {
+  double tol;                /* stop when the candidate's relative KKT <= tol
+                                (Sec. 5 Criteria; default 1e-4) */
+  int64_t max_iter;          /* cap on iterations (every prox sweep counts) */
+  int32_t eval_every;        /* iterations between KKT / restart checks (64) */
+  int32_t search;            /* PDHCG_SEARCH_* */
+  int32_t sections;          /* k of the k-section search (32, Sec. 2.2.1) */
+  int32_t max_search_rounds; /* cap on search rounds per row (16) */
+  double search_rtol;        /* a row search stops when U - L <= rtol * U */
+  int32_t step_mode;         /* PDHCG_STEP_* (adaptive, Sec. 5) */
+  int32_t restart;           /* PDHCG_RESTART_* (adaptive, Sec. 5) */
+  double beta_sufficient;    /* 0.2 (Sec. 5) */
+  double beta_necessary;     /* 0.8 (Sec. 5) */
+  double beta_artificial;    /* 0.2 (Sec. 5) */
+  double theta;              /* primal-weight smoothing, 0.2 (Sec. 5) */
+  int32_t omega_check_every; /* restarts between primal-weight checks (3) */
+  int32_t output;            /* PDHCG_OUTPUT_* */
+  double omega_bound;        /* reset omega to omega0 when outside
+                                [omega0/bound, omega0*bound] */
+  double eta0;               /* <= 0: 1 in adaptive mode, 0.9/||K|| fixed */
+  double omega0;             /* <= 0: sum(w) / (20 m), a twentieth of the
+                                mean equilibrium price */
+  int32_t normalize_rows;    /* divide each buyer's utilities by their
+                                maximum (Sec. 5 Preprocessing; 1) */
+  int32_t verbose;           /* print one line per check to stderr */
+  int32_t timing;            /* 1: time every row-kernel launch with HIP
+                                events on the handle's stream (fills the
+                                row_pass_* fields of pdhcg_info) */
+} pdhcg_params;
+
+/* Result of a solve or a KKT evaluation (host struct). */
+typedef struct pdhcg_info {
+  double rel_kkt;            /* max of the three relative residuals */
+  double rel_primal;
+  double rel_dual;
+  double rel_gap;
+  double eta;                /* final step size */
+  double omega;              /* final primal weight */
+  double seconds;            /* wall time of the solve */
+  int64_t iters;             /* iterations (prox sweeps) */
+  int64_t accepted;          /* iterations kept by the step-size rule */
+  int32_t restarts;
+  int32_t status;
+  int32_t evals;             /* KKT checks performed */
+  int32_t search_rounds_max; /* largest number of search rounds of any row */
+  double search_rounds_mean; /* mean search rounds per row and iteration */
+  double row_pass_seconds;   /* summed device time of the row-kernel launches
+                                (params.timing = 1), else 0 */
+  int64_t row_pass_launches; /* number of timed row-kernel launch groups */
+} pdhcg_info;
+
+int32_t pdhcg_abi_version(void);
+const char *pdhcg_status_string(int32_t status);
+/* Description of the last error raised on the calling thread ("" if none). */
+const char *pdhcg_last_error(void);
+void pdhcg_default_params(pdhcg_params *params);
+
+/* Host-side validation of a market given in host memory (all pointers
+ * host).  Checks sizes, CSR shape, strictly increasing in-range columns,
+ * finite u >= 0, finite w > 0 (PDHCG_ERR_ARG), then Assumption 1 of Sec. 2
+ * on the positive entries (PDHCG_ERR_ASSUMPTION).  Needs no GPU. */
+int32_t pdhcg_validate_host(int32_t n, int32_t m, int64_t nnz,
+                            const int32_t *row_ptr, const int32_t *col,
+                            const float *u, const float *w);
+
+/* Create a market handle from device arrays (Sec. 1 problem data: U on its
+ * CSR pattern, budgets w).  The inputs are validated (as
+ * pdhcg_validate_host), copied, and preprocessed on the device: each row of
+ * U is divided by its maximum (Sec. 5), column degrees and ||K|| are
+ * computed, and the row kernels are chosen from the degree profile.  The
+ * caller may free its inputs afterwards.  stream: a hipStream_t (NULL =
+ * default stream).  On failure *out is NULL. */
+int32_t pdhcg_market_create(int32_t n, int32_t m, int64_t nnz,
+                            const int32_t *row_ptr, const int32_t *col,
+                            const float *u, const float *w, void *stream,
+                            pdhcg_market *out);
+
+/* Replace the budgets (device pointer, n floats, all > 0).  Used by the
+ * Arrow-Debreu outer loop (Sec. 4, Alg. 4). */
+int32_t pdhcg_set_budgets(pdhcg_market market, const float *w);
+
+/* Solve the Fisher market by restarted PDHCG (Alg. 2 with the Sec. 5
+ * enhancements).
+ *   p [m]   device.  warm != 0: starting prices on entry.  Out: prices.
+ *   x [nnz] device.  warm != 0: starting allocation on entry (CSR order).
+ *           Out: allocation.
+ *   t [n]   device, may be NULL.  Out: utilities sum_j u_ij x_ij in the
+ *           caller's (unnormalised) units.
+ *   info    host, may be NULL.
+ * Returns PDHCG_OK when the candidate's relative KKT reached tol,
+ * PDHCG_MAX_ITER when max_iter ran out (outputs hold the last candidate). */
+int32_t pdhcg_solve(pdhcg_market market, const pdhcg_params *params,
+                    int32_t warm, float *p, float *x, float *t,
+                    pdhcg_info *info);
+
+/* Relative KKT error (Sec. 5 Criteria, with t_i = u_i^T x_i, y = w/t) of a
+ * given point (device p[m], x[nnz]) on the normalised market; float64
+ * reductions.  Fills rel_kkt / rel_primal / rel_dual / rel_gap of info. */
+int32_t pdhcg_kkt(pdhcg_market market, const float *p, const float *x,
+                  pdhcg_info *info);
+
+/* One parallel row update of Alg. 2 on its own: for every buyer i, the
+ * minimiser of  -w_i log(u_i^T x_i) + p^T x_i + |x_i - x_in_i|^2/(2 tau)
+ * over x_i >= 0 (Sec. 2.2), using the market's normalised utilities and
+ * the search selected in params (NULL: defaults).  All arrays device:
+ * x_in, x_out [nnz], p [m], s_out [n] (may be NULL; receives u_i^T x_i of
+ * the normalised row).  Enqueued on the handle's stream; no
+ * synchronisation. */
+int32_t pdhcg_row_prox(pdhcg_market market, const float *x_in,
+                       const float *p, double tau,
+                       const pdhcg_params *params, float *x_out,
+                       float *s_out);
+
+/* Arrow-Debreu exchange market by the fixed-point iteration w <- E p(w)
+ * (Sec. 4, Alg. 4).  E: device CSR (e_row_ptr[n+1], e_col[e_nnz],
+ * e_val[e_nnz]) with column sums one (Sec. 4).  Each Fisher solve uses
+ * `inner` and is warm-started from the previous prices and allocation.
+ * Stops when ||p^k - p^{k-1}||_inf / ||p^{k-1}||_inf <= outer_tol.
+ *   w  [n] device: initial budgets on entry, final budgets E p on exit.
+ *   p  [m], x [nnz] device: outputs.
+ *   outer_iters, inner_iters: host, may be NULL. */
+int32_t pdhcg_arrow_debreu(pdhcg_market market, const int32_t *e_row_ptr,
+                           const int32_t *e_col, const float *e_val,
+                           int64_t e_nnz, const pdhcg_params *inner,
+                           double outer_tol, int32_t outer_max, float *w,
+                           float *p, float *x, int32_t *outer_iters,
+                           int64_t *inner_iters, pdhcg_info *info);
+
+/* Number of market rows in each kernel bin and the bin shapes chosen at
+ * creation (host arrays of length cap; returns the number of bins). */
+int32_t pdhcg_market_bins(pdhcg_market market, int32_t cap,
+                          int32_t *lanes_per_row, int32_t *entries_per_lane,
+                          int32_t *rows);
+
+void pdhcg_market_destroy(pdhcg_market market);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDHCG_H */

@@ -1,0 +1,925 @@
+// C ABI of the gfx950 PDHCG library (include/pdhcg.h): validation, market
+// creation (copies, row normalisation, degree binning), the host control of
+// restarted PDHCG (Alg. 2 with the Sec. 5 enhancements) and the
+// Arrow-Debreu fixed point (Alg. 4).  The per-iteration work runs in the
+// kernels of pdhcg_kernels.hip; the host only acts every eval_every
+// iterations (KKT check, restart, primal weight).
+#include "../../include/pdhcg.h"
+#include "pdhcg_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace pdhcg;
+
+namespace {
+
+thread_local std::string g_err;
+
+int32_t fail(int32_t st, const std::string &msg) {
+  g_err = msg;
+  return st;
+}
+
+#define HIPC(call)                                                                  \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      return fail(PDHCG_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct Bin {
+  int G = 0, E = 0;
+  std::vector<int32_t> rows;  // empty = identity (all rows)
+  int32_t *d_rows = nullptr;
+  int32_t nrows = 0;
+  int32_t nwg = 0;
+  int32_t wg_offset = 0;
+  int32_t rows_per_wg = 0;
+  int64_t nnz = 0;
+};
+
+template <typename T>
+hipError_t dalloc(T **p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc((void **)p, count * sizeof(T));
+}
+
+}  // namespace
+
+struct pdhcg_market_s {
+  int32_t n = 0, m = 0;
+  int64_t nnz = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  // problem data (device)
+  int32_t *row_ptr = nullptr, *col = nullptr, *deg = nullptr;
+  float *uh = nullptr, *rowmax = nullptr, *w = nullptr;
+  // workspace (device)
+  float *X[3] = {nullptr, nullptr, nullptr};
+  double *P[3] = {nullptr, nullptr, nullptr};
+  double *C[3] = {nullptr, nullptr, nullptr};
+  float *XA = nullptr;
+  double *PA = nullptr;
+  double *Pk = nullptr;  // float64 copy of caller prices (kkt, row_prox)
+  float *T[2] = {nullptr, nullptr};
+  float *colpart = nullptr, *evalpart = nullptr;
+  double *rowpart = nullptr, *colblk = nullptr, *cacc = nullptr, *colchunk = nullptr;
+  uint32_t *tile_ticket = nullptr;
+  DevState *S = nullptr;   // device
+  DevState *hS = nullptr;  // pinned host shadow
+  // host data
+  std::vector<int32_t> h_deg_col;
+  int32_t maxdeg_col = 0, maxdeg_row = 0;
+  double sumw = 0.0;
+  std::vector<Bin> bins;
+  int32_t total_wg = 0;
+  int lds_row = 0, lds_eval = 0;
+  int col_blocks = 0;
+
+  MarketDev dev() const {
+    MarketDev d;
+    d.n = n;
+    d.m = m;
+    d.nnz = nnz;
+    d.row_ptr = row_ptr;
+    d.col = col;
+    d.uh = uh;
+    d.w = w;
+    d.X0 = X[0];
+    d.X1 = X[1];
+    d.X2 = X[2];
+    d.P0 = P[0];
+    d.P1 = P[1];
+    d.P2 = P[2];
+    d.C0 = C[0];
+    d.C1 = C[1];
+    d.C2 = C[2];
+    d.XA = XA;
+    d.PA = PA;
+    d.colpart = colpart;
+    d.rowpart = rowpart;
+    d.colblk = colblk;
+    d.colchunk = colchunk;
+    d.tile_ticket = tile_ticket;
+    d.S = S;
+    return d;
+  }
+  BinDev bindev(const Bin &b) const {
+    BinDev d;
+    d.rows = b.d_rows;
+    d.nrows = b.nrows;
+    d.wg_offset = b.wg_offset;
+    d.rows_per_wg = b.rows_per_wg;
+    return d;
+  }
+};
+
+extern "C" {
+
+int32_t pdhcg_abi_version(void) { return PDHCG_ABI_VERSION; }
+
+const char *pdhcg_status_string(int32_t st) {
+  switch (st) {
+    case PDHCG_OK: return "ok";
+    case PDHCG_MAX_ITER: return "iteration limit reached";
+    case PDHCG_ERR_ARG: return "invalid argument";
+    case PDHCG_ERR_ASSUMPTION: return "Assumption 1 violated (buyer or good without positive utility)";
+    case PDHCG_ERR_NUMERIC: return "numerical failure";
+    case PDHCG_ERR_OOM: return "out of memory";
+    case PDHCG_ERR_HIP: return "HIP runtime error";
+    case PDHCG_ERR_UNSUPPORTED: return "unsupported shape";
+    default: return "unknown status";
+  }
+}
+
+const char *pdhcg_last_error(void) { return g_err.c_str(); }
+
+void pdhcg_default_params(pdhcg_params *p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->tol = 1e-4;
+  p->max_iter = 100000;
+  p->eval_every = 64;
+  p->search = PDHCG_SEARCH_ACTIVESET;
+  p->sections = 32;
+  p->max_search_rounds = 16;
+  p->search_rtol = 1e-10;
+  p->step_mode = PDHCG_STEP_ADAPTIVE;
+  p->restart = PDHCG_RESTART_ADAPTIVE;
+  p->beta_sufficient = 0.2;
+  p->beta_necessary = 0.8;
+  p->beta_artificial = 0.2;
+  p->theta = 0.2;
+  p->omega_check_every = 3;
+  p->output = PDHCG_OUTPUT_CANDIDATE;
+  p->omega_bound = 1e4;
+  p->eta0 = 0.0;
+  p->omega0 = 0.0;
+  p->normalize_rows = 1;
+  p->verbose = 0;
+}
+
+int32_t pdhcg_validate_host(int32_t n, int32_t m, int64_t nnz, const int32_t *row_ptr,
+                            const int32_t *col, const float *u, const float *w) {
+  if (n <= 0 || m <= 0 || nnz <= 0 || nnz > INT32_MAX)
+    return fail(PDHCG_ERR_ARG, "sizes must satisfy n, m > 0 and 0 < nnz <= 2^31-1");
+  if (!row_ptr || !col || !u || !w) return fail(PDHCG_ERR_ARG, "null pointer");
+  if (row_ptr[0] != 0 || (int64_t)row_ptr[n] != nnz)
+    return fail(PDHCG_ERR_ARG, "row_ptr[0] must be 0 and row_ptr[n] must equal nnz");
+  std::vector<char> good((size_t)m, 0);
+  for (int32_t i = 0; i < n; ++i) {
+    const int32_t b = row_ptr[i], e = row_ptr[i + 1];
+    if (e < b) return fail(PDHCG_ERR_ARG, "row_ptr decreases at row " + std::to_string(i));
+    if (!(w[i] > 0.0f) || !std::isfinite(w[i]))
+      return fail(PDHCG_ERR_ARG, "budget w[" + std::to_string(i) + "] must be finite and > 0");
+    bool liked = false;
+    for (int32_t k = b; k < e; ++k) {
+      const int32_t c = col[k];
+      if (c < 0 || c >= m) return fail(PDHCG_ERR_ARG, "column index out of range at " + std::to_string(k));
+      if (k > b && c <= col[k - 1])
+        return fail(PDHCG_ERR_ARG, "columns not strictly increasing in row " + std::to_string(i));
+      if (!(u[k] >= 0.0f) || !std::isfinite(u[k]))
+        return fail(PDHCG_ERR_ARG, "utility u[" + std::to_string(k) + "] must be finite and >= 0");
+      if (u[k] > 0.0f) {
+        liked = true;
+        good[(size_t)c] = 1;
+      }
+    }
+    if (!liked)
+      return fail(PDHCG_ERR_ASSUMPTION, "buyer " + std::to_string(i) + " has no positive utility");
+  }
+  for (int32_t j = 0; j < m; ++j)
+    if (!good[(size_t)j])
+      return fail(PDHCG_ERR_ASSUMPTION, "good " + std::to_string(j) + " has no positive utility");
+  return PDHCG_OK;
+}
+
+void pdhcg_market_destroy(pdhcg_market mk) {
+  if (!mk) return;
+  auto f = [](void *p) {
+    if (p) (void)hipFree(p);
+  };
+  f(mk->row_ptr); f(mk->col); f(mk->deg); f(mk->uh); f(mk->rowmax); f(mk->w);
+  for (int q = 0; q < 3; ++q) { f(mk->X[q]); f(mk->P[q]); f(mk->C[q]); }
+  f(mk->XA); f(mk->PA); f(mk->Pk); f(mk->T[0]); f(mk->T[1]);
+  f(mk->colpart); f(mk->evalpart); f(mk->rowpart); f(mk->colblk); f(mk->cacc); f(mk->S);
+  f(mk->colchunk); f(mk->tile_ticket);
+  for (auto &b : mk->bins) f(b.d_rows);
+  if (mk->hS) (void)hipHostFree(mk->hS);
+  delete mk;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Row kernel shape for a row of degree d: G lanes x E entries per lane
+// covering d with the fewest slots, then the fewest lanes (G >= 8 keeps
+// each load of a segment at least 32 contiguous bytes).
+void choose_shape(int d, int *G, int *E) {
+  static const int Gs[] = {8, 16, 32, 64};
+  static const int Es[] = {1, 2, 4, 8};
+  int bestG = 64, bestE = 16, best = 1 << 30;
+  for (int g : Gs)
+    for (int e : Es) {
+      const int slots = g * e;
+      if (slots >= d && slots < best) {
+        best = slots;
+        bestG = g;
+        bestE = e;
+      }
+    }
+  if (best == (1 << 30)) {  // beyond 512 entries
+    bestG = 64;
+    bestE = 16;
+  }
+  const char *eg = std::getenv("PDHCG_ROW_G");
+  const char *ee = std::getenv("PDHCG_ROW_E");
+  if (eg && ee) {
+    const int g = std::atoi(eg), e = std::atoi(ee);
+    if (row_variant_exists(g, e) && g * e >= d) {
+      bestG = g;
+      bestE = e;
+    }
+  }
+  *G = bestG;
+  *E = bestE;
+}
+
+int32_t build_bins(pdhcg_market mk, const std::vector<int32_t> &h_row_ptr) {
+  // group rows by kernel shape
+  std::vector<std::pair<int, int>> shapes;
+  std::vector<int> shape_of((size_t)mk->n);
+  for (int32_t i = 0; i < mk->n; ++i) {
+    const int d = h_row_ptr[(size_t)i + 1] - h_row_ptr[(size_t)i];
+    if (d > 1024)
+      return fail(PDHCG_ERR_UNSUPPORTED,
+                  "row " + std::to_string(i) + " has " + std::to_string(d) +
+                      " entries; rows longer than 1024 are not supported yet");
+    int G, E;
+    choose_shape(d, &G, &E);
+    auto key = std::make_pair(G, E);
+    auto it = std::find(shapes.begin(), shapes.end(), key);
+    int s;
+    if (it == shapes.end()) {
+      shapes.push_back(key);
+      s = (int)shapes.size() - 1;
+    } else {
+      s = (int)(it - shapes.begin());
+    }
+    shape_of[(size_t)i] = s;
+  }
+  mk->bins.assign(shapes.size(), Bin());
+  for (size_t s = 0; s < shapes.size(); ++s) {
+    mk->bins[s].G = shapes[s].first;
+    mk->bins[s].E = shapes[s].second;
+  }
+  for (int32_t i = 0; i < mk->n; ++i) {
+    Bin &b = mk->bins[(size_t)shape_of[(size_t)i]];
+    b.rows.push_back(i);
+    b.nnz += h_row_ptr[(size_t)i + 1] - h_row_ptr[(size_t)i];
+  }
+  // workgroup budget: about two resident workgroups per CU
+  int cus = 256;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, mk->device) == hipSuccess && prop.multiProcessorCount > 0)
+    cus = prop.multiProcessorCount;
+  const int budget = 2 * cus;
+  int off = 0;
+  const int kWaves = kRowBlock / kWave;
+  for (auto &b : mk->bins) {
+    b.nrows = (int32_t)b.rows.size();
+    const int per_pass = kWaves * (kWave / b.G);
+    const int64_t passes = (b.nrows + per_pass - 1) / per_pass;
+    int nwg = (int)std::max<int64_t>(
+        1, std::min<int64_t>(passes, (int64_t)std::ceil((double)budget * (double)b.nnz /
+                                                       (double)std::max<int64_t>(mk->nnz, 1))));
+    const int64_t passes_per_wg = (passes + nwg - 1) / nwg;
+    b.rows_per_wg = (int32_t)(passes_per_wg * per_pass);
+    b.nwg = (int32_t)((b.nrows + b.rows_per_wg - 1) / b.rows_per_wg);
+    b.wg_offset = off;
+    off += b.nwg;
+    if (mk->bins.size() == 1) {
+      b.rows.clear();  // identity
+      b.d_rows = nullptr;
+    } else {
+      HIPC(dalloc(&b.d_rows, b.rows.size()));
+      HIPC(hipMemcpy(b.d_rows, b.rows.data(), b.rows.size() * sizeof(int32_t),
+                     hipMemcpyHostToDevice));
+    }
+  }
+  mk->total_wg = off;
+  return PDHCG_OK;
+}
+
+}  // namespace
+
+extern "C" int32_t pdhcg_market_create(int32_t n, int32_t m, int64_t nnz, const int32_t *row_ptr,
+                                       const int32_t *col, const float *u, const float *w,
+                                       void *stream, pdhcg_market *out) {
+  if (!out) return fail(PDHCG_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (n <= 0 || m <= 0 || nnz <= 0 || nnz > INT32_MAX)
+    return fail(PDHCG_ERR_ARG, "sizes must satisfy n, m > 0 and 0 < nnz <= 2^31-1");
+  if (!row_ptr || !col || !u || !w) return fail(PDHCG_ERR_ARG, "null pointer");
+  hipStream_t st = (hipStream_t)stream;
+  // validate on the host
+  std::vector<int32_t> h_rp((size_t)n + 1), h_col((size_t)nnz);
+  std::vector<float> h_u((size_t)nnz), h_w((size_t)n);
+  HIPC(hipMemcpyAsync(h_rp.data(), row_ptr, h_rp.size() * 4, hipMemcpyDeviceToHost, st));
+  HIPC(hipMemcpyAsync(h_col.data(), col, h_col.size() * 4, hipMemcpyDeviceToHost, st));
+  HIPC(hipMemcpyAsync(h_u.data(), u, h_u.size() * 4, hipMemcpyDeviceToHost, st));
+  HIPC(hipMemcpyAsync(h_w.data(), w, h_w.size() * 4, hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  int32_t rc = pdhcg_validate_host(n, m, nnz, h_rp.data(), h_col.data(), h_u.data(), h_w.data());
+  if (rc != PDHCG_OK) return rc;
+
+  pdhcg_market mk = new (std::nothrow) pdhcg_market_s();
+  if (!mk) return fail(PDHCG_ERR_OOM, "host allocation failed");
+  mk->n = n;
+  mk->m = m;
+  mk->nnz = nnz;
+  mk->stream = st;
+  (void)hipGetDevice(&mk->device);
+  auto cleanup = [&](int32_t code) {
+    pdhcg_market_destroy(mk);
+    return code;
+  };
+  mk->h_deg_col.assign((size_t)m, 0);
+  for (int64_t k = 0; k < nnz; ++k) mk->h_deg_col[(size_t)h_col[(size_t)k]] += 1;
+  mk->maxdeg_col = *std::max_element(mk->h_deg_col.begin(), mk->h_deg_col.end());
+  for (int32_t i = 0; i < n; ++i)
+    mk->maxdeg_row = std::max(mk->maxdeg_row, h_rp[(size_t)i + 1] - h_rp[(size_t)i]);
+  mk->sumw = 0.0;
+  for (int32_t i = 0; i < n; ++i) mk->sumw += (double)h_w[(size_t)i];
+
+#define MK_HIPC(call)                                                                 \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess) {                                                           \
+      int32_t code_ = (e_ == hipErrorOutOfMemory) ? PDHCG_ERR_OOM : PDHCG_ERR_HIP;    \
+      fail(code_, std::string(#call) + ": " + hipGetErrorString(e_));                 \
+      return cleanup(code_);                                                          \
+    }                                                                                 \
+  } while (0)
+
+  rc = build_bins(mk, h_rp);
+  if (rc != PDHCG_OK) return cleanup(rc);
+  size_t lds_cap = 64 * 1024;
+  {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, mk->device) == hipSuccess && prop.sharedMemPerBlock > 0)
+      lds_cap = prop.sharedMemPerBlock;
+  }
+  const size_t static_lds = 1024;  // the kernels' own __shared__ arrays
+  // Row pass: float32 column partials in LDS when they fit, plus a float64
+  // copy of the prices when that fits too (PDHCG_P_LDS=0 keeps the prices
+  // in global memory).
+  mk->lds_row = 0;
+  if ((size_t)m * sizeof(float) + static_lds <= lds_cap) mk->lds_row = 1;
+  if ((size_t)m * (sizeof(double) + sizeof(float)) + static_lds <= lds_cap) mk->lds_row = 3;
+  if (const char *e = std::getenv("PDHCG_P_LDS")) {
+    if (!std::atoi(e) && mk->lds_row == 3) mk->lds_row = 1;
+  }
+  mk->lds_eval = ((size_t)3 * m * sizeof(float) + static_lds <= lds_cap) ? 1 : 0;
+  if (const char *e = std::getenv("PDHCG_NO_LDS")) {
+    if (std::atoi(e)) {
+      mk->lds_row = 0;
+      mk->lds_eval = 0;
+    }
+  }
+  mk->col_blocks = (m + kColBlock - 1) / kColBlock;
+
+  MK_HIPC(dalloc(&mk->row_ptr, (size_t)n + 1));
+  MK_HIPC(dalloc(&mk->col, (size_t)nnz));
+  MK_HIPC(dalloc(&mk->deg, (size_t)m));
+  MK_HIPC(dalloc(&mk->uh, (size_t)nnz));
+  MK_HIPC(dalloc(&mk->rowmax, (size_t)n));
+  MK_HIPC(dalloc(&mk->w, (size_t)n));
+  for (int q = 0; q < 3; ++q) {
+    MK_HIPC(dalloc(&mk->X[q], (size_t)nnz));
+    MK_HIPC(dalloc(&mk->P[q], (size_t)m));
+    MK_HIPC(dalloc(&mk->C[q], (size_t)m));
+  }
+  MK_HIPC(dalloc(&mk->XA, (size_t)nnz));
+  MK_HIPC(dalloc(&mk->PA, (size_t)m));
+  MK_HIPC(dalloc(&mk->Pk, (size_t)m));
+  MK_HIPC(dalloc(&mk->T[0], (size_t)n));
+  MK_HIPC(dalloc(&mk->T[1], (size_t)n));
+  MK_HIPC(dalloc(&mk->colpart, (mk->lds_row & 1) ? (size_t)mk->total_wg * m : 1));
+  MK_HIPC(dalloc(&mk->evalpart, mk->lds_eval ? (size_t)3 * mk->total_wg * m : (size_t)2 * m));
+  MK_HIPC(dalloc(&mk->cacc, (size_t)m));
+  MK_HIPC(dalloc(&mk->rowpart, (size_t)mk->total_wg * std::max(kRowStats, kEvalRowStats)));
+  MK_HIPC(dalloc(&mk->colblk, (size_t)mk->col_blocks * std::max(kColStats, kEvalColStats)));
+  MK_HIPC(dalloc(&mk->colchunk, (size_t)kColChunks * m));
+  MK_HIPC(dalloc(&mk->tile_ticket, (size_t)mk->col_blocks));
+  MK_HIPC(hipMemsetAsync(mk->tile_ticket, 0, (size_t)mk->col_blocks * sizeof(uint32_t), st));
+  MK_HIPC(dalloc(&mk->S, 1));
+  MK_HIPC(hipHostMalloc((void **)&mk->hS, sizeof(DevState), hipHostMallocDefault));
+  std::memset(mk->hS, 0, sizeof(DevState));
+
+  MK_HIPC(hipMemcpyAsync(mk->row_ptr, row_ptr, ((size_t)n + 1) * 4, hipMemcpyDeviceToDevice, st));
+  MK_HIPC(hipMemcpyAsync(mk->col, col, (size_t)nnz * 4, hipMemcpyDeviceToDevice, st));
+  MK_HIPC(hipMemcpyAsync(mk->w, w, (size_t)n * 4, hipMemcpyDeviceToDevice, st));
+  MK_HIPC(hipMemcpyAsync(mk->deg, mk->h_deg_col.data(), (size_t)m * 4, hipMemcpyHostToDevice, st));
+  MK_HIPC(launch_normalize(mk->row_ptr, u, mk->uh, mk->rowmax, n, st));
+  MK_HIPC(hipMemsetAsync(mk->S, 0, sizeof(DevState), st));
+  MK_HIPC(hipStreamSynchronize(st));
+  *out = mk;
+  return PDHCG_OK;
+#undef MK_HIPC
+}
+
+extern "C" int32_t pdhcg_set_budgets(pdhcg_market mk, const float *w) {
+  if (!mk || !w) return fail(PDHCG_ERR_ARG, "null argument");
+  std::vector<float> h((size_t)mk->n);
+  HIPC(hipMemcpyAsync(h.data(), w, h.size() * 4, hipMemcpyDeviceToHost, mk->stream));
+  HIPC(hipStreamSynchronize(mk->stream));
+  double s = 0.0;
+  for (int32_t i = 0; i < mk->n; ++i) {
+    if (!(h[(size_t)i] > 0.0f) || !std::isfinite(h[(size_t)i]))
+      return fail(PDHCG_ERR_ARG, "budget w[" + std::to_string(i) + "] must be finite and > 0");
+    s += (double)h[(size_t)i];
+  }
+  mk->sumw = s;
+  HIPC(hipMemcpyAsync(mk->w, w, (size_t)mk->n * 4, hipMemcpyDeviceToDevice, mk->stream));
+  HIPC(hipStreamSynchronize(mk->stream));
+  return PDHCG_OK;
+}
+
+extern "C" int32_t pdhcg_market_bins(pdhcg_market mk, int32_t cap, int32_t *lanes,
+                                     int32_t *entries, int32_t *rows) {
+  if (!mk) return fail(PDHCG_ERR_ARG, "null market");
+  const int32_t nb = (int32_t)mk->bins.size();
+  for (int32_t b = 0; b < nb && b < cap; ++b) {
+    if (lanes) lanes[b] = mk->bins[(size_t)b].G;
+    if (entries) entries[b] = mk->bins[(size_t)b].E;
+    if (rows) rows[b] = mk->bins[(size_t)b].nrows;
+  }
+  return nb;
+}
+
+namespace {
+
+int32_t check_params(const pdhcg_params *p) {
+  if (!p) return fail(PDHCG_ERR_ARG, "params is NULL");
+  if (!(p->tol >= 0.0) || p->max_iter < 0 || p->eval_every <= 0)
+    return fail(PDHCG_ERR_ARG, "tol >= 0, max_iter >= 0 and eval_every > 0 required");
+  if (p->search != PDHCG_SEARCH_ACTIVESET && p->search != PDHCG_SEARCH_KSECTION)
+    return fail(PDHCG_ERR_ARG, "unknown search");
+  if (p->search == PDHCG_SEARCH_KSECTION && (p->sections < 1 || p->sections > kMaxSections))
+    return fail(PDHCG_ERR_ARG, "sections must be in [1, 32]");
+  if (p->max_search_rounds < 1) return fail(PDHCG_ERR_ARG, "max_search_rounds must be >= 1");
+  if (p->step_mode != PDHCG_STEP_FIXED && p->step_mode != PDHCG_STEP_ADAPTIVE)
+    return fail(PDHCG_ERR_ARG, "unknown step_mode");
+  if (p->output < 0 || p->output > 2) return fail(PDHCG_ERR_ARG, "unknown output");
+  if (!p->normalize_rows)
+    return fail(PDHCG_ERR_UNSUPPORTED, "normalize_rows = 0 is not supported");
+  return PDHCG_OK;
+}
+
+RowIO row_io_state(const pdhcg_params *p) {
+  RowIO io;
+  std::memset(&io, 0, sizeof(io));
+  io.use_state = 1;
+  io.colsum = 1;
+  io.search = p->search;
+  io.sections = p->sections;
+  io.max_rounds = p->max_search_rounds;
+  io.rtol = p->search_rtol;
+  return io;
+}
+
+// One trial step: price step, row pass over every bin, column kernel.
+// ev0/ev1 (optional) bracket the row-pass launches.
+int32_t enqueue_step(pdhcg_market mk, const RowIO &io, hipEvent_t ev0 = nullptr,
+                     hipEvent_t ev1 = nullptr) {
+  const MarketDev md = mk->dev();
+  HIPC(launch_pstep(md, (mk->lds_row & 1) ? 0 : 1, mk->stream));
+  if (ev0) HIPC(hipEventRecord(ev0, mk->stream));
+  for (const Bin &b : mk->bins)
+    HIPC(launch_row_pass(md, mk->bindev(b), b.G, b.E, mk->lds_row, io, b.nwg, mk->stream));
+  if (ev1) HIPC(hipEventRecord(ev1, mk->stream));
+  HIPC(launch_col_decide(md, mk->total_wg, mk->lds_row & 1, mk->stream));
+  return PDHCG_OK;
+}
+
+// Per-solve HIP events for timing the row passes.
+struct EventPool {
+  std::vector<hipEvent_t> ev;
+  ~EventPool() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+  }
+};
+
+// KKT pass over (xc, pc) and optionally the averaged point.
+int32_t enqueue_eval(pdhcg_market mk, EvalIO io) {
+  const MarketDev md = mk->dev();
+  io.evalpart = mk->evalpart;
+  io.cacc = mk->cacc;
+  if (!mk->lds_eval) {
+    HIPC(hipMemsetAsync(mk->evalpart, 0, (size_t)2 * mk->m * sizeof(float), mk->stream));
+    HIPC(hipMemsetAsync(mk->cacc, 0, (size_t)mk->m * sizeof(double), mk->stream));
+  }
+  for (const Bin &b : mk->bins)
+    HIPC(launch_eval_row(md, mk->bindev(b), b.G, b.E, mk->lds_eval, io, b.nwg, mk->total_wg,
+                         mk->stream));
+  HIPC(launch_eval_col(md, io, mk->total_wg, mk->lds_eval, mk->stream));
+  return PDHCG_OK;
+}
+
+int32_t pull_state(pdhcg_market mk) {
+  HIPC(hipMemcpyAsync(mk->hS, mk->S, sizeof(DevState), hipMemcpyDeviceToHost, mk->stream));
+  HIPC(hipStreamSynchronize(mk->stream));
+  return PDHCG_OK;
+}
+
+int32_t push_state(pdhcg_market mk) {
+  HIPC(hipMemcpyAsync(mk->S, mk->hS, sizeof(DevState), hipMemcpyHostToDevice, mk->stream));
+  return PDHCG_OK;
+}
+
+double kkt_max(const double *k) { return std::max(k[0], std::max(k[1], k[2])); }
+
+}  // namespace
+
+extern "C" int32_t pdhcg_kkt(pdhcg_market mk, const float *p, const float *x, pdhcg_info *info) {
+  if (!mk || !p || !x) return fail(PDHCG_ERR_ARG, "null argument");
+  HIPC(launch_f32_to_f64(p, mk->Pk, mk->m, mk->stream));
+  EvalIO io;
+  std::memset(&io, 0, sizeof(io));
+  io.xc = x;
+  io.pc = mk->Pk;
+  io.want_cc = 1;
+  io.rowscale = mk->rowmax;
+  int32_t rc = enqueue_eval(mk, io);
+  if (rc != PDHCG_OK) return rc;
+  rc = pull_state(mk);
+  if (rc != PDHCG_OK) return rc;
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->rel_primal = mk->hS->kkt[0][0];
+    info->rel_dual = mk->hS->kkt[0][1];
+    info->rel_gap = mk->hS->kkt[0][2];
+    info->rel_kkt = kkt_max(mk->hS->kkt[0]);
+    info->status = PDHCG_OK;
+  }
+  return PDHCG_OK;
+}
+
+extern "C" int32_t pdhcg_row_prox(pdhcg_market mk, const float *x_in, const float *p, double tau,
+                                  const pdhcg_params *params, float *x_out, float *s_out) {
+  if (!mk || !x_in || !p || !x_out) return fail(PDHCG_ERR_ARG, "null argument");
+  if (!(tau > 0.0) || !std::isfinite(tau)) return fail(PDHCG_ERR_ARG, "tau must be finite and > 0");
+  pdhcg_params dflt;
+  pdhcg_default_params(&dflt);
+  const pdhcg_params *prm = params ? params : &dflt;
+  int32_t rc = check_params(prm);
+  if (rc != PDHCG_OK) return rc;
+  RowIO io = row_io_state(prm);
+  io.use_state = 0;
+  io.colsum = 0;
+  HIPC(launch_f32_to_f64(p, mk->Pk, mk->m, mk->stream));
+  io.xin = x_in;
+  io.p = mk->Pk;
+  io.xout = x_out;
+  io.s_out = s_out;
+  io.tau = tau;
+  io.wfold = 0.0f;
+  const MarketDev md = mk->dev();
+  for (const Bin &b : mk->bins)
+    HIPC(launch_row_pass(md, mk->bindev(b), b.G, b.E, mk->lds_row, io, b.nwg, mk->stream));
+  return PDHCG_OK;
+}
+
+extern "C" int32_t pdhcg_solve(pdhcg_market mk, const pdhcg_params *params, int32_t warm,
+                               float *p, float *x, float *t, pdhcg_info *info) {
+  if (!mk || !p || !x) return fail(PDHCG_ERR_ARG, "null argument");
+  pdhcg_params dflt;
+  pdhcg_default_params(&dflt);
+  const pdhcg_params *prm = params ? params : &dflt;
+  int32_t rc = check_params(prm);
+  if (rc != PDHCG_OK) return rc;
+  hipStream_t st = mk->stream;
+  const auto t0 = std::chrono::steady_clock::now();
+  const int m = mk->m;
+  const int64_t nnz = mk->nnz;
+
+  // Initial point (reading of Alg. 2's unspecified start): x0_ij = 1/deg_j
+  // (every column sums to one), p0_j = sum(w)/m (Sec. 3, Fact 1: the prices
+  // sum to the budgets).  A warm start copies the caller's point.
+  if (warm) {
+    HIPC(hipMemcpyAsync(mk->X[0], x, (size_t)nnz * 4, hipMemcpyDeviceToDevice, st));
+    HIPC(launch_f32_to_f64(p, mk->P[0], m, st));
+  } else {
+    HIPC(launch_init_point(mk->col, mk->deg, nnz, mk->X[0], mk->P[0], m,
+                           mk->sumw / (double)m, st));
+  }
+  DevState &S = *mk->hS;
+  std::memset(&S, 0, sizeof(S));
+  S.ix[0] = 0; S.ix[1] = 1; S.ix[2] = 2;
+  S.ip[0] = 0; S.ip[1] = 1; S.ip[2] = 2;
+  S.ic[0] = 0; S.ic[1] = 1; S.ic[2] = 2;
+  rc = push_state(mk);
+  if (rc != PDHCG_OK) return rc;
+
+  // Column sums and KKT error of the starting point.
+  {
+    EvalIO io;
+    std::memset(&io, 0, sizeof(io));
+    io.xc = mk->X[0];
+    io.pc = mk->P[0];
+    io.want_cc = 1;
+    io.cavg_out = mk->C[1];
+    io.rowscale = mk->rowmax;
+    rc = enqueue_eval(mk, io);
+    if (rc != PDHCG_OK) return rc;
+  }
+  rc = pull_state(mk);
+  if (rc != PDHCG_OK) return rc;
+  double kkt0 = kkt_max(S.kkt[0]);
+  HIPC(launch_copy_f64(mk->C[1], mk->C[0], m, st));
+  HIPC(launch_copy_f32(mk->X[0], mk->XA, nnz, st));
+  HIPC(launch_copy_f64(mk->P[0], mk->PA, m, st));
+
+  // Steps (Sec. 5): tau = eta/omega, sigma = eta*omega.
+  const double knorm = std::sqrt((double)mk->maxdeg_col);
+  const bool adaptive = prm->step_mode == PDHCG_STEP_ADAPTIVE;
+  const double eta0 = prm->eta0 > 0.0 ? prm->eta0 : (adaptive ? 1.0 : 0.9 / knorm);
+  const double omega0 = prm->omega0 > 0.0 ? prm->omega0 : 0.05 * mk->sumw / (double)m;
+  double omega = omega0;
+  std::memset(&S, 0, sizeof(S));
+  S.ix[0] = 0; S.ix[1] = 1; S.ix[2] = 2;
+  S.ip[0] = 0; S.ip[1] = 1; S.ip[2] = 2;
+  S.ic[0] = 0; S.ic[1] = 1; S.ic[2] = 2;
+  S.step_mode = adaptive ? 1 : 0;
+  S.eta = eta0;
+  S.eta0 = eta0;
+  S.eta_lo = 0.01 * eta0;
+  S.eta_hi = adaptive ? 3.0 * eta0 : eta0;
+  S.omega = omega;
+  S.tau = eta0 / omega;
+  S.sigma = eta0 * omega;
+  rc = push_state(mk);
+  if (rc != PDHCG_OK) return rc;
+
+  const RowIO step_io = row_io_state(prm);
+  EventPool pool;
+  if (prm->timing) {
+    pool.ev.resize(2 * (size_t)prm->eval_every, nullptr);
+    for (auto &e : pool.ev) HIPC(hipEventCreate(&e));
+  }
+  double row_seconds = 0.0;
+  int64_t row_launches = 0;
+  double kkt_prev = INFINITY, kbest = INFINITY, kout[3] = {NAN, NAN, NAN};
+  int32_t restarts = 0, evals = 0, status = PDHCG_MAX_ITER;
+  bool cand_avg = false;
+  int64_t total = 0;
+  while (true) {
+    const int64_t left = prm->max_iter - total;
+    const int64_t nstep = std::min<int64_t>(prm->eval_every - (total % prm->eval_every), left);
+    for (int64_t q = 0; q < nstep; ++q) {
+      if (prm->timing)
+        rc = enqueue_step(mk, step_io, pool.ev[2 * (size_t)q], pool.ev[2 * (size_t)q + 1]);
+      else
+        rc = enqueue_step(mk, step_io);
+      if (rc != PDHCG_OK) return rc;
+    }
+    rc = pull_state(mk);
+    if (rc != PDHCG_OK) return rc;
+    if (prm->timing) {
+      for (int64_t q = 0; q < nstep; ++q) {
+        float ms = 0.0f;
+        HIPC(hipEventElapsedTime(&ms, pool.ev[2 * (size_t)q], pool.ev[2 * (size_t)q + 1]));
+        row_seconds += 1e-3 * (double)ms;
+        ++row_launches;
+      }
+    }
+    if (S.total != total + nstep)
+      return fail(PDHCG_ERR_HIP, "device iteration counter did not advance as expected");
+    total = S.total;
+    // KKT check of the current and the averaged point (Sec. 5 Criteria).
+    const bool has_avg = S.k_in > 0;
+    EvalIO io;
+    std::memset(&io, 0, sizeof(io));
+    io.xc = mk->X[S.ix[0]];
+    io.pc = mk->P[S.ip[0]];
+    io.xa = has_avg ? mk->X[S.ix[2]] : nullptr;
+    io.pa = mk->P[S.ip[2]];
+    io.wfold = (has_avg && S.fold) ? (float)(1.0 / (double)S.k_in) : 0.0f;
+    io.xanc = mk->XA;
+    io.panc = mk->PA;
+    io.tc = mk->T[0];
+    io.ta = mk->T[1];
+    io.rowscale = mk->rowmax;
+    io.want_cc = 0;
+    io.ccur = mk->C[S.ic[1]];
+    io.cavg_out = mk->C[S.ic[2]];
+    io.pa_out = mk->P[S.ip[2]];
+    rc = enqueue_eval(mk, io);
+    if (rc != PDHCG_OK) return rc;
+    rc = pull_state(mk);
+    if (rc != PDHCG_OK) return rc;
+    S.fold = 0;
+    ++evals;
+    const double kc = kkt_max(S.kkt[0]);
+    const double ka = has_avg ? kkt_max(S.kkt[1]) : INFINITY;
+    if (!std::isfinite(kc) && !std::isfinite(ka)) {
+      status = PDHCG_ERR_NUMERIC;
+      fail(status, "non-finite KKT error at iteration " + std::to_string(total));
+      break;
+    }
+    cand_avg = ka < kc;
+    const double kcand = cand_avg ? ka : kc;
+    std::memcpy(kout, cand_avg ? S.kkt[1] : S.kkt[0], sizeof(kout));
+    kbest = kcand;
+    if (prm->verbose)
+      std::fprintf(stderr,
+                   "[pdhcg] it=%lld kin=%lld acc=%lld cur=%.3e (%.2e %.2e %.2e) avg=%.3e "
+                   "(%.2e %.2e %.2e) eta=%.3e omega=%.3e emax=%.3e dx2=%.3e/%.3e "
+                   "dp2=%.3e/%.3e\n",
+                   (long long)total, (long long)S.k_in, (long long)S.accepted, kc,
+                   S.kkt[0][0], S.kkt[0][1], S.kkt[0][2], ka, S.kkt[1][0], S.kkt[1][1],
+                   S.kkt[1][2], S.eta, omega, S.emax_last, S.dxa2[0], S.dxa2[1], S.dpa2[0],
+                   S.dpa2[1]);
+    if (kcand <= prm->tol) {
+      status = PDHCG_OK;
+      break;
+    }
+    if (total >= prm->max_iter) {
+      status = PDHCG_MAX_ITER;
+      break;
+    }
+    if (prm->restart == PDHCG_RESTART_ADAPTIVE) {
+      const bool do_restart =
+          (kcand <= prm->beta_sufficient * kkt0) ||
+          (kcand <= prm->beta_necessary * kkt0 && kcand > kkt_prev) ||
+          ((double)S.since >= prm->beta_artificial * (double)S.total);
+      if (do_restart) {
+        if (cand_avg) {
+          std::swap(S.ix[0], S.ix[2]);
+          std::swap(S.ip[0], S.ip[2]);
+          std::swap(S.ic[1], S.ic[2]);  // column sums of the average are in the trial slot
+        }
+        HIPC(launch_copy_f64(mk->C[S.ic[1]], mk->C[S.ic[0]], m, st));
+        HIPC(launch_copy_f32(mk->X[S.ix[0]], mk->XA, nnz, st));
+        HIPC(launch_copy_f64(mk->P[S.ip[0]], mk->PA, m, st));
+        const double dx = std::sqrt(S.dxa2[cand_avg ? 1 : 0]);
+        const double dp = std::sqrt(S.dpa2[cand_avg ? 1 : 0]);
+        if (dx > 1e-10 && dp > 1e-10)
+          omega = std::exp(prm->theta * std::log(dp / dx) + (1.0 - prm->theta) * std::log(omega));
+        ++restarts;
+        if (prm->omega_check_every > 0 && restarts % prm->omega_check_every == 0 &&
+            (omega < omega0 / prm->omega_bound || omega > omega0 * prm->omega_bound))
+          omega = omega0;
+        kkt0 = kcand;
+        kkt_prev = INFINITY;
+        S.k_in = 0;
+        S.since = 0;
+        cand_avg = false;
+      } else {
+        kkt_prev = kcand;
+      }
+    }
+    S.omega = omega;
+    S.tau = S.eta / omega;
+    S.sigma = S.eta * omega;
+    rc = push_state(mk);
+    if (rc != PDHCG_OK) return rc;
+  }
+
+  // Output the requested point.
+  bool out_avg = false;
+  if (prm->output == PDHCG_OUTPUT_CANDIDATE) out_avg = cand_avg;
+  if (prm->output == PDHCG_OUTPUT_AVERAGE) out_avg = S.k_in > 0;
+  const float *xs = mk->X[out_avg ? S.ix[2] : S.ix[0]];
+  const double *ps = mk->P[out_avg ? S.ip[2] : S.ip[0]];
+  HIPC(hipMemcpyAsync(x, xs, (size_t)nnz * 4, hipMemcpyDeviceToDevice, st));
+  HIPC(launch_f64_to_f32(ps, p, m, st));
+  if (t) HIPC(hipMemcpyAsync(t, mk->T[out_avg ? 1 : 0], (size_t)mk->n * 4, hipMemcpyDeviceToDevice, st));
+  if (prm->output != PDHCG_OUTPUT_CANDIDATE) {
+    const int z = out_avg ? 1 : 0;
+    std::memcpy(kout, S.kkt[z], sizeof(kout));
+    kbest = kkt_max(S.kkt[z]);
+  }
+  HIPC(hipStreamSynchronize(st));
+  const double secs =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (info) {
+    info->rel_kkt = kbest;
+    info->rel_primal = kout[0];
+    info->rel_dual = kout[1];
+    info->rel_gap = kout[2];
+    info->eta = S.eta;
+    info->omega = omega;
+    info->seconds = secs;
+    info->iters = S.total;
+    info->accepted = S.accepted;
+    info->restarts = restarts;
+    info->status = status;
+    info->evals = evals;
+    info->search_rounds_max = (int32_t)S.rounds_max;
+    info->search_rounds_mean =
+        S.rows_searched ? (double)S.rounds_sum / (double)S.rows_searched : 0.0;
+    info->row_pass_seconds = row_seconds;
+    info->row_pass_launches = row_launches;
+  }
+  return status;
+}
+
+extern "C" int32_t pdhcg_arrow_debreu(pdhcg_market mk, const int32_t *e_row_ptr,
+                                      const int32_t *e_col, const float *e_val, int64_t e_nnz,
+                                      const pdhcg_params *inner, double outer_tol,
+                                      int32_t outer_max, float *w, float *p, float *x,
+                                      int32_t *outer_iters, int64_t *inner_iters,
+                                      pdhcg_info *info) {
+  if (!mk || !e_row_ptr || !e_col || !e_val || !w || !p || !x)
+    return fail(PDHCG_ERR_ARG, "null argument");
+  if (e_nnz <= 0 || outer_max <= 0 || !(outer_tol >= 0.0))
+    return fail(PDHCG_ERR_ARG, "e_nnz > 0, outer_max > 0 and outer_tol >= 0 required");
+  hipStream_t st = mk->stream;
+  const int n = mk->n, m = mk->m;
+  // Validate E on the host: CSR shape, e >= 0, every agent owns something,
+  // every column sums to one (Sec. 4 normalisation) within 1e-4.
+  {
+    std::vector<int32_t> rp((size_t)n + 1), cl((size_t)e_nnz);
+    std::vector<float> ev((size_t)e_nnz);
+    HIPC(hipMemcpyAsync(rp.data(), e_row_ptr, rp.size() * 4, hipMemcpyDeviceToHost, st));
+    HIPC(hipMemcpyAsync(cl.data(), e_col, cl.size() * 4, hipMemcpyDeviceToHost, st));
+    HIPC(hipMemcpyAsync(ev.data(), e_val, ev.size() * 4, hipMemcpyDeviceToHost, st));
+    HIPC(hipStreamSynchronize(st));
+    if (rp[0] != 0 || (int64_t)rp[(size_t)n] != e_nnz) return fail(PDHCG_ERR_ARG, "bad E row_ptr");
+    std::vector<double> cs((size_t)m, 0.0);
+    for (int i = 0; i < n; ++i) {
+      if (rp[(size_t)i + 1] < rp[(size_t)i]) return fail(PDHCG_ERR_ARG, "bad E row_ptr");
+      bool owns = false;
+      for (int32_t k = rp[(size_t)i]; k < rp[(size_t)i + 1]; ++k) {
+        if (cl[(size_t)k] < 0 || cl[(size_t)k] >= m || !(ev[(size_t)k] >= 0.0f) ||
+            !std::isfinite(ev[(size_t)k]))
+          return fail(PDHCG_ERR_ARG, "bad E entry " + std::to_string(k));
+        cs[(size_t)cl[(size_t)k]] += ev[(size_t)k];
+        owns |= ev[(size_t)k] > 0.0f;
+      }
+      if (!owns) return fail(PDHCG_ERR_ASSUMPTION, "agent " + std::to_string(i) + " owns nothing");
+    }
+    for (int j = 0; j < m; ++j)
+      if (std::fabs(cs[(size_t)j] - 1.0) > 1e-4)
+        return fail(PDHCG_ERR_ARG, "column " + std::to_string(j) + " of E does not sum to one");
+  }
+  std::vector<float> pprev((size_t)m), pcur((size_t)m);
+  int32_t rc = PDHCG_MAX_ITER, k = 0;
+  int64_t tot_inner = 0;
+  pdhcg_info last;
+  std::memset(&last, 0, sizeof(last));
+  const auto t0 = std::chrono::steady_clock::now();
+  for (k = 0; k < outer_max; ++k) {
+    int32_t r = pdhcg_set_budgets(mk, w);
+    if (r != PDHCG_OK) return r;
+    r = pdhcg_solve(mk, inner, k > 0 ? 1 : 0, p, x, nullptr, &last);
+    tot_inner += last.iters;
+    if (r < 0) {
+      rc = r;
+      break;
+    }
+    HIPC(hipMemcpyAsync(pcur.data(), p, (size_t)m * 4, hipMemcpyDeviceToHost, st));
+    HIPC(launch_budget_spmv(e_row_ptr, e_col, e_val, p, w, n, st));
+    HIPC(hipStreamSynchronize(st));
+    double change = INFINITY;
+    if (k > 0) {
+      double num = 0.0, den = 0.0;
+      for (int j = 0; j < m; ++j) {
+        num = std::max(num, (double)std::fabs(pcur[(size_t)j] - pprev[(size_t)j]));
+        den = std::max(den, (double)std::fabs(pprev[(size_t)j]));
+      }
+      change = num / den;
+    }
+    pprev.swap(pcur);
+    if (inner && inner->verbose)
+      std::fprintf(stderr, "[pdhcg-ad] outer=%d inner_iters=%lld kkt=%.3e change=%.3e\n", k,
+                   (long long)last.iters, last.rel_kkt, change);
+    if (k > 0 && change <= outer_tol) {
+      rc = PDHCG_OK;
+      ++k;
+      break;
+    }
+  }
+  if (outer_iters) *outer_iters = k;
+  if (inner_iters) *inner_iters = tot_inner;
+  if (info) {
+    *info = last;
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    info->iters = tot_inner;
+    info->status = rc;
+  }
+  return rc;
+}

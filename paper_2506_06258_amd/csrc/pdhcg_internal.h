@@ -1,0 +1,146 @@
+// Internal declarations of the gfx950 PDHCG library (kernels <-> host side).
+// Not part of the public ABI (include/pdhcg.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace pdhcg {
+
+constexpr int kWave = 64;        // CDNA wavefront
+constexpr int kRowBlock = 512;   // threads per row-kernel workgroup (8 waves)
+constexpr int kColBlock = 256;   // threads per column-kernel block
+constexpr int kMaxSections = 32; // largest k of the k-section search
+constexpr int kRowStats = 4;     // per-workgroup partials of the row kernel
+constexpr int kEvalRowStats = 12;
+constexpr int kColStats = 2;
+constexpr int kEvalColStats = 12;
+constexpr int kColChunks = 16;   // partial-row chunks per column tile
+
+// Device-resident solver state.  The step kernels read it at launch and the
+// last block of the column kernel updates it (step-size rule, role swaps);
+// the host reads and rewrites it only while the stream is idle.
+struct DevState {
+  int32_t ix[3];  // allocation buffers: [0] current, [1] trial, [2] average
+  int32_t ip[3];  // price buffers, same roles
+  int32_t ic[3];  // column-sum buffers: [0] previous, [1] current, [2] trial
+  int32_t fold;   // 1: the current iterate is not yet in the averages
+  int32_t step_mode;
+  int32_t accept_last;
+  int32_t pad0;
+  int64_t total;     // iterations (trial steps) so far
+  int64_t since;     // iterations since the last restart
+  int64_t k_in;      // kept steps since the last restart
+  int64_t accepted;  // kept steps overall
+  double eta, omega, eta0, eta_lo, eta_hi, tau, sigma;
+  double emax_last;
+  uint32_t ticket;      // arrival counter of the column kernel
+  uint32_t ticket_eval; // arrival counter of the KKT column kernel
+  uint32_t rounds_max;
+  uint32_t pad1;
+  uint64_t rounds_sum;
+  uint64_t rows_searched;
+  // results of the last KKT evaluation: [0] current, [1] average
+  double kkt[2][3];     // r_primal, r_dual, r_gap
+  double dxa2[2];       // |x - x_anchor|^2
+  double dpa2[2];       // |p - p_anchor|^2
+};
+
+// Device view of one market (passed by value to kernels).
+struct MarketDev {
+  int32_t n, m;
+  int64_t nnz;
+  const int32_t *row_ptr;
+  const int32_t *col;
+  const float *uh;   // row-normalised utilities
+  const float *w;    // budgets
+  float *X0, *X1, *X2;
+  double *P0, *P1, *P2;  // prices (float64: O(m), updates fall below float32 resolution)
+  double *C0, *C1, *C2;
+  float *XA;         // restart anchor x^{n,0}
+  double *PA;        // restart anchor p^{n,0}
+  float *colpart;    // [total_wg][m] per-workgroup column partials
+  double *rowpart;   // [total_wg][kRowStats]
+  double *colblk;    // [col blocks][kColStats or kEvalColStats]
+  double *colchunk;  // [kColChunks][m] chunk sums of the column partials
+  uint32_t *tile_ticket; // [col blocks] arrival counters (zero between launches)
+  DevState *S;
+};
+
+// Rows handled by one kernel variant.
+struct BinDev {
+  const int32_t *rows;  // row ids of this bin
+  int32_t nrows;
+  int32_t wg_offset;    // first partial slot of this bin
+  int32_t rows_per_wg;
+};
+
+// Inputs/outputs of a row pass.  With use_state = 1 the kernel takes the
+// buffers and tau from DevState roles; otherwise from the fields below.
+struct RowIO {
+  const float *xin;
+  const double *p;
+  float *xout;
+  float *xavg;      // averaged allocation to fold xin into (nullable)
+  float *s_out;     // per-row root (nullable)
+  double tau;
+  float wfold;      // fold weight 1/k (0: no fold)
+  int32_t use_state;
+  int32_t colsum;   // accumulate column sums of xout
+  int32_t search;   // 0 active-set, 1 k-section
+  int32_t sections;
+  int32_t max_rounds;
+  double rtol;
+};
+
+// Inputs/outputs of a KKT pass over one or two points.
+struct EvalIO {
+  const float *xc;   // current allocation
+  const double *pc;  // current prices
+  float *xa;         // averaged allocation (nullable), folded in place
+  const double *pa;  // averaged prices (before the fold)
+  float wfold;       // fold weight for the averaged point (0: none)
+  const float *xanc; // restart anchor (nullable)
+  float *tc;         // per-row utility of the current point (nullable)
+  float *ta;         // per-row utility of the averaged point (nullable)
+  const float *rowscale; // multiply t by this (original units)
+  float *evalpart;   // partials: [3][total_wg][m] (LDS mode) or [2][m]
+  double *cacc;      // [m] float64 column-sum accumulator (non-LDS mode)
+  int32_t want_cc;   // sum the columns of xc (no average; ccur unused)
+  const double *ccur;// column sums of xc (float64) when !want_cc
+  double *cavg_out;  // receives the float64 column sums this pass computed
+                     // (of the averaged point, or of xc when want_cc)
+  double *pa_out;    // receives the folded averaged prices
+  const double *panc;// price anchor (nullable)
+};
+
+// Launchers (pdhcg_kernels.hip).
+hipError_t launch_row_pass(const MarketDev &md, const BinDev &bin, int G, int E,
+                           int lds_mode, const RowIO &io, int nwg, hipStream_t st);
+hipError_t launch_pstep(const MarketDev &md, int zero_ctry, hipStream_t st);
+hipError_t launch_col_decide(const MarketDev &md, int total_wg, int from_partials,
+                             hipStream_t st);
+hipError_t launch_eval_row(const MarketDev &md, const BinDev &bin, int G, int E,
+                           int lds_mode, const EvalIO &io, int nwg, int total_wg,
+                           hipStream_t st);
+hipError_t launch_eval_col(const MarketDev &md, const EvalIO &io, int total_wg,
+                           int partials, hipStream_t st);
+hipError_t launch_normalize(const int32_t *row_ptr, const float *u, float *uh,
+                            float *rowmax, int n, hipStream_t st);
+hipError_t launch_degrees(const int32_t *col, int64_t nnz, int32_t *deg, hipStream_t st);
+hipError_t launch_init_point(const int32_t *col, const int32_t *deg, int64_t nnz,
+                             float *x, double *p, int m, double p0, hipStream_t st);
+hipError_t launch_f32_to_f64(const float *src, double *dst, int64_t len, hipStream_t st);
+hipError_t launch_f64_to_f32(const double *src, float *dst, int64_t len, hipStream_t st);
+hipError_t launch_copy_f32(const float *src, float *dst, int64_t len, hipStream_t st);
+hipError_t launch_copy_f64(const double *src, double *dst, int64_t len, hipStream_t st);
+hipError_t launch_fill_f64(double *dst, double v, int64_t len, hipStream_t st);
+hipError_t launch_scale_rows(const float *t, const float *rowscale, float *out, int n,
+                             hipStream_t st);
+hipError_t launch_budget_spmv(const int32_t *e_row_ptr, const int32_t *e_col,
+                              const float *e_val, const float *p, float *w, int n,
+                              hipStream_t st);
+bool row_variant_exists(int G, int E);
+
+}  // namespace pdhcg

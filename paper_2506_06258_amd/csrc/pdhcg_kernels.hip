@@ -1,0 +1,1086 @@
+// HIP kernels (gfx950) of restarted PDHCG for linear Fisher markets.
+//
+// One iteration of Alg. 2 is three launches that read the device-resident
+// solver state (DevState):
+//   k_pstep      price step p_try = p + sigma (2 c - c_prev - 1)  (eq. update:py)
+//                and the lagged fold of the kept price into its average;
+//   k_row_pass   every buyer's prox subproblem (Sec. 2.2) on its CSR row,
+//                the lagged fold of the kept allocation into its average,
+//                |x_try - x|^2 and per-workgroup column sums of x_try;
+//   k_col_decide float64 column sums, dp^T K dx and |dp|^2, and in its last
+//                block the step-size rule (Sec. 5): keep or reject the trial,
+//                rotate buffer roles, next eta.
+// Every eval_every iterations k_eval_row / k_eval_col compute the relative
+// KKT error (Sec. 5 Criteria) of the current and averaged points in float64.
+//
+// Memory layout: CSR row_ptr/col int32, values float32 aligned with col.
+// A row is owned by a segment of G lanes of one wave (G in 4..64); lane r of
+// the segment holds the row entries r, r+G, ..., r+(E-1)G in registers for
+// the whole search, so the row is read from HBM once per iteration.  Loads
+// of a segment are contiguous.  Column sums are privatised per workgroup in
+// LDS and reduced in float64 by the column kernel.
+#include "pdhcg_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <cmath>
+#include <cstdint>
+
+namespace pdhcg {
+
+// ---------------------------------------------------------------- helpers --
+
+template <typename T>
+__device__ __forceinline__ T pick3(T a, T b, T c, int i) {
+  return i == 0 ? a : (i == 1 ? b : c);
+}
+
+// Cross-lane exchange of one 32-bit value within a wave.  Lane masks below
+// 16 use DPP (quad_perm / row mirrors), 16 uses ds_swizzle inside 32-lane
+// halves, 32 uses ds_bpermute.  For a sum or max every pairing works as
+// long as it combines disjoint partial results, which these do.
+template <int MASK>
+__device__ __forceinline__ int xchg32(int v) {
+  if constexpr (MASK == 1) {
+    return __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+  } else if constexpr (MASK == 2) {
+    return __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+  } else if constexpr (MASK == 4) {
+    return __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+  } else if constexpr (MASK == 8) {
+    return __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false);  // row_mirror
+  } else if constexpr (MASK == 16) {
+    return __builtin_amdgcn_ds_swizzle(v, 0x401F);  // lane ^ 16 within 32 lanes
+  } else {
+    return __shfl_xor(v, MASK);
+  }
+}
+
+template <int MASK>
+__device__ __forceinline__ double xchg64(double v) {
+  const int lo = xchg32<MASK>(__double2loint(v));
+  const int hi = xchg32<MASK>(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+// Sum / max over the aligned segment of G lanes; every lane gets the result.
+template <int G>
+__device__ __forceinline__ double seg_sum_d(double v) {
+  if constexpr (G >= 2) v += xchg64<1>(v);
+  if constexpr (G >= 4) v += xchg64<2>(v);
+  if constexpr (G >= 8) v += xchg64<4>(v);
+  if constexpr (G >= 16) v += xchg64<8>(v);
+  if constexpr (G >= 32) v += xchg64<16>(v);
+  if constexpr (G >= 64) v += xchg64<32>(v);
+  return v;
+}
+
+template <int G>
+__device__ __forceinline__ double seg_max_d(double v) {
+  if constexpr (G >= 2) v = fmax(v, xchg64<1>(v));
+  if constexpr (G >= 4) v = fmax(v, xchg64<2>(v));
+  if constexpr (G >= 8) v = fmax(v, xchg64<4>(v));
+  if constexpr (G >= 16) v = fmax(v, xchg64<8>(v));
+  if constexpr (G >= 32) v = fmax(v, xchg64<16>(v));
+  if constexpr (G >= 64) v = fmax(v, xchg64<32>(v));
+  return v;
+}
+
+// 1/x in float64 from the hardware reciprocal estimate and two
+// Newton-Raphson steps (each step squares the relative error).
+__device__ __forceinline__ double fast_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max_d(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+// Bits of a segment inside a wave ballot.
+template <int G>
+__device__ __forceinline__ bool seg_any(bool pred) {
+  const unsigned long long b = __ballot(pred);
+  if constexpr (G == 64) {
+    return b != 0ull;
+  } else {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int sh = lane & ~(G - 1);
+    return ((b >> sh) & ((1ull << G) - 1ull)) != 0ull;
+  }
+}
+
+// ------------------------------------------------------------- row pass ----
+
+// Positive root of s^2 - A s - B = 0 (B >= 0), float64, cancellation-free.
+__device__ __forceinline__ double pos_root_d(double A, double B) {
+  const double disc = sqrt(fma(A, A, 4.0 * B));
+  if (A >= 0.0) return 0.5 * (A + disc);
+  const double den = disc - A;
+  return den > 0.0 ? 2.0 * B * fast_rcp(den) : 0.0;
+}
+
+// Precision: the streamed per-edge data (u_hat, col, x, x_avg) is float32;
+// prices are float64 (O(m) values whose updates fall below float32
+// resolution near the solution), and the row root is found in float64:
+// x_new = x - tau p + tau w u / s subtracts two terms of size tau p to get
+// a term of the size of x, which float32 cannot resolve once tau p >> x.
+//
+// LDS_MODE bits: 1 = float32 column partials in LDS (else float64 global
+// atomics); 2 = float64 copy of the prices in LDS (else gathered from
+// global memory, where they stay L2-resident).
+template <int G, int E, int MODE, int LDS_MODE>
+__global__ __launch_bounds__(kRowBlock) void k_row_pass(MarketDev md, BinDev bin,
+                                                        RowIO io) {
+  extern __shared__ double lds_d[];
+  const int m = md.m;
+  const float *xin = io.xin;
+  const double *pp = io.p;
+  float *xout = io.xout;
+  float *xavg = io.xavg;
+  double tau = io.tau;
+  float wfold = io.wfold;
+  double *cglob = nullptr;
+  if (io.use_state) {
+    const DevState *S = md.S;
+    xin = pick3<float *>(md.X0, md.X1, md.X2, S->ix[0]);
+    xout = pick3<float *>(md.X0, md.X1, md.X2, S->ix[1]);
+    xavg = pick3<float *>(md.X0, md.X1, md.X2, S->ix[2]);
+    pp = pick3<double *>(md.P0, md.P1, md.P2, S->ip[1]);
+    cglob = pick3<double *>(md.C0, md.C1, md.C2, S->ic[2]);
+    tau = S->tau;
+    wfold = S->fold ? (float)(1.0 / (double)S->k_in) : 0.0f;
+  }
+  double *lp = lds_d;  // [m] prices (LDS_MODE & 2)
+  float *lc = reinterpret_cast<float *>((LDS_MODE & 2) ? lds_d + m : lds_d);  // [m] partials
+  if (LDS_MODE != 0) {
+    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+      if (LDS_MODE & 2) lp[j] = pp[j];
+      if (LDS_MODE & 1) lc[j] = 0.0f;
+    }
+    __syncthreads();
+  }
+
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  const int r = lane & (G - 1);         // lane inside the segment
+  const int seg = lane / G;             // segment inside the wave
+  constexpr int kSeg = kWave / G;       // rows per wave pass
+  constexpr int kWaves = kRowBlock / kWave;
+  const int wg = blockIdx.x;
+  const int row_lo = wg * bin.rows_per_wg;
+  const int row_hi = min(row_lo + bin.rows_per_wg, bin.nrows);
+  const double rtol = io.rtol;
+
+  float dx2 = 0.0f;
+  uint32_t rmax = 0;
+  uint32_t rsum = 0, rcount = 0;
+
+  for (int base = row_lo + wave * kSeg; base < row_hi; base += kWaves * kSeg) {
+    const int slot = base + seg;
+    const bool rv = slot < row_hi;
+    const int i = rv ? (bin.rows ? bin.rows[slot] : slot) : 0;
+    const int beg = rv ? md.row_ptr[i] : 0;
+    const int d = rv ? md.row_ptr[i + 1] - beg : 0;
+    const double tw = rv ? tau * (double)md.w[i] : 0.0;
+
+    double a[E], b[E];
+    float uh[E], xk[E];
+    int cj[E];
+    double s0 = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int idx = r + G * e;
+      const bool v = idx < d;
+      const int k = beg + idx;
+      float u = 0.0f, x = 0.0f;
+      double pj = 0.0;
+      int c = 0;
+      if (v) {
+        u = md.uh[k];
+        x = xin[k];
+        c = md.col[k];
+        pj = (LDS_MODE & 2) ? lp[c] : pp[c];
+      }
+      uh[e] = u;
+      xk[e] = x;
+      cj[e] = c;
+      a[e] = fma(-tau, pj, (double)x);  // x^k - tau p
+      b[e] = tw * (double)u;            // tau w u
+      s0 = fma((double)u, (double)x, s0);
+    }
+    // Lagged fold of the kept iterate into the running average (Alg. 2).
+    if (wfold != 0.0f) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int idx = r + G * e;
+        if (idx < d) {
+          const int k = beg + idx;
+          const float xb = xavg[k];
+          xavg[k] = (wfold == 1.0f) ? xk[e] : fmaf(xk[e] - xb, wfold, xb);
+        }
+      }
+    }
+    s0 = seg_sum_d<G>(s0);
+
+    // Trial value: s = u^T x^k (Alg. 3); if zero, the best single-good
+    // lower bound (the root of s = u_j (a_j + b_j/s) for one good j).
+    double s = s0;
+    if (!(s > 0.0)) {
+      double lb = 0.0;
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+        if (uh[e] > 0.0f)
+          lb = fmax(lb, pos_root_d((double)uh[e] * a[e], (double)uh[e] * b[e]));
+      lb = seg_max_d<G>(lb);
+      s = lb > 0.0 ? lb : 1.0;  // 1.0: ragged slot without entries
+    }
+
+    double L = 0.0, U = INFINITY;
+    double sfin = s;
+    bool done = !rv;
+    int rounds = 0;
+    if (MODE == 0) {
+      // Bracketing search with active-set trial points.  At trial s:
+      //   g(s) = sum_j u_j [a_j + b_j/s]_+ = A + B/s on the active set at s;
+      //   [min(s, g), max(s, g)] brackets s* (Sec. 2.2);
+      //   the positive root of s^2 - A s - B (the quadratic of the active
+      //   set at s) is a lower bound on s*, and it is s* itself once the
+      //   active set at that root equals the one at s.
+      for (int it = 0; it < io.max_rounds; ++it) {
+        if (!__any(!done)) break;
+        const double inv = fast_rcp(s);
+        double A = 0.0, B = 0.0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const double v = fma(b[e], inv, a[e]);
+          const double on = v > 0.0 ? (double)uh[e] : 0.0;
+          A = fma(on, a[e], A);
+          B = fma(on, b[e], B);
+        }
+        A = seg_sum_d<G>(A);
+        B = seg_sum_d<G>(B);
+        const double g = fma(B, inv, A);
+        const double sA = pos_root_d(A, B);
+        bool same = false;
+        if (sA > 0.0) {
+          const double invA = fast_rcp(sA);
+          bool diff = false;
+#pragma unroll
+          for (int e = 0; e < E; ++e) {
+            const bool on_s = fma(b[e], inv, a[e]) > 0.0;
+            const bool on_a = fma(b[e], invA, a[e]) > 0.0;
+            diff |= (on_s != on_a);
+          }
+          same = !seg_any<G>(diff);
+        }
+        if (!done) {
+          ++rounds;
+          U = fmin(U, fmax(s, g));
+          L = fmax(L, fmin(s, g));
+          if (sA > 0.0) L = fmax(L, sA);
+          if (same || sA == s) {
+            sfin = sA;
+            done = true;
+          } else if (U - L <= rtol * U) {
+            sfin = 0.5 * (L + U);
+            done = true;
+          } else {
+            // next trial: the best lower bound, or the bracket midpoint
+            // while no positive lower bound is known
+            s = (L > 0.0) ? L : 0.5 * U;
+            sfin = s;
+          }
+        }
+      }
+      if (!done) sfin = (U < INFINITY) ? 0.5 * (L + U) : s;
+    } else {
+      // k-section search (Sec. 2.2.1): bracket from the trial s = u^T x^k
+      // (Alg. 3), then rounds of K candidates s_l = L + l (U - L)/(K + 1),
+      // U = min(U, min_l max(s_l, g_l)), L = max(L, max_l min(s_l, g_l)).
+      {
+        const double inv = fast_rcp(s);
+        double g = 0.0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) g = fma((double)uh[e], fmax(fma(b[e], inv, a[e]), 0.0), g);
+        g = seg_sum_d<G>(g);
+        U = fmax(s, g);
+        L = fmin(s, g);
+      }
+      const int K = io.sections;
+      for (int it = 0; it < io.max_rounds; ++it) {
+        const bool need = !done && (U - L > rtol * U);
+        if (!__any(need)) break;
+        const double step = (U - L) / (double)(K + 1);
+        double nU = U, nL = L;
+        for (int l = 1; l <= K; ++l) {
+          const double sl = fma((double)l, step, L);
+          const double inv = fast_rcp(sl);
+          double acc = 0.0;
+#pragma unroll
+          for (int e = 0; e < E; ++e)
+            acc = fma((double)uh[e], fmax(fma(b[e], inv, a[e]), 0.0), acc);
+          const double gl = seg_sum_d<G>(acc);
+          nU = fmin(nU, fmax(sl, gl));
+          nL = fmax(nL, fmin(sl, gl));
+        }
+        if (need) {
+          ++rounds;
+          U = nU;
+          L = nL;
+        }
+      }
+      sfin = 0.5 * (L + U);
+    }
+
+    // x^{k+1} = [a + b/s]_+ (eq. bisection), |x^{k+1} - x^k|^2, column sums.
+    const double invf = fast_rcp(sfin);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int idx = r + G * e;
+      if (idx < d) {
+        const int k = beg + idx;
+        const float xn = (float)fmax(fma(b[e], invf, a[e]), 0.0);
+        xout[k] = xn;
+        const float df = xn - xk[e];
+        dx2 = fmaf(df, df, dx2);
+        if (io.colsum) {
+          if (LDS_MODE & 1)
+            atomicAdd(&lc[cj[e]], xn);
+          else
+            atomicAdd(&cglob[cj[e]], (double)xn);
+        }
+      }
+    }
+    if (rv && r == 0) {
+      if (io.s_out) io.s_out[i] = (float)sfin;
+      rmax = max(rmax, (uint32_t)rounds);
+      rsum += (uint32_t)rounds;
+      rcount += 1;
+    }
+  }
+
+  // Workgroup partials.
+  __shared__ double red[kWaves];
+  __shared__ uint32_t red_rmax, red_rsum, red_rcnt;
+  if (threadIdx.x == 0) {
+    red_rmax = 0;
+    red_rsum = 0;
+    red_rcnt = 0;
+  }
+  double dsum = wave_sum_d((double)dx2);
+  __syncthreads();
+  if (lane == 0) red[wave] = dsum;
+  if (rcount) {
+    atomicMax(&red_rmax, rmax);
+    atomicAdd(&red_rsum, rsum);
+    atomicAdd(&red_rcnt, rcount);
+  }
+  __syncthreads();
+  const int slot = bin.wg_offset + wg;
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < kWaves; ++q) t += red[q];
+    if (md.rowpart) {
+      md.rowpart[(size_t)slot * kRowStats + 0] = t;
+    }
+    if (io.use_state) {
+      atomicMax(&md.S->rounds_max, red_rmax);
+      atomicAdd((unsigned long long *)&md.S->rounds_sum, (unsigned long long)red_rsum);
+      atomicAdd((unsigned long long *)&md.S->rows_searched, (unsigned long long)red_rcnt);
+    }
+  }
+  if ((LDS_MODE & 1) && io.colsum) {
+    float *dst = md.colpart + (size_t)slot * m;
+    for (int j = threadIdx.x; j < m; j += blockDim.x) dst[j] = lc[j];
+  }
+}
+
+// ------------------------------------------------------------ price step ---
+
+__global__ __launch_bounds__(kColBlock) void k_pstep(MarketDev md, int zero_ctry) {
+  const DevState *S = md.S;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= md.m) return;
+  const double *pc = pick3<double *>(md.P0, md.P1, md.P2, S->ip[0]);
+  double *pt = pick3<double *>(md.P0, md.P1, md.P2, S->ip[1]);
+  double *pa = pick3<double *>(md.P0, md.P1, md.P2, S->ip[2]);
+  const double *cprev = pick3<double *>(md.C0, md.C1, md.C2, S->ic[0]);
+  const double *ccur = pick3<double *>(md.C0, md.C1, md.C2, S->ic[1]);
+  double *ctry = pick3<double *>(md.C0, md.C1, md.C2, S->ic[2]);
+  const double p = pc[j];
+  pt[j] = p + S->sigma * (2.0 * ccur[j] - cprev[j] - 1.0);
+  if (S->fold) {
+    const double q = pa[j];
+    pa[j] = (S->k_in == 1) ? p : q + (p - q) / (double)S->k_in;
+  }
+  if (zero_ctry) ctry[j] = 0.0;
+}
+
+// ---------------------------------------------- column sums + step rule ----
+
+// Grid (column tiles, chunks).  With per-workgroup partials, block (t, q)
+// sums partial rows [q*per, (q+1)*per) of tile t's columns into
+// colchunk[q][j]; the last chunk block of a tile to arrive adds the chunks
+// in a fixed order (deterministic float64 column sums), forms the tile's
+// dp^T (c_try - c) and |dp|^2, and the last tile to arrive applies the
+// step-size rule of Sec. 5 and updates DevState.  Without partials (global
+// atomics) there is one chunk and c_try is already complete.
+__global__ __launch_bounds__(kColBlock) void k_col_decide(MarketDev md, int total_wg,
+                                                          int from_partials) {
+  DevState *S = md.S;
+  const int m = md.m;
+  const int tile = blockIdx.x, q = blockIdx.y, nq = gridDim.y;
+  const int j = tile * kColBlock + threadIdx.x;
+  const double *pc = pick3<double *>(md.P0, md.P1, md.P2, S->ip[0]);
+  const double *pt = pick3<double *>(md.P0, md.P1, md.P2, S->ip[1]);
+  const double *ccur = pick3<double *>(md.C0, md.C1, md.C2, S->ic[1]);
+  double *ctry = pick3<double *>(md.C0, md.C1, md.C2, S->ic[2]);
+  __shared__ bool last_chunk, last_tile;
+  if (from_partials) {
+    const int per = (total_wg + nq - 1) / nq;
+    const int b0 = q * per, b1 = min(total_wg, b0 + per);
+    if (j < m) {
+      double c = 0.0;
+      const float *src = md.colpart + j;
+      int b = b0;
+      for (; b + 4 <= b1; b += 4) {
+        const float v0 = src[(size_t)(b + 0) * m];
+        const float v1 = src[(size_t)(b + 1) * m];
+        const float v2 = src[(size_t)(b + 2) * m];
+        const float v3 = src[(size_t)(b + 3) * m];
+        c += ((double)v0 + (double)v1) + ((double)v2 + (double)v3);
+      }
+      for (; b < b1; ++b) c += (double)src[(size_t)b * m];
+      md.colchunk[(size_t)q * m + j] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();
+      const uint32_t t = atomicAdd(&md.tile_ticket[tile], 1u);
+      last_chunk = (t == (uint32_t)nq - 1);
+    }
+    __syncthreads();
+    if (!last_chunk) return;
+    __threadfence();
+    if (j < m) {
+      double c = 0.0;
+      for (int k = 0; k < nq; ++k) c += md.colchunk[(size_t)k * m + j];
+      ctry[j] = c;
+    }
+    if (threadIdx.x == 0) md.tile_ticket[tile] = 0u;
+  }
+  double inter = 0.0, dp2 = 0.0;
+  if (j < m) {
+    const double c = ctry[j];
+    const double dp = pt[j] - pc[j];
+    inter = dp * (c - ccur[j]);
+    dp2 = dp * dp;
+  }
+  __shared__ double sh[2][kColBlock / kWave];
+  __shared__ double shx[kColBlock / kWave];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  inter = wave_sum_d(inter);
+  dp2 = wave_sum_d(dp2);
+  if (lane == 0) {
+    sh[0][wave] = inter;
+    sh[1][wave] = dp2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, qq = 0.0;
+    for (int w = 0; w < kColBlock / kWave; ++w) {
+      a += sh[0][w];
+      qq += sh[1][w];
+    }
+    md.colblk[(size_t)tile * kColStats + 0] = a;
+    md.colblk[(size_t)tile * kColStats + 1] = qq;
+    __threadfence();
+    const uint32_t t = atomicAdd(&S->ticket, 1u);
+    last_tile = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!last_tile) return;
+  __threadfence();
+  // Last tile: global sums and the step-size rule.
+  double a = 0.0, qq = 0.0, x2 = 0.0;
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
+    a += md.colblk[(size_t)b * kColStats + 0];
+    qq += md.colblk[(size_t)b * kColStats + 1];
+  }
+  for (int b = threadIdx.x; b < total_wg; b += blockDim.x) x2 += md.rowpart[(size_t)b * kRowStats];
+  a = wave_sum_d(a);
+  qq = wave_sum_d(qq);
+  x2 = wave_sum_d(x2);
+  __syncthreads();
+  if (lane == 0) {
+    sh[0][wave] = a;
+    sh[1][wave] = qq;
+    shx[wave] = x2;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  a = qq = x2 = 0.0;
+  for (int w = 0; w < kColBlock / kWave; ++w) {
+    a += sh[0][w];
+    qq += sh[1][w];
+    x2 += shx[w];
+  }
+  S->ticket = 0u;
+  S->total += 1;
+  S->since += 1;
+  bool accept = true;
+  if (S->step_mode == 1) {
+    // Adaptive step (Sec. 5): keep the trial when
+    // eta <= (omega |dx|^2 + |dp|^2 / omega) / (2 |dp^T K dx|).
+    const double om = S->omega, eta = S->eta;
+    const double emax = fabs(a) > 0.0 ? (om * x2 + qq / om) / (2.0 * fabs(a)) : INFINITY;
+    const double kk = (double)(S->total + 1);
+    double enew = fmin((1.0 - pow(kk, -0.3)) * emax, (1.0 + pow(kk, -0.6)) * eta);
+    enew = fmin(fmax(enew, S->eta_lo), S->eta_hi);
+    accept = (eta <= emax) || (eta <= S->eta_lo);
+    S->emax_last = emax;
+    S->eta = enew;
+    S->tau = enew / om;
+    S->sigma = enew * om;
+  }
+  if (accept) {
+    int t = S->ix[0]; S->ix[0] = S->ix[1]; S->ix[1] = t;
+    t = S->ip[0]; S->ip[0] = S->ip[1]; S->ip[1] = t;
+    const int cp = S->ic[0], cc = S->ic[1], ct = S->ic[2];
+    S->ic[0] = cc; S->ic[1] = ct; S->ic[2] = cp;
+    S->k_in += 1;
+    S->accepted += 1;
+    S->fold = 1;
+  } else {
+    S->fold = 0;
+  }
+  S->accept_last = accept ? 1 : 0;
+  __threadfence();
+}
+
+// ---------------------------------------------------------- KKT row pass ---
+
+// Per workgroup row statistics (float64):
+//  0 max y_c, 1 max gap_c, 2 max (p - u y)_+ c, 3 max x_c,
+//  4 max y_a, 5 max gap_a, 6 max (p - u y)_+ a, 7 max x_a,
+//  8 |x_c - anchor|^2, 9 |x_a - anchor|^2
+// Column quantities: M_c, M_a (column maxima of u_ij y_i, as float bits,
+// max-reduced as unsigned because they are non-negative) and the column
+// sums of the averaged point (or of the current point when want_cc).
+// LDS_MODE 1: per-workgroup partials in LDS, written to evalpart
+// [3][total_wg][m].  LDS_MODE 0: device-wide atomics into evalpart [2][m]
+// (maxima) and io.cacc [m] (float64 sums), all zeroed by the caller.
+template <int G, int E, int LDS_MODE>
+__global__ __launch_bounds__(kRowBlock) void k_eval_row(MarketDev md, BinDev bin,
+                                                        EvalIO io, int total_wg) {
+  extern __shared__ float lds[];
+  const int m = md.m;
+  const bool has_avg = io.xa != nullptr;
+  const bool sum_avg = has_avg && !io.want_cc;
+  unsigned int *lMc = reinterpret_cast<unsigned int *>(lds);
+  unsigned int *lMa = reinterpret_cast<unsigned int *>(lds + m);
+  float *lcs = lds + 2 * m;
+  if (LDS_MODE == 1) {
+    for (int j = threadIdx.x; j < 3 * m; j += blockDim.x) lds[j] = 0.0f;
+    __syncthreads();
+  }
+  const size_t TW = (LDS_MODE == 1) ? (size_t)total_wg * m : (size_t)m;
+  unsigned int *gMc = reinterpret_cast<unsigned int *>(io.evalpart);
+  unsigned int *gMa = reinterpret_cast<unsigned int *>(io.evalpart + TW);
+
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  const int r = lane & (G - 1);
+  const int seg = lane / G;
+  constexpr int kSeg = kWave / G;
+  constexpr int kWaves = kRowBlock / kWave;
+  const int wg = blockIdx.x;
+  const int row_lo = wg * bin.rows_per_wg;
+  const int row_hi = min(row_lo + bin.rows_per_wg, bin.nrows);
+  const float wf = io.wfold;
+
+  double st[10];
+#pragma unroll
+  for (int q = 0; q < 10; ++q) st[q] = 0.0;
+
+  for (int base = row_lo + wave * kSeg; base < row_hi; base += kWaves * kSeg) {
+    const int slot = base + seg;
+    const bool rv = slot < row_hi;
+    const int i = rv ? (bin.rows ? bin.rows[slot] : slot) : 0;
+    const int beg = rv ? md.row_ptr[i] : 0;
+    const int d = rv ? md.row_ptr[i + 1] - beg : 0;
+    const double wi = rv ? (double)md.w[i] : 0.0;
+    float uh[E], xc[E], xa[E];
+    double pcj[E], paj[E];
+    int cj[E];
+    double tc = 0.0, ta = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int idx = r + G * e;
+      const bool v = idx < d;
+      const int k = beg + idx;
+      float u = 0.0f, x = 0.0f, y = 0.0f;
+      double p = 0.0, q = 0.0;
+      int c = 0;
+      if (v) {
+        u = md.uh[k];
+        x = io.xc[k];
+        c = md.col[k];
+        p = io.pc[c];
+        if (has_avg) {
+          y = io.xa[k];
+          if (wf != 0.0f) {
+            y = (wf == 1.0f) ? x : fmaf(x - y, wf, y);
+            io.xa[k] = y;
+          }
+          q = io.pa[c];
+          if (wf != 0.0f) q = (wf == 1.0f) ? p : q + (p - q) * (double)wf;
+        }
+        if (io.xanc) {
+          const float z = io.xanc[k];
+          st[8] += (double)(x - z) * (double)(x - z);
+          if (has_avg) st[9] += (double)(y - z) * (double)(y - z);
+        }
+      }
+      uh[e] = u;
+      xc[e] = x;
+      xa[e] = y;
+      pcj[e] = p;
+      paj[e] = q;
+      cj[e] = c;
+      tc += (double)u * (double)x;
+      ta += (double)u * (double)y;
+    }
+    tc = seg_sum_d<G>(tc);
+    ta = seg_sum_d<G>(ta);
+    const double yc = rv ? wi / tc : 0.0;
+    const double ya = (rv && has_avg) ? wi / ta : 0.0;
+    if (rv && r == 0) {
+      if (io.tc) io.tc[i] = (float)(tc * (double)io.rowscale[i]);
+      if (io.ta && has_avg) io.ta[i] = (float)(ta * (double)io.rowscale[i]);
+      st[0] = fmax(st[0], yc);
+      st[4] = fmax(st[4], ya);
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int idx = r + G * e;
+      if (idx < d) {
+        const int c = cj[e];
+        const double vc = (double)uh[e] * yc;
+        const double rc = pcj[e] - vc;
+        if (rc > 0.0) {
+          st[2] = fmax(st[2], rc);
+          st[1] = fmax(st[1], (double)xc[e] * rc);
+        }
+        st[3] = fmax(st[3], (double)xc[e]);
+        const unsigned int bc = __float_as_uint((float)vc);
+        if (LDS_MODE == 1) atomicMax(&lMc[c], bc);
+        else atomicMax(&gMc[c], bc);
+        if (has_avg) {
+          const double va = (double)uh[e] * ya;
+          const double ra = paj[e] - va;
+          if (ra > 0.0) {
+            st[6] = fmax(st[6], ra);
+            st[5] = fmax(st[5], (double)xa[e] * ra);
+          }
+          st[7] = fmax(st[7], (double)xa[e]);
+          const unsigned int ba = __float_as_uint((float)va);
+          if (LDS_MODE == 1) atomicMax(&lMa[c], ba);
+          else atomicMax(&gMa[c], ba);
+        }
+        if (sum_avg || io.want_cc) {
+          const float add = io.want_cc ? xc[e] : xa[e];
+          if (LDS_MODE == 1) atomicAdd(&lcs[c], add);
+          else atomicAdd(&io.cacc[c], (double)add);
+        }
+      }
+    }
+  }
+  __shared__ double red[kWaves][10];
+#pragma unroll
+  for (int q = 0; q < 10; ++q) {
+    const double v = (q >= 8) ? wave_sum_d(st[q]) : wave_max_d(st[q]);
+    if (lane == 0) red[wave][q] = v;
+  }
+  __syncthreads();
+  const int slot = bin.wg_offset + wg;
+  if (threadIdx.x < 10) {
+    const int q = threadIdx.x;
+    double v = red[0][q];
+    for (int w = 1; w < kWaves; ++w) v = (q >= 8) ? v + red[w][q] : fmax(v, red[w][q]);
+    md.rowpart[(size_t)slot * kEvalRowStats + q] = v;
+  }
+  if (LDS_MODE == 1) {
+    unsigned int *dMc = gMc + (size_t)slot * m;
+    unsigned int *dMa = gMa + (size_t)slot * m;
+    float *dcs = io.evalpart + 2 * TW + (size_t)slot * m;
+    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+      dMc[j] = lMc[j];
+      dMa[j] = lMa[j];
+      dcs[j] = lcs[j];
+    }
+  }
+}
+
+// ------------------------------------------------------- KKT column pass ---
+
+// Column statistics per block (float64):
+//  0 max |c_c - 1|, 1 max |c_c|, 2 max (M_c - p_c)_+, 3 max (p_c - M_c),
+//  4 max |c_a - 1|, 5 max |c_a|, 6 max (M_a - p_a)_+, 7 max (p_a - M_a),
+//  8 |p_c - p_anchor|^2, 9 |p_a - p_anchor|^2
+// The last block combines them with the row statistics into the relative
+// KKT error of Sec. 5 and writes it, with the anchor distances, to DevState.
+__global__ __launch_bounds__(kColBlock) void k_eval_col(MarketDev md, EvalIO io, int total_wg,
+                                                        int partials) {
+  DevState *S = md.S;
+  const int m = md.m;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool has_avg = io.xa != nullptr;
+  const bool sum_avg = has_avg && !io.want_cc;
+  const size_t TW = partials ? (size_t)total_wg * m : (size_t)m;
+  double st[10];
+  for (int q = 0; q < 10; ++q) st[q] = 0.0;
+  st[3] = -INFINITY;
+  st[7] = -INFINITY;
+  if (j < m) {
+    unsigned int bMc = 0u, bMa = 0u;
+    double cs = 0.0;
+    const unsigned int *sMc = reinterpret_cast<const unsigned int *>(io.evalpart) + j;
+    const unsigned int *sMa = reinterpret_cast<const unsigned int *>(io.evalpart + TW) + j;
+    if (partials) {
+      const float *scs = io.evalpart + 2 * TW + j;
+      for (int b = 0; b < total_wg; ++b) {
+        bMc = max(bMc, sMc[(size_t)b * m]);
+        if (has_avg) bMa = max(bMa, sMa[(size_t)b * m]);
+        if (sum_avg || io.want_cc) cs += (double)scs[(size_t)b * m];
+      }
+    } else {
+      bMc = sMc[0];
+      if (has_avg) bMa = sMa[0];
+      if (sum_avg || io.want_cc) cs = io.cacc[j];
+    }
+    const double Mc = (double)__uint_as_float(bMc);
+    const double Ma = (double)__uint_as_float(bMa);
+    const double cc = io.want_cc ? cs : io.ccur[j];
+    const double pc = io.pc[j];
+    st[0] = fabs(cc - 1.0);
+    st[1] = fabs(cc);
+    st[2] = fmax(0.0, Mc - pc);
+    st[3] = pc - Mc;
+    if (io.panc) st[8] = (pc - io.panc[j]) * (pc - io.panc[j]);
+    if ((sum_avg || io.want_cc) && io.cavg_out) io.cavg_out[j] = cs;
+    if (has_avg) {
+      double q = io.pa[j];
+      if (io.wfold != 0.0f) q = (io.wfold == 1.0f) ? pc : q + (pc - q) * (double)io.wfold;
+      if (io.pa_out) io.pa_out[j] = q;
+      const double pa = q;
+      st[4] = fabs(cs - 1.0);
+      st[5] = fabs(cs);
+      st[6] = fmax(0.0, Ma - pa);
+      st[7] = pa - Ma;
+      if (io.panc) st[9] = (pa - io.panc[j]) * (pa - io.panc[j]);
+    }
+  }
+  __shared__ double red[kColBlock / kWave][10];
+  __shared__ bool last;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  for (int q = 0; q < 10; ++q) {
+    const double v = (q >= 8) ? wave_sum_d(st[q]) : wave_max_d(st[q]);
+    if (lane == 0) red[wave][q] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 0; q < 10; ++q) {
+      double v = red[0][q];
+      for (int w = 1; w < kColBlock / kWave; ++w)
+        v = (q >= 8) ? v + red[w][q] : fmax(v, red[w][q]);
+      md.colblk[(size_t)blockIdx.x * kEvalColStats + q] = v;
+    }
+    __threadfence();
+    const uint32_t t = atomicAdd(&S->ticket_eval, 1u);
+    last = (t == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  if (threadIdx.x != 0) return;
+  double c[10], rw[10];
+  for (int q = 0; q < 10; ++q) {
+    c[q] = (q == 3 || q == 7) ? -INFINITY : 0.0;
+    rw[q] = 0.0;
+  }
+  for (int b = 0; b < (int)gridDim.x; ++b)
+    for (int q = 0; q < 10; ++q) {
+      const double v = md.colblk[(size_t)b * kEvalColStats + q];
+      c[q] = (q >= 8) ? c[q] + v : fmax(c[q], v);
+    }
+  for (int b = 0; b < total_wg; ++b)
+    for (int q = 0; q < 10; ++q) {
+      const double v = md.rowpart[(size_t)b * kEvalRowStats + q];
+      rw[q] = (q >= 8) ? rw[q] + v : fmax(rw[q], v);
+    }
+  // Relative KKT error (Sec. 5 Criteria) with t = Ux, y = w / t:
+  //   r_primal = max|c - 1| / (1 + max(max|c|, 1))
+  //   r_dual   = max (M - p)_+ / (1 + max(max y, max (p - M)))
+  //   r_gap    = max x (p - u y)_+ / (1 + max(max x, max (p - u y)_+))
+  for (int z = 0; z < 2; ++z) {
+    const int o = 4 * z;
+    S->kkt[z][0] = c[o + 0] / (1.0 + fmax(c[o + 1], 1.0));
+    S->kkt[z][1] = c[o + 2] / (1.0 + fmax(rw[o + 0], c[o + 3]));
+    S->kkt[z][2] = rw[o + 1] / (1.0 + fmax(rw[o + 3], rw[o + 2]));
+  }
+  S->dxa2[0] = rw[8];
+  S->dxa2[1] = rw[9];
+  S->dpa2[0] = c[8];
+  S->dpa2[1] = c[9];
+  S->ticket_eval = 0u;
+  __threadfence();
+}
+
+// ------------------------------------------------------------ utilities ----
+
+__global__ void k_normalize(const int32_t *row_ptr, const float *u, float *uh, float *rowmax,
+                            int n) {
+  // one wave per row
+  const int lane = threadIdx.x & (kWave - 1);
+  const int i = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (i >= n) return;
+  const int b = row_ptr[i], e = row_ptr[i + 1];
+  float mx = 0.0f;
+  for (int k = b + lane; k < e; k += kWave) mx = fmaxf(mx, u[k]);
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o));
+  for (int k = b + lane; k < e; k += kWave) uh[k] = u[k] / mx;
+  if (lane == 0) rowmax[i] = mx;
+}
+
+__global__ void k_degrees(const int32_t *col, int64_t nnz, int32_t *deg) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nnz;
+       k += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&deg[col[k]], 1);
+}
+
+__global__ void k_init_point(const int32_t *col, const int32_t *deg, int64_t nnz, float *x,
+                             double *p, int m, double p0) {
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = g; k < nnz; k += stride) x[k] = 1.0f / (float)deg[col[k]];
+  for (int64_t j = g; j < m; j += stride) p[j] = p0;
+}
+
+__global__ void k_copy_f32(const float *src, float *dst, int64_t len) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < len;
+       k += (int64_t)gridDim.x * blockDim.x)
+    dst[k] = src[k];
+}
+
+__global__ void k_copy_f64(const double *src, double *dst, int64_t len) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < len;
+       k += (int64_t)gridDim.x * blockDim.x)
+    dst[k] = src[k];
+}
+
+__global__ void k_f32_to_f64(const float *src, double *dst, int64_t len) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < len;
+       k += (int64_t)gridDim.x * blockDim.x)
+    dst[k] = (double)src[k];
+}
+
+__global__ void k_f64_to_f32(const double *src, float *dst, int64_t len) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < len;
+       k += (int64_t)gridDim.x * blockDim.x)
+    dst[k] = (float)src[k];
+}
+
+__global__ void k_fill_f64(double *dst, double v, int64_t len) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < len;
+       k += (int64_t)gridDim.x * blockDim.x)
+    dst[k] = v;
+}
+
+__global__ void k_scale_rows(const float *t, const float *s, float *out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = t[i] * s[i];
+}
+
+// w_i = sum_j e_ij p_j (Alg. 4), one wave per agent.
+__global__ void k_budget_spmv(const int32_t *rp, const int32_t *col, const float *val,
+                              const float *p, float *w, int n) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int i = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int k = rp[i] + lane; k < rp[i + 1]; k += kWave) s += (double)val[k] * (double)p[col[k]];
+  s = wave_sum_d(s);
+  if (lane == 0) w[i] = (float)s;
+}
+
+// -------------------------------------------------------------- launchers --
+
+static int grid_for(int64_t len, int block) {
+  int64_t g = (len + block - 1) / block;
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+#define PDHCG_ROW_VARIANTS(X) \
+  X(4, 1) X(4, 2) X(4, 4) X(4, 8) \
+  X(8, 1) X(8, 2) X(8, 4) X(8, 8) \
+  X(16, 1) X(16, 2) X(16, 4) X(16, 8) \
+  X(32, 1) X(32, 2) X(32, 4) X(32, 8) \
+  X(64, 1) X(64, 2) X(64, 4) X(64, 8) X(64, 16)
+
+bool row_variant_exists(int G, int E) {
+#define PDHCG_EXISTS(g, e) \
+  if (G == g && E == e) return true;
+  PDHCG_ROW_VARIANTS(PDHCG_EXISTS)
+#undef PDHCG_EXISTS
+  return false;
+}
+
+template <int G, int E, int MODE, int LDSM>
+static hipError_t row_launch_t(const MarketDev &md, const BinDev &bin, const RowIO &io, int nwg,
+                               hipStream_t st) {
+  const size_t shm = (size_t)md.m * (((LDSM & 2) ? sizeof(double) : 0) +
+                                      ((LDSM & 1) ? sizeof(float) : 0));
+  hipLaunchKernelGGL((k_row_pass<G, E, MODE, LDSM>), dim3(nwg), dim3(kRowBlock), shm, st, md,
+                     bin, io);
+  return hipGetLastError();
+}
+
+hipError_t launch_row_pass(const MarketDev &md, const BinDev &bin, int G, int E, int lds_mode,
+                           const RowIO &io, int nwg, hipStream_t st) {
+  const int mode = io.search;
+#define PDHCG_ROW_LDS(g, e, md_)                                                  \
+  switch (lds_mode) {                                                             \
+    case 3: return row_launch_t<g, e, md_, 3>(md, bin, io, nwg, st);              \
+    case 1: return row_launch_t<g, e, md_, 1>(md, bin, io, nwg, st);              \
+    case 0: return row_launch_t<g, e, md_, 0>(md, bin, io, nwg, st);              \
+    default: return hipErrorInvalidValue;                                         \
+  }
+#define PDHCG_ROW_DISPATCH(g, e)                                                   \
+  if (G == g && E == e) {                                                          \
+    if (mode == 0) { PDHCG_ROW_LDS(g, e, 0) }                                     \
+    PDHCG_ROW_LDS(g, e, 1)                                                         \
+  }
+  PDHCG_ROW_VARIANTS(PDHCG_ROW_DISPATCH)
+#undef PDHCG_ROW_DISPATCH
+#undef PDHCG_ROW_LDS
+  return hipErrorInvalidValue;
+}
+
+template <int G, int E, int LDSM>
+static hipError_t eval_launch_t(const MarketDev &md, const BinDev &bin, const EvalIO &io,
+                                int nwg, int total_wg, hipStream_t st) {
+  const size_t shm = LDSM == 1 ? (size_t)3 * md.m * sizeof(float) : 0;
+  hipLaunchKernelGGL((k_eval_row<G, E, LDSM>), dim3(nwg), dim3(kRowBlock), shm, st, md, bin,
+                     io, total_wg);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_row(const MarketDev &md, const BinDev &bin, int G, int E, int lds_mode,
+                           const EvalIO &io, int nwg, int total_wg, hipStream_t st) {
+#define PDHCG_EVAL_DISPATCH(g, e)                                                    \
+  if (G == g && E == e)                                                              \
+    return lds_mode ? eval_launch_t<g, e, 1>(md, bin, io, nwg, total_wg, st)        \
+                    : eval_launch_t<g, e, 0>(md, bin, io, nwg, total_wg, st);
+  PDHCG_ROW_VARIANTS(PDHCG_EVAL_DISPATCH)
+#undef PDHCG_EVAL_DISPATCH
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_pstep(const MarketDev &md, int zero_ctry, hipStream_t st) {
+  hipLaunchKernelGGL(k_pstep, dim3((md.m + kColBlock - 1) / kColBlock), dim3(kColBlock), 0, st,
+                     md, zero_ctry);
+  return hipGetLastError();
+}
+
+hipError_t launch_col_decide(const MarketDev &md, int total_wg, int from_partials,
+                             hipStream_t st) {
+  const int tiles = (md.m + kColBlock - 1) / kColBlock;
+  const int chunks = from_partials ? (total_wg < kColChunks ? total_wg : kColChunks) : 1;
+  hipLaunchKernelGGL(k_col_decide, dim3(tiles, chunks), dim3(kColBlock), 0, st, md, total_wg,
+                     from_partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_col(const MarketDev &md, const EvalIO &io, int total_wg,
+                           int partials, hipStream_t st) {
+  hipLaunchKernelGGL(k_eval_col, dim3((md.m + kColBlock - 1) / kColBlock), dim3(kColBlock), 0,
+                     st, md, io, total_wg, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_normalize(const int32_t *row_ptr, const float *u, float *uh, float *rowmax,
+                            int n, hipStream_t st) {
+  const int rows_per_block = 256 / kWave;
+  hipLaunchKernelGGL(k_normalize, dim3((n + rows_per_block - 1) / rows_per_block), dim3(256), 0,
+                     st, row_ptr, u, uh, rowmax, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_degrees(const int32_t *col, int64_t nnz, int32_t *deg, hipStream_t st) {
+  hipLaunchKernelGGL(k_degrees, dim3(grid_for(nnz, 256)), dim3(256), 0, st, col, nnz, deg);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_point(const int32_t *col, const int32_t *deg, int64_t nnz, float *x,
+                             double *p, int m, double p0, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_point, dim3(grid_for(nnz > m ? nnz : m, 256)), dim3(256), 0, st, col,
+                     deg, nnz, x, p, m, p0);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_f32(const float *src, float *dst, int64_t len, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_f32, dim3(grid_for(len, 256)), dim3(256), 0, st, src, dst, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_f64(const double *src, double *dst, int64_t len, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_f64, dim3(grid_for(len, 256)), dim3(256), 0, st, src, dst, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_f32_to_f64(const float *src, double *dst, int64_t len, hipStream_t st) {
+  hipLaunchKernelGGL(k_f32_to_f64, dim3(grid_for(len, 256)), dim3(256), 0, st, src, dst, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_f64_to_f32(const double *src, float *dst, int64_t len, hipStream_t st) {
+  hipLaunchKernelGGL(k_f64_to_f32, dim3(grid_for(len, 256)), dim3(256), 0, st, src, dst, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_f64(double *dst, double v, int64_t len, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(len, 256)), dim3(256), 0, st, dst, v, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_rows(const float *t, const float *rowscale, float *out, int n,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_rows, dim3((n + 255) / 256), dim3(256), 0, st, t, rowscale, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_budget_spmv(const int32_t *e_row_ptr, const int32_t *e_col, const float *e_val,
+                              const float *p, float *w, int n, hipStream_t st) {
+  const int rows_per_block = 256 / kWave;
+  hipLaunchKernelGGL(k_budget_spmv, dim3((n + rows_per_block - 1) / rows_per_block), dim3(256),
+                     0, st, e_row_ptr, e_col, e_val, p, w, n);
+  return hipGetLastError();
+}
+
+}  // namespace pdhcg

@@ -1,0 +1,227 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.
+
+Tolerances come from the arithmetic of the device path:
+* row prox (Sec. 2.2): the root is found in float64, but the device
+  normalises u in float32 and stores x in float32, so
+  |x_gpu - x_exact| <= 64 eps32 (|a_j| + b_j/s*) per entry, where
+  a_j = x^k_j - tau p_j and b_j = tau w u_j are the entry's two terms, and
+  |s_gpu - s*| <= 1e-5 s*;
+* trajectories (fixed step, no restarts): float32 rounding of O(1e-7) per
+  step grows slowly over 40 steps; prices and allocations agree to 2e-4 of
+  their scale;
+* solves: relative price error <= 1e-5 at relative KKT <= 1e-6 (prices are
+  unique, Sec. 3 Fact 1; allocations are not, so x is checked through the
+  equilibrium conditions instead of elementwise).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2506_06258_amd import pdhcg, synth
+
+pytestmark = pytest.mark.gpu
+EPS32 = 2.0 ** -23
+
+
+def tensors(mk, dev):
+    return (torch.as_tensor(mk.row_ptr, dtype=torch.int32, device=dev),
+            torch.as_tensor(mk.col, dtype=torch.int32, device=dev),
+            torch.as_tensor(mk.u, dtype=torch.float32, device=dev),
+            torch.as_tensor(mk.w, dtype=torch.float32, device=dev))
+
+
+def f32(mk):
+    return mk.as_float32()
+
+
+def rel_err(p, q):
+    return float(np.max(np.abs(p - q)) / np.max(np.abs(q)))
+
+
+def prox_state(mk, rng, kind):
+    deg = np.bincount(mk.col, minlength=mk.m)
+    if kind == "init":
+        x = 1.0 / deg[mk.col]
+    elif kind == "random":
+        x = rng.uniform(0, 2.0 / deg[mk.col]) * (rng.random(mk.nnz) < 0.6)
+    else:  # sparse: most entries zero
+        x = rng.uniform(0, 0.5, mk.nnz) * (rng.random(mk.nnz) < 0.05)
+    p = float(mk.w.sum() / mk.m) * rng.uniform(0.5, 1.5, mk.m)
+    return x.astype(np.float32), p.astype(np.float32)
+
+
+def check_row_prox(mk, dev, x_in, p, tau, params=None):
+    M = pdhcg.Market.from_synth(mk, device=dev)
+    xg, sg = M.row_prox(torch.as_tensor(x_in, device=dev), torch.as_tensor(p, device=dev), tau,
+                        params)
+    torch.cuda.synchronize()
+    xg, sg = xg.cpu().numpy().astype(np.float64), sg.cpu().numpy().astype(np.float64)
+    uh, _ = oracle.normalize_rows(mk.row_ptr, mk.u.astype(np.float64))
+    x_ref, s_ref = oracle.row_prox_all(mk.row_ptr, mk.col, uh, mk.w, x_in, p, tau)
+    rows = mk.rows()
+    a = x_in.astype(np.float64) - tau * p.astype(np.float64)[mk.col]
+    b = tau * mk.w.astype(np.float64)[rows] * uh
+    scale = np.abs(a) + b / s_ref[rows]
+    err = np.abs(xg - x_ref)
+    bad = err > 64 * EPS32 * scale + 1e-30
+    assert not bad.any(), (f"{bad.sum()} entries off; worst ratio "
+                           f"{np.max(err / (scale + 1e-300)) / EPS32:.1f} eps32")
+    assert np.max(np.abs(sg - s_ref) / s_ref) < 1e-5
+    M.close()
+
+
+@pytest.mark.parametrize("kind", ["init", "random", "sparse"])
+@pytest.mark.parametrize("tau_scale", [1e-3, 1e-1, 10.0])
+def test_row_prox_small_market(cuda, kind, tau_scale):
+    mk = f32(synth.fisher_small(0))
+    rng = np.random.default_rng(hash((kind, tau_scale)) % 2**32)
+    x_in, p = prox_state(mk, rng, kind)
+    check_row_prox(mk, cuda, x_in, p, tau_scale / (mk.w.sum() / mk.m))
+
+
+@pytest.mark.parametrize("search,sections", [(pdhcg.PDHCG_SEARCH_KSECTION, 32),
+                                             (pdhcg.PDHCG_SEARCH_KSECTION, 4),
+                                             (pdhcg.PDHCG_SEARCH_ACTIVESET, 32)])
+def test_row_prox_search_variants(cuda, search, sections):
+    mk = f32(synth.fisher_small(1))
+    rng = np.random.default_rng(7)
+    x_in, p = prox_state(mk, rng, "random")
+    prm = pdhcg.pdhcg_default_params(search=search, sections=sections, max_search_rounds=40)
+    check_row_prox(mk, cuda, x_in, p, 0.05, prm)
+
+
+@pytest.mark.parametrize("d", [1, 3, 8, 17, 40, 64, 100, 129, 257, 500])
+def test_row_prox_degree_variants(cuda, d):
+    """Every row-kernel shape (lanes x entries) with a ragged last pass."""
+    n = 997
+    m = max(d, 60)
+    mk = f32(synth.fixed_degree_market(n, m, d, 100 + d, "uniform"))
+    M = pdhcg.Market.from_synth(mk, device=cuda)
+    (G, E, rows), = M.bins()
+    assert G * E >= d and rows == n
+    M.close()
+    rng = np.random.default_rng(d)
+    x_in, p = prox_state(mk, rng, "random")
+    check_row_prox(mk, cuda, x_in, p, 0.3 / (mk.w.sum() / mk.m))
+
+
+def test_row_prox_mixed_degrees(cuda):
+    """Several bins in one market (Bernoulli degrees spread over shapes)."""
+    rng = np.random.default_rng(3)
+    mk = f32(synth.bernoulli_market(3000, 700, 0.04, 5, w_mode="uniform"))
+    # add a few long rows
+    assert len(pdhcg.Market.from_synth(mk, device=cuda).bins()) >= 2
+    x_in, p = prox_state(mk, rng, "random")
+    check_row_prox(mk, cuda, x_in, p, 0.01)
+
+
+def trajectory(mk, dev, iters, **kw):
+    deg = np.bincount(mk.col, minlength=mk.m)
+    eta = 0.9 / np.sqrt(deg.max())
+    omega = 0.05 * float(mk.w.astype(np.float64).sum()) / mk.m
+    common = dict(tol=0.0, max_iter=iters, eval_every=16, step_mode=0, restart=0,
+                  eta0=eta, omega0=omega, output=1)
+    M = pdhcg.Market.from_synth(mk, device=dev)
+    g = M.solve(**common, **kw)
+    ora = oracle.solve(mk.n, mk.m, mk.row_ptr, mk.col, mk.u.astype(np.float64),
+                       mk.w.astype(np.float64), **common)
+    M.close()
+    return g, ora
+
+
+def test_trajectory_parity_fixed_step(cuda):
+    """40 fixed-step iterations without restarts follow the oracle's iterates."""
+    mk = f32(synth.fisher_small(2))
+    g, ora = trajectory(mk, cuda, 40)
+    pg, xg = g.p.cpu().numpy(), g.x.cpu().numpy()
+    assert g.info.iters == 40 and ora.iters == 40
+    assert np.max(np.abs(pg - ora.p)) <= 2e-4 * np.max(np.abs(ora.p))
+    assert np.max(np.abs(xg - ora.x)) <= 2e-4 * np.max(np.abs(ora.x))
+
+
+def test_trajectory_parity_ksection(cuda):
+    mk = f32(synth.fisher_small(2))
+    g, ora = trajectory(mk, cuda, 24, search=pdhcg.PDHCG_SEARCH_KSECTION, sections=32,
+                        max_search_rounds=40)
+    assert np.max(np.abs(g.p.cpu().numpy() - ora.p)) <= 2e-4 * np.max(np.abs(ora.p))
+
+
+@pytest.fixture(scope="module")
+def small_reference():
+    mk = f32(synth.fisher_small(0))
+    ora = oracle.solve(mk.n, mk.m, mk.row_ptr, mk.col, mk.u.astype(np.float64),
+                       mk.w.astype(np.float64), tol=1e-11, max_iter=400000)
+    assert ora.status == oracle.OK
+    return mk, ora
+
+
+def test_solve_small_market_parity(cuda, small_reference):
+    mk, ora = small_reference
+    M = pdhcg.Market.from_synth(mk, device=cuda)
+    sol = M.solve(tol=1e-6, max_iter=200000)
+    assert sol.info.status == pdhcg.PDHCG_OK, pdhcg.pdhcg_last_error()
+    assert sol.info.rel_kkt <= 1e-6
+    p, x, t = (v.cpu().numpy().astype(np.float64) for v in (sol.p, sol.x, sol.t))
+    # KKT recomputed by the oracle in float64 from the float32 outputs
+    uh, _ = oracle.normalize_rows(mk.row_ptr, mk.u.astype(np.float64))
+    r, _ = oracle.kkt(mk.n, mk.m, mk.row_ptr, mk.col, uh, mk.w, x, p)
+    assert r <= 2e-6
+    assert rel_err(p, ora.p) <= 1e-5
+    assert rel_err(t, ora.t) <= 1e-4
+    assert abs(p.sum() - mk.w.sum()) / mk.w.sum() <= 1e-5
+    M.close()
+
+
+def test_kkt_entry_point_matches_oracle(cuda, small_reference):
+    mk, ora = small_reference
+    M = pdhcg.Market.from_synth(mk, device=cuda)
+    rng = np.random.default_rng(0)
+    for scale in (0.0, 1e-3, 1e-1):
+        p = (ora.p * (1 + scale * rng.standard_normal(mk.m))).astype(np.float32)
+        x = np.maximum(ora.x * (1 + scale * rng.standard_normal(mk.nnz)), 0).astype(np.float32)
+        info = M.kkt(torch.as_tensor(p, device=cuda), torch.as_tensor(x, device=cuda))
+        uh, _ = oracle.normalize_rows(mk.row_ptr, mk.u.astype(np.float64))
+        r, parts = oracle.kkt(mk.n, mk.m, mk.row_ptr, mk.col, uh, mk.w, x.astype(np.float64),
+                              p.astype(np.float64))
+        got = np.array([info.rel_primal, info.rel_dual, info.rel_gap])
+        # the device sums columns from float32 per-workgroup partials and
+        # keeps column maxima as float32: |error| <= 1e-7 absolute here
+        assert np.all(np.abs(got - parts) <= 1e-7 + 1e-6 * parts), (got, parts)
+    M.close()
+
+
+def test_solve_variants_reach_same_prices(cuda, small_reference):
+    mk, ora = small_reference
+    M = pdhcg.Market.from_synth(mk, device=cuda)
+    for kw in (dict(step_mode=0), dict(search=pdhcg.PDHCG_SEARCH_KSECTION, sections=32),
+               dict(output=pdhcg.PDHCG_OUTPUT_AVERAGE)):
+        sol = M.solve(tol=1e-5, max_iter=200000, **kw)
+        assert sol.info.status == pdhcg.PDHCG_OK, kw
+        assert rel_err(sol.p.cpu().numpy(), ora.p) <= 1e-4, kw
+    M.close()
+
+
+def test_warm_start_and_max_iter(cuda, small_reference):
+    mk, ora = small_reference
+    M = pdhcg.Market.from_synth(mk, device=cuda)
+    s1 = M.solve(tol=1e-14, max_iter=64)
+    assert s1.info.status == pdhcg.PDHCG_MAX_ITER and s1.info.iters == 64
+    s2 = M.solve(tol=1e-5, max_iter=200000, p0=s1.p, x0=s1.x)
+    assert s2.info.status == pdhcg.PDHCG_OK
+    assert rel_err(s2.p.cpu().numpy(), ora.p) <= 1e-4
+    M.close()
+
+
+def test_create_rejects_bad_input(cuda):
+    mk = f32(synth.fisher_small(0))
+    rp, col, u, w = tensors(mk, cuda)
+    u_bad = u.clone()
+    u_bad[0] = -1.0
+    with pytest.raises(pdhcg.PDHCGError) as e:
+        pdhcg.pdhcg_market_create(mk.n, mk.m, mk.nnz, rp, col, u_bad, w)
+    assert e.value.status == pdhcg.PDHCG_ERR_ARG
+    with pytest.raises(pdhcg.PDHCGError) as e:
+        pdhcg.pdhcg_market_create(mk.n, mk.m + 1, mk.nnz, rp, col, u, w)
+    assert e.value.status == pdhcg.PDHCG_ERR_ASSUMPTION

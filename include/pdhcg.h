@@ -208,6 +208,44 @@ int32_t pdhcg_market_bins(pdhcg_market market, int32_t cap,
 
 void pdhcg_market_destroy(pdhcg_market market);
 
+/* ---- Batched markets -------------------------------------------------- */
+
+typedef struct pdhcg_batch_s *pdhcg_batch;
+
+/* Create a batch of `count` independent Fisher markets (each as in
+ * pdhcg_market_create).  n[count], m[count]: host arrays of market sizes
+ * (1 <= m[b] <= 2048).  Device arrays, markets concatenated in order:
+ *   row_ptr_cat [sum_b (n[b] + 1)]  each market's own CSR row pointer
+ *                                   (starting at 0),
+ *   col_cat, u_cat [sum_b nnz_b]    local good ids (0..m[b]-1) and
+ *                                   utilities,
+ *   w_cat [sum_b n[b]]              budgets.
+ * Every market is validated (status of the first bad market is returned),
+ * copied and row-normalised (Sec. 5).  The caller may free its inputs. */
+int32_t pdhcg_batch_create(int32_t count, const int32_t *n, const int32_t *m,
+                           const int32_t *row_ptr_cat, const int32_t *col_cat,
+                           const float *u_cat, const float *w_cat, void *stream,
+                           pdhcg_batch *out);
+
+/* Solve every market of the batch by restarted PDHCG (Alg. 2 with the
+ * Sec. 5 enhancements, active-set search) in ONE persistent launch: each
+ * workgroup takes markets from a work queue (largest first) and runs a
+ * market's whole solve with workgroup barriers only, so markets converge
+ * and retire independently.
+ *   p_cat [sum m] and x_cat [sum nnz]: device outputs, concatenated like
+ *   the inputs; infos [count]: host, per-market results (may be NULL).
+ * Returns PDHCG_OK when every market reached tol, PDHCG_MAX_ITER when some
+ * market ran out of iterations, or the most negative error status. */
+int32_t pdhcg_batch_solve(pdhcg_batch batch, const pdhcg_params *params,
+                          float *p_cat, float *x_cat, pdhcg_info *infos);
+
+/* Offsets of market b's goods and edges in the concatenated arrays (host
+ * arrays of count + 1 entries, either may be NULL). */
+int32_t pdhcg_batch_layout(pdhcg_batch batch, int64_t *good_off,
+                           int64_t *edge_off);
+
+void pdhcg_batch_destroy(pdhcg_batch batch);
+
 #ifdef __cplusplus
 }
 #endif

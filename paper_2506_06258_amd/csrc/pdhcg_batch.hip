@@ -1,0 +1,984 @@
+// Batched PDHCG: many independent linear Fisher markets in one persistent
+// launch.  Each workgroup takes markets from a work queue (largest first)
+// and runs the whole restarted PDHCG solve of a market by itself: price
+// step (eq. update:py), row prox (Sec. 2.2), running averages (Alg. 2),
+// column sums, the adaptive step rule, the relative KKT check, restarts and
+// primal weight (Sec. 5).  Every synchronisation is a workgroup barrier, so
+// no workgroup ever waits for another and each market converges (and
+// retires) on its own: the per-market convergence mask is the work queue.
+//
+// The control logic follows the same readings as the single-market host
+// loop (pdhcg_api.hip), executed by thread 0 between barriers.
+#include "../../include/pdhcg.h"
+#include "pdhcg_device.h"
+#include "pdhcg_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+namespace pdhcg {
+
+constexpr int kBatchBlock = 512;
+constexpr int kBatchWaves = kBatchBlock / kWave;
+constexpr int kBatchMaxGoods = 2048;
+
+struct BatchParamsDev {
+  double tol;
+  int64_t max_iter;
+  int32_t eval_every, max_rounds, step_mode, restart;
+  double rtol, beta_suff, beta_nec, beta_art, theta, omega_bound, eta0, omega0;
+  int32_t omega_check_every, output;
+};
+
+struct BatchInfoDev {
+  double kkt[3];
+  double rel_kkt, eta, omega;
+  int64_t iters, accepted;
+  int32_t restarts, status, evals, pad;
+};
+
+struct BatchDev {
+  int32_t count;
+  const int32_t *order, *n, *m, *shape;
+  const int64_t *rp_off, *row_off, *good_off, *edge_off;
+  const double *sumw;
+  const int32_t *row_ptr, *col, *deg;
+  const float *uh, *w, *rowmax;
+  float *X0, *X1, *X2, *XA;
+  double *P0, *P1, *P2, *PA, *C0, *C1, *C2;
+  float *p_out, *x_out;
+  BatchInfoDev *info;
+  uint32_t *queue;
+};
+
+// Pointers of one market.  Role buffers are selected with pick3 (no
+// dynamically indexed arrays, which would live in scratch memory).
+struct MView {
+  int n, m;
+  const int32_t *rp, *col, *deg;
+  const float *uh, *w, *rowmax;
+  float *X0, *X1, *X2, *XA;
+  double *P0, *P1, *P2, *PA, *C0, *C1, *C2;
+  __device__ float *X(int i) const { return pick3<float *>(X0, X1, X2, i); }
+  __device__ double *P(int i) const { return pick3<double *>(P0, P1, P2, i); }
+  __device__ double *C(int i) const { return pick3<double *>(C0, C1, C2, i); }
+};
+
+struct WGState {
+  int ix[3], ip[3], ic[3];
+  int fold, done, status, restarts, evals, cand_avg, do_restart, market;
+  int64_t total, since, k_in, accepted;
+  double eta, omega, eta0, omega0, tau, sigma, kkt0, kkt_prev, kbest;
+  double kout[3];
+  double kc[3], ka[3];
+};
+
+// Values every lane holds alike (read from LDS after a barrier): move them
+// to scalar registers so that pointers derived from them stay scalar.
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ double uni(double x) {
+  const int lo = __builtin_amdgcn_readfirstlane(__double2loint(x));
+  const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(x));
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double block_sum(double v, double *red) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  v = wave_sum_d(v);
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  for (int q = 0; q < kBatchWaves; ++q) t += red[q];
+  __syncthreads();
+  return t;
+}
+
+__device__ __forceinline__ double block_max(double v, double *red) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  v = wave_max_d(v);
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double t = red[0];
+  for (int q = 1; q < kBatchWaves; ++q) t = fmax(t, red[q]);
+  __syncthreads();
+  return t;
+}
+
+// Row root for rows longer than a wave holds in registers: one wave per
+// row, every search round re-reads the row (it stays in cache).  Same
+// search as prox_row (active-set trial points inside the Alg. 3 bracket).
+template <class PGet>
+__device__ double prox_row_long(int beg, int d, double tau, double tw, const float *uh,
+                                const int32_t *col, const float *xin, PGet pget, int max_rounds,
+                                double rtol, int &rounds) {
+  const int lane = threadIdx.x & (kWave - 1);
+  double s0 = 0.0;
+  for (int k = lane; k < d; k += kWave) s0 = fma((double)uh[beg + k], (double)xin[beg + k], s0);
+  s0 = seg_sum_d<kWave>(s0);
+  double s = s0;
+  if (!(s > 0.0)) {
+    double lb = 0.0;
+    for (int k = lane; k < d; k += kWave) {
+      const double u = uh[beg + k];
+      if (u > 0.0) {
+        const double a = fma(-tau, pget(col[beg + k]), (double)xin[beg + k]);
+        lb = fmax(lb, pos_root_d(u * a, tw * u * u));
+      }
+    }
+    lb = seg_max_d<kWave>(lb);
+    s = lb > 0.0 ? lb : 1.0;
+  }
+  double L = 0.0, U = INFINITY, sfin = s;
+  rounds = 0;
+  for (int it = 0; it < max_rounds; ++it) {
+    const double inv = fast_rcp(s), ti = tw * inv;
+    double A = 0.0, Q = 0.0;
+    for (int k = lane; k < d; k += kWave) {
+      const double u = uh[beg + k];
+      const double a = fma(-tau, pget(col[beg + k]), (double)xin[beg + k]);
+      const double on = fma(u, ti, a) > 0.0 ? u : 0.0;
+      A = fma(on, a, A);
+      Q = fma(on, u, Q);
+    }
+    A = seg_sum_d<kWave>(A);
+    Q = seg_sum_d<kWave>(Q);
+    const double B = tw * Q, g = fma(B, inv, A), sA = pos_root_d(A, B);
+    bool same = false;
+    if (sA > 0.0) {
+      const double tA = tw * fast_rcp(sA);
+      bool diff = false;
+      for (int k = lane; k < d; k += kWave) {
+        const double u = uh[beg + k];
+        const double a = fma(-tau, pget(col[beg + k]), (double)xin[beg + k]);
+        diff |= ((fma(u, ti, a) > 0.0) != (fma(u, tA, a) > 0.0));
+      }
+      same = !seg_any<kWave>(diff);
+    }
+    ++rounds;
+    U = fmin(U, fmax(s, g));
+    L = fmax(L, fmin(s, g));
+    if (sA > 0.0) L = fmax(L, sA);
+    if (same || sA == s) return sA;
+    if (U - L <= rtol * U) return 0.5 * (L + U);
+    s = (L > 0.0) ? L : 0.5 * U;
+    sfin = s;
+  }
+  return (U < INFINITY) ? 0.5 * (L + U) : sfin;
+}
+
+// One trial step's row pass over the market for shape (G, E): x_try,
+// lagged fold of x_cur into x_avg, |x_try - x_cur|^2 (returned, this
+// thread's share) and float64 column sums into lc.
+template <int G, int E>
+__device__ double wg_rows_step(const MView &v, const double *lp, double *lc, const float *xin,
+                               float *xout, float *xavg, double tau, float wfold, int max_rounds,
+                               double rtol) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int r = lane & (G - 1), seg = lane / G;
+  constexpr int kSeg = kWave / G;
+  double dx2 = 0.0;
+  auto pget = [&](int c) { return lp[c]; };
+  for (int base = wave * kSeg; base < v.n; base += kBatchWaves * kSeg) {
+    const int i = base + seg;
+    const bool rv = i < v.n;
+    const int beg = rv ? v.rp[i] : 0;
+    const int d = rv ? v.rp[i + 1] - beg : 0;
+    const double tw = rv ? tau * (double)v.w[i] : 0.0;
+    // rows beyond the register capacity: whole-wave path (only G = 64)
+    if (G == kWave && E * G < d) {
+      int rounds = 0;
+      const double sfin =
+          prox_row_long(beg, d, tau, tw, v.uh, v.col, xin, pget, max_rounds, rtol, rounds);
+      const double tf = tw * fast_rcp(sfin);
+      for (int k = lane; k < d; k += kWave) {
+        const int q = beg + k;
+        const float xk = xin[q];
+        const double a = fma(-tau, lp[v.col[q]], (double)xk);
+        const float xn = (float)fmax(fma((double)v.uh[q], tf, a), 0.0);
+        xout[q] = xn;
+        if (wfold != 0.0f) xavg[q] = (wfold == 1.0f) ? xk : fmaf(xk - xavg[q], wfold, xavg[q]);
+        dx2 += (double)(xn - xk) * (double)(xn - xk);
+        atomicAdd(&lc[v.col[q]], (double)xn);
+      }
+      continue;
+    }
+    double a[E];
+    float uh[E], xk[E];
+    int cj[E];
+    int rounds = 0;
+    const double sfin = prox_row<G, E, 0>(rv, beg, d, r, tau, tw, v.uh, v.col, xin, pget,
+                                          max_rounds, rtol, 0, a, uh, xk, cj, rounds);
+    const double tf = tw * fast_rcp(sfin);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int idx = r + G * e;
+      if (idx < d) {
+        const int q = beg + idx;
+        const float xn = (float)fmax(fma((double)uh[e], tf, a[e]), 0.0);
+        xout[q] = xn;
+        if (wfold != 0.0f) {
+          const float xb = xavg[q];
+          xavg[q] = (wfold == 1.0f) ? xk[e] : fmaf(xk[e] - xb, wfold, xb);
+        }
+        const double df = (double)xn - (double)xk[e];
+        dx2 = fma(df, df, dx2);
+        atomicAdd(&lc[cj[e]], (double)xn);
+      }
+    }
+  }
+  return dx2;
+}
+
+// KKT row pass (Sec. 5 Criteria) over the current point and, if xa is not
+// NULL, the averaged point (folded in place with weight wf).  G lanes per
+// row, entries visited with stride G.  Row statistics go to st[0..9]
+// (same layout as the single-market KKT pass); column maxima of u y go to
+// lMc/lMa (float bits), column sums of the averaged point (or of the
+// current point when sum_cur) to lcs.
+template <int G>
+__device__ void wg_rows_eval(const MView &v, const float *xc, const double *pc, float *xa,
+                             const double *pa_folded, float wf, const float *xanc, bool sum_cur,
+                             unsigned int *lMc, unsigned int *lMa, double *lcs, double *st,
+                             float *tc_out, float *ta_out) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int r = lane & (G - 1), seg = lane / G;
+  constexpr int kSeg = kWave / G;
+  const bool has_avg = xa != nullptr;
+  for (int base = wave * kSeg; base < v.n; base += kBatchWaves * kSeg) {
+    const int i = base + seg;
+    const bool rv = i < v.n;
+    const int beg = rv ? v.rp[i] : 0;
+    const int d = rv ? v.rp[i + 1] - beg : 0;
+    double tc = 0.0, ta = 0.0;
+    for (int k = r; k < d; k += G) {
+      const int q = beg + k;
+      const float x = xc[q];
+      tc = fma((double)v.uh[q], (double)x, tc);
+      if (has_avg) {
+        float y = xa[q];
+        if (wf != 0.0f) {
+          y = (wf == 1.0f) ? x : fmaf(x - y, wf, y);
+          xa[q] = y;
+        }
+        ta = fma((double)v.uh[q], (double)y, ta);
+        if (xanc) {
+          const double z = xanc[q];
+          st[9] += ((double)y - z) * ((double)y - z);
+        }
+      }
+      if (xanc) {
+        const double z = xanc[q];
+        st[8] += ((double)x - z) * ((double)x - z);
+      }
+    }
+    tc = seg_sum_d<G>(tc);
+    ta = seg_sum_d<G>(ta);
+    if (!rv) continue;
+    const double wi = v.w[i];
+    const double yc = wi / tc, ya = has_avg ? wi / ta : 0.0;
+    if (r == 0) {
+      st[0] = fmax(st[0], yc);
+      if (has_avg) st[4] = fmax(st[4], ya);
+      if (tc_out) tc_out[i] = (float)(tc * (double)v.rowmax[i]);
+      if (ta_out && has_avg) ta_out[i] = (float)(ta * (double)v.rowmax[i]);
+    }
+    for (int k = r; k < d; k += G) {
+      const int q = beg + k;
+      const int c = v.col[q];
+      const double u = v.uh[q];
+      const double x = xc[q];
+      const double vc = u * yc, rc = pc[c] - vc;
+      if (rc > 0.0) {
+        st[2] = fmax(st[2], rc);
+        st[1] = fmax(st[1], x * rc);
+      }
+      st[3] = fmax(st[3], x);
+      atomicMax(&lMc[c], __float_as_uint((float)vc));
+      if (has_avg) {
+        const double y = xa[q];
+        const double va = u * ya, ra = pa_folded[c] - va;
+        if (ra > 0.0) {
+          st[6] = fmax(st[6], ra);
+          st[5] = fmax(st[5], y * ra);
+        }
+        st[7] = fmax(st[7], y);
+        atomicMax(&lMa[c], __float_as_uint((float)va));
+        if (!sum_cur) atomicAdd(&lcs[c], y);
+      }
+      if (sum_cur) atomicAdd(&lcs[c], x);
+    }
+  }
+}
+
+template <int G>
+__device__ void wg_colsum_x(const MView &v, const float *x, double *lc) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int r = lane & (G - 1), seg = lane / G;
+  constexpr int kSeg = kWave / G;
+  for (int base = wave * kSeg; base < v.n; base += kBatchWaves * kSeg) {
+    const int i = base + seg;
+    if (i >= v.n) continue;
+    for (int k = v.rp[i] + r; k < v.rp[i + 1]; k += G) atomicAdd(&lc[v.col[k]], (double)x[k]);
+  }
+}
+
+struct EvalOut {
+  double kc[3], ka[3], dxa2[2], dpa2[2];
+};
+
+// Full KKT check of the current point (and the average when has_avg) of
+// one market; returns the residuals in `out` (valid in thread 0).
+__device__ void wg_eval(const MView &v, int shape, WGState &S, bool has_avg, float wf,
+                        double *lp, double *lc, unsigned int *lMc, unsigned int *lMa,
+                        double *red10, double *tot10, EvalOut &out, float *tc_out,
+                        float *ta_out) {
+  const float *xc = v.X(uni(S.ix[0]));
+  const double *pc = v.P(uni(S.ip[0]));
+  float *xa = has_avg ? v.X(uni(S.ix[2])) : nullptr;
+  double *pa = v.P(uni(S.ip[2]));
+  for (int j = threadIdx.x; j < v.m; j += blockDim.x) {
+    lMc[j] = 0u;
+    lMa[j] = 0u;
+    lc[j] = 0.0;
+    if (has_avg) {
+      double q = pa[j];
+      if (wf != 0.0f) q = (wf == 1.0f) ? pc[j] : q + (pc[j] - q) * (double)wf;
+      lp[j] = q;
+      pa[j] = q;
+    }
+  }
+  __syncthreads();
+  double st[10];
+  for (int q = 0; q < 10; ++q) st[q] = 0.0;
+  switch (shape) {
+    case 0: wg_rows_eval<8>(v, xc, pc, xa, lp, wf, v.XA, false, lMc, lMa, lc, st, tc_out, ta_out); break;
+    case 1: wg_rows_eval<16>(v, xc, pc, xa, lp, wf, v.XA, false, lMc, lMa, lc, st, tc_out, ta_out); break;
+    case 2: wg_rows_eval<32>(v, xc, pc, xa, lp, wf, v.XA, false, lMc, lMa, lc, st, tc_out, ta_out); break;
+    default: wg_rows_eval<64>(v, xc, pc, xa, lp, wf, v.XA, false, lMc, lMa, lc, st, tc_out, ta_out); break;
+  }
+  // wave-level reduction of the row statistics, combined by one thread
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+#pragma unroll
+  for (int q = 0; q < 10; ++q) {
+    const double x = (q >= 8) ? wave_sum_d(st[q]) : wave_max_d(st[q]);
+    if (lane == 0) red10[wave * 10 + q] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < 10) {
+    const int q = threadIdx.x;
+    double x = red10[q];
+    for (int w = 1; w < kBatchWaves; ++w) x = (q >= 8) ? x + red10[w * 10 + q] : fmax(x, red10[w * 10 + q]);
+    tot10[q] = x;
+  }
+  __syncthreads();
+  double cs[10];
+#pragma unroll
+  for (int q = 0; q < 10; ++q) cs[q] = (q == 3 || q == 7 || q == 2 || q == 6) ? -INFINITY : 0.0;
+  const double *cc = v.C(uni(S.ic[1]));
+  double *cavg = v.C(uni(S.ic[2]));
+  for (int j = threadIdx.x; j < v.m; j += blockDim.x) {
+    const double Mc = __uint_as_float(lMc[j]);
+    const double p = pc[j];
+    cs[0] = fmax(cs[0], fabs(cc[j] - 1.0));
+    cs[1] = fmax(cs[1], fabs(cc[j]));
+    cs[2] = fmax(cs[2], Mc - p);
+    cs[3] = fmax(cs[3], p - Mc);
+    cs[8] += (p - v.PA[j]) * (p - v.PA[j]);
+    if (has_avg) {
+      const double Ma = __uint_as_float(lMa[j]);
+      const double ca = lc[j];
+      const double q = lp[j];
+      cavg[j] = ca;
+      cs[4] = fmax(cs[4], fabs(ca - 1.0));
+      cs[5] = fmax(cs[5], fabs(ca));
+      cs[6] = fmax(cs[6], Ma - q);
+      cs[7] = fmax(cs[7], q - Ma);
+      cs[9] += (q - v.PA[j]) * (q - v.PA[j]);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 10; ++q) {
+    const double x = (q >= 8) ? wave_sum_d(cs[q]) : wave_max_d(cs[q]);
+    if (lane == 0) red10[wave * 10 + q] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < 10) {
+    const int q = threadIdx.x;
+    double x = red10[q];
+    for (int w = 1; w < kBatchWaves; ++w) x = (q >= 8) ? x + red10[w * 10 + q] : fmax(x, red10[w * 10 + q]);
+    tot10[10 + q] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double *rw = tot10, *c = tot10 + 10;
+  // relative KKT error (Sec. 5 Criteria) with t = Ux, y = w/t
+  for (int z = 0; z < 2; ++z) {
+    const int o = 4 * z;
+    double *k = z == 0 ? out.kc : out.ka;
+    k[0] = c[o + 0] / (1.0 + fmax(c[o + 1], 1.0));
+    k[1] = fmax(0.0, c[o + 2]) / (1.0 + fmax(rw[o + 0], c[o + 3]));
+    k[2] = rw[o + 1] / (1.0 + fmax(rw[o + 3], rw[o + 2]));
+  }
+  out.dxa2[0] = rw[8];
+  out.dxa2[1] = rw[9];
+  out.dpa2[0] = c[8];
+  out.dpa2[1] = c[9];
+}
+
+__global__ __launch_bounds__(kBatchBlock) void k_batch_solve(BatchDev bd, BatchParamsDev prm) {
+  __shared__ double lp[kBatchMaxGoods];
+  __shared__ double lc[kBatchMaxGoods];
+  __shared__ unsigned int lMc[kBatchMaxGoods];
+  __shared__ unsigned int lMa[kBatchMaxGoods];
+  __shared__ double red[kBatchWaves];
+  __shared__ double red10[kBatchWaves * 10];
+  __shared__ double tot10[20];
+  __shared__ WGState S;
+  __shared__ EvalOut E;
+
+  while (true) {
+    if (threadIdx.x == 0) {
+      const uint32_t t = atomicAdd(bd.queue, 1u);
+      S.market = (t < (uint32_t)bd.count) ? bd.order[t] : -1;
+    }
+    __syncthreads();
+    const int b = uni(S.market);
+    if (b < 0) return;
+    MView v;
+    v.n = bd.n[b];
+    v.m = bd.m[b];
+    const int64_t ro = bd.row_off[b], go = bd.good_off[b], eo = bd.edge_off[b];
+    v.rp = bd.row_ptr + bd.rp_off[b];
+    v.col = bd.col + eo;
+    v.deg = bd.deg + go;
+    v.uh = bd.uh + eo;
+    v.w = bd.w + ro;
+    v.rowmax = bd.rowmax + ro;
+    v.X0 = bd.X0 + eo; v.X1 = bd.X1 + eo; v.X2 = bd.X2 + eo; v.XA = bd.XA + eo;
+    v.P0 = bd.P0 + go; v.P1 = bd.P1 + go; v.P2 = bd.P2 + go; v.PA = bd.PA + go;
+    v.C0 = bd.C0 + go; v.C1 = bd.C1 + go; v.C2 = bd.C2 + go;
+    const int shape = uni(bd.shape[b]);
+    const int nnz = v.rp[v.n];
+
+    // Initial point (x0 = 1/deg_j, p0 = sum(w)/m), its column sums and KKT.
+    const double p0 = bd.sumw[b] / (double)v.m;
+    for (int k = threadIdx.x; k < nnz; k += blockDim.x) {
+      const float x0 = 1.0f / (float)v.deg[v.col[k]];
+      v.X(0)[k] = x0;
+      v.XA[k] = x0;
+    }
+    for (int j = threadIdx.x; j < v.m; j += blockDim.x) {
+      v.P(0)[j] = p0;
+      v.PA[j] = p0;
+      lc[j] = 0.0;
+    }
+    if (threadIdx.x == 0) {
+      S.ix[0] = 0; S.ix[1] = 1; S.ix[2] = 2;
+      S.ip[0] = 0; S.ip[1] = 1; S.ip[2] = 2;
+      S.ic[0] = 0; S.ic[1] = 1; S.ic[2] = 2;
+      S.fold = 0; S.done = 0; S.status = PDHCG_MAX_ITER; S.restarts = 0; S.evals = 0;
+      S.cand_avg = 0; S.do_restart = 0;
+      S.total = 0; S.since = 0; S.k_in = 0; S.accepted = 0;
+      const bool adaptive = prm.step_mode == 1;
+      double kmax = 0.0;
+      for (int j = 0; j < v.m; ++j) kmax = fmax(kmax, (double)v.deg[j]);
+      S.eta0 = prm.eta0 > 0.0 ? prm.eta0 : (adaptive ? 1.0 : 0.9 / sqrt(kmax));
+      S.omega0 = prm.omega0 > 0.0 ? prm.omega0 : 0.05 * bd.sumw[b] / (double)v.m;
+      S.eta = S.eta0;
+      S.omega = S.omega0;
+      S.tau = S.eta / S.omega;
+      S.sigma = S.eta * S.omega;
+      S.kkt_prev = INFINITY;
+      S.kbest = INFINITY;
+    }
+    __syncthreads();
+    switch (shape) {
+      case 0: wg_colsum_x<8>(v, v.X(0), lc); break;
+      case 1: wg_colsum_x<16>(v, v.X(0), lc); break;
+      case 2: wg_colsum_x<32>(v, v.X(0), lc); break;
+      default: wg_colsum_x<64>(v, v.X(0), lc); break;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < v.m; j += blockDim.x) {
+      v.C(0)[j] = lc[j];
+      v.C(1)[j] = lc[j];
+    }
+    __syncthreads();
+    wg_eval(v, shape, S, false, 0.0f, lp, lc, lMc, lMa, red10, tot10, E, nullptr, nullptr);
+    __syncthreads();
+    if (threadIdx.x == 0) S.kkt0 = fmax(E.kc[0], fmax(E.kc[1], E.kc[2]));
+    __syncthreads();
+
+    while (!S.done) {
+      // ---- price step (eq. update:py) and lagged fold of p into p_avg
+      {
+        const double *pc = v.P(uni(S.ip[0]));
+        double *pt = v.P(uni(S.ip[1]));
+        double *pa = v.P(uni(S.ip[2]));
+        const double *cp = v.C(uni(S.ic[0])), *cc = v.C(uni(S.ic[1]));
+        const double sigma = uni(S.sigma);
+        const bool fold = uni(S.fold) != 0;
+        const double kin = (double)uni((int)S.k_in);
+        for (int j = threadIdx.x; j < v.m; j += blockDim.x) {
+          const double p = pc[j];
+          const double q = p + sigma * (2.0 * cc[j] - cp[j] - 1.0);
+          pt[j] = q;
+          lp[j] = q;
+          lc[j] = 0.0;
+          if (fold) pa[j] = (kin == 1.0) ? p : pa[j] + (p - pa[j]) / kin;
+        }
+      }
+      __syncthreads();
+      // ---- row prox (Sec. 2.2), lagged fold of x, column sums
+      const float wfold = uni(S.fold) ? (float)(1.0 / (double)uni((int)S.k_in)) : 0.0f;
+      const double tau = uni(S.tau);
+      const float *xin = v.X(uni(S.ix[0]));
+      float *xout = v.X(uni(S.ix[1]));
+      float *xavg = v.X(uni(S.ix[2]));
+      double dx2 = 0.0;
+      switch (shape) {
+        case 0: dx2 = wg_rows_step<8, 4>(v, lp, lc, xin, xout, xavg, tau, wfold, prm.max_rounds, prm.rtol); break;
+        case 1: dx2 = wg_rows_step<16, 4>(v, lp, lc, xin, xout, xavg, tau, wfold, prm.max_rounds, prm.rtol); break;
+        case 2: dx2 = wg_rows_step<32, 4>(v, lp, lc, xin, xout, xavg, tau, wfold, prm.max_rounds, prm.rtol); break;
+        case 3: dx2 = wg_rows_step<64, 4>(v, lp, lc, xin, xout, xavg, tau, wfold, prm.max_rounds, prm.rtol); break;
+        default: dx2 = wg_rows_step<64, 8>(v, lp, lc, xin, xout, xavg, tau, wfold, prm.max_rounds, prm.rtol); break;
+      }
+      dx2 = block_sum(dx2, red);  // contains the barrier after the row pass
+      // ---- column sums, dp^T K dx and |dp|^2
+      double inter = 0.0, dp2 = 0.0;
+      {
+        const double *pc = v.P(uni(S.ip[0])), *pt = v.P(uni(S.ip[1]));
+        const double *cc = v.C(uni(S.ic[1]));
+        double *ct = v.C(uni(S.ic[2]));
+        for (int j = threadIdx.x; j < v.m; j += blockDim.x) {
+          const double c = lc[j];
+          ct[j] = c;
+          const double dp = pt[j] - pc[j];
+          inter = fma(dp, c - cc[j], inter);
+          dp2 = fma(dp, dp, dp2);
+        }
+      }
+      inter = block_sum(inter, red);
+      dp2 = block_sum(dp2, red);
+      // ---- step-size rule (Sec. 5) and role rotation
+      if (threadIdx.x == 0) {
+        S.total += 1;
+        S.since += 1;
+        bool accept = true;
+        if (prm.step_mode == 1) {
+          const double om = S.omega, eta = S.eta;
+          const double emax =
+              fabs(inter) > 0.0 ? (om * dx2 + dp2 / om) / (2.0 * fabs(inter)) : INFINITY;
+          const double kk = (double)(S.total + 1);
+          double enew = fmin((1.0 - pow(kk, -0.3)) * emax, (1.0 + pow(kk, -0.6)) * eta);
+          enew = fmin(fmax(enew, 0.01 * S.eta0), 3.0 * S.eta0);
+          accept = (eta <= emax) || (eta <= 0.01 * S.eta0);
+          S.eta = enew;
+          S.tau = enew / om;
+          S.sigma = enew * om;
+        }
+        if (accept) {
+          int t = S.ix[0]; S.ix[0] = S.ix[1]; S.ix[1] = t;
+          t = S.ip[0]; S.ip[0] = S.ip[1]; S.ip[1] = t;
+          const int cp = S.ic[0], cc = S.ic[1], ct = S.ic[2];
+          S.ic[0] = cc; S.ic[1] = ct; S.ic[2] = cp;
+          S.k_in += 1;
+          S.accepted += 1;
+          S.fold = 1;
+        } else {
+          S.fold = 0;
+        }
+      }
+      __syncthreads();
+      const bool eval = (S.total % prm.eval_every == 0) || S.total >= prm.max_iter;
+      if (!eval) continue;
+      // ---- KKT check, restart, primal weight (Sec. 5)
+      const bool has_avg = S.k_in > 0;
+      const float wf = (has_avg && S.fold) ? (float)(1.0 / (double)S.k_in) : 0.0f;
+      wg_eval(v, shape, S, has_avg, wf, lp, lc, lMc, lMa, red10, tot10, E, nullptr, nullptr);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        S.fold = 0;
+        S.evals += 1;
+        const double kc = fmax(E.kc[0], fmax(E.kc[1], E.kc[2]));
+        const double ka = has_avg ? fmax(E.ka[0], fmax(E.ka[1], E.ka[2])) : INFINITY;
+        S.cand_avg = ka < kc;
+        const double kcand = S.cand_avg ? ka : kc;
+        for (int q = 0; q < 3; ++q) S.kout[q] = S.cand_avg ? E.ka[q] : E.kc[q];
+        S.kbest = kcand;
+        S.do_restart = 0;
+        if (!(kcand == kcand)) {
+          S.status = PDHCG_ERR_NUMERIC;
+          S.done = 1;
+        } else if (kcand <= prm.tol) {
+          S.status = PDHCG_OK;
+          S.done = 1;
+        } else if (S.total >= prm.max_iter) {
+          S.status = PDHCG_MAX_ITER;
+          S.done = 1;
+        } else if (prm.restart) {
+          const bool rs = (kcand <= prm.beta_suff * S.kkt0) ||
+                          (kcand <= prm.beta_nec * S.kkt0 && kcand > S.kkt_prev) ||
+                          ((double)S.since >= prm.beta_art * (double)S.total);
+          if (rs) {
+            S.do_restart = 1;
+            if (S.cand_avg) {
+              int t = S.ix[0]; S.ix[0] = S.ix[2]; S.ix[2] = t;
+              t = S.ip[0]; S.ip[0] = S.ip[2]; S.ip[2] = t;
+              t = S.ic[1]; S.ic[1] = S.ic[2]; S.ic[2] = t;
+            }
+            const double dx = sqrt(E.dxa2[S.cand_avg ? 1 : 0]);
+            const double dp = sqrt(E.dpa2[S.cand_avg ? 1 : 0]);
+            if (dx > 1e-10 && dp > 1e-10)
+              S.omega = exp(prm.theta * log(dp / dx) + (1.0 - prm.theta) * log(S.omega));
+            S.restarts += 1;
+            if (prm.omega_check_every > 0 && S.restarts % prm.omega_check_every == 0 &&
+                (S.omega < S.omega0 / prm.omega_bound || S.omega > S.omega0 * prm.omega_bound))
+              S.omega = S.omega0;
+            S.kkt0 = kcand;
+            S.kkt_prev = INFINITY;
+            S.k_in = 0;
+            S.since = 0;
+            S.cand_avg = 0;
+          } else {
+            S.kkt_prev = kcand;
+          }
+        }
+        S.tau = S.eta / S.omega;
+        S.sigma = S.eta * S.omega;
+      }
+      __syncthreads();
+      if (S.do_restart) {
+        const float *xs = v.X(uni(S.ix[0]));
+        for (int k = threadIdx.x; k < nnz; k += blockDim.x) v.XA[k] = xs[k];
+        const double *ps = v.P(uni(S.ip[0]));
+        const double *cs = v.C(uni(S.ic[1]));
+        double *cp = v.C(uni(S.ic[0]));
+        for (int j = threadIdx.x; j < v.m; j += blockDim.x) {
+          v.PA[j] = ps[j];
+          cp[j] = cs[j];
+        }
+        __syncthreads();
+      }
+    }
+
+    // ---- outputs: the candidate (Sec. 5) or the requested point
+    bool out_avg = S.cand_avg;
+    if (prm.output == PDHCG_OUTPUT_CURRENT) out_avg = false;
+    if (prm.output == PDHCG_OUTPUT_AVERAGE) out_avg = S.k_in > 0;
+    const float *xs = v.X(uni(out_avg ? S.ix[2] : S.ix[0]));
+    const double *ps = v.P(uni(out_avg ? S.ip[2] : S.ip[0]));
+    for (int k = threadIdx.x; k < nnz; k += blockDim.x) bd.x_out[eo + k] = xs[k];
+    for (int j = threadIdx.x; j < v.m; j += blockDim.x) bd.p_out[go + j] = (float)ps[j];
+    if (threadIdx.x == 0) {
+      BatchInfoDev &I = bd.info[b];
+      for (int q = 0; q < 3; ++q) I.kkt[q] = S.kout[q];
+      I.rel_kkt = S.kbest;
+      I.eta = S.eta;
+      I.omega = S.omega;
+      I.iters = S.total;
+      I.accepted = S.accepted;
+      I.restarts = S.restarts;
+      I.status = S.status;
+      I.evals = S.evals;
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace pdhcg
+
+// ---------------------------------------------------------------- host API --
+
+using namespace pdhcg;
+
+struct pdhcg_batch_s {
+  int32_t count = 0;
+  hipStream_t stream = nullptr;
+  std::vector<int32_t> h_n, h_m;
+  std::vector<int64_t> h_rp_off, h_row_off, h_good_off, h_edge_off;
+  int64_t total_rows = 0, total_goods = 0, total_edges = 0;
+  // device
+  int32_t *order = nullptr, *n = nullptr, *m = nullptr, *shape = nullptr;
+  int64_t *rp_off = nullptr, *row_off = nullptr, *good_off = nullptr, *edge_off = nullptr;
+  double *sumw = nullptr;
+  int32_t *row_ptr = nullptr, *col = nullptr, *deg = nullptr;
+  float *uh = nullptr, *w = nullptr, *rowmax = nullptr;
+  float *X[3] = {nullptr, nullptr, nullptr}, *XA = nullptr;
+  double *P[3] = {nullptr, nullptr, nullptr}, *PA = nullptr;
+  double *C[3] = {nullptr, nullptr, nullptr};
+  BatchInfoDev *info = nullptr;
+  uint32_t *queue = nullptr;
+};
+
+namespace {
+
+template <typename T>
+hipError_t balloc(T **p, size_t count) {
+  *p = nullptr;
+  return hipMalloc((void **)p, (count ? count : 1) * sizeof(T));
+}
+
+}  // namespace
+
+// Error text of the batch calls is shared with the single-market calls.
+void pdhcg_internal_set_error(const char *msg);
+
+namespace {
+int32_t bfail(int32_t st, const std::string &msg) {
+  pdhcg_internal_set_error(msg.c_str());
+  return st;
+}
+}  // namespace
+
+#define BHIPC(call)                                                                  \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return bfail(e_ == hipErrorOutOfMemory ? PDHCG_ERR_OOM : PDHCG_ERR_HIP,        \
+                   std::string(#call) + ": " + hipGetErrorString(e_));               \
+  } while (0)
+
+extern "C" void pdhcg_batch_destroy(pdhcg_batch bt) {
+  if (!bt) return;
+  auto f = [](void *p) {
+    if (p) (void)hipFree(p);
+  };
+  f(bt->order); f(bt->n); f(bt->m); f(bt->shape); f(bt->rp_off); f(bt->row_off);
+  f(bt->good_off); f(bt->edge_off); f(bt->sumw); f(bt->row_ptr); f(bt->col); f(bt->deg);
+  f(bt->uh); f(bt->w); f(bt->rowmax); f(bt->XA); f(bt->PA); f(bt->info);
+  f(bt->queue);
+  for (int q = 0; q < 3; ++q) { f(bt->X[q]); f(bt->P[q]); f(bt->C[q]); }
+  delete bt;
+}
+
+extern "C" int32_t pdhcg_batch_create(int32_t count, const int32_t *n, const int32_t *m,
+                                      const int32_t *row_ptr_cat, const int32_t *col_cat,
+                                      const float *u_cat, const float *w_cat, void *stream,
+                                      pdhcg_batch *out) {
+  if (!out) return bfail(PDHCG_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (count <= 0 || !n || !m || !row_ptr_cat || !col_cat || !u_cat || !w_cat)
+    return bfail(PDHCG_ERR_ARG, "count > 0 and non-null arrays required");
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<int64_t> rp_off(count + 1), row_off(count + 1), good_off(count + 1);
+  rp_off[0] = row_off[0] = good_off[0] = 0;
+  for (int b = 0; b < count; ++b) {
+    if (n[b] <= 0 || m[b] <= 0) return bfail(PDHCG_ERR_ARG, "market sizes must be positive");
+    if (m[b] > kBatchMaxGoods)
+      return bfail(PDHCG_ERR_UNSUPPORTED, "market " + std::to_string(b) + " has more than " +
+                                              std::to_string(kBatchMaxGoods) + " goods");
+    rp_off[b + 1] = rp_off[b] + n[b] + 1;
+    row_off[b + 1] = row_off[b] + n[b];
+    good_off[b + 1] = good_off[b] + m[b];
+  }
+  std::vector<int32_t> h_rp(rp_off[count]);
+  BHIPC(hipMemcpyAsync(h_rp.data(), row_ptr_cat, h_rp.size() * 4, hipMemcpyDeviceToHost, st));
+  BHIPC(hipStreamSynchronize(st));
+  std::vector<int64_t> edge_off(count + 1);
+  edge_off[0] = 0;
+  for (int b = 0; b < count; ++b) edge_off[b + 1] = edge_off[b] + h_rp[rp_off[b] + n[b]];
+  const int64_t E = edge_off[count];
+  if (E <= 0 || E > INT32_MAX) return bfail(PDHCG_ERR_ARG, "total edges must be in (0, 2^31)");
+  std::vector<int32_t> h_col(E);
+  std::vector<float> h_u(E), h_w(row_off[count]);
+  BHIPC(hipMemcpyAsync(h_col.data(), col_cat, E * 4, hipMemcpyDeviceToHost, st));
+  BHIPC(hipMemcpyAsync(h_u.data(), u_cat, E * 4, hipMemcpyDeviceToHost, st));
+  BHIPC(hipMemcpyAsync(h_w.data(), w_cat, h_w.size() * 4, hipMemcpyDeviceToHost, st));
+  BHIPC(hipStreamSynchronize(st));
+  std::vector<double> sumw(count);
+  std::vector<int32_t> shape(count), deg(good_off[count], 0);
+  for (int b = 0; b < count; ++b) {
+    const int32_t rc = pdhcg_validate_host(n[b], m[b], h_rp[rp_off[b] + n[b]], h_rp.data() + rp_off[b],
+                                           h_col.data() + edge_off[b], h_u.data() + edge_off[b],
+                                           h_w.data() + row_off[b]);
+    if (rc != PDHCG_OK) {
+      return bfail(rc, "market " + std::to_string(b) + ": " + pdhcg_last_error());
+    }
+    double s = 0.0;
+    int dmax = 0;
+    for (int i = 0; i < n[b]; ++i) {
+      s += h_w[row_off[b] + i];
+      dmax = std::max(dmax, h_rp[rp_off[b] + i + 1] - h_rp[rp_off[b] + i]);
+    }
+    for (int64_t k = edge_off[b]; k < edge_off[b + 1]; ++k) deg[good_off[b] + h_col[k]] += 1;
+    sumw[b] = s;
+    // row shape: 8x4, 16x4, 32x4, 64x4, 64x8 (+ whole-wave path beyond 512)
+    shape[b] = dmax <= 32 ? 0 : dmax <= 64 ? 1 : dmax <= 128 ? 2 : dmax <= 256 ? 3 : 4;
+  }
+  std::vector<int32_t> order(count);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return edge_off[a + 1] - edge_off[a] > edge_off[b + 1] - edge_off[b];
+  });
+
+  pdhcg_batch bt = new (std::nothrow) pdhcg_batch_s();
+  if (!bt) return bfail(PDHCG_ERR_OOM, "host allocation failed");
+  bt->count = count;
+  bt->stream = st;
+  bt->h_n.assign(n, n + count);
+  bt->h_m.assign(m, m + count);
+  bt->h_rp_off = rp_off;
+  bt->h_row_off = row_off;
+  bt->h_good_off = good_off;
+  bt->h_edge_off = edge_off;
+  bt->total_rows = row_off[count];
+  bt->total_goods = good_off[count];
+  bt->total_edges = E;
+  auto cleanup = [&](int32_t code) {
+    pdhcg_batch_destroy(bt);
+    return code;
+  };
+#define BK(call)                                                                     \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess) {                                                          \
+      bfail(e_ == hipErrorOutOfMemory ? PDHCG_ERR_OOM : PDHCG_ERR_HIP,               \
+            std::string(#call) + ": " + hipGetErrorString(e_));                      \
+      return cleanup(e_ == hipErrorOutOfMemory ? PDHCG_ERR_OOM : PDHCG_ERR_HIP);     \
+    }                                                                                \
+  } while (0)
+  BK(balloc(&bt->order, count)); BK(balloc(&bt->n, count)); BK(balloc(&bt->m, count));
+  BK(balloc(&bt->shape, count)); BK(balloc(&bt->rp_off, count + 1));
+  BK(balloc(&bt->row_off, count + 1)); BK(balloc(&bt->good_off, count + 1));
+  BK(balloc(&bt->edge_off, count + 1)); BK(balloc(&bt->sumw, count));
+  BK(balloc(&bt->row_ptr, rp_off[count])); BK(balloc(&bt->col, E)); BK(balloc(&bt->deg, good_off[count]));
+  BK(balloc(&bt->uh, E)); BK(balloc(&bt->w, row_off[count])); BK(balloc(&bt->rowmax, row_off[count]));
+  for (int q = 0; q < 3; ++q) {
+    BK(balloc(&bt->X[q], E));
+    BK(balloc(&bt->P[q], good_off[count]));
+    BK(balloc(&bt->C[q], good_off[count]));
+  }
+  BK(balloc(&bt->XA, E)); BK(balloc(&bt->PA, good_off[count]));
+  BK(balloc(&bt->info, count)); BK(balloc(&bt->queue, 1));
+  // normalised utilities (Sec. 5 preprocessing), on the host copy
+  std::vector<float> h_uh(E), h_rowmax(row_off[count]);
+  for (int b = 0; b < count; ++b)
+    for (int i = 0; i < n[b]; ++i) {
+      const int64_t r0 = edge_off[b] + h_rp[rp_off[b] + i], r1 = edge_off[b] + h_rp[rp_off[b] + i + 1];
+      float mx = 0.0f;
+      for (int64_t k = r0; k < r1; ++k) mx = std::max(mx, h_u[k]);
+      h_rowmax[row_off[b] + i] = mx;
+      for (int64_t k = r0; k < r1; ++k) h_uh[k] = h_u[k] / mx;
+    }
+  BK(hipMemcpyAsync(bt->order, order.data(), count * 4, hipMemcpyHostToDevice, st));
+  BK(hipMemcpyAsync(bt->n, n, count * 4, hipMemcpyHostToDevice, st));
+  BK(hipMemcpyAsync(bt->m, m, count * 4, hipMemcpyHostToDevice, st));
+  BK(hipMemcpyAsync(bt->shape, shape.data(), count * 4, hipMemcpyHostToDevice, st));
+  BK(hipMemcpyAsync(bt->rp_off, rp_off.data(), (count + 1) * 8, hipMemcpyHostToDevice, st));
+  BK(hipMemcpyAsync(bt->row_off, row_off.data(), (count + 1) * 8, hipMemcpyHostToDevice, st));
+  BK(hipMemcpyAsync(bt->good_off, good_off.data(), (count + 1) * 8, hipMemcpyHostToDevice, st));
+  BK(hipMemcpyAsync(bt->edge_off, edge_off.data(), (count + 1) * 8, hipMemcpyHostToDevice, st));
+  BK(hipMemcpyAsync(bt->sumw, sumw.data(), count * 8, hipMemcpyHostToDevice, st));
+  BK(hipMemcpyAsync(bt->row_ptr, row_ptr_cat, rp_off[count] * 4, hipMemcpyDeviceToDevice, st));
+  BK(hipMemcpyAsync(bt->col, col_cat, E * 4, hipMemcpyDeviceToDevice, st));
+  BK(hipMemcpyAsync(bt->deg, deg.data(), deg.size() * 4, hipMemcpyHostToDevice, st));
+  BK(hipMemcpyAsync(bt->uh, h_uh.data(), E * 4, hipMemcpyHostToDevice, st));
+  BK(hipMemcpyAsync(bt->w, w_cat, row_off[count] * 4, hipMemcpyDeviceToDevice, st));
+  BK(hipMemcpyAsync(bt->rowmax, h_rowmax.data(), row_off[count] * 4, hipMemcpyHostToDevice, st));
+  BK(hipStreamSynchronize(st));
+#undef BK
+  *out = bt;
+  return PDHCG_OK;
+}
+
+extern "C" int32_t pdhcg_batch_solve(pdhcg_batch bt, const pdhcg_params *params, float *p_cat,
+                                     float *x_cat, pdhcg_info *infos) {
+  if (!bt || !p_cat || !x_cat) return bfail(PDHCG_ERR_ARG, "null argument");
+  pdhcg_params dflt;
+  pdhcg_default_params(&dflt);
+  const pdhcg_params *p = params ? params : &dflt;
+  if (!(p->tol >= 0.0) || p->max_iter < 0 || p->eval_every <= 0 || p->max_search_rounds < 1)
+    return bfail(PDHCG_ERR_ARG, "invalid parameters");
+  if (p->search != PDHCG_SEARCH_ACTIVESET)
+    return bfail(PDHCG_ERR_UNSUPPORTED, "the batched solver uses the active-set search");
+  BatchParamsDev d;
+  d.tol = p->tol;
+  d.max_iter = p->max_iter;
+  d.eval_every = p->eval_every;
+  d.max_rounds = p->max_search_rounds;
+  d.step_mode = p->step_mode;
+  d.restart = p->restart;
+  d.rtol = p->search_rtol;
+  d.beta_suff = p->beta_sufficient;
+  d.beta_nec = p->beta_necessary;
+  d.beta_art = p->beta_artificial;
+  d.theta = p->theta;
+  d.omega_bound = p->omega_bound;
+  d.eta0 = p->eta0;
+  d.omega0 = p->omega0;
+  d.omega_check_every = p->omega_check_every;
+  d.output = p->output;
+  BatchDev bd;
+  bd.count = bt->count;
+  bd.order = bt->order; bd.n = bt->n; bd.m = bt->m; bd.shape = bt->shape;
+  bd.rp_off = bt->rp_off; bd.row_off = bt->row_off; bd.good_off = bt->good_off;
+  bd.edge_off = bt->edge_off; bd.sumw = bt->sumw;
+  bd.row_ptr = bt->row_ptr; bd.col = bt->col; bd.deg = bt->deg;
+  bd.uh = bt->uh; bd.w = bt->w; bd.rowmax = bt->rowmax;
+  bd.X0 = bt->X[0]; bd.X1 = bt->X[1]; bd.X2 = bt->X[2]; bd.XA = bt->XA;
+  bd.P0 = bt->P[0]; bd.P1 = bt->P[1]; bd.P2 = bt->P[2]; bd.PA = bt->PA;
+  bd.C0 = bt->C[0]; bd.C1 = bt->C[1]; bd.C2 = bt->C[2];
+  bd.p_out = p_cat; bd.x_out = x_cat;
+  bd.info = bt->info; bd.queue = bt->queue;
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+    cus = prop.multiProcessorCount;
+  int per_cu = 0;
+  BHIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_solve, kBatchBlock, 0));
+  if (per_cu < 1) per_cu = 1;
+  const int grid = std::min<int64_t>((int64_t)cus * per_cu, bt->count);
+  BHIPC(hipMemsetAsync(bt->queue, 0, sizeof(uint32_t), bt->stream));
+  const auto t0 = std::chrono::steady_clock::now();
+  hipLaunchKernelGGL(k_batch_solve, dim3(grid), dim3(kBatchBlock), 0, bt->stream, bd, d);
+  BHIPC(hipGetLastError());
+  std::vector<BatchInfoDev> hi(bt->count);
+  BHIPC(hipMemcpyAsync(hi.data(), bt->info, hi.size() * sizeof(BatchInfoDev),
+                       hipMemcpyDeviceToHost, bt->stream));
+  BHIPC(hipStreamSynchronize(bt->stream));
+  const double secs =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int32_t worst = PDHCG_OK;
+  for (int b = 0; b < bt->count; ++b) {
+    if (hi[b].status < 0) worst = std::min(worst, hi[b].status);
+    else if (hi[b].status == PDHCG_MAX_ITER && worst == PDHCG_OK) worst = PDHCG_MAX_ITER;
+    if (infos) {
+      pdhcg_info &I = infos[b];
+      std::memset(&I, 0, sizeof(I));
+      I.rel_primal = hi[b].kkt[0];
+      I.rel_dual = hi[b].kkt[1];
+      I.rel_gap = hi[b].kkt[2];
+      I.rel_kkt = hi[b].rel_kkt;
+      I.eta = hi[b].eta;
+      I.omega = hi[b].omega;
+      I.iters = hi[b].iters;
+      I.accepted = hi[b].accepted;
+      I.restarts = hi[b].restarts;
+      I.status = hi[b].status;
+      I.evals = hi[b].evals;
+      I.seconds = secs;
+    }
+  }
+  return worst;
+}
+
+extern "C" int32_t pdhcg_batch_layout(pdhcg_batch bt, int64_t *good_off, int64_t *edge_off) {
+  if (!bt) return bfail(PDHCG_ERR_ARG, "null batch");
+  for (int b = 0; b <= bt->count; ++b) {
+    if (good_off) good_off[b] = bt->h_good_off[b];
+    if (edge_off) edge_off[b] = bt->h_edge_off[b];
+  }
+  return PDHCG_OK;
+}

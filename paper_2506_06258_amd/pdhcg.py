@@ -34,6 +34,7 @@ EXPORTS = (
     "pdhcg_default_params", "pdhcg_validate_host", "pdhcg_market_create",
     "pdhcg_set_budgets", "pdhcg_solve", "pdhcg_kkt", "pdhcg_row_prox",
     "pdhcg_arrow_debreu", "pdhcg_market_bins", "pdhcg_market_destroy",
+    "pdhcg_batch_create", "pdhcg_batch_solve", "pdhcg_batch_layout", "pdhcg_batch_destroy",
 )
 
 
@@ -93,6 +94,10 @@ def lib() -> C.CDLL:
                                      C.POINTER(pdhcg_info)]),
         "pdhcg_market_bins": (i32, [vp, i32, vp, vp, vp]),
         "pdhcg_market_destroy": (None, [vp]),
+        "pdhcg_batch_create": (i32, [i32, vp, vp, vp, vp, vp, vp, vp, C.POINTER(vp)]),
+        "pdhcg_batch_solve": (i32, [vp, C.POINTER(pdhcg_params), vp, vp, vp]),
+        "pdhcg_batch_layout": (i32, [vp, vp, vp]),
+        "pdhcg_batch_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -331,3 +336,74 @@ class Market:
         st, outer, inner_it, info = pdhcg_arrow_debreu(self._h, erp, ecl, ev, ecl.numel(), inner,
                                                        outer_tol, outer_max, w, p, x)
         return dict(status=st, p=p, w=w, x=x, outer=outer, inner=inner_it, info=info)
+
+
+def pdhcg_batch_create(count, n, m, row_ptr_cat, col_cat, u_cat, w_cat, stream=None):
+    """n, m: host int32 arrays; the CSR arrays are device tensors."""
+    import numpy as np
+    nn = np.ascontiguousarray(n, dtype=np.int32)
+    mm = np.ascontiguousarray(m, dtype=np.int32)
+    h = C.c_void_p()
+    st = lib().pdhcg_batch_create(int(count), _host_ptr(nn, "n"), _host_ptr(mm, "m"),
+                                  _dev_ptr(row_ptr_cat, torch.int32, "row_ptr_cat"),
+                                  _dev_ptr(col_cat, torch.int32, "col_cat"),
+                                  _dev_ptr(u_cat, torch.float32, "u_cat"),
+                                  _dev_ptr(w_cat, torch.float32, "w_cat"),
+                                  _stream_handle(stream), C.byref(h))
+    _check(st, "pdhcg_batch_create")
+    return h
+
+
+def pdhcg_batch_solve(h, params: pdhcg_params, p_cat, x_cat, count: int):
+    infos = (pdhcg_info * count)()
+    st = lib().pdhcg_batch_solve(h, C.byref(params), _dev_ptr(p_cat, torch.float32, "p_cat"),
+                                 _dev_ptr(x_cat, torch.float32, "x_cat"), infos)
+    _check(st, "pdhcg_batch_solve", ok=(PDHCG_OK, PDHCG_MAX_ITER))
+    return st, list(infos)
+
+
+def pdhcg_batch_layout(h, count: int):
+    import numpy as np
+    g = np.zeros(count + 1, np.int64)
+    e = np.zeros(count + 1, np.int64)
+    _check(lib().pdhcg_batch_layout(h, _host_ptr(g, "good_off"), _host_ptr(e, "edge_off")),
+           "pdhcg_batch_layout")
+    return g, e
+
+
+def pdhcg_batch_destroy(h) -> None:
+    if h:
+        lib().pdhcg_batch_destroy(h)
+
+
+class Batch:
+    """Many independent markets solved in one persistent launch."""
+
+    def __init__(self, batch, device="cuda", stream=None):
+        dev = torch.device(device)
+        self.count = int(batch.count)
+        self.device = dev
+        rp = torch.as_tensor(batch.row_ptr, dtype=torch.int32).to(dev).contiguous()
+        col = torch.as_tensor(batch.col, dtype=torch.int32).to(dev).contiguous()
+        u = torch.as_tensor(batch.u).to(dev, torch.float32).contiguous()
+        w = torch.as_tensor(batch.w).to(dev, torch.float32).contiguous()
+        self._h = pdhcg_batch_create(self.count, batch.n, batch.m, rp, col, u, w, stream)
+        self.good_off, self.edge_off = pdhcg_batch_layout(self._h, self.count)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            pdhcg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, params: Optional[pdhcg_params] = None, **kw):
+        prm = params if params is not None else pdhcg_default_params(**kw)
+        p = torch.empty(int(self.good_off[-1]), dtype=torch.float32, device=self.device)
+        x = torch.empty(int(self.edge_off[-1]), dtype=torch.float32, device=self.device)
+        st, infos = pdhcg_batch_solve(self._h, prm, p, x, self.count)
+        return st, p, x, infos

@@ -168,3 +168,128 @@ def fisher_1e8(seed: int = 1, n: int = 1_000_000, m: int = 10_000, d: int = 100)
     u ~ LogNormal(0, 1), w ~ U(0.5, 1.5), float32."""
     return fixed_degree_market(n, m, d, seed, "lognormal", 0.5, 1.5, np.float32,
                                name=f"fisher-{n}x{m}-d{d}-s{seed}")
+
+
+def arrow_debreu_market(n: int, m: int, deg_u: int, deg_e: int, seed: int,
+                        dtype=np.float32, name: str = "") -> Market:
+    """Exchange market (Sec. 4): every agent values ``deg_u`` distinct
+    uniform goods with u ~ LogNormal(0, 1) and owns ``deg_e`` distinct
+    uniform goods with weights ~ U(0, 1); a good nobody owns gets one random
+    owner; then every column of E is normalised to sum one (Sec. 4).
+    Initial budgets w^0 = 1."""
+    rng = np.random.default_rng(seed)
+    Cu = _distinct_sorted_rows(rng, n, deg_u, m)
+    col = Cu.reshape(-1)
+    if (np.bincount(col, minlength=m) == 0).any():
+        raise RuntimeError("a good received no buyer; raise n*deg_u relative to m")
+    row_ptr = (np.arange(n + 1, dtype=np.int64) * deg_u).astype(np.int32)
+    u = np.exp(rng.standard_normal(col.size)).astype(dtype)
+    Ce = _distinct_sorted_rows(rng, n, deg_e, m)
+    ev = rng.uniform(0.0, 1.0, Ce.shape)
+    rows_e = np.repeat(np.arange(n), deg_e)
+    cols_e = Ce.reshape(-1)
+    vals_e = ev.reshape(-1)
+    owned = np.bincount(cols_e, minlength=m) > 0
+    orphans = np.nonzero(~owned)[0]
+    if orphans.size:
+        rows_e = np.concatenate([rows_e, rng.integers(0, n, orphans.size)])
+        cols_e = np.concatenate([cols_e, orphans])
+        vals_e = np.concatenate([vals_e, rng.uniform(0.0, 1.0, orphans.size)])
+    order = np.lexsort((cols_e, rows_e))
+    rows_e, cols_e, vals_e = rows_e[order], cols_e[order], vals_e[order]
+    colsum = np.bincount(cols_e, weights=vals_e, minlength=m)
+    vals_e = vals_e / colsum[cols_e]
+    e_row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows_e, minlength=n), out=e_row_ptr[1:])
+    mk = Market(n, m, row_ptr, col, u, np.ones(n, dtype=dtype),
+                name or f"ad-{n}x{m}-du{deg_u}-de{deg_e}-s{seed}",
+                e_row_ptr.astype(np.int32), cols_e.astype(np.int32), vals_e.astype(dtype))
+    return mk
+
+
+@dataclass
+class MarketBatch:
+    """Independent Fisher markets concatenated: market b owns rows
+    row_off[b]..row_off[b+1] (local row pointers concatenated in row_ptr,
+    each starting at 0), edges edge_off[b]..edge_off[b+1] (local good ids in
+    col) and goods good_off[b]..good_off[b+1]."""
+
+    count: int
+    n: np.ndarray  # int32 [count]
+    m: np.ndarray  # int32 [count]
+    row_ptr: np.ndarray  # int32 [sum(n) + count] local row pointers
+    col: np.ndarray  # int32 [sum nnz] local good ids
+    u: np.ndarray  # float32 [sum nnz]
+    w: np.ndarray  # float32 [sum n]
+    name: str = ""
+
+    @property
+    def nnz(self) -> np.ndarray:
+        return np.array([self.market(b).nnz for b in range(self.count)])
+
+    def offsets(self):
+        n, m = self.n.astype(np.int64), self.m.astype(np.int64)
+        rp_off = np.concatenate([[0], np.cumsum(n + 1)])
+        row_off = np.concatenate([[0], np.cumsum(n)])
+        good_off = np.concatenate([[0], np.cumsum(m)])
+        nnz = self.row_ptr[rp_off[1:] - 1].astype(np.int64)
+        edge_off = np.concatenate([[0], np.cumsum(nnz)])
+        return rp_off, row_off, good_off, edge_off
+
+    def market(self, b: int) -> Market:
+        rp_off, row_off, good_off, edge_off = self.offsets()
+        rp = self.row_ptr[rp_off[b]:rp_off[b + 1]]
+        e0, e1 = edge_off[b], edge_off[b + 1]
+        return Market(int(self.n[b]), int(self.m[b]), rp, self.col[e0:e1], self.u[e0:e1],
+                      self.w[row_off[b]:row_off[b + 1]], f"{self.name}[{b}]")
+
+
+def _sample_market(rng, n: int, m: int, q: float):
+    """A random pattern with round(n m q) edges placed uniformly (at least
+    one per buyer and per good), u ~ U(0.01, 1), w ~ U(0.5, 1.5)."""
+    k = max(1, int(round(n * m * q)))
+    pos = np.sort(rng.choice(n * m, size=k, replace=False))
+    rows, cols = pos // m, pos % m
+    have_r = np.bincount(rows, minlength=n) > 0
+    have_c = np.bincount(cols, minlength=m) > 0
+    extra_r = np.nonzero(~have_r)[0]
+    extra_c = np.nonzero(~have_c)[0]
+    add = [(r, int(rng.integers(0, m))) for r in extra_r] + \
+          [(int(rng.integers(0, n)), c) for c in extra_c]
+    if add:
+        pos = np.unique(np.concatenate([pos, np.array([r * m + c for r, c in add], np.int64)]))
+        rows, cols = pos // m, pos % m
+    row_ptr = np.zeros(n + 1, np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=row_ptr[1:])
+    u = rng.uniform(0.01, 1.0, pos.size).astype(np.float32)
+    w = rng.uniform(0.5, 1.5, n).astype(np.float32)
+    return row_ptr.astype(np.int32), cols.astype(np.int32), u, w
+
+
+def batch_markets(count: int, seed: int, n_range=(64, 8192), m_range=(16, 2048),
+                  q_range=(0.05, 0.30)) -> MarketBatch:
+    """``count`` independent markets: n, m log-uniform over the ranges,
+    density q ~ U(q_range), u ~ U(0.01, 1), w ~ U(0.5, 1.5), float32.
+    Market b uses its own generator seeded with (seed, b)."""
+    ns, ms, rps, cols, us, ws = [], [], [], [], [], []
+    for b in range(count):
+        rng = np.random.default_rng([seed, b])
+        n = int(round(np.exp(rng.uniform(np.log(n_range[0]), np.log(n_range[1])))))
+        m = int(round(np.exp(rng.uniform(np.log(m_range[0]), np.log(m_range[1])))))
+        q = float(rng.uniform(*q_range))
+        rp, c, u, w = _sample_market(rng, n, m, q)
+        ns.append(n); ms.append(m); rps.append(rp); cols.append(c); us.append(u); ws.append(w)
+    return MarketBatch(count, np.array(ns, np.int32), np.array(ms, np.int32),
+                       np.concatenate(rps), np.concatenate(cols), np.concatenate(us),
+                       np.concatenate(ws), f"batch-{count}-s{seed}")
+
+
+def batch_from_markets(markets, name: str = "") -> MarketBatch:
+    """Concatenate independent markets into a MarketBatch."""
+    return MarketBatch(len(markets), np.array([mk.n for mk in markets], np.int32),
+                       np.array([mk.m for mk in markets], np.int32),
+                       np.concatenate([np.asarray(mk.row_ptr, np.int32) for mk in markets]),
+                       np.concatenate([np.asarray(mk.col, np.int32) for mk in markets]),
+                       np.concatenate([np.asarray(mk.u, np.float32) for mk in markets]),
+                       np.concatenate([np.asarray(mk.w, np.float32) for mk in markets]),
+                       name or f"batch-of-{len(markets)}")

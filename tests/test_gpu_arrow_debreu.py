@@ -1,0 +1,50 @@
+"""Arrow-Debreu fixed point (Sec. 4, Alg. 4) on the GPU through the C ABI,
+against the oracle's fixed point on the same seeded exchange market.
+
+Tolerance: each inner solve stops at relative KKT 1e-7 on the device (float32
+allocations), so prices carry ~1e-6 relative noise; the fixed point is
+compared at 1e-4 relative, and its defining identities (sum of budgets kept,
+E p = w) at float32 rounding."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2506_06258_amd import pdhcg, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def test_arrow_debreu_matches_oracle(cuda):
+    mk = synth.arrow_debreu_market(400, 300, 25, 4, 7)
+    inner64 = oracle.default_params(tol=1e-11, max_iter=400000)
+    ref = oracle.arrow_debreu(mk.n, mk.m, mk.row_ptr, mk.col, mk.u.astype(np.float64),
+                              mk.e_row_ptr, mk.e_col, mk.e_val.astype(np.float64),
+                              np.ones(mk.n), inner64, outer_tol=1e-8, outer_max=400)
+    assert ref["status"] == oracle.OK
+
+    M = pdhcg.Market.from_synth(mk, device=cuda)
+    inner = pdhcg.pdhcg_default_params(tol=1e-7, max_iter=200000)
+    res = M.arrow_debreu(mk.e_row_ptr, mk.e_col, mk.e_val, np.ones(mk.n, np.float32), inner,
+                         outer_tol=1e-5, outer_max=200)
+    assert res["status"] == pdhcg.PDHCG_OK, pdhcg.pdhcg_last_error()
+    p = res["p"].double().cpu().numpy()
+    w = res["w"].double().cpu().numpy()
+    assert abs(w.sum() - mk.n) / mk.n < 1e-5
+    assert abs(p.sum() - mk.n) / mk.n < 1e-5
+    rows_e = np.repeat(np.arange(mk.n), np.diff(mk.e_row_ptr))
+    Ep = np.bincount(rows_e, weights=mk.e_val.astype(np.float64) * p[mk.e_col], minlength=mk.n)
+    assert np.max(np.abs(Ep - w) / w) < 1e-5
+    assert np.max(np.abs(p - ref["p"])) / np.max(ref["p"]) < 1e-4
+    M.close()
+
+
+def test_arrow_debreu_rejects_bad_endowments(cuda):
+    mk = synth.arrow_debreu_market(50, 40, 8, 2, 3)
+    M = pdhcg.Market.from_synth(mk, device=cuda)
+    bad = mk.e_val.copy()
+    bad[0] *= 2.0  # the column of that entry no longer sums to one
+    with pytest.raises(pdhcg.PDHCGError) as e:
+        M.arrow_debreu(mk.e_row_ptr, mk.e_col, bad, np.ones(mk.n, np.float32))
+    assert e.value.status == pdhcg.PDHCG_ERR_ARG
+    M.close()

@@ -233,3 +233,25 @@ def test_max_iter_status(small_market):
     mk = small_market
     s = oracle.solve(mk.n, mk.m, mk.row_ptr, mk.col, mk.u, mk.w, tol=1e-14, max_iter=10)
     assert s.status == oracle.MAX_ITER and s.iters == 10
+
+
+def test_arrow_debreu_fixed_point():
+    """Alg. 4: the budgets keep their sum (sum_i (E p)_i = sum_j p_j =
+    sum_i w_i, Sec. 4) and the limit satisfies w = E p(w)."""
+    mk = synth.arrow_debreu_market(60, 50, 10, 3, 2, dtype=np.float64)
+    inner = oracle.default_params(tol=1e-11, max_iter=400000)
+    res = oracle.arrow_debreu(mk.n, mk.m, mk.row_ptr, mk.col, mk.u, mk.e_row_ptr, mk.e_col,
+                              mk.e_val, np.ones(mk.n), inner, outer_tol=1e-9, outer_max=400)
+    assert res["status"] == oracle.OK, res
+    assert res["w"].sum() == pytest.approx(mk.n, rel=1e-9)
+    assert res["p"].sum() == pytest.approx(mk.n, rel=1e-8)
+    rows_e = np.repeat(np.arange(mk.n), np.diff(mk.e_row_ptr))
+    Ep = np.bincount(rows_e, weights=mk.e_val * res["p"][mk.e_col], minlength=mk.n)
+    assert np.max(np.abs(Ep - res["w"]) / res["w"]) < 1e-12
+    # the prices are the Fisher equilibrium for the final budgets
+    fis = oracle.solve(mk.n, mk.m, mk.row_ptr, mk.col, mk.u, res["w"], tol=1e-11,
+                       max_iter=400000)
+    assert rel_err(res["p"], fis.p) < 1e-6
+    # ... and (nearly) a fixed point: E p(w) reproduces w
+    Ep2 = np.bincount(rows_e, weights=mk.e_val * fis.p[mk.e_col], minlength=mk.n)
+    assert np.max(np.abs(Ep2 - res["w"]) / res["w"]) < 1e-6

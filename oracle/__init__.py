@@ -92,6 +92,9 @@ def lib():
                                        C.POINTER(C.c_int), C.POINTER(C.c_int64),
                                        C.POINTER(C.c_double)]
         L.ora_arrow_debreu.restype = C.c_int
+        L.ora_implicit_grad.argtypes = [C.c_int, C.c_int, ip64, ip32, dp, dp, dp, dp, dp,
+                                        C.c_double, dp, dp, C.POINTER(C.c_int)]
+        L.ora_implicit_grad.restype = C.c_int
         _lib = L
     return _lib
 
@@ -264,3 +267,19 @@ def arrow_debreu(n, m, row_ptr, col, u, e_row_ptr, e_col, e_val, w0, inner: OraP
                                 _ptr(x, C.c_double), C.byref(oi), C.byref(ii), C.byref(ch))
     return dict(p=p, w=w, x=x, status=int(st), outer=oi.value, inner=ii.value,
                 change=ch.value)
+
+
+def implicit_grad(n, m, row_ptr, col, u, w, x, p, dL_dp, act_tol=1e-9):
+    """dL/du (on the stored pattern) and dL/dw of a loss L(p) at the
+    equilibrium (x, p), by the implicit function theorem on the equilibrium
+    conditions over the active support.  Returns (status, dL_du, dL_dw, dim)."""
+    rp, cl = _csr(row_ptr, col)
+    u, w, x, p, g = _d(u), _d(w), _d(x), _d(p), _d(dL_dp)
+    du = np.zeros(int(rp[-1]))
+    dw = np.zeros(n)
+    dim = C.c_int(0)
+    st = lib().ora_implicit_grad(n, m, _ptr(rp, C.c_int64), _ptr(cl, C.c_int32),
+                                 _ptr(u, C.c_double), _ptr(w, C.c_double), _ptr(x, C.c_double),
+                                 _ptr(p, C.c_double), _ptr(g, C.c_double), float(act_tol),
+                                 _ptr(du, C.c_double), _ptr(dw, C.c_double), C.byref(dim))
+    return int(st), du, dw, dim.value

@@ -735,3 +735,115 @@ int ora_arrow_debreu(int n, int m, const int64_t *row_ptr, const int32_t *col,
   free(pprev);
   return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Derivatives of the equilibrium prices with respect to u and w, by the    */
+/* implicit function theorem on the equilibrium conditions (the KKT system  */
+/* of Sec. 3, eq. KKT-system-pdhcg) restricted to the active support        */
+/* S = {(i,j) : x_ij > act_tol}.  Unknowns z = (x_S, p, a) with a_i the     */
+/* buyer's best utility per unit of money (Fact 1: every bought good        */
+/* attains it):                                                             */
+/*   F_ij = u_ij - a_i p_j                 for (i,j) in S,                  */
+/*   F_i  = sum_{j:(i,j) in S} p_j x_ij - w_i       (budget spent),         */
+/*   F_j  = sum_{i:(i,j) in S} x_ij - 1              (market clears).        */
+/* J = dF/dz is square (|S| + m + n).  For a loss L(p), J^T lam = dL/dz     */
+/* (dL/dp in the p block, zero elsewhere) and dL/dtheta = -(dF/dtheta)^T    */
+/* lam; dF_ij/du_ij = 1 and dF_i/dw_i = -1 give                             */
+/*   dL/du_ij = -lam_ij on S, 0 off S;   dL/dw_i = lam_i.                   */
+/* Off S the derivative is zero because a nondegenerate equilibrium keeps   */
+/* its support under small perturbations.  u is the caller's (not row-      */
+/* normalised) utility: the conditions are homogeneous in each row.         */
+/* Dense Gaussian elimination with partial pivoting: small markets only.    */
+/* Returns ORA_ERR_NUMERIC when J is singular (a degenerate support) and    */
+/* writes the size of the system to *dim.                                   */
+/* ------------------------------------------------------------------------ */
+static int dense_solve(int N, double *A, double *b) {
+  /* A row-major N x N, overwritten; b overwritten by the solution */
+  double amax = 0.0;
+  for (int64_t q = 0; q < (int64_t)N * N; ++q) amax = fmax(amax, fabs(A[q]));
+  for (int k = 0; k < N; ++k) {
+    int piv = k;
+    for (int r = k + 1; r < N; ++r)
+      if (fabs(A[(int64_t)r * N + k]) > fabs(A[(int64_t)piv * N + k])) piv = r;
+    if (!(fabs(A[(int64_t)piv * N + k]) > 1e-12 * amax)) return ORA_ERR_NUMERIC;
+    if (piv != k) {
+      for (int c = 0; c < N; ++c) {
+        double t = A[(int64_t)k * N + c];
+        A[(int64_t)k * N + c] = A[(int64_t)piv * N + c];
+        A[(int64_t)piv * N + c] = t;
+      }
+      double t = b[k]; b[k] = b[piv]; b[piv] = t;
+    }
+    for (int r = k + 1; r < N; ++r) {
+      double f = A[(int64_t)r * N + k] / A[(int64_t)k * N + k];
+      if (f == 0.0) continue;
+      for (int c = k; c < N; ++c) A[(int64_t)r * N + c] -= f * A[(int64_t)k * N + c];
+      b[r] -= f * b[k];
+    }
+  }
+  for (int k = N - 1; k >= 0; --k) {
+    double s = b[k];
+    for (int c = k + 1; c < N; ++c) s -= A[(int64_t)k * N + c] * b[c];
+    b[k] = s / A[(int64_t)k * N + k];
+  }
+  return ORA_OK;
+}
+
+int ora_implicit_grad(int n, int m, const int64_t *row_ptr, const int32_t *col,
+                      const double *u, const double *w, const double *x, const double *p,
+                      const double *dL_dp, double act_tol, double *dL_du, double *dL_dw,
+                      int *dim) {
+  (void)w;
+  int64_t nnz = row_ptr[n];
+  int64_t *sidx = (int64_t *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int64_t));
+  int32_t *srow = (int32_t *)malloc((size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t));
+  double *a = (double *)calloc((size_t)n, sizeof(double));
+  if (!sidx || !srow || !a) { free(sidx); free(srow); free(a); return ORA_ERR_OOM; }
+  int S = 0;
+  for (int i = 0; i < n; ++i) {
+    int cnt = 0;
+    for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q)
+      if (x[q] > act_tol) {
+        sidx[S] = q;
+        srow[S] = i;
+        ++S;
+        a[i] += u[q] / p[col[q]];
+        ++cnt;
+      }
+    if (cnt == 0) { free(sidx); free(srow); free(a); return ORA_ERR_NUMERIC; }
+    a[i] /= cnt;
+  }
+  const int N = S + m + n;
+  if (dim) *dim = N;
+  double *J = (double *)calloc((size_t)N * N, sizeof(double));
+  double *At = (double *)malloc((size_t)N * N * sizeof(double));
+  double *lam = (double *)calloc((size_t)N, sizeof(double));
+  if (!J || !At || !lam) {
+    free(J); free(At); free(lam); free(sidx); free(srow); free(a);
+    return ORA_ERR_OOM;
+  }
+  /* unknown columns: x_S -> [0, S), p -> [S, S+m), a -> [S+m, N)           */
+  /* equation rows:   F_ij -> [0, S), F_i -> [S, S+n), F_j -> [S+n, N)      */
+#define JX(r, c) J[(int64_t)(r) * N + (c)]
+  for (int s = 0; s < S; ++s) {
+    const int i = srow[s];
+    const int j = col[sidx[s]];
+    JX(s, S + m + i) = -p[j];         /* dF_ij/da_i */
+    JX(s, S + j) = -a[i];             /* dF_ij/dp_j */
+    JX(S + i, s) = p[j];              /* dF_i/dx_ij */
+    JX(S + i, S + j) += x[sidx[s]];   /* dF_i/dp_j  */
+    JX(S + n + j, s) = 1.0;           /* dF_j/dx_ij */
+  }
+#undef JX
+  for (int r = 0; r < N; ++r)
+    for (int c = 0; c < N; ++c) At[(int64_t)r * N + c] = J[(int64_t)c * N + r];
+  for (int j = 0; j < m; ++j) lam[S + j] = dL_dp[j];
+  int rc = dense_solve(N, At, lam);
+  if (rc == ORA_OK) {
+    for (int64_t q = 0; q < nnz; ++q) dL_du[q] = 0.0;
+    for (int s = 0; s < S; ++s) dL_du[sidx[s]] = -lam[s];
+    for (int i = 0; i < n; ++i) dL_dw[i] = lam[S + i];
+  }
+  free(J); free(At); free(lam); free(sidx); free(srow); free(a);
+  return rc;
+}

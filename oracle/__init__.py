@@ -95,6 +95,9 @@ def lib():
         L.ora_implicit_grad.argtypes = [C.c_int, C.c_int, ip64, ip32, dp, dp, dp, dp, dp,
                                         C.c_double, dp, dp, C.POINTER(C.c_int)]
         L.ora_implicit_grad.restype = C.c_int
+        L.ora_unrolled_grad.argtypes = [C.c_int, C.c_int, ip64, ip32, dp, dp, dp, dp, C.c_double,
+                                        C.c_double, C.c_int, dp, dp, dp, dp]
+        L.ora_unrolled_grad.restype = C.c_int
         _lib = L
     return _lib
 
@@ -283,3 +286,19 @@ def implicit_grad(n, m, row_ptr, col, u, w, x, p, dL_dp, act_tol=1e-9):
                                  _ptr(p, C.c_double), _ptr(g, C.c_double), float(act_tol),
                                  _ptr(du, C.c_double), _ptr(dw, C.c_double), C.byref(dim))
     return int(st), du, dw, dim.value
+
+
+def unrolled_grad(n, m, row_ptr, col, u, w, x0, p0, tau, sigma, K, dL_dp):
+    """Reverse mode through K fixed-step PDHCG iterations from (x0, p0) for a
+    loss of the final prices.  Returns (status, dL_du, dL_dw, p_K)."""
+    rp, cl = _csr(row_ptr, col)
+    u, w, x0, p0, g = _d(u), _d(w), _d(x0), _d(p0), _d(dL_dp)
+    du = np.zeros(int(rp[-1]))
+    dw = np.zeros(n)
+    pK = np.zeros(m)
+    st = lib().ora_unrolled_grad(n, m, _ptr(rp, C.c_int64), _ptr(cl, C.c_int32),
+                                 _ptr(u, C.c_double), _ptr(w, C.c_double), _ptr(x0, C.c_double),
+                                 _ptr(p0, C.c_double), float(tau), float(sigma), int(K),
+                                 _ptr(g, C.c_double), _ptr(du, C.c_double), _ptr(dw, C.c_double),
+                                 _ptr(pK, C.c_double))
+    return int(st), du, dw, pK

@@ -847,3 +847,139 @@ int ora_implicit_grad(int n, int m, const int64_t *row_ptr, const int32_t *col,
   free(J); free(At); free(lam); free(sidx); free(srow); free(a);
   return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Reverse mode through K fixed-step PDHCG iterations (the price step of    */
+/* eq. update:py and the exact row prox of Sec. 2.2) started from a given   */
+/* point (x0, p0), for a loss L(p_K) of the final prices.  The start point  */
+/* is held constant, so as K grows the result tends to the derivative of    */
+/* the fixed point, i.e. to ora_implicit_grad at an equilibrium.            */
+/*                                                                          */
+/* Forward, k = 0..K-1 (c^{-1} = colsum(x0)):                               */
+/*   c^k = colsum(x^k);  p^{k+1} = p^k + sigma (2 c^k - c^{k-1} - 1);       */
+/*   x^{k+1}_i = prox_i(x^k_i - tau p^{k+1}; w_i, uh_i).                    */
+/* Row prox derivative: on the active set A (x^{k+1}_ij > 0) with           */
+/* s = sum_A uh_j x^{k+1}_j, x_j = a_j + tau w uh_j / s, so for an incoming */
+/* adjoint g_j = dL/dx^{k+1}_ij:                                            */
+/*   D = 1 + tau w sum_A uh_j^2 / s^2,                                      */
+/*   h = (tau w / s^2) sum_A g_j uh_j / D,  r_j = g_j - h uh_j on A, 0 off; */
+/*   dL/da_j = r_j,  dL/dw_i += (tau/s) sum_A r_j uh_j,                     */
+/*   dL/duh_j += r_j tau w / s - h x^{k+1}_j  (on A).                       */
+/* With a = x^k - tau p^{k+1} and the linear price step:                    */
+/*   Pt = dL/dp^{k+1} - tau colsum(r);  dL/dp^k = Pt;                       */
+/*   dL/dx^k_ij = r_ij + 2 sigma Pt_j + Cn_j,  Cn_j = dL/dc^k from step k+1;*/
+/*   dL/dc^{k-1} = -sigma Pt.                                               */
+/* Finally through uh = u / max_j u_ij (first maximum):                     */
+/*   dL/du_ij = g_ij / r_i - [j = argmax] sum_k uh_ik g_ik / r_i.           */
+/* p_out (nullable) receives p^K.  Stores all K+1 iterates: small markets.  */
+/* ------------------------------------------------------------------------ */
+int ora_unrolled_grad(int n, int m, const int64_t *row_ptr, const int32_t *col,
+                      const double *u, const double *w, const double *x0, const double *p0,
+                      double tau, double sigma, int K, const double *dL_dp, double *dL_du,
+                      double *dL_dw, double *p_out) {
+  int rc = ora_validate(n, m, row_ptr, col, u, w);
+  if (rc != ORA_OK) return rc;
+  if (K < 0 || !(tau > 0.0) || !(sigma > 0.0)) return ORA_ERR_ARG;
+  const int64_t nnz = row_ptr[n];
+  int dmax = 0;
+  for (int i = 0; i < n; ++i) {
+    int d = (int)(row_ptr[i + 1] - row_ptr[i]);
+    if (d > dmax) dmax = d;
+  }
+  double *uh = (double *)malloc((size_t)nnz * sizeof(double));
+  double *rs = (double *)malloc((size_t)n * sizeof(double));
+  double *xs = (double *)malloc((size_t)(K + 1) * (size_t)nnz * sizeof(double));
+  double *p = (double *)malloc((size_t)m * sizeof(double));
+  double *c = (double *)malloc((size_t)m * sizeof(double));
+  double *cprev = (double *)malloc((size_t)m * sizeof(double));
+  double *R = (double *)calloc((size_t)nnz, sizeof(double));
+  double *r = (double *)calloc((size_t)nnz, sizeof(double));
+  double *duh = (double *)calloc((size_t)nnz, sizeof(double));
+  double *B = (double *)calloc((size_t)m, sizeof(double));
+  double *P = (double *)malloc((size_t)m * sizeof(double));
+  double *Cn = (double *)calloc((size_t)m, sizeof(double));
+  double *rc_col = (double *)malloc((size_t)m * sizeof(double));
+  if (!uh || !rs || !xs || !p || !c || !cprev || !R || !r || !duh || !B || !P || !Cn || !rc_col) {
+    rc = ORA_ERR_OOM;
+    goto done;
+  }
+  for (int i = 0; i < n; ++i) {
+    double mx = 0.0;
+    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+      if (u[k] > mx) mx = u[k];
+    rs[i] = mx;
+    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) uh[k] = u[k] / mx;
+  }
+  /* forward */
+  ora_params prm;
+  ora_default_params(&prm);
+  prm.prox = 0;
+  memcpy(xs, x0, (size_t)nnz * sizeof(double));
+  memcpy(p, p0, (size_t)m * sizeof(double));
+  colsum(n, m, row_ptr, col, x0, cprev);
+  for (int k = 0; k < K; ++k) {
+    const double *xk = xs + (size_t)k * nnz;
+    colsum(n, m, row_ptr, col, xk, c);
+    for (int j = 0; j < m; ++j) p[j] += sigma * (2.0 * c[j] - cprev[j] - 1.0);
+    rc = prox_sweep(n, row_ptr, col, uh, w, xk, p, tau, &prm, dmax, xs + (size_t)(k + 1) * nnz,
+                    NULL);
+    if (rc != ORA_OK) goto done;
+    memcpy(cprev, c, (size_t)m * sizeof(double));
+  }
+  if (p_out) memcpy(p_out, p, (size_t)m * sizeof(double));
+  /* reverse: dL/dx^{k+1} = R + B[col], dL/dp^{k+1} = P, dL/dc^k = Cn */
+  memcpy(P, dL_dp, (size_t)m * sizeof(double));
+  for (int i = 0; i < n; ++i) dL_dw[i] = 0.0;
+  for (int k = K - 1; k >= 0; --k) {
+    const double *xn = xs + (size_t)(k + 1) * nnz;
+    for (int i = 0; i < n; ++i) {
+      double s = 0.0, Q = 0.0, Gu = 0.0;
+      for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q) {
+        if (xn[q] > 0.0) {
+          const double g = R[q] + B[col[q]];
+          s += uh[q] * xn[q];
+          Q += uh[q] * uh[q];
+          Gu += g * uh[q];
+        }
+      }
+      const double D = 1.0 + tau * w[i] * Q / (s * s);
+      const double h = (tau * w[i] / (s * s)) * Gu / D;
+      double ru = 0.0;
+      for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q) {
+        if (xn[q] > 0.0) {
+          const double g = R[q] + B[col[q]];
+          r[q] = g - h * uh[q];
+          ru += r[q] * uh[q];
+          duh[q] += r[q] * tau * w[i] / s - h * xn[q];
+        } else {
+          r[q] = 0.0;
+        }
+      }
+      dL_dw[i] += tau / s * ru;
+    }
+    colsum(n, m, row_ptr, col, r, rc_col);
+    for (int j = 0; j < m; ++j) {
+      const double Pt = P[j] - tau * rc_col[j];
+      B[j] = 2.0 * sigma * Pt + Cn[j];
+      Cn[j] = -sigma * Pt;
+      P[j] = Pt;
+    }
+    memcpy(R, r, (size_t)nnz * sizeof(double));
+  }
+  /* through the row normalisation */
+  for (int i = 0; i < n; ++i) {
+    double gs = 0.0;
+    int64_t qmax = row_ptr[i];
+    for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q) {
+      gs += uh[q] * duh[q];
+      if (u[q] > u[qmax]) qmax = q;
+    }
+    for (int64_t q = row_ptr[i]; q < row_ptr[i + 1]; ++q) dL_du[q] = duh[q] / rs[i];
+    dL_du[qmax] -= gs / rs[i];
+  }
+  rc = ORA_OK;
+done:
+  free(uh); free(rs); free(xs); free(p); free(c); free(cprev); free(R); free(r); free(duh);
+  free(B); free(P); free(Cn); free(rc_col);
+  return rc;
+}

@@ -10,6 +10,11 @@
   6 x 5 market, for active and inactive utilities and for budgets.
 A degenerate support (a cycle of bought goods, so x is not unique) must be
 reported as singular, not given a gradient.
+
+The reverse-mode oracle through the unrolled fixed-step iteration
+(``oracle.unrolled_grad``) is pinned by central finite differences of the
+unrolled map itself (start point held fixed, away from equilibrium) and by
+its limit: started at an equilibrium it tends to the implicit derivative.
 """
 import numpy as np
 import pytest
@@ -162,3 +167,78 @@ def test_prices_sum_gradient_is_budget_sum():
     assert st == oracle.OK
     np.testing.assert_allclose(dw, 1.0, rtol=1e-9)
     np.testing.assert_allclose(du, 0.0, atol=1e-9)
+
+
+# ---------------------------------------------------------------------------
+# Reverse mode through the unrolled fixed-step iteration (oracle.unrolled_grad)
+
+
+def _market(seed, n, m, q):
+    rng = np.random.default_rng(seed)
+    U = rng.uniform(0.05, 1.0, (n, m)) * (rng.uniform(size=(n, m)) < q)
+    for i in range(n):
+        if not U[i].any():
+            U[i, rng.integers(m)] = 0.5
+    for j in range(m):
+        if not U[:, j].any():
+            U[rng.integers(n), j] = 0.5
+    w = rng.uniform(0.5, 1.5, n)
+    return U, w, rng
+
+
+def _steps(rp, col, m, omega):
+    deg = np.bincount(col, minlength=m)
+    eta = 0.9 / np.sqrt(deg.max())
+    return eta / omega, eta * omega
+
+
+def test_unrolled_grad_matches_finite_differences_of_the_unrolled_map():
+    # reverse mode must equal the derivative of p_K(u, w) with the start
+    # point held fixed, for any K (here a start away from equilibrium)
+    U, w, rng = _market(21, 7, 5, 0.6)
+    rp, col, u = dense_to_csr(U)
+    n, m = U.shape
+    x0 = rng.uniform(0.05, 0.3, len(u))
+    p0 = rng.uniform(0.5, 1.5, m)
+    tau, sigma = _steps(rp, col, m, 0.7)
+    g = rng.normal(size=m)
+    K = 6
+    st, du, dw, pK = oracle.unrolled_grad(n, m, rp, col, u, w, x0, p0, tau, sigma, K, g)
+    assert st == oracle.OK
+
+    def loss(uu, ww):
+        _, _, _, p = oracle.unrolled_grad(n, m, rp, col, uu, ww, x0, p0, tau, sigma, K,
+                                          np.zeros(m))
+        return g @ p
+
+    h = 1e-6
+    for q in range(len(u)):
+        e = np.zeros(len(u))
+        e[q] = h
+        fd = (loss(u + e, w) - loss(u - e, w)) / (2 * h)
+        assert abs(fd - du[q]) <= 1e-6 * (1 + abs(fd)), (q, fd, du[q])
+    for i in range(n):
+        e = np.zeros(n)
+        e[i] = h
+        fd = (loss(u, w + e) - loss(u, w - e)) / (2 * h)
+        assert abs(fd - dw[i]) <= 1e-6 * (1 + abs(fd)), (i, fd, dw[i])
+
+
+def test_unrolled_grad_tends_to_implicit_grad():
+    U, w, rng = _market(3, 30, 10, 0.5)
+    rp, col, u = dense_to_csr(U)
+    n, m = U.shape
+    s = oracle.solve(n, m, rp, col, u, w, tol=1e-13, max_iter=2000000)
+    assert s.status == oracle.OK
+    g = rng.normal(size=m)
+    st, du_i, dw_i, _ = oracle.implicit_grad(n, m, rp, col, u, w, s.x, s.p, g)
+    assert st == oracle.OK
+    tau, sigma = _steps(rp, col, m, s.omega)
+    errs = []
+    for K in (50, 2000):
+        st, du, dw, pK = oracle.unrolled_grad(n, m, rp, col, u, w, s.x, s.p, tau, sigma, K, g)
+        assert st == oracle.OK
+        np.testing.assert_allclose(pK, s.p, rtol=1e-9)  # the start is a fixed point
+        errs.append(max(np.max(np.abs(du - du_i)) / np.max(np.abs(du_i)),
+                        np.max(np.abs(dw - dw_i)) / np.max(np.abs(dw_i))))
+    assert errs[1] <= 1e-9 and errs[1] < errs[0]

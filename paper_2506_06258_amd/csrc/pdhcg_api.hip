@@ -46,6 +46,8 @@ struct Bin {
   int G = 0, E = 0;
   std::vector<int32_t> rows;  // empty = identity (all rows)
   int32_t *d_rows = nullptr;
+  int32_t *d_rbeg = nullptr;  // per slot: first entry and end of its row
+  int32_t *d_rend = nullptr;
   int32_t nrows = 0;
   int32_t nwg = 0;
   int32_t wg_offset = 0;
@@ -123,6 +125,8 @@ struct pdhcg_market_s {
   BinDev bindev(const Bin &b) const {
     BinDev d;
     d.rows = b.d_rows;
+    d.rlo = b.d_rows ? b.d_rbeg : row_ptr;
+    d.rhi = b.d_rows ? b.d_rend : row_ptr + 1;
     d.nrows = b.nrows;
     d.wg_offset = b.wg_offset;
     d.rows_per_wg = b.rows_per_wg;
@@ -220,7 +224,11 @@ void pdhcg_market_destroy(pdhcg_market mk) {
   f(mk->XA); f(mk->PA); f(mk->Pk); f(mk->T[0]); f(mk->T[1]);
   f(mk->colpart); f(mk->evalpart); f(mk->rowpart); f(mk->colblk); f(mk->cacc); f(mk->S);
   f(mk->colchunk); f(mk->tile_ticket);
-  for (auto &b : mk->bins) f(b.d_rows);
+  for (auto &b : mk->bins) {
+    f(b.d_rows);
+    f(b.d_rbeg);
+    f(b.d_rend);
+  }
   if (mk->hS) (void)hipHostFree(mk->hS);
   delete mk;
 }
@@ -239,6 +247,9 @@ void choose_shape(int d, int *G, int *E) {
   for (int g : Gs)
     for (int e : Es) {
       const int slots = g * e;
+      // fewest slots; among those the fewest lanes per row (fewer
+      // reduction steps per row; measured faster on 100-entry rows:
+      // G=16,E=8 0.80 ms, 32,4 0.83 ms, 64,2 1.01 ms per pass)
       if (slots >= d && slots < best) {
         best = slots;
         bestG = g;
@@ -319,8 +330,19 @@ int32_t build_bins(pdhcg_market mk, const std::vector<int32_t> &h_row_ptr) {
       b.rows.clear();  // identity
       b.d_rows = nullptr;
     } else {
+      std::vector<int32_t> rbeg(b.rows.size()), rend(b.rows.size());
+      for (size_t q = 0; q < b.rows.size(); ++q) {
+        rbeg[q] = h_row_ptr[(size_t)b.rows[q]];
+        rend[q] = h_row_ptr[(size_t)b.rows[q] + 1];
+      }
       HIPC(dalloc(&b.d_rows, b.rows.size()));
+      HIPC(dalloc(&b.d_rbeg, b.rows.size()));
+      HIPC(dalloc(&b.d_rend, b.rows.size()));
       HIPC(hipMemcpy(b.d_rows, b.rows.data(), b.rows.size() * sizeof(int32_t),
+                     hipMemcpyHostToDevice));
+      HIPC(hipMemcpy(b.d_rbeg, rbeg.data(), rbeg.size() * sizeof(int32_t),
+                     hipMemcpyHostToDevice));
+      HIPC(hipMemcpy(b.d_rend, rend.data(), rend.size() * sizeof(int32_t),
                      hipMemcpyHostToDevice));
     }
   }
@@ -338,6 +360,9 @@ extern "C" int32_t pdhcg_market_create(int32_t n, int32_t m, int64_t nnz, const 
   if (n <= 0 || m <= 0 || nnz <= 0 || nnz > INT32_MAX)
     return fail(PDHCG_ERR_ARG, "sizes must satisfy n, m > 0 and 0 < nnz <= 2^31-1");
   if (!row_ptr || !col || !u || !w) return fail(PDHCG_ERR_ARG, "null pointer");
+  if (nnz > kMaxBufferEntries)
+    return fail(PDHCG_ERR_UNSUPPORTED, "markets with more than 2^29 stored entries are not "
+                                       "supported (32-bit buffer offsets)");
   hipStream_t st = (hipStream_t)stream;
   // validate on the host
   std::vector<int32_t> h_rp((size_t)n + 1), h_col((size_t)nnz);
@@ -388,15 +413,17 @@ extern "C" int32_t pdhcg_market_create(int32_t n, int32_t m, int64_t nnz, const 
       lds_cap = prop.sharedMemPerBlock;
   }
   const size_t static_lds = 1024;  // the kernels' own __shared__ arrays
-  // Row pass: float32 column partials in LDS when they fit.  Prices are
-  // gathered from global memory (they stay L2-resident): an LDS copy costs
-  // occupancy and measured slower on the 1e8-edge market (1.24 vs 1.06 ms
-  // per pass); PDHCG_P_LDS=1 selects it when it fits.
+  // Row pass: float32 column partials and a float64 copy of the prices in
+  // LDS when both fit.  Price gathers from global memory miss the vector L1
+  // on most lanes and hold its miss slots, which starves the stream of row
+  // data (1e8-edge market: 0.90 ms per pass with global gathers, 0.55 ms
+  // for the same pass without the search when the prices are in LDS).
+  // PDHCG_P_LDS=0 keeps the prices in global memory.
   mk->lds_row = 0;
   if ((size_t)m * sizeof(float) + static_lds <= lds_cap) mk->lds_row = 1;
+  if ((size_t)m * (sizeof(double) + sizeof(float)) + static_lds <= lds_cap) mk->lds_row = 3;
   if (const char *e = std::getenv("PDHCG_P_LDS")) {
-    if (std::atoi(e) && (size_t)m * (sizeof(double) + sizeof(float)) + static_lds <= lds_cap)
-      mk->lds_row = 3;
+    if (!std::atoi(e) && mk->lds_row == 3) mk->lds_row = 1;
   }
   mk->lds_eval = ((size_t)3 * m * sizeof(float) + static_lds <= lds_cap) ? 1 : 0;
   if (const char *e = std::getenv("PDHCG_NO_LDS")) {

@@ -19,19 +19,21 @@ __device__ __forceinline__ T pick3(T a, T b, T c, int i) {
 }
 
 // Cross-lane exchange of one 32-bit value within a wave.  Lane masks below
-// 16 use DPP (quad_perm / row mirrors), 16 uses ds_swizzle inside 32-lane
-// halves, 32 uses ds_bpermute.  For a sum or max every pairing works as
-// long as it combines disjoint partial results, which these do.
+// 16 use DPP moves (quad_perm / row mirrors; bound_ctrl with every row and
+// bank enabled, so no lane keeps an old value and no copy is needed), 16
+// uses ds_swizzle inside 32-lane halves, 32 uses ds_bpermute.  For a sum or
+// max every pairing works as long as it combines disjoint partial results,
+// which these do.
 template <int MASK>
 __device__ __forceinline__ int xchg32(int v) {
   if constexpr (MASK == 1) {
-    return __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+    return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true);  // quad_perm [1,0,3,2]
   } else if constexpr (MASK == 2) {
-    return __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+    return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);  // quad_perm [2,3,0,1]
   } else if constexpr (MASK == 4) {
-    return __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+    return __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true);  // row_half_mirror
   } else if constexpr (MASK == 8) {
-    return __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false);  // row_mirror
+    return __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, true);  // row_mirror
   } else if constexpr (MASK == 16) {
     return __builtin_amdgcn_ds_swizzle(v, 0x401F);  // lane ^ 16 within 32 lanes
   } else {
@@ -78,6 +80,20 @@ __device__ __forceinline__ double fast_rcp(double x) {
   return r;
 }
 
+// sqrt(x) in float64 for a normal x > 0 (no range scaling; x = 0 gives
+// NaN): the hardware 1/sqrt estimate y, then one coupled Newton step on
+// (s, h) ~ (x y, y/2) and two residual corrections s += (x - s^2) h.
+__device__ __forceinline__ double fast_sqrt(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  double s = x * y, h = 0.5 * y;
+  const double r = fma(-s, h, 0.5);
+  s = fma(s, r, s);
+  h = fma(h, r, h);
+  s = fma(fma(-s, s, x), h, s);
+  s = fma(fma(-s, s, x), h, s);
+  return s;
+}
+
 __device__ __forceinline__ double wave_sum_d(double v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
@@ -103,12 +119,13 @@ __device__ __forceinline__ bool seg_any(bool pred) {
   }
 }
 
-// Positive root of s^2 - A s - B = 0 (B >= 0), float64, cancellation-free.
+// Positive root of s^2 - A s - B = 0 (B >= 0), float64, cancellation-free
+// and branch-free: (A + d)/2 for A >= 0, 2B/(d - A) for A < 0, with
+// d = sqrt(A^2 + 4B); 0 when A <= 0 and B = 0 (no positive root).
 __device__ __forceinline__ double pos_root_d(double A, double B) {
-  const double disc = sqrt(fma(A, A, 4.0 * B));
-  if (A >= 0.0) return 0.5 * (A + disc);
-  const double den = disc - A;
-  return den > 0.0 ? 2.0 * B * fast_rcp(den) : 0.0;
+  const double q = fabs(A) + fast_sqrt(fma(A, A, 4.0 * B));
+  const double r = (A >= 0.0) ? 0.5 * q : 2.0 * B * fast_rcp(q);
+  return (q > 0.0 && (A > 0.0 || B > 0.0)) ? r : 0.0;
 }
 
 // Precision: the streamed per-edge data (u_hat, col, x, x_avg) is float32;
@@ -122,42 +139,23 @@ __device__ __forceinline__ double pos_root_d(double A, double B) {
 // global memory, where they stay L2-resident).
 
 // One row of the prox step (Sec. 2.2) for the segment of G lanes that owns
-// it.  Lane r holds entries r, r+G, ... of the row: u_j, x^k_j, the good j
-// and a_j = x^k_j - tau p_j (float64).  With b_j = tau w_i u_j,
+// it.  Lane r holds entries r, r+G, ... of the row: u_j, x^k_j and
+// a_j = x^k_j - tau p_j (float64).  ok[e] marks the slots inside the row;
+// slots past the row end must hold u = 0 (x and a are then ignored).
+// With b_j = tau w_i u_j,
 //   a_j + b_j/s = a_j + u_j (tau w_i / s),
 //   g(s) = sum_j u_j [a_j + b_j/s]_+,   phi(s) = s - g(s),
 // so b_j is never stored.  Returns the root s* of phi (or the midpoint of
 // the final bracket if max_rounds ran out); the caller forms
-// x_j = [a_j + u_j tau w_i / s*]_+.  pget(j) returns the price of good j.
-template <int G, int E, int MODE, class PGet>
-__device__ __forceinline__ double prox_row(bool rv, int beg, int d, int r, double tau, double tw,
-                                           const float *__restrict__ uhp,
-                                           const int32_t *__restrict__ colp,
-                                           const float *__restrict__ xin, PGet pget,
-                                           int max_rounds, double rtol, int K, double (&a)[E],
-                                           float (&uh)[E], float (&xk)[E], int (&cj)[E],
-                                           int &rounds) {
+// x_j = [a_j + u_j tau w_i / s*]_+.
+template <int G, int E, int MODE>
+__device__ __forceinline__ double prox_solve(bool rv, double tw, int max_rounds, double rtol,
+                                             int K, const bool (&ok)[E], const double (&a)[E],
+                                             const float (&uh)[E], const float (&xk)[E],
+                                             int &rounds) {
   double s0 = 0.0;
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int idx = r + G * e;
-    const bool v = idx < d;
-    const int k = beg + idx;
-    float u = 0.0f, x = 0.0f;
-    double pj = 0.0;
-    int c = 0;
-    if (v) {
-      u = uhp[k];
-      x = xin[k];
-      c = colp[k];
-      pj = pget(c);
-    }
-    uh[e] = u;
-    xk[e] = x;
-    cj[e] = c;
-    a[e] = fma(-tau, pj, (double)x);  // x^k - tau p
-    s0 = fma((double)u, (double)x, s0);
-  }
+  for (int e = 0; e < E; ++e) s0 = fma((double)uh[e], (double)xk[e], s0);
   s0 = seg_sum_d<G>(s0);
 
   // Trial value: s = u^T x^k (Alg. 3); if zero, the best single-good lower
@@ -191,31 +189,28 @@ __device__ __forceinline__ double prox_row(bool rv, int beg, int d, int r, doubl
       const double inv = fast_rcp(s);
       const double ti = tw * inv;
       double A = 0.0, Q = 0.0;
+      bool on_s[E];
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         const double u = (double)uh[e];
-        const double on = fma(u, ti, a[e]) > 0.0 ? u : 0.0;
-        A = fma(on, a[e], A);
-        Q = fma(on, u, Q);
+        on_s[e] = ok[e] && fma(u, ti, a[e]) > 0.0;
+        const double fu = (on_s[e] ? 1.0 : 0.0) * u;  // u on the active set, else 0
+        A = fma(fu, a[e], A);
+        Q = fma(fu, u, Q);
       }
       A = seg_sum_d<G>(A);
       Q = seg_sum_d<G>(Q);
       const double B = tw * Q;
       const double g = fma(B, inv, A);
       const double sA = pos_root_d(A, B);
-      bool same = false;
-      if (sA > 0.0) {
-        const double tA = tw * fast_rcp(sA);
-        bool diff = false;
+      const double tA = tw * fast_rcp(sA > 0.0 ? sA : 1.0);
+      bool diff = false;
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-          const double u = (double)uh[e];
-          const bool on_s = fma(u, ti, a[e]) > 0.0;
-          const bool on_a = fma(u, tA, a[e]) > 0.0;
-          diff |= (on_s != on_a);
-        }
-        same = !seg_any<G>(diff);
+      for (int e = 0; e < E; ++e) {
+        const bool on_a = ok[e] && fma((double)uh[e], tA, a[e]) > 0.0;
+        diff |= (on_s[e] != on_a);
       }
+      const bool same = sA > 0.0 && !seg_any<G>(diff);
       if (!done) {
         ++rounds;
         U = fmin(U, fmax(s, g));
@@ -279,6 +274,41 @@ __device__ __forceinline__ double prox_row(bool rv, int beg, int d, int r, doubl
     sfin = 0.5 * (L + U);
   }
   return sfin;
+}
+
+// prox_solve on a row read here: lane r of the segment loads entries r,
+// r+G, ... of the row starting at beg (d entries); pget(j) returns the
+// price of good j.  The loaded values stay in uh/xk/cj and a for the caller.
+template <int G, int E, int MODE, class PGet>
+__device__ __forceinline__ double prox_row(bool rv, int beg, int d, int r, double tau, double tw,
+                                           const float *__restrict__ uhp,
+                                           const int32_t *__restrict__ colp,
+                                           const float *__restrict__ xin, PGet pget,
+                                           int max_rounds, double rtol, int K, double (&a)[E],
+                                           float (&uh)[E], float (&xk)[E], int (&cj)[E],
+                                           int &rounds) {
+  bool ok[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int idx = r + G * e;
+    const bool v = idx < d;
+    const int k = beg + idx;
+    float u = 0.0f, x = 0.0f;
+    double pj = 0.0;
+    int c = 0;
+    if (v) {
+      u = uhp[k];
+      x = xin[k];
+      c = colp[k];
+      pj = pget(c);
+    }
+    uh[e] = u;
+    xk[e] = x;
+    cj[e] = c;
+    a[e] = fma(-tau, pj, (double)x);  // x^k - tau p
+    ok[e] = v;
+  }
+  return prox_solve<G, E, MODE>(rv, tw, max_rounds, rtol, K, ok, a, uh, xk, rounds);
 }
 
 }  // namespace pdhcg

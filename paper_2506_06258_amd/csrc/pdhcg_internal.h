@@ -17,6 +17,9 @@ constexpr int kEvalRowStats = 12;
 constexpr int kColStats = 2;
 constexpr int kEvalColStats = 12;
 constexpr int kColChunks = 16;   // partial-row chunks per column tile
+// Per-edge arrays are addressed with 32-bit byte offsets, and offsets from
+// 2^31 up mark idle lanes: markets have at most 2^29 stored entries.
+constexpr int64_t kMaxBufferEntries = int64_t(1) << 29;
 
 // Device-resident solver state.  The step kernels read it at launch and the
 // last block of the column kernel updates it (step-size rule, role swaps);
@@ -70,7 +73,9 @@ struct MarketDev {
 
 // Rows handled by one kernel variant.
 struct BinDev {
-  const int32_t *rows;  // row ids of this bin
+  const int32_t *rows;  // row ids of this bin (null: slot s is row s)
+  const int32_t *rlo;   // per slot: first entry of its row (row_ptr without rows)
+  const int32_t *rhi;   // per slot: one past its last entry (row_ptr + 1 without rows)
   int32_t nrows;
   int32_t wg_offset;    // first partial slot of this bin
   int32_t rows_per_wg;

@@ -30,6 +30,78 @@
 
 namespace pdhcg {
 
+// Bounds of the row in one slot of a bin, as loaded.  Three loads for every
+// bin kind (the row id is a dummy load without an index list), so that the
+// number of memory instructions a wave issues never depends on data: the
+// vector memory counters of CDNA retire in issue order, and a wait for an
+// older load after a branch that may skip newer ones has to wait for all of
+// them.  Slots past the end read the last slot of the range.
+struct RowBounds {
+  int id, lo, hi;
+};
+
+__device__ __forceinline__ RowBounds fetch_bounds(const BinDev &bin, const int32_t *ids,
+                                                  int slot, int slot_last) {
+  const int sl = min(slot, slot_last);
+  RowBounds rb;
+  rb.id = ids[sl];
+  rb.lo = bin.rlo[sl];
+  rb.hi = bin.rhi[sl];
+  return rb;
+}
+
+// Per-edge arrays are addressed through buffer resources with 32-bit byte
+// offsets: one offset register per lane and row, the entry index folded into
+// the instruction's immediate offset.  An access at or beyond the resource's
+// size is dropped (store) or returns zero (load), so idle lanes store to
+// kOutOfRange instead of branching, and a resource of size zero turns every
+// access into a no-op.  Market creation keeps nnz <= kMaxBufferEntries.
+constexpr uint32_t kOutOfRange = 0x80000000u;
+constexpr uint32_t kBufWord3 = 0x00020000u;  // raw 32-bit buffer (gfx9 family)
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes,
+                                           (int)kBufWord3);
+}
+__device__ __forceinline__ float bload_f(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ int bload_i(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return (int)__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void bstore_f(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)off, 0, 0);
+}
+
+// The E entries lane r of a segment holds, as loaded: slots past the row end
+// hold whatever follows the row (or zero past the array); the consumer
+// masks them.
+template <int E>
+struct RowRegs {
+  float u[E], x[E];
+  int c[E];
+};
+
+template <int G, int E>
+__device__ __forceinline__ void row_fetch(uint32_t off, __amdgpu_buffer_rsrc_t ru,
+                                          __amdgpu_buffer_rsrc_t rc,
+                                          __amdgpu_buffer_rsrc_t rx, RowRegs<E> &R) {
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    R.u[e] = bload_f(ru, off + 4u * G * e);
+    R.x[e] = bload_f(rx, off + 4u * G * e);
+    R.c[e] = bload_i(rc, off + 4u * G * e);
+  }
+}
+
+// Software pipeline per wave, two passes deep: while the rows of pass t are
+// searched, the entries of pass t+1 and the bounds of pass t+2 are loading,
+// so each wave keeps a pass of HBM reads in flight through its compute
+// phase.  Loads are issued in the order they are consumed (prices and
+// averaged allocation of pass t, then the prefetch), the two register sets
+// swap roles between the two halves of the loop body (no copies of loaded
+// registers, which would wait for them), and no memory instruction sits
+// behind a data-dependent branch.
 template <int G, int E, int MODE, int LDS_MODE>
 __global__ __launch_bounds__(kRowBlock) void k_row_pass(MarketDev md, BinDev bin,
                                                         RowIO io) {
@@ -68,68 +140,121 @@ __global__ __launch_bounds__(kRowBlock) void k_row_pass(MarketDev md, BinDev bin
   const int seg = lane / G;             // segment inside the wave
   constexpr int kSeg = kWave / G;       // rows per wave pass
   constexpr int kWaves = kRowBlock / kWave;
+  constexpr int kStep = kWaves * kSeg;  // rows per workgroup pass
   const int wg = blockIdx.x;
   const int row_lo = wg * bin.rows_per_wg;
   const int row_hi = min(row_lo + bin.rows_per_wg, bin.nrows);
+  const int last = row_hi - 1;
   const double rtol = io.rtol;
+  const bool fold = wfold != 0.0f;
+  const bool fold_read = fold && wfold != 1.0f;  // weight 1 replaces the average
+  const int32_t *ids = bin.rows ? bin.rows : bin.rlo;
+  const uint32_t ebytes = (uint32_t)md.nnz * 4u;
+  const __amdgpu_buffer_rsrc_t ru = make_rsrc(md.uh, ebytes);
+  const __amdgpu_buffer_rsrc_t rc = make_rsrc(md.col, ebytes);
+  const __amdgpu_buffer_rsrc_t rx = make_rsrc(xin, ebytes);
+  const __amdgpu_buffer_rsrc_t ro = make_rsrc(xout, ebytes);
+  // the average is read only when folded with a weight below one, and
+  // written only when folded
+  const __amdgpu_buffer_rsrc_t ry = make_rsrc(xavg, fold_read ? ebytes : 0u);
+  const __amdgpu_buffer_rsrc_t ryw = make_rsrc(xavg, fold ? ebytes : 0u);
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(io.s_out, io.s_out ? (uint32_t)md.n * 4u : 0u);
 
   float dx2 = 0.0f;
   uint32_t rmax = 0;
   uint32_t rsum = 0, rcount = 0;
 
-  for (int base = row_lo + wave * kSeg; base < row_hi; base += kWaves * kSeg) {
+  int base = row_lo + wave * kSeg;
+  auto row_id = [&](const RowBounds &rb, int slot) { return bin.rows ? rb.id : min(slot, last); };
+  auto row_len = [&](const RowBounds &rb, int slot) { return slot < row_hi ? rb.hi - rb.lo : 0; };
+  auto lane_off = [&](const RowBounds &rb) { return 4u * (uint32_t)(rb.lo + r); };
+
+  // prologue: bounds of passes 0 and 1, entries and budget of pass 0, all
+  // complete before the loop: the loop header is then entered with nothing
+  // in flight from the prologue, and its wait counts are those of the back
+  // edge alone.
+  RowBounds bA = fetch_bounds(bin, ids, base + seg, last);
+  RowBounds bB = fetch_bounds(bin, ids, base + kStep + seg, last);
+  RowRegs<E> RA, RB;
+  int dA = row_len(bA, base + seg), dB = 0;
+  row_fetch<G, E>(lane_off(bA), ru, rc, rx, RA);
+  float wA = md.w[row_id(bA, base + seg)], wB = 0.0f;
+  __builtin_amdgcn_s_waitcnt(0);
+
+  // Head of a pass: gather the prices of its goods into a and load the
+  // averaged allocation into y.
+  double a[E];
+  float y[E];
+  auto head = [&](const RowRegs<E> &Rc, const RowBounds &bc) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) a[e] = (LDS_MODE & 2) ? lp[Rc.c[e]] : pp[Rc.c[e]];
+    const uint32_t off = lane_off(bc);
+#pragma unroll
+    for (int e = 0; e < E; ++e) y[e] = bload_f(ry, off + 4u * G * e);
+  };
+  // Body of a pass: entries Rc (dc entries, budget wc, bounds bc) and its
+  // prices are in flight or resident; bn holds the bounds of the next pass.
+  // Loads the next pass into Rn, dn, wn and the bounds of the pass after
+  // into bc, then solves and stores this pass.
+  auto body = [&](const RowRegs<E> &Rc, RowBounds &bc, int dc, float wc, RowRegs<E> &Rn,
+                  const RowBounds &bn, int &dn, float &wn) {
     const int slot = base + seg;
     const bool rv = slot < row_hi;
-    const int i = rv ? (bin.rows ? bin.rows[slot] : slot) : 0;
-    const int beg = rv ? md.row_ptr[i] : 0;
-    const int d = rv ? md.row_ptr[i + 1] - beg : 0;
-    const double tw = rv ? tau * (double)md.w[i] : 0.0;
+    const uint32_t off = lane_off(bc);
+    const int rid = row_id(bc, slot);
+    const int d = dc;
+    dn = row_len(bn, slot + kStep);
+    row_fetch<G, E>(lane_off(bn), ru, rc, rx, Rn);
+    wn = md.w[row_id(bn, slot + kStep)];
+    bc = fetch_bounds(bin, ids, slot + 2 * kStep, last);
 
-    double a[E];
-    float uh[E], xk[E];
-    int cj[E];
-    int rounds = 0;
-    const double sfin = prox_row<G, E, MODE>(
-        rv, beg, d, r, tau, tw, md.uh, md.col, xin,
-        [&](int c) { return (LDS_MODE & 2) ? lp[c] : pp[c]; }, io.max_rounds, rtol, io.sections,
-        a, uh, xk, cj, rounds);
-    // Lagged fold of the kept iterate into the running average (Alg. 2).
-    if (wfold != 0.0f) {
+    const double tw = rv ? tau * (double)wc : 0.0;
+    bool ok[E];
+    float uh[E];
 #pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const int idx = r + G * e;
-        if (idx < d) {
-          const int k = beg + idx;
-          const float xb = xavg[k];
-          xavg[k] = (wfold == 1.0f) ? xk[e] : fmaf(xk[e] - xb, wfold, xb);
-        }
-      }
+    for (int e = 0; e < E; ++e) {
+      ok[e] = r + G * e < d;
+      uh[e] = ok[e] ? Rc.u[e] : 0.0f;
+      a[e] = fma(-tau, a[e], (double)Rc.x[e]);  // x^k - tau p
     }
-    // x^{k+1} = [a + b/s]_+ (eq. bisection), |x^{k+1} - x^k|^2, column sums.
+    int rounds = 0;
+    const double sfin = prox_solve<G, E, MODE>(rv, tw, io.max_rounds, rtol, io.sections, ok, a,
+                                               uh, Rc.x, rounds);
+    // x^{k+1} = [a + b/s]_+ (eq. bisection), |x^{k+1} - x^k|^2, column sums,
+    // and the lagged fold of the kept iterate into the running average
+    // (Alg. 2).
     const double tf = tw * fast_rcp(sfin);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int idx = r + G * e;
-      if (idx < d) {
-        const int k = beg + idx;
-        const float xn = (float)fmax(fma((double)uh[e], tf, a[e]), 0.0);
-        xout[k] = xn;
-        const float df = xn - xk[e];
-        dx2 = fmaf(df, df, dx2);
-        if (io.colsum) {
-          if (LDS_MODE & 1)
-            atomicAdd(&lc[cj[e]], xn);
-          else
-            atomicAdd(&cglob[cj[e]], (double)xn);
-        }
+      const uint32_t o = (ok[e] ? off : kOutOfRange) + 4u * G * e;
+      const float xk = Rc.x[e];
+      const float xn = (float)fmax(fma((double)uh[e], tf, a[e]), 0.0);
+      bstore_f(ro, o, xn);
+      bstore_f(ryw, o, fold_read ? fmaf(xk - y[e], wfold, y[e]) : xk);
+      const float df = ok[e] ? xn - xk : 0.0f;
+      dx2 = fmaf(df, df, dx2);
+      if (io.colsum) {
+        if (LDS_MODE & 1)
+          atomicAdd(&lc[Rc.c[e]], ok[e] ? xn : 0.0f);
+        else
+          atomicAdd(&cglob[Rc.c[e]], ok[e] ? (double)xn : 0.0);
       }
     }
+    bstore_f(rs, (rv && r == 0) ? 4u * (uint32_t)rid : kOutOfRange, (float)sfin);
     if (rv && r == 0) {
-      if (io.s_out) io.s_out[i] = (float)sfin;
       rmax = max(rmax, (uint32_t)rounds);
       rsum += (uint32_t)rounds;
       rcount += 1;
     }
+    base += kStep;
+  };
+
+  while (base < row_hi) {
+    head(RA, bA);
+    body(RA, bA, dA, wA, RB, bB, dB, wB);
+    if (base >= row_hi) break;
+    head(RB, bB);
+    body(RB, bB, dB, wB, RA, bA, dA, wA);
   }
 
   // Workgroup partials.

@@ -1,0 +1,179 @@
+"""Workloads for rocprofv3 runs and the summaries kept with the sources.
+
+  python -m paper_2506_06258_amd.profile_run copy  [--mib 1024] [--reps 4]
+  python -m paper_2506_06258_amd.profile_run solve [--iters 64]
+  python -m paper_2506_06258_amd.profile_run summarize --stats DIR
+  python -m paper_2506_06258_amd.profile_run counters --copy-fetch DIR --copy-write DIR \
+        --fetch DIR --write DIR [--mib 1024] [--out FILE]
+
+``copy`` runs torch's device-to-device copy of a float32 tensor of a known
+size: the calibration kernel for the HBM byte counters.  ``solve`` runs a
+fixed number of PDHCG iterations (fixed step, no restarts, so every
+iteration launches the same kernels) on the 1e8-edge market (n = 1e6
+buyers, m = 1e4 goods, 100 goods per buyer).  ``summarize`` prints the
+per-kernel table of a ``--kernel-trace --stats`` run; ``counters`` turns
+FETCH_SIZE / WRITE_SIZE runs (KiB per dispatch) into HBM bytes per row-pass
+launch, scaled by what the same counters read for the copy of known size.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+import statistics
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+KERNEL_SRC = os.path.join(HERE, "csrc", "pdhcg_kernels.hip")
+ROW_KERNEL = "k_row_pass"
+
+
+def kernel_source_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def run_copy(mib: int, reps: int) -> None:
+    import torch
+
+    n = mib * (1 << 20) // 4
+    src = torch.rand(n, device="cuda:0", dtype=torch.float32)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(f"copied {reps} x {mib} MiB", flush=True)
+
+
+def run_solve(iters: int) -> None:
+    import torch
+
+    sys.path.insert(0, ROOT)
+    from paper_2506_06258_amd import pdhcg, synth
+
+    mk = synth.fisher_1e8(1)
+    M = pdhcg.Market.from_synth(mk, device=torch.device("cuda:0"))
+    prm = pdhcg.pdhcg_default_params(tol=0.0, max_iter=iters, step_mode=pdhcg.PDHCG_STEP_FIXED,
+                                     restart=pdhcg.PDHCG_RESTART_NONE, eval_every=iters)
+    s = M.solve(prm)
+    torch.cuda.synchronize()
+    print(f"solve: {s.info.iters} iterations, rel. KKT {s.info.rel_kkt:.3e}", flush=True)
+    M.close()
+
+
+def _rows(path_glob: str):
+    files = sorted(glob.glob(path_glob, recursive=True))
+    if not files:
+        raise SystemExit(f"no file matches {path_glob}")
+    with open(files[0], newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def _key(row: dict, *names: str) -> str:
+    for n in names:
+        for k in row:
+            if k.lower() == n.lower():
+                return k
+    raise KeyError(names)
+
+
+def short_name(name: str) -> str:
+    base = name.split("(")[0]
+    for tok in ("pdhcg::", "void "):
+        base = base.replace(tok, "")
+    return base.strip()
+
+
+def summarize(stats_dir: str) -> str:
+    rows = _rows(os.path.join(stats_dir, "**", "*kernel_stats.csv"))
+    kn = _key(rows[0], "Name", "Kernel_Name")
+    lines = ["| kernel | calls | total ms | avg us | min us | max us | % |",
+             "|---|---|---|---|---|---|---|"]
+    for r in rows:
+        lines.append("| {} | {} | {:.3f} | {:.2f} | {:.2f} | {:.2f} | {:.2f} |".format(
+            short_name(r[kn]), r[_key(r, "Calls")], float(r[_key(r, "TotalDurationNs")]) / 1e6,
+            float(r[_key(r, "AverageNs")]) / 1e3, float(r[_key(r, "MinNs")]) / 1e3,
+            float(r[_key(r, "MaxNs")]) / 1e3, float(r[_key(r, "Percentage")])))
+    return "\n".join(lines)
+
+
+def counter_per_dispatch(run_dir: str, counter: str, kernel: str) -> list[float]:
+    rows = _rows(os.path.join(run_dir, "**", "*counter_collection.csv"))
+    kn = _key(rows[0], "Kernel_Name")
+    cn = _key(rows[0], "Counter_Name")
+    cv = _key(rows[0], "Counter_Value")
+    di = _key(rows[0], "Dispatch_Id", "Dispatch_ID")
+    per = {}
+    for r in rows:
+        if kernel in r[kn] and r[cn] == counter:
+            per[r[di]] = per.get(r[di], 0.0) + float(r[cv])
+    if not per:
+        raise SystemExit(f"no {counter} rows for a kernel named like {kernel} in {run_dir}")
+    return list(per.values())
+
+
+def counters(args) -> dict:
+    copy_bytes = args.mib * (1 << 20)
+    cf = statistics.median(counter_per_dispatch(args.copy_fetch, "FETCH_SIZE", args.copy_kernel))
+    cw = statistics.median(counter_per_dispatch(args.copy_write, "WRITE_SIZE", args.copy_kernel))
+    rf = counter_per_dispatch(args.fetch, "FETCH_SIZE", ROW_KERNEL)
+    rw = counter_per_dispatch(args.write, "WRITE_SIZE", ROW_KERNEL)
+    f_scale = copy_bytes / (cf * 1024.0)  # bytes per counted KiB
+    w_scale = copy_bytes / (cw * 1024.0)
+    fetch = statistics.median(rf) * 1024.0 * f_scale
+    write = statistics.median(rw) * 1024.0 * w_scale
+    return {
+        "kernel": ROW_KERNEL,
+        "workload": "1e8-edge Fisher market (n=1e6, m=1e4, 100 goods per buyer), fixed step",
+        "kernel_source_sha256_16": kernel_source_hash(),
+        "copy_calibration": {"bytes": copy_bytes, "fetch_kib": cf, "write_kib": cw,
+                             "fetch_scale": f_scale, "write_scale": w_scale},
+        "row_pass_dispatches": len(rf),
+        "fetch_kib_median": statistics.median(rf),
+        "write_kib_median": statistics.median(rw),
+        "fetch_bytes_per_launch": fetch,
+        "write_bytes_per_launch": write,
+        "bytes_per_launch": fetch + write,
+    }
+
+
+def main() -> None:
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    c = sub.add_parser("copy")
+    c.add_argument("--mib", type=int, default=1024)
+    c.add_argument("--reps", type=int, default=4)
+    s = sub.add_parser("solve")
+    s.add_argument("--iters", type=int, default=64)
+    m = sub.add_parser("summarize")
+    m.add_argument("--stats", required=True)
+    k = sub.add_parser("counters")
+    k.add_argument("--copy-fetch", required=True)
+    k.add_argument("--copy-write", required=True)
+    k.add_argument("--fetch", required=True)
+    k.add_argument("--write", required=True)
+    k.add_argument("--mib", type=int, default=1024)
+    k.add_argument("--copy-kernel", default="copy")
+    k.add_argument("--out", default=None)
+    a = ap.parse_args()
+    if a.cmd == "copy":
+        run_copy(a.mib, a.reps)
+    elif a.cmd == "solve":
+        run_solve(a.iters)
+    elif a.cmd == "summarize":
+        print(summarize(a.stats))
+    else:
+        res = counters(a)
+        text = json.dumps(res, indent=1)
+        if a.out:
+            with open(a.out, "w") as f:
+                f.write(text + "\n")
+        print(text)
+
+
+if __name__ == "__main__":
+    main()

@@ -80,7 +80,8 @@ struct pdhcg_market_s {
   double *PA = nullptr;
   double *Pk = nullptr;  // float64 copy of caller prices (kkt, row_prox)
   float *T[2] = {nullptr, nullptr};
-  float *colpart = nullptr, *evalpart = nullptr;
+  double *colpart = nullptr;
+  float *evalpart = nullptr;
   double *rowpart = nullptr, *colblk = nullptr, *cacc = nullptr, *colchunk = nullptr;
   uint32_t *tile_ticket = nullptr;
   DevState *S = nullptr;   // device
@@ -413,15 +414,17 @@ extern "C" int32_t pdhcg_market_create(int32_t n, int32_t m, int64_t nnz, const 
       lds_cap = prop.sharedMemPerBlock;
   }
   const size_t static_lds = 1024;  // the kernels' own __shared__ arrays
-  // Row pass: float32 column partials and a float64 copy of the prices in
-  // LDS when both fit.  Price gathers from global memory miss the vector L1
-  // on most lanes and hold its miss slots, which starves the stream of row
-  // data (1e8-edge market: 0.90 ms per pass with global gathers, 0.55 ms
-  // for the same pass without the search when the prices are in LDS).
-  // PDHCG_P_LDS=0 keeps the prices in global memory.
+  // Row pass: float64 column partials and a float64 copy of the prices in
+  // LDS when both fit.  Float64 LDS atomics: float32 LDS atomic adds measured
+  // about 8x slower than float64 ones on gfx950 (198 vs 25 cycles per wave
+  // instruction per CU, random slots of a 1e4-entry array), and they were
+  // the limit of the pass.  Price gathers from global memory miss the vector
+  // L1 on most lanes and hold its miss slots, which starves the stream of
+  // row data (1e8-edge market: 0.90 ms per pass with global gathers, 0.80
+  // ms with prices in LDS).  PDHCG_P_LDS=0 keeps the prices in global memory.
   mk->lds_row = 0;
-  if ((size_t)m * sizeof(float) + static_lds <= lds_cap) mk->lds_row = 1;
-  if ((size_t)m * (sizeof(double) + sizeof(float)) + static_lds <= lds_cap) mk->lds_row = 3;
+  if ((size_t)m * sizeof(double) + static_lds <= lds_cap) mk->lds_row = 1;
+  if ((size_t)m * 2 * sizeof(double) + static_lds <= lds_cap) mk->lds_row = 3;
   if (const char *e = std::getenv("PDHCG_P_LDS")) {
     if (!std::atoi(e) && mk->lds_row == 3) mk->lds_row = 1;
   }

@@ -63,7 +63,7 @@ struct MarketDev {
   double *C0, *C1, *C2;
   float *XA;         // restart anchor x^{n,0}
   double *PA;        // restart anchor p^{n,0}
-  float *colpart;    // [total_wg][m] per-workgroup column partials
+  double *colpart;   // [total_wg][m] per-workgroup column partials
   double *rowpart;   // [total_wg][kRowStats]
   double *colblk;    // [col blocks][kColStats or kEvalColStats]
   double *colchunk;  // [kColChunks][m] chunk sums of the column partials

@@ -125,11 +125,11 @@ __global__ __launch_bounds__(kRowBlock) void k_row_pass(MarketDev md, BinDev bin
     wfold = S->fold ? (float)(1.0 / (double)S->k_in) : 0.0f;
   }
   double *lp = lds_d;  // [m] prices (LDS_MODE & 2)
-  float *lc = reinterpret_cast<float *>((LDS_MODE & 2) ? lds_d + m : lds_d);  // [m] partials
+  double *lc = (LDS_MODE & 2) ? lds_d + m : lds_d;  // [m] column partials
   if (LDS_MODE != 0) {
     for (int j = threadIdx.x; j < m; j += blockDim.x) {
       if (LDS_MODE & 2) lp[j] = pp[j];
-      if (LDS_MODE & 1) lc[j] = 0.0f;
+      if (LDS_MODE & 1) lc[j] = 0.0;
     }
     __syncthreads();
   }
@@ -234,10 +234,7 @@ __global__ __launch_bounds__(kRowBlock) void k_row_pass(MarketDev md, BinDev bin
       const float df = ok[e] ? xn - xk : 0.0f;
       dx2 = fmaf(df, df, dx2);
       if (io.colsum) {
-        if (LDS_MODE & 1)
-          atomicAdd(&lc[Rc.c[e]], ok[e] ? xn : 0.0f);
-        else
-          atomicAdd(&cglob[Rc.c[e]], ok[e] ? (double)xn : 0.0);
+        atomicAdd((LDS_MODE & 1) ? &lc[Rc.c[e]] : &cglob[Rc.c[e]], ok[e] ? (double)xn : 0.0);
       }
     }
     bstore_f(rs, (rv && r == 0) ? 4u * (uint32_t)rid : kOutOfRange, (float)sfin);
@@ -288,7 +285,7 @@ __global__ __launch_bounds__(kRowBlock) void k_row_pass(MarketDev md, BinDev bin
     }
   }
   if ((LDS_MODE & 1) && io.colsum) {
-    float *dst = md.colpart + (size_t)slot * m;
+    double *dst = md.colpart + (size_t)slot * m;
     for (int j = threadIdx.x; j < m; j += blockDim.x) dst[j] = lc[j];
   }
 }
@@ -339,16 +336,16 @@ __global__ __launch_bounds__(kColBlock) void k_col_decide(MarketDev md, int tota
     const int b0 = q * per, b1 = min(total_wg, b0 + per);
     if (j < m) {
       double c = 0.0;
-      const float *src = md.colpart + j;
+      const double *src = md.colpart + j;
       int b = b0;
       for (; b + 4 <= b1; b += 4) {
-        const float v0 = src[(size_t)(b + 0) * m];
-        const float v1 = src[(size_t)(b + 1) * m];
-        const float v2 = src[(size_t)(b + 2) * m];
-        const float v3 = src[(size_t)(b + 3) * m];
-        c += ((double)v0 + (double)v1) + ((double)v2 + (double)v3);
+        const double v0 = src[(size_t)(b + 0) * m];
+        const double v1 = src[(size_t)(b + 1) * m];
+        const double v2 = src[(size_t)(b + 2) * m];
+        const double v3 = src[(size_t)(b + 3) * m];
+        c += (v0 + v1) + (v2 + v3);
       }
-      for (; b < b1; ++b) c += (double)src[(size_t)b * m];
+      for (; b < b1; ++b) c += src[(size_t)b * m];
       md.colchunk[(size_t)q * m + j] = c;
     }
     __syncthreads();
@@ -841,7 +838,7 @@ template <int G, int E, int MODE, int LDSM>
 static hipError_t row_launch_t(const MarketDev &md, const BinDev &bin, const RowIO &io, int nwg,
                                hipStream_t st) {
   const size_t shm = (size_t)md.m * (((LDSM & 2) ? sizeof(double) : 0) +
-                                      ((LDSM & 1) ? sizeof(float) : 0));
+                                      ((LDSM & 1) ? sizeof(double) : 0));
   hipLaunchKernelGGL((k_row_pass<G, E, MODE, LDSM>), dim3(nwg), dim3(kRowBlock), shm, st, md,
                      bin, io);
   return hipGetLastError();

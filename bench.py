@@ -23,7 +23,8 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "row_pass_fisher1e8_counters.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2506_06258_amd", "csrc", "pdhcg_kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2506_06258_amd", "csrc", f)
+               for f in ("pdhcg_kernels.hip", "pdhcg_device.h", "pdhcg_internal.h")]
 
 
 def log(msg):
@@ -31,7 +32,11 @@ def log(msg):
 
 
 def kernel_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    """Hash of the sources the row kernel is compiled from."""
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def traffic_from_profile(n_launch_bytes_key="row_pass"):

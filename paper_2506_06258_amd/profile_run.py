@@ -28,12 +28,17 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-KERNEL_SRC = os.path.join(HERE, "csrc", "pdhcg_kernels.hip")
+# sources the row kernel is compiled from
+KERNEL_SRCS = [os.path.join(HERE, "csrc", f)
+               for f in ("pdhcg_kernels.hip", "pdhcg_device.h", "pdhcg_internal.h")]
 ROW_KERNEL = "k_row_pass"
 
 
 def kernel_source_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def run_copy(mib: int, reps: int) -> None:

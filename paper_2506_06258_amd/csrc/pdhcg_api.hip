@@ -82,6 +82,8 @@ struct pdhcg_market_s {
   float *T[2] = {nullptr, nullptr};
   double *colpart = nullptr;
   float *evalpart = nullptr;
+  double *evalcs = nullptr;
+  uint32_t *evalchunk = nullptr;
   double *rowpart = nullptr, *colblk = nullptr, *cacc = nullptr, *colchunk = nullptr;
   uint32_t *tile_ticket = nullptr;
   DevState *S = nullptr;   // device
@@ -223,7 +225,8 @@ void pdhcg_market_destroy(pdhcg_market mk) {
   f(mk->row_ptr); f(mk->col); f(mk->deg); f(mk->uh); f(mk->rowmax); f(mk->w);
   for (int q = 0; q < 3; ++q) { f(mk->X[q]); f(mk->P[q]); f(mk->C[q]); }
   f(mk->XA); f(mk->PA); f(mk->Pk); f(mk->T[0]); f(mk->T[1]);
-  f(mk->colpart); f(mk->evalpart); f(mk->rowpart); f(mk->colblk); f(mk->cacc); f(mk->S);
+  f(mk->colpart); f(mk->evalpart); f(mk->evalcs); f(mk->evalchunk);
+  f(mk->rowpart); f(mk->colblk); f(mk->cacc); f(mk->S);
   f(mk->colchunk); f(mk->tile_ticket);
   for (auto &b : mk->bins) {
     f(b.d_rows);
@@ -274,7 +277,7 @@ void choose_shape(int d, int *G, int *E) {
   *E = bestE;
 }
 
-int32_t build_bins(pdhcg_market mk, const std::vector<int32_t> &h_row_ptr) {
+int32_t build_bins(pdhcg_market mk, const std::vector<int32_t> &h_row_ptr, int wg_per_cu) {
   // group rows by kernel shape
   std::vector<std::pair<int, int>> shapes;
   std::vector<int> shape_of((size_t)mk->n);
@@ -307,12 +310,13 @@ int32_t build_bins(pdhcg_market mk, const std::vector<int32_t> &h_row_ptr) {
     b.rows.push_back(i);
     b.nnz += h_row_ptr[(size_t)i + 1] - h_row_ptr[(size_t)i];
   }
-  // workgroup budget: about two resident workgroups per CU
+  // workgroup budget: the resident workgroups per CU (at most two), so that
+  // the row pass runs in one round and writes as few partial rows as it can
   int cus = 256;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, mk->device) == hipSuccess && prop.multiProcessorCount > 0)
     cus = prop.multiProcessorCount;
-  const int budget = 2 * cus;
+  const int budget = std::max(1, std::min(2, wg_per_cu)) * cus;
   int off = 0;
   const int kWaves = kRowBlock / kWave;
   for (auto &b : mk->bins) {
@@ -405,13 +409,13 @@ extern "C" int32_t pdhcg_market_create(int32_t n, int32_t m, int64_t nnz, const 
     }                                                                                 \
   } while (0)
 
-  rc = build_bins(mk, h_rp);
-  if (rc != PDHCG_OK) return cleanup(rc);
-  size_t lds_cap = 64 * 1024;
+  size_t lds_cap = 64 * 1024, lds_cu = 64 * 1024;
   {
     hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, mk->device) == hipSuccess && prop.sharedMemPerBlock > 0)
+    if (hipGetDeviceProperties(&prop, mk->device) == hipSuccess && prop.sharedMemPerBlock > 0) {
       lds_cap = prop.sharedMemPerBlock;
+      lds_cu = std::max(lds_cap, (size_t)prop.maxSharedMemoryPerMultiProcessor);
+    }
   }
   const size_t static_lds = 1024;  // the kernels' own __shared__ arrays
   // Row pass: float64 column partials and a float64 copy of the prices in
@@ -428,7 +432,8 @@ extern "C" int32_t pdhcg_market_create(int32_t n, int32_t m, int64_t nnz, const 
   if (const char *e = std::getenv("PDHCG_P_LDS")) {
     if (!std::atoi(e) && mk->lds_row == 3) mk->lds_row = 1;
   }
-  mk->lds_eval = ((size_t)3 * m * sizeof(float) + static_lds <= lds_cap) ? 1 : 0;
+  mk->lds_eval =
+      ((size_t)m * (sizeof(double) + 2 * sizeof(uint32_t)) + static_lds <= lds_cap) ? 1 : 0;
   if (const char *e = std::getenv("PDHCG_NO_LDS")) {
     if (std::atoi(e)) {
       mk->lds_row = 0;
@@ -436,6 +441,12 @@ extern "C" int32_t pdhcg_market_create(int32_t n, int32_t m, int64_t nnz, const 
     }
   }
   mk->col_blocks = (m + kColBlock - 1) / kColBlock;
+  {
+    const size_t row_lds = (size_t)m * (((mk->lds_row & 2) ? sizeof(double) : 0) +
+                                        ((mk->lds_row & 1) ? sizeof(double) : 0)) + static_lds;
+    rc = build_bins(mk, h_rp, (int)(lds_cu / row_lds));
+    if (rc != PDHCG_OK) return cleanup(rc);
+  }
 
   MK_HIPC(dalloc(&mk->row_ptr, (size_t)n + 1));
   MK_HIPC(dalloc(&mk->col, (size_t)nnz));
@@ -454,8 +465,10 @@ extern "C" int32_t pdhcg_market_create(int32_t n, int32_t m, int64_t nnz, const 
   MK_HIPC(dalloc(&mk->T[0], (size_t)n));
   MK_HIPC(dalloc(&mk->T[1], (size_t)n));
   MK_HIPC(dalloc(&mk->colpart, (mk->lds_row & 1) ? (size_t)mk->total_wg * m : 1));
-  MK_HIPC(dalloc(&mk->evalpart, mk->lds_eval ? (size_t)3 * mk->total_wg * m : (size_t)2 * m));
-  MK_HIPC(dalloc(&mk->cacc, (size_t)m));
+  MK_HIPC(dalloc(&mk->evalpart, mk->lds_eval ? (size_t)2 * mk->total_wg * m : (size_t)2 * m));
+  MK_HIPC(dalloc(&mk->evalcs, mk->lds_eval ? (size_t)mk->total_wg * m : (size_t)1));
+  MK_HIPC(dalloc(&mk->evalchunk, mk->lds_eval ? (size_t)2 * kColChunks * m : (size_t)1));
+  MK_HIPC(dalloc(&mk->cacc, (size_t)kColChunks * m));  // chunk sums in LDS mode
   MK_HIPC(dalloc(&mk->rowpart, (size_t)mk->total_wg * std::max(kRowStats, kEvalRowStats)));
   MK_HIPC(dalloc(&mk->colblk, (size_t)mk->col_blocks * std::max(kColStats, kEvalColStats)));
   MK_HIPC(dalloc(&mk->colchunk, (size_t)kColChunks * m));
@@ -568,9 +581,12 @@ int32_t enqueue_eval(pdhcg_market mk, EvalIO io) {
     HIPC(hipMemsetAsync(mk->evalpart, 0, (size_t)2 * mk->m * sizeof(float), mk->stream));
     HIPC(hipMemsetAsync(mk->cacc, 0, (size_t)mk->m * sizeof(double), mk->stream));
   }
+  io.evalcs = mk->evalcs;
+  io.evalchunk = mk->evalchunk;
   for (const Bin &b : mk->bins)
     HIPC(launch_eval_row(md, mk->bindev(b), b.G, b.E, mk->lds_eval, io, b.nwg, mk->total_wg,
                          mk->stream));
+  if (mk->lds_eval) HIPC(launch_eval_chunks(md, io, mk->total_wg, mk->stream));
   HIPC(launch_eval_col(md, io, mk->total_wg, mk->lds_eval, mk->stream));
   return PDHCG_OK;
 }

@@ -110,8 +110,11 @@ struct EvalIO {
   float *tc;         // per-row utility of the current point (nullable)
   float *ta;         // per-row utility of the averaged point (nullable)
   const float *rowscale; // multiply t by this (original units)
-  float *evalpart;   // partials: [3][total_wg][m] (LDS mode) or [2][m]
-  double *cacc;      // [m] float64 column-sum accumulator (non-LDS mode)
+  float *evalpart;   // column maxima (float bits): [2][total_wg][m] (LDS mode) or [2][m]
+  double *evalcs;    // [total_wg][m] float64 column-sum partials (LDS mode)
+  uint32_t *evalchunk; // [2][kColChunks][m] chunk maxima (LDS mode)
+  double *cacc;      // [m] float64 column sums: accumulator (non-LDS mode), else
+                     // [kColChunks][m] chunk sums
   int32_t want_cc;   // sum the columns of xc (no average; ccur unused)
   const double *ccur;// column sums of xc (float64) when !want_cc
   double *cavg_out;  // receives the float64 column sums this pass computed
@@ -131,6 +134,8 @@ hipError_t launch_eval_row(const MarketDev &md, const BinDev &bin, int G, int E,
                            hipStream_t st);
 hipError_t launch_eval_col(const MarketDev &md, const EvalIO &io, int total_wg,
                            int partials, hipStream_t st);
+hipError_t launch_eval_chunks(const MarketDev &md, const EvalIO &io, int total_wg,
+                              hipStream_t st);
 hipError_t launch_normalize(const int32_t *row_ptr, const float *u, float *uh,
                             float *rowmax, int n, hipStream_t st);
 hipError_t launch_degrees(const int32_t *col, int64_t nnz, int32_t *deg, hipStream_t st);

@@ -338,12 +338,11 @@ __global__ __launch_bounds__(kColBlock) void k_col_decide(MarketDev md, int tota
       double c = 0.0;
       const double *src = md.colpart + j;
       int b = b0;
-      for (; b + 4 <= b1; b += 4) {
-        const double v0 = src[(size_t)(b + 0) * m];
-        const double v1 = src[(size_t)(b + 1) * m];
-        const double v2 = src[(size_t)(b + 2) * m];
-        const double v3 = src[(size_t)(b + 3) * m];
-        c += (v0 + v1) + (v2 + v3);
+      for (; b + 8 <= b1; b += 8) {  // eight loads in flight per thread
+        double v[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) v[t] = src[(size_t)(b + t) * m];
+        c += ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
       }
       for (; b < b1; ++b) c += src[(size_t)b * m];
       md.colchunk[(size_t)q * m + j] = c;
@@ -462,21 +461,27 @@ __global__ __launch_bounds__(kColBlock) void k_col_decide(MarketDev md, int tota
 // Column quantities: M_c, M_a (column maxima of u_ij y_i, as float bits,
 // max-reduced as unsigned because they are non-negative) and the column
 // sums of the averaged point (or of the current point when want_cc).
-// LDS_MODE 1: per-workgroup partials in LDS, written to evalpart
-// [3][total_wg][m].  LDS_MODE 0: device-wide atomics into evalpart [2][m]
-// (maxima) and io.cacc [m] (float64 sums), all zeroed by the caller.
+// LDS_MODE 1: per-workgroup partials in LDS (float64 sums: float32 LDS
+// atomic adds are slow on gfx950), written to evalpart [2][total_wg][m]
+// (maxima) and evalcs [total_wg][m] (sums).  LDS_MODE 0: device-wide atomics
+// into evalpart [2][m] (maxima) and io.cacc [m] (float64 sums), all zeroed by
+// the caller.
 template <int G, int E, int LDS_MODE>
 __global__ __launch_bounds__(kRowBlock) void k_eval_row(MarketDev md, BinDev bin,
                                                         EvalIO io, int total_wg) {
-  extern __shared__ float lds[];
+  extern __shared__ double lds_e[];
   const int m = md.m;
   const bool has_avg = io.xa != nullptr;
   const bool sum_avg = has_avg && !io.want_cc;
-  unsigned int *lMc = reinterpret_cast<unsigned int *>(lds);
-  unsigned int *lMa = reinterpret_cast<unsigned int *>(lds + m);
-  float *lcs = lds + 2 * m;
+  double *lcs = lds_e;
+  unsigned int *lMc = reinterpret_cast<unsigned int *>(lds_e + m);
+  unsigned int *lMa = lMc + m;
   if (LDS_MODE == 1) {
-    for (int j = threadIdx.x; j < 3 * m; j += blockDim.x) lds[j] = 0.0f;
+    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+      lcs[j] = 0.0;
+      lMc[j] = 0u;
+      lMa[j] = 0u;
+    }
     __syncthreads();
   }
   const size_t TW = (LDS_MODE == 1) ? (size_t)total_wg * m : (size_t)m;
@@ -584,9 +589,8 @@ __global__ __launch_bounds__(kRowBlock) void k_eval_row(MarketDev md, BinDev bin
           else atomicMax(&gMa[c], ba);
         }
         if (sum_avg || io.want_cc) {
-          const float add = io.want_cc ? xc[e] : xa[e];
-          if (LDS_MODE == 1) atomicAdd(&lcs[c], add);
-          else atomicAdd(&io.cacc[c], (double)add);
+          const double add = io.want_cc ? xc[e] : xa[e];
+          atomicAdd((LDS_MODE == 1) ? &lcs[c] : &io.cacc[c], add);
         }
       }
     }
@@ -608,7 +612,7 @@ __global__ __launch_bounds__(kRowBlock) void k_eval_row(MarketDev md, BinDev bin
   if (LDS_MODE == 1) {
     unsigned int *dMc = gMc + (size_t)slot * m;
     unsigned int *dMa = gMa + (size_t)slot * m;
-    float *dcs = io.evalpart + 2 * TW + (size_t)slot * m;
+    double *dcs = io.evalcs + (size_t)slot * m;
     for (int j = threadIdx.x; j < m; j += blockDim.x) {
       dMc[j] = lMc[j];
       dMa[j] = lMa[j];
@@ -618,6 +622,35 @@ __global__ __launch_bounds__(kRowBlock) void k_eval_row(MarketDev md, BinDev bin
 }
 
 // ------------------------------------------------------- KKT column pass ---
+
+// Per-workgroup KKT partials reduced in kColChunks chunks of workgroups:
+// block (t, q) covers tile t's columns and workgroups [q per, (q+1) per);
+// maxima into evalchunk [2][kColChunks][m], sums (float64, fixed order) into
+// cacc [kColChunks][m].
+__global__ __launch_bounds__(kColBlock) void k_eval_chunks(MarketDev md, EvalIO io,
+                                                           int total_wg) {
+  const int m = md.m;
+  const int j = blockIdx.x * kColBlock + threadIdx.x;
+  const int q = blockIdx.y;
+  if (j >= m) return;
+  const bool has_avg = io.xa != nullptr;
+  const bool want_sum = (has_avg && !io.want_cc) || io.want_cc;
+  const size_t TW = (size_t)total_wg * m;
+  const int per = (total_wg + kColChunks - 1) / kColChunks;
+  const int b0 = q * per, b1 = min(total_wg, b0 + per);
+  const unsigned int *sMc = reinterpret_cast<const unsigned int *>(io.evalpart) + j;
+  const unsigned int *sMa = reinterpret_cast<const unsigned int *>(io.evalpart + TW) + j;
+  unsigned int bMc = 0u, bMa = 0u;
+  double cs = 0.0;
+  for (int b = b0; b < b1; ++b) {
+    bMc = max(bMc, sMc[(size_t)b * m]);
+    if (has_avg) bMa = max(bMa, sMa[(size_t)b * m]);
+    if (want_sum) cs += io.evalcs[(size_t)b * m + j];
+  }
+  io.evalchunk[(size_t)q * m + j] = bMc;
+  io.evalchunk[(size_t)(kColChunks + q) * m + j] = bMa;
+  io.cacc[(size_t)q * m + j] = cs;
+}
 
 // Column statistics per block (float64):
 //  0 max |c_c - 1|, 1 max |c_c|, 2 max (M_c - p_c)_+, 3 max (p_c - M_c),
@@ -643,11 +676,11 @@ __global__ __launch_bounds__(kColBlock) void k_eval_col(MarketDev md, EvalIO io,
     const unsigned int *sMc = reinterpret_cast<const unsigned int *>(io.evalpart) + j;
     const unsigned int *sMa = reinterpret_cast<const unsigned int *>(io.evalpart + TW) + j;
     if (partials) {
-      const float *scs = io.evalpart + 2 * TW + j;
-      for (int b = 0; b < total_wg; ++b) {
-        bMc = max(bMc, sMc[(size_t)b * m]);
-        if (has_avg) bMa = max(bMa, sMa[(size_t)b * m]);
-        if (sum_avg || io.want_cc) cs += (double)scs[(size_t)b * m];
+      // chunk results of k_eval_chunks, combined in a fixed order
+      for (int q = 0; q < kColChunks; ++q) {
+        bMc = max(bMc, io.evalchunk[(size_t)q * m + j]);
+        if (has_avg) bMa = max(bMa, io.evalchunk[(size_t)(kColChunks + q) * m + j]);
+        if (sum_avg || io.want_cc) cs += io.cacc[(size_t)q * m + j];
       }
     } else {
       bMc = sMc[0];
@@ -868,7 +901,7 @@ hipError_t launch_row_pass(const MarketDev &md, const BinDev &bin, int G, int E,
 template <int G, int E, int LDSM>
 static hipError_t eval_launch_t(const MarketDev &md, const BinDev &bin, const EvalIO &io,
                                 int nwg, int total_wg, hipStream_t st) {
-  const size_t shm = LDSM == 1 ? (size_t)3 * md.m * sizeof(float) : 0;
+  const size_t shm = LDSM == 1 ? (size_t)md.m * (sizeof(double) + 2 * sizeof(uint32_t)) : 0;
   hipLaunchKernelGGL((k_eval_row<G, E, LDSM>), dim3(nwg), dim3(kRowBlock), shm, st, md, bin,
                      io, total_wg);
   return hipGetLastError();
@@ -897,6 +930,13 @@ hipError_t launch_col_decide(const MarketDev &md, int total_wg, int from_partial
   const int chunks = from_partials ? (total_wg < kColChunks ? total_wg : kColChunks) : 1;
   hipLaunchKernelGGL(k_col_decide, dim3(tiles, chunks), dim3(kColBlock), 0, st, md, total_wg,
                      from_partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_chunks(const MarketDev &md, const EvalIO &io, int total_wg,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(k_eval_chunks, dim3((md.m + kColBlock - 1) / kColBlock, kColChunks),
+                     dim3(kColBlock), 0, st, md, io, total_wg);
   return hipGetLastError();
 }
 

@@ -200,6 +200,28 @@ int32_t pdhcg_arrow_debreu(pdhcg_market market, const int32_t *e_row_ptr,
                            float *p, float *x, int32_t *outer_iters,
                            int64_t *inner_iters, pdhcg_info *info);
 
+/* Gradient of a loss L(p) of the prices with respect to the utilities u
+ * and budgets w, by reverse mode through `unroll` fixed-step PDHCG
+ * iterations (the price step of eq. update:py and the row prox of Sec. 2.2,
+ * step eta = 0.9/||K||, tau = eta/omega, sigma = eta*omega) started from
+ * (x, p), normally the solution pdhcg_solve returned; the start point is
+ * held constant, so at an equilibrium the result tends, as unroll grows, to
+ * the derivative of the equilibrium prices (implicit function theorem on
+ * the equilibrium conditions, Sec. 3).  The forward states are kept every
+ * `ckpt_every` iterations and recomputed in between (memory
+ * (unroll/ckpt_every + ckpt_every) nnz floats, allocated by the call).
+ * Loss: L(p^unroll) with dL/dp given.
+ *   x [nnz], p [m], dL_dp [m]: device inputs (float32);
+ *   omega: the primal weight (pdhcg_info.omega of the solve), > 0;
+ *   dL_du [nnz] (CSR order, the caller's unnormalised u), dL_dw [n]:
+ *   device outputs.
+ * Synchronises the handle's stream before returning.  ERR_ARG on null
+ * pointers, omega <= 0, unroll < 1 or ckpt_every < 1; ERR_HIP / ERR_OOM on
+ * device failures. */
+int32_t pdhcg_backward(pdhcg_market market, const float *x, const float *p,
+                       double omega, int32_t unroll, int32_t ckpt_every,
+                       const float *dL_dp, float *dL_du, float *dL_dw);
+
 /* Number of market rows in each kernel bin and the bin shapes chosen at
  * creation (host arrays of length cap; returns the number of bins). */
 int32_t pdhcg_market_bins(pdhcg_market market, int32_t cap,

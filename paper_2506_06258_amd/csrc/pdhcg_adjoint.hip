@@ -1,0 +1,277 @@
+// Reverse mode through fixed-step PDHCG iterations (gfx950).
+//
+// The forward map of one step (Alg. 2 with a fixed step, no restarts):
+//   c^k = colsum(x^k),  p^{k+1} = p^k + sigma (2 c^k - c^{k-1} - 1)
+//   (eq. update:py),  x^{k+1}_i = prox_i(x^k_i - tau p^{k+1}; w_i, uh_i)
+//   (Sec. 2.2).
+// The forward steps run with the row pass of pdhcg_kernels.hip in explicit
+// mode.  The reverse of one step, for an incoming adjoint
+// g = dL/dx^{k+1} = R + B[col] (R per entry, B per good):
+//   on the active set A of row i (x^{k+1}_ij > 0), with s = sum_A uh x^{k+1},
+//   D = 1 + tau w_i sum_A uh^2 / s^2 and h = (tau w_i / s^2) sum_A g uh / D,
+//   r_j = g_j - h uh_j on A (0 off A) is dL/d(x^k - tau p^{k+1}),
+//   dL/dw_i += (tau / s) sum_A r uh,  dL/duh_j += r_j tau w_i / s - h x_j;
+// then with Pt = dL/dp^{k+1} - tau colsum(r):
+//   dL/dp^k = Pt,  dL/dx^k = r + (2 sigma Pt + Cn)[col],  Cn' = -sigma Pt,
+// where Cn = dL/dc^k carried from the step after.  (x_j = a_j + tau w uh_j/s
+// on A, s = sum_A uh x; differentiating and solving for ds gives D.)
+#include "pdhcg_internal.h"
+#include "pdhcg_device.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+namespace pdhcg {
+
+namespace {
+
+int grid_1d(int64_t n, int block) { return (int)((n + block - 1) / block); }
+
+}  // namespace
+
+// p += sigma (2 c - cprev - 1), float64.
+__global__ void k_adj_pstep(double *p, const double *c, const double *cprev, double sigma,
+                            int m) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < m) p[j] += sigma * (2.0 * c[j] - cprev[j] - 1.0);
+}
+
+// Per-workgroup column partials [rows][m] summed in kColChunks chunks of
+// rows, each chunk in a fixed order: chunk[q][j].
+__global__ __launch_bounds__(kColBlock) void k_sum_partials(const double *part, int rows, int m,
+                                                            double *chunk) {
+  const int j = blockIdx.x * kColBlock + threadIdx.x;
+  const int q = blockIdx.y;
+  if (j >= m) return;
+  const int per = (rows + kColChunks - 1) / kColChunks;
+  const int b0 = q * per, b1 = min(rows, b0 + per);
+  double c = 0.0;
+  for (int b = b0; b < b1; ++b) c += part[(size_t)b * m + j];
+  chunk[(size_t)q * m + j] = c;
+}
+
+// out[j] = sum_q chunk[q][j] in order.
+__global__ void k_finish_colsum(const double *chunk, int m, double *out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  double c = 0.0;
+  for (int q = 0; q < kColChunks; ++q) c += chunk[(size_t)q * m + j];
+  out[j] = c;
+}
+
+// Column sums of x by float64 device atomics (one-time use).
+__global__ void k_colsum_atomic(const int32_t *col, const float *x, int64_t nnz, double *out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nnz) atomicAdd(&out[col[k]], (double)x[k]);
+}
+
+__global__ void k_zero_f64(double *a, int64_t len) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < len) a[k] = 0.0;
+}
+
+__global__ void k_zero_f32(float *a, int64_t len) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < len) a[k] = 0.0f;
+}
+
+// Reverse of the row prox for every row (see the file comment).  Lane r of
+// a segment of G lanes handles entries r, r+G, ... of its row.  Column sums
+// of r go to float64 LDS partials (LDS_MODE 1, written to md.colpart) or to
+// io.csum by device atomics (LDS_MODE 0).
+template <int G, int E, int LDS_MODE>
+__global__ __launch_bounds__(kRowBlock) void k_adj_row(MarketDev md, BinDev bin, AdjIO io) {
+  extern __shared__ double lcs[];
+  const int m = md.m;
+  if (LDS_MODE) {
+    for (int j = threadIdx.x; j < m; j += blockDim.x) lcs[j] = 0.0;
+    __syncthreads();
+  }
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  const int r = lane & (G - 1);
+  const int seg = lane / G;
+  constexpr int kSeg = kWave / G;
+  constexpr int kWaves = kRowBlock / kWave;
+  const int wg = blockIdx.x;
+  const int row_lo = wg * bin.rows_per_wg;
+  const int row_hi = min(row_lo + bin.rows_per_wg, bin.nrows);
+  const double tau = io.tau;
+  for (int base = row_lo + wave * kSeg; base < row_hi; base += kWaves * kSeg) {
+    const int slot = base + seg;
+    const bool rv = slot < row_hi;
+    const int i = rv ? (bin.rows ? bin.rows[slot] : slot) : 0;
+    const int beg = rv ? md.row_ptr[i] : 0;
+    const int d = rv ? md.row_ptr[i + 1] - beg : 0;
+    const double tw = rv ? tau * (double)md.w[i] : 0.0;
+    float uh[E], xn[E];
+    double g[E];
+    int cj[E];
+    bool act[E];
+    double s = 0.0, Q = 0.0, Gu = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int idx = r + G * e;
+      const bool v = idx < d;
+      const int k = beg + (v ? idx : 0);
+      uh[e] = v ? md.uh[k] : 0.0f;
+      xn[e] = v ? io.xn[k] : 0.0f;
+      cj[e] = v ? md.col[k] : 0;
+      g[e] = v ? (double)io.r_in[k] + io.b[cj[e]] : 0.0;
+      act[e] = v && xn[e] > 0.0f;
+      const double u = act[e] ? (double)uh[e] : 0.0;
+      s = fma(u, (double)xn[e], s);
+      Q = fma(u, u, Q);
+      Gu = fma(u, g[e], Gu);
+    }
+    s = seg_sum_d<G>(s);
+    Q = seg_sum_d<G>(Q);
+    Gu = seg_sum_d<G>(Gu);
+    const bool live = rv && s > 0.0;
+    const double is = live ? fast_rcp(s) : 0.0;
+    const double tws2 = tw * is * is;
+    const double h = live ? tws2 * Gu / (1.0 + tws2 * Q) : 0.0;
+    double ru = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int idx = r + G * e;
+      if (idx < d) {
+        const int k = beg + idx;
+        const double rr = (live && act[e]) ? g[e] - h * (double)uh[e] : 0.0;
+        io.r_out[k] = (float)rr;
+        if (live && act[e])
+          io.duh[k] += (float)(rr * tw * is - h * (double)xn[e]);
+        ru = fma(rr, (double)uh[e], ru);
+        if (LDS_MODE)
+          atomicAdd(&lcs[cj[e]], rr);
+        else
+          atomicAdd(&io.csum[cj[e]], rr);
+      }
+    }
+    ru = seg_sum_d<G>(ru);
+    if (live && r == 0) io.dw[i] += (float)(tau * is * ru);
+  }
+  if (LDS_MODE) {
+    __syncthreads();
+    double *dst = md.colpart + (size_t)(bin.wg_offset + wg) * m;
+    for (int j = threadIdx.x; j < m; j += blockDim.x) dst[j] = lcs[j];
+  }
+}
+
+// Column part of the reverse step: Pt = P - tau colsum(r), B = 2 sigma Pt +
+// Cn, Cn = -sigma Pt, P = Pt.  colsum(r) from chunk sums (chunked != 0) or
+// from the atomic accumulator.
+__global__ void k_adj_col(const double *csrc, int chunked, double *P, double *B, double *Cn,
+                          double tau, double sigma, int m) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= m) return;
+  double cr = 0.0;
+  if (chunked) {
+    for (int q = 0; q < kColChunks; ++q) cr += csrc[(size_t)q * m + j];
+  } else {
+    cr = csrc[j];
+  }
+  const double pt = P[j] - tau * cr;
+  B[j] = 2.0 * sigma * pt + Cn[j];
+  Cn[j] = -sigma * pt;
+  P[j] = pt;
+}
+
+// dL/du from dL/duh through uh = u / max_j u_ij: the row's first entry with
+// uh == 1 is its first maximum.  One wave per row.
+__global__ void k_adj_unnormalize(const int32_t *row_ptr, const float *uh, const float *rowmax,
+                                  const float *duh, int n, float *du) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int i = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  if (i >= n) return;
+  const int beg = row_ptr[i], end = row_ptr[i + 1];
+  double gs = 0.0;
+  int first = end;
+  for (int k = beg + lane; k < end; k += kWave) {
+    gs = fma((double)uh[k], (double)duh[k], gs);
+    if (uh[k] == 1.0f) first = min(first, k);
+  }
+  gs = wave_sum_d(gs);
+  for (int o = 32; o >= 1; o >>= 1) first = min(first, __shfl_xor(first, o));
+  const double inv = 1.0 / (double)rowmax[i];
+  for (int k = beg + lane; k < end; k += kWave) {
+    double v = (double)duh[k] * inv;
+    if (k == first) v -= gs * inv;
+    du[k] = (float)v;
+  }
+}
+
+// ------------------------------------------------------------- launchers --
+
+hipError_t launch_adj_pstep(double *p, const double *c, const double *cprev, double sigma, int m,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_pstep, dim3(grid_1d(m, 256)), dim3(256), 0, st, p, c, cprev, sigma, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_partials(const double *part, int rows, int m, double *chunk,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_sum_partials, dim3(grid_1d(m, kColBlock), kColChunks), dim3(kColBlock), 0,
+                     st, part, rows, m, chunk);
+  return hipGetLastError();
+}
+
+hipError_t launch_finish_colsum(const double *chunk, int m, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_finish_colsum, dim3(grid_1d(m, 256)), dim3(256), 0, st, chunk, m, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_colsum_atomic(const int32_t *col, const float *x, int64_t nnz, double *out,
+                                int m, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_f64, dim3(grid_1d(m, 256)), dim3(256), 0, st, out, (int64_t)m);
+  hipLaunchKernelGGL(k_colsum_atomic, dim3(grid_1d(nnz, 256)), dim3(256), 0, st, col, x, nnz, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_f64(double *a, int64_t len, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_f64, dim3(grid_1d(len, 256)), dim3(256), 0, st, a, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_f32(float *a, int64_t len, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_f32, dim3(grid_1d(len, 256)), dim3(256), 0, st, a, len);
+  return hipGetLastError();
+}
+
+template <int G, int E, int LDSM>
+static hipError_t adj_launch_t(const MarketDev &md, const BinDev &bin, const AdjIO &io, int nwg,
+                               hipStream_t st) {
+  const size_t shm = LDSM ? (size_t)md.m * sizeof(double) : 0;
+  hipLaunchKernelGGL((k_adj_row<G, E, LDSM>), dim3(nwg), dim3(kRowBlock), shm, st, md, bin, io);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_row(const MarketDev &md, const BinDev &bin, int G, int E, int lds,
+                          const AdjIO &io, int nwg, hipStream_t st) {
+#define PDHCG_ADJ_DISPATCH(g, e)                                              \
+  if (G == g && E == e)                                                       \
+    return lds ? adj_launch_t<g, e, 1>(md, bin, io, nwg, st)                  \
+               : adj_launch_t<g, e, 0>(md, bin, io, nwg, st);
+  PDHCG_ROW_VARIANTS(PDHCG_ADJ_DISPATCH)
+#undef PDHCG_ADJ_DISPATCH
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_adj_col(const double *csrc, int chunked, double *P, double *B, double *Cn,
+                          double tau, double sigma, int m, hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_col, dim3(grid_1d(m, 256)), dim3(256), 0, st, csrc, chunked, P, B, Cn,
+                     tau, sigma, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_unnormalize(const int32_t *row_ptr, const float *uh, const float *rowmax,
+                                  const float *duh, int n, float *du, hipStream_t st) {
+  const int rows_per_block = 256 / kWave;
+  hipLaunchKernelGGL(k_adj_unnormalize, dim3(grid_1d(n, rows_per_block)), dim3(256), 0, st,
+                     row_ptr, uh, rowmax, duh, n, du);
+  return hipGetLastError();
+}
+
+}  // namespace pdhcg

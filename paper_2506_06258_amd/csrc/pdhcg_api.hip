@@ -976,3 +976,175 @@ extern "C" int32_t pdhcg_arrow_debreu(pdhcg_market mk, const int32_t *e_row_ptr,
   }
   return rc;
 }
+
+// ------------------------------------------------------------ reverse mode --
+
+namespace {
+
+// Device buffers of one backward call (freed on every exit path).
+struct AdjBuffers {
+  std::vector<void *> owned;
+  ~AdjBuffers() {
+    for (void *p : owned)
+      if (p) (void)hipFree(p);
+  }
+  template <typename T>
+  hipError_t get(T **p, size_t count) {
+    hipError_t e = dalloc(p, count);
+    if (e == hipSuccess) owned.push_back(*p);
+    return e;
+  }
+};
+
+// Column sums of the row pass just launched (explicit mode) into out.
+int32_t finish_colsum(pdhcg_market mk, double *chunk, double *atomic_sum, double *out) {
+  if (mk->lds_row & 1) {
+    HIPC(launch_sum_partials(mk->colpart, mk->total_wg, mk->m, chunk, mk->stream));
+    HIPC(launch_finish_colsum(chunk, mk->m, out, mk->stream));
+  } else {
+    HIPC(hipMemcpyAsync(out, atomic_sum, (size_t)mk->m * sizeof(double),
+                        hipMemcpyDeviceToDevice, mk->stream));
+  }
+  return PDHCG_OK;
+}
+
+}  // namespace
+
+extern "C" int32_t pdhcg_backward(pdhcg_market mk, const float *x, const float *p, double omega,
+                                  int32_t unroll, int32_t ckpt_every, const float *dL_dp,
+                                  float *dL_du, float *dL_dw) {
+  if (!mk || !x || !p || !dL_dp || !dL_du || !dL_dw) return fail(PDHCG_ERR_ARG, "null argument");
+  if (!(omega > 0.0) || !std::isfinite(omega))
+    return fail(PDHCG_ERR_ARG, "omega must be finite and > 0");
+  if (unroll < 1 || ckpt_every < 1) return fail(PDHCG_ERR_ARG, "unroll and ckpt_every must be >= 1");
+  const int n = mk->n, m = mk->m;
+  const int64_t nnz = mk->nnz;
+  const hipStream_t st = mk->stream;
+  const MarketDev md = mk->dev();
+  const int K = unroll, L = std::min(ckpt_every, unroll);
+  const int nck = (K + L - 1) / L;
+  // fixed step (Lemma 1): eta = 0.9 / ||K||, ||K|| = sqrt(max column degree)
+  const double eta = 0.9 / std::sqrt((double)std::max(1, mk->maxdeg_col));
+  const double tau = eta / omega, sigma = eta * omega;
+
+  AdjBuffers buf;
+  float *ck_x = nullptr, *seg_x = nullptr, *xa = nullptr, *xb = nullptr;
+  float *R0 = nullptr, *R1 = nullptr, *duh = nullptr, *dw = nullptr;
+  double *ck_p = nullptr, *ck_c = nullptr, *ck_cp = nullptr, *pw = nullptr, *c = nullptr;
+  double *cp = nullptr, *chunk = nullptr, *asum = nullptr, *P = nullptr, *B = nullptr,
+         *Cn = nullptr;
+  HIPC(buf.get(&ck_x, (size_t)nck * nnz));
+  HIPC(buf.get(&seg_x, (size_t)L * nnz));
+  HIPC(buf.get(&xa, (size_t)nnz));
+  HIPC(buf.get(&xb, (size_t)nnz));
+  HIPC(buf.get(&R0, (size_t)nnz));
+  HIPC(buf.get(&R1, (size_t)nnz));
+  HIPC(buf.get(&duh, (size_t)nnz));
+  HIPC(buf.get(&dw, (size_t)n));
+  HIPC(buf.get(&ck_p, (size_t)nck * m));
+  HIPC(buf.get(&ck_c, (size_t)nck * m));
+  HIPC(buf.get(&ck_cp, (size_t)nck * m));
+  HIPC(buf.get(&pw, (size_t)m));
+  HIPC(buf.get(&c, (size_t)m));
+  HIPC(buf.get(&cp, (size_t)m));
+  HIPC(buf.get(&chunk, (size_t)kColChunks * m));
+  HIPC(buf.get(&asum, (size_t)m));
+  HIPC(buf.get(&P, (size_t)m));
+  HIPC(buf.get(&B, (size_t)m));
+  HIPC(buf.get(&Cn, (size_t)m));
+
+  pdhcg_params dflt;
+  pdhcg_default_params(&dflt);
+  RowIO io = row_io_state(&dflt);
+  io.use_state = 0;
+  io.colsum = 1;
+  io.tau = tau;
+  io.wfold = 0.0f;
+  io.csum = asum;
+  io.p = pw;
+  // One forward step from (xin, pw = p^j, c = c^j, cp = c^{j-1}) to xout,
+  // pw = p^{j+1}, c = c^{j+1}, cp = c^j.
+  auto forward = [&](const float *xin, float *xout) -> int32_t {
+    HIPC(launch_adj_pstep(pw, c, cp, sigma, m, st));
+    HIPC(hipMemcpyAsync(cp, c, (size_t)m * sizeof(double), hipMemcpyDeviceToDevice, st));
+    if (!(mk->lds_row & 1)) HIPC(launch_zero_f64(asum, m, st));
+    io.xin = xin;
+    io.xout = xout;
+    for (const Bin &b : mk->bins)
+      HIPC(launch_row_pass(md, mk->bindev(b), b.G, b.E, mk->lds_row, io, b.nwg, st));
+    return finish_colsum(mk, chunk, asum, c);
+  };
+
+  // forward sweep from the given point, one checkpoint every L steps
+  HIPC(launch_f32_to_f64(p, pw, m, st));
+  HIPC(launch_colsum_atomic(mk->col, x, nnz, c, m, st));
+  HIPC(hipMemcpyAsync(cp, c, (size_t)m * sizeof(double), hipMemcpyDeviceToDevice, st));
+  const float *xcur = x;
+  for (int j = 0; j < K; ++j) {
+    if (j % L == 0) {
+      const int q = j / L;
+      HIPC(hipMemcpyAsync(ck_x + (size_t)q * nnz, xcur, (size_t)nnz * sizeof(float),
+                          hipMemcpyDeviceToDevice, st));
+      HIPC(hipMemcpyAsync(ck_p + (size_t)q * m, pw, (size_t)m * sizeof(double),
+                          hipMemcpyDeviceToDevice, st));
+      HIPC(hipMemcpyAsync(ck_c + (size_t)q * m, c, (size_t)m * sizeof(double),
+                          hipMemcpyDeviceToDevice, st));
+      HIPC(hipMemcpyAsync(ck_cp + (size_t)q * m, cp, (size_t)m * sizeof(double),
+                          hipMemcpyDeviceToDevice, st));
+    }
+    float *xnext = (j % 2 == 0) ? xa : xb;
+    int32_t rc = forward(xcur, xnext);
+    if (rc != PDHCG_OK) return rc;
+    xcur = xnext;
+  }
+
+  // reverse sweep, one segment at a time (recomputed from its checkpoint)
+  HIPC(launch_zero_f32(R0, nnz, st));
+  HIPC(launch_zero_f32(duh, nnz, st));
+  HIPC(launch_zero_f32(dw, n, st));
+  HIPC(launch_zero_f64(B, m, st));
+  HIPC(launch_zero_f64(Cn, m, st));
+  HIPC(launch_f32_to_f64(dL_dp, P, m, st));
+  float *rin = R0, *rout = R1;
+  for (int q = nck - 1; q >= 0; --q) {
+    const int j0 = q * L, j1 = std::min(K, j0 + L);
+    HIPC(hipMemcpyAsync(pw, ck_p + (size_t)q * m, (size_t)m * sizeof(double),
+                        hipMemcpyDeviceToDevice, st));
+    HIPC(hipMemcpyAsync(c, ck_c + (size_t)q * m, (size_t)m * sizeof(double),
+                        hipMemcpyDeviceToDevice, st));
+    HIPC(hipMemcpyAsync(cp, ck_cp + (size_t)q * m, (size_t)m * sizeof(double),
+                        hipMemcpyDeviceToDevice, st));
+    const float *xin = ck_x + (size_t)q * nnz;
+    for (int j = j0; j < j1; ++j) {
+      float *xo = seg_x + (size_t)(j - j0) * nnz;  // x^{j+1}
+      int32_t rc = forward(xin, xo);
+      if (rc != PDHCG_OK) return rc;
+      xin = xo;
+    }
+    for (int j = j1 - 1; j >= j0; --j) {
+      AdjIO aio;
+      aio.xn = seg_x + (size_t)(j - j0) * nnz;
+      aio.r_in = rin;
+      aio.b = B;
+      aio.r_out = rout;
+      aio.duh = duh;
+      aio.dw = dw;
+      aio.csum = asum;
+      aio.tau = tau;
+      if (!(mk->lds_row & 1)) HIPC(launch_zero_f64(asum, m, st));
+      for (const Bin &b : mk->bins)
+        HIPC(launch_adj_row(md, mk->bindev(b), b.G, b.E, mk->lds_row & 1, aio, b.nwg, st));
+      if (mk->lds_row & 1) {
+        HIPC(launch_sum_partials(mk->colpart, mk->total_wg, m, chunk, st));
+        HIPC(launch_adj_col(chunk, 1, P, B, Cn, tau, sigma, m, st));
+      } else {
+        HIPC(launch_adj_col(asum, 0, P, B, Cn, tau, sigma, m, st));
+      }
+      std::swap(rin, rout);
+    }
+  }
+  HIPC(launch_adj_unnormalize(mk->row_ptr, mk->uh, mk->rowmax, duh, n, dL_du, st));
+  HIPC(hipMemcpyAsync(dL_dw, dw, (size_t)n * sizeof(float), hipMemcpyDeviceToDevice, st));
+  HIPC(hipStreamSynchronize(st));  // the buffers above are freed on return
+  return PDHCG_OK;
+}

@@ -71,6 +71,14 @@ struct MarketDev {
   DevState *S;
 };
 
+// Row kernel shapes (G lanes per row, E entries per lane) that are built.
+#define PDHCG_ROW_VARIANTS(X) \
+  X(4, 1) X(4, 2) X(4, 4) X(4, 8) \
+  X(8, 1) X(8, 2) X(8, 4) X(8, 8) \
+  X(16, 1) X(16, 2) X(16, 4) X(16, 8) \
+  X(32, 1) X(32, 2) X(32, 4) X(32, 8) \
+  X(64, 1) X(64, 2) X(64, 4) X(64, 8) X(64, 16)
+
 // Rows handled by one kernel variant.
 struct BinDev {
   const int32_t *rows;  // row ids of this bin (null: slot s is row s)
@@ -97,6 +105,20 @@ struct RowIO {
   int32_t sections;
   int32_t max_rounds;
   double rtol;
+  double *csum;     // float64 column sums of xout by device atomics (explicit
+                    // mode without LDS partials), zeroed by the caller
+};
+
+// Reverse step of the row prox (pdhcg_adjoint.hip).
+struct AdjIO {
+  const float *xn;    // x^{k+1}, the prox output of the step being reversed
+  const float *r_in;  // adjoint of x^{k+1}: r_in + b[col]
+  const double *b;
+  float *r_out;       // r, the adjoint of x^k - tau p^{k+1}
+  float *duh;         // += dL/d uh (row-normalised utilities)
+  float *dw;          // += dL/dw
+  double *csum;       // column sums of r by device atomics (no LDS partials)
+  double tau;
 };
 
 // Inputs/outputs of a KKT pass over one or two points.
@@ -152,5 +174,21 @@ hipError_t launch_budget_spmv(const int32_t *e_row_ptr, const int32_t *e_col,
                               const float *e_val, const float *p, float *w, int n,
                               hipStream_t st);
 bool row_variant_exists(int G, int E);
+// Reverse mode (pdhcg_adjoint.hip).
+hipError_t launch_adj_pstep(double *p, const double *c, const double *cprev, double sigma, int m,
+                            hipStream_t st);
+hipError_t launch_sum_partials(const double *part, int rows, int m, double *chunk,
+                               hipStream_t st);
+hipError_t launch_finish_colsum(const double *chunk, int m, double *out, hipStream_t st);
+hipError_t launch_colsum_atomic(const int32_t *col, const float *x, int64_t nnz, double *out,
+                                int m, hipStream_t st);
+hipError_t launch_zero_f64(double *a, int64_t len, hipStream_t st);
+hipError_t launch_zero_f32(float *a, int64_t len, hipStream_t st);
+hipError_t launch_adj_row(const MarketDev &md, const BinDev &bin, int G, int E, int lds,
+                          const AdjIO &io, int nwg, hipStream_t st);
+hipError_t launch_adj_col(const double *csrc, int chunked, double *P, double *B, double *Cn,
+                          double tau, double sigma, int m, hipStream_t st);
+hipError_t launch_adj_unnormalize(const int32_t *row_ptr, const float *uh, const float *rowmax,
+                                  const float *duh, int n, float *du, hipStream_t st);
 
 }  // namespace pdhcg

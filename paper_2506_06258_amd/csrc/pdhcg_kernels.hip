@@ -113,7 +113,7 @@ __global__ __launch_bounds__(kRowBlock) void k_row_pass(MarketDev md, BinDev bin
   float *xavg = io.xavg;
   double tau = io.tau;
   float wfold = io.wfold;
-  double *cglob = nullptr;
+  double *cglob = io.csum;
   if (io.use_state) {
     const DevState *S = md.S;
     xin = pick3<float *>(md.X0, md.X1, md.X2, S->ix[0]);
@@ -852,12 +852,6 @@ static int grid_for(int64_t len, int block) {
   return (int)g;
 }
 
-#define PDHCG_ROW_VARIANTS(X) \
-  X(4, 1) X(4, 2) X(4, 4) X(4, 8) \
-  X(8, 1) X(8, 2) X(8, 4) X(8, 8) \
-  X(16, 1) X(16, 2) X(16, 4) X(16, 8) \
-  X(32, 1) X(32, 2) X(32, 4) X(32, 8) \
-  X(64, 1) X(64, 2) X(64, 4) X(64, 8) X(64, 16)
 
 bool row_variant_exists(int G, int E) {
 #define PDHCG_EXISTS(g, e) \

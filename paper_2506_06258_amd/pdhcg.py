@@ -33,7 +33,7 @@ EXPORTS = (
     "pdhcg_abi_version", "pdhcg_status_string", "pdhcg_last_error",
     "pdhcg_default_params", "pdhcg_validate_host", "pdhcg_market_create",
     "pdhcg_set_budgets", "pdhcg_solve", "pdhcg_kkt", "pdhcg_row_prox",
-    "pdhcg_arrow_debreu", "pdhcg_market_bins", "pdhcg_market_destroy",
+    "pdhcg_arrow_debreu", "pdhcg_backward", "pdhcg_market_bins", "pdhcg_market_destroy",
     "pdhcg_batch_create", "pdhcg_batch_solve", "pdhcg_batch_layout", "pdhcg_batch_destroy",
 )
 
@@ -92,6 +92,7 @@ def lib() -> C.CDLL:
         "pdhcg_arrow_debreu": (i32, [vp, vp, vp, vp, i64, C.POINTER(pdhcg_params), dbl, i32,
                                      vp, vp, vp, C.POINTER(i32), C.POINTER(i64),
                                      C.POINTER(pdhcg_info)]),
+        "pdhcg_backward": (i32, [vp, vp, vp, dbl, i32, i32, vp, vp, vp]),
         "pdhcg_market_bins": (i32, [vp, i32, vp, vp, vp]),
         "pdhcg_market_destroy": (None, [vp]),
         "pdhcg_batch_create": (i32, [i32, vp, vp, vp, vp, vp, vp, vp, C.POINTER(vp)]),
@@ -226,6 +227,14 @@ def pdhcg_row_prox(h, x_in, p, tau: float, params: Optional[pdhcg_params], x_out
                                 _dev_ptr(s_out, torch.float32, "s_out")), "pdhcg_row_prox")
 
 
+def pdhcg_backward(h, x, p, omega: float, unroll: int, ckpt_every: int, dL_dp, dL_du, dL_dw):
+    _check(lib().pdhcg_backward(h, _dev_ptr(x, torch.float32, "x"), _dev_ptr(p, torch.float32, "p"),
+                                float(omega), int(unroll), int(ckpt_every),
+                                _dev_ptr(dL_dp, torch.float32, "dL_dp"),
+                                _dev_ptr(dL_du, torch.float32, "dL_du"),
+                                _dev_ptr(dL_dw, torch.float32, "dL_dw")), "pdhcg_backward")
+
+
 def pdhcg_arrow_debreu(h, e_row_ptr, e_col, e_val, e_nnz, inner: pdhcg_params, outer_tol,
                        outer_max, w, p, x):
     oi, ii, info = C.c_int32(0), C.c_int64(0), pdhcg_info()
@@ -324,6 +333,15 @@ class Market:
     def bins(self):
         return pdhcg_market_bins(self._h)
 
+    def backward(self, x, p, omega: float, dL_dp, unroll: int = 1024, ckpt_every: int = 32):
+        """(dL/du, dL/dw) by reverse mode through `unroll` fixed-step
+        iterations from (x, p); see pdhcg_backward."""
+        du = torch.empty(self.nnz, dtype=torch.float32, device=self.device)
+        dw = torch.empty(self.n, dtype=torch.float32, device=self.device)
+        g = torch.as_tensor(dL_dp).to(self.device, torch.float32).contiguous()
+        pdhcg_backward(self._h, x.contiguous(), p.contiguous(), omega, unroll, ckpt_every, g, du, dw)
+        return du, dw
+
     def arrow_debreu(self, e_row_ptr, e_col, e_val, w0, inner: Optional[pdhcg_params] = None,
                      outer_tol: float = 1e-6, outer_max: int = 100):
         inner = inner if inner is not None else pdhcg_default_params()
@@ -407,3 +425,38 @@ class Batch:
         x = torch.empty(int(self.edge_off[-1]), dtype=torch.float32, device=self.device)
         st, infos = pdhcg_batch_solve(self._h, prm, p, x, self.count)
         return st, p, x, infos
+
+
+class FisherPrices(torch.autograd.Function):
+    """Equilibrium prices of a linear Fisher market as a differentiable
+    function of the utilities (CSR values) and budgets.
+
+    ``p = FisherPrices.apply(u, w, row_ptr, col, m, params, unroll, ckpt_every)``
+
+    Forward: restarted PDHCG (pdhcg_solve) with ``params`` (a pdhcg_params
+    or None for the defaults).  Backward: pdhcg_backward from the solution
+    with the solve's primal weight, ``unroll`` fixed-step iterations with a
+    checkpoint every ``ckpt_every``; gradients for u and w (float32), None
+    for the structure arguments."""
+
+    @staticmethod
+    def forward(ctx, u, w, row_ptr, col, m, params=None, unroll=1024, ckpt_every=32):
+        M = Market(row_ptr, col, u.detach(), w.detach(), m=m, device=u.device)
+        sol = M.solve(params)
+        if sol.info.status not in (PDHCG_OK, PDHCG_MAX_ITER):
+            M.close()
+            raise PDHCGError(sol.info.status, "FisherPrices.forward")
+        ctx.market = M
+        ctx.omega = sol.info.omega
+        ctx.unroll, ctx.ckpt = int(unroll), int(ckpt_every)
+        ctx.save_for_backward(sol.x, sol.p)
+        ctx.u_dtype, ctx.w_dtype = u.dtype, w.dtype
+        return sol.p
+
+    @staticmethod
+    def backward(ctx, grad_p):
+        x, p = ctx.saved_tensors
+        M = ctx.market
+        du, dw = M.backward(x, p, ctx.omega, grad_p.float(), ctx.unroll, ctx.ckpt)
+        M.close()
+        return (du.to(ctx.u_dtype), dw.to(ctx.w_dtype), None, None, None, None, None, None)

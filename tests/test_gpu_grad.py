@@ -1,0 +1,152 @@
+"""Gradients of equilibrium prices on the GPU (pdhcg_backward, FisherPrices)
+against the FP64 oracle, through the C ABI.
+
+Reference: the oracle's implicit derivative of the equilibrium prices on the
+active support (oracle.implicit_grad, pinned by closed forms and finite
+differences in test_oracle_grad.py).  The GPU unrolls 1024 fixed-step
+iterations from its own solution; the unrolled derivative converges to the
+implicit one geometrically (the oracle pins that too), so the bar is the
+north-star's 1e-4, relative to the largest gradient entry.  The oracle's
+own unrolled reverse mode from its own solution is a second reference with
+the same bar.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2506_06258_amd import pdhcg
+
+pytestmark = pytest.mark.gpu
+
+
+def _market(seed, n, m, q):
+    rng = np.random.default_rng(seed)
+    U = rng.uniform(0.05, 1.0, (n, m)) * (rng.uniform(size=(n, m)) < q)
+    for i in range(n):
+        if not U[i].any():
+            U[i, rng.integers(m)] = 0.5
+    for j in range(m):
+        if not U[:, j].any():
+            U[rng.integers(n), j] = 0.5
+    rows, cols = np.nonzero(U)
+    row_ptr = np.zeros(n + 1, np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=row_ptr[1:])
+    u = U[rows, cols].astype(np.float32)  # both sides solve the float32 instance
+    w = rng.uniform(0.5, 1.5, n).astype(np.float32)
+    return row_ptr, cols.astype(np.int32), u, w, rng
+
+
+def _rel(a, b):
+    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-30)
+
+
+@pytest.mark.parametrize("seed,n,m", [(3, 30, 10), (5, 60, 20)])
+def test_backward_matches_oracle(cuda, seed, n, m):
+    rp, col, u, w, rng = _market(seed, n, m, 0.5)
+    ref = oracle.solve(n, m, rp, col, u.astype(np.float64), w.astype(np.float64), tol=1e-13,
+                       max_iter=2000000)
+    assert ref.status == oracle.OK
+    g = rng.normal(size=m)
+    st, du_i, dw_i, _ = oracle.implicit_grad(n, m, rp, col, u, w, ref.x, ref.p, g)
+    assert st == oracle.OK
+    deg = np.bincount(col, minlength=m)
+    eta = 0.9 / np.sqrt(deg.max())
+    st, du_u, dw_u, _ = oracle.unrolled_grad(n, m, rp, col, u, w, ref.x, ref.p, eta / ref.omega,
+                                             eta * ref.omega, 1024, g)
+    assert st == oracle.OK
+
+    M = pdhcg.Market(rp, col, u, w, m=m, device=cuda)
+    sol = M.solve(tol=1e-7, max_iter=200000)
+    assert sol.info.status == pdhcg.PDHCG_OK
+    du, dw = M.backward(sol.x, sol.p, sol.info.omega, torch.tensor(g, dtype=torch.float32),
+                        unroll=1024, ckpt_every=32)
+    du = du.double().cpu().numpy()
+    dw = dw.double().cpu().numpy()
+    assert np.all(np.isfinite(du)) and np.all(np.isfinite(dw))
+    assert _rel(du, du_i) <= 1e-4, _rel(du, du_i)
+    assert _rel(dw, dw_i) <= 1e-4, _rel(dw, dw_i)
+    assert _rel(du, du_u) <= 1e-4 and _rel(dw, dw_u) <= 1e-4
+    M.close()
+
+
+def test_checkpoint_spacing_does_not_change_the_gradient(cuda):
+    rp, col, u, w, rng = _market(8, 40, 12, 0.5)
+    M = pdhcg.Market(rp, col, u, w, m=12, device=cuda)
+    sol = M.solve(tol=1e-7, max_iter=200000)
+    g = torch.tensor(rng.normal(size=12), dtype=torch.float32)
+    out = [M.backward(sol.x, sol.p, sol.info.omega, g, unroll=300, ckpt_every=c) for c in (1, 7, 300)]
+    # recomputed segments repeat the forward steps; column sums are added by
+    # float64 LDS atomics in no fixed order, so equal to rounding only
+    for du, dw in out[1:]:
+        assert torch.allclose(du, out[0][0], rtol=1e-5, atol=1e-6 * float(out[0][0].abs().max()))
+        assert torch.allclose(dw, out[0][1], rtol=1e-5, atol=1e-6 * float(out[0][1].abs().max()))
+    M.close()
+
+
+def test_fisher_prices_autograd(cuda):
+    n, m = 50, 15
+    rp, col, u, w, rng = _market(13, n, m, 0.5)
+    ref = oracle.solve(n, m, rp, col, u.astype(np.float64), w.astype(np.float64), tol=1e-13,
+                       max_iter=2000000)
+    target = ref.p * (1.0 + 0.05 * rng.normal(size=m))
+    # d/dp sum (p - p*)^2 at the oracle equilibrium
+    st, du_i, dw_i, _ = oracle.implicit_grad(n, m, rp, col, u, w, ref.x, ref.p,
+                                             2.0 * (ref.p - target))
+    assert st == oracle.OK
+    ut = torch.tensor(u, device=cuda, requires_grad=True)
+    wt = torch.tensor(w, device=cuda, requires_grad=True)
+    prm = pdhcg.pdhcg_default_params(tol=1e-7, max_iter=200000)
+    p = pdhcg.FisherPrices.apply(ut, wt, torch.tensor(rp, dtype=torch.int32, device=cuda),
+                                 torch.tensor(col, device=cuda), m, prm, 1024, 32)
+    loss = ((p.double() - torch.tensor(target, device=cuda)) ** 2).sum()
+    loss.backward()
+    assert _rel(ut.grad.double().cpu().numpy(), du_i) <= 1e-4
+    assert _rel(wt.grad.double().cpu().numpy(), dw_i) <= 1e-4
+
+
+def test_backward_central_differences_of_gpu_solves(cuda):
+    # a coarse check that needs no oracle: central differences of float32
+    # GPU solves (noise ~1e-6 relative in p) on a few budgets and utilities
+    n, m = 30, 10
+    rp, col, u, w, rng = _market(3, n, m, 0.5)
+    g = rng.normal(size=m)
+    M = pdhcg.Market(rp, col, u, w, m=m, device=cuda)
+    sol = M.solve(tol=1e-8, max_iter=400000)
+    du, dw = M.backward(sol.x, sol.p, sol.info.omega, torch.tensor(g, dtype=torch.float32))
+    du, dw = du.double().cpu().numpy(), dw.double().cpu().numpy()
+    M.close()
+
+    def loss(uu, ww):
+        Mx = pdhcg.Market(rp, col, uu, ww, m=m, device=cuda)
+        s = Mx.solve(tol=1e-8, max_iter=400000)
+        Mx.close()
+        return float(g @ s.p.double().cpu().numpy())
+
+    h = 2e-3
+    for i in (0, 7, 19):
+        e = np.zeros(n, np.float32)
+        e[i] = h
+        fd = (loss(u, w + e) - loss(u, w - e)) / (2 * h)
+        assert abs(fd - dw[i]) <= 2e-2 * (1 + abs(fd)), (i, fd, dw[i])
+    big = np.argsort(-np.abs(du))[:3]
+    for q in big:
+        e = np.zeros(len(u), np.float32)
+        e[q] = h
+        fd = (loss(u + e, w) - loss(u - e, w)) / (2 * h)
+        assert abs(fd - du[q]) <= 2e-2 * (1 + abs(fd)), (q, fd, du[q])
+
+
+def test_backward_rejects_bad_arguments(cuda):
+    rp, col, u, w, _ = _market(3, 20, 6, 0.5)
+    M = pdhcg.Market(rp, col, u, w, m=6, device=cuda)
+    sol = M.solve(tol=1e-5)
+    g = torch.ones(6)
+    for kw in (dict(omega=0.0), dict(omega=float("nan"))):
+        with pytest.raises(pdhcg.PDHCGError) as e:
+            M.backward(sol.x, sol.p, kw["omega"], g)
+        assert e.value.status == pdhcg.PDHCG_ERR_ARG
+    with pytest.raises(pdhcg.PDHCGError) as e:
+        M.backward(sol.x, sol.p, 1.0, g, unroll=0)
+    assert e.value.status == pdhcg.PDHCG_ERR_ARG
+    M.close()

@@ -250,6 +250,7 @@ static hipError_t adj_launch_t(const MarketDev &md, const BinDev &bin, const Adj
 
 hipError_t launch_adj_row(const MarketDev &md, const BinDev &bin, int G, int E, int lds,
                           const AdjIO &io, int nwg, hipStream_t st) {
+  if (G == 0) return launch_adj_long(md, bin, lds, io, nwg, st);
 #define PDHCG_ADJ_DISPATCH(g, e)                                              \
   if (G == g && E == e)                                                       \
     return lds ? adj_launch_t<g, e, 1>(md, bin, io, nwg, st)                  \

@@ -283,12 +283,8 @@ int32_t build_bins(pdhcg_market mk, const std::vector<int32_t> &h_row_ptr, int w
   std::vector<int> shape_of((size_t)mk->n);
   for (int32_t i = 0; i < mk->n; ++i) {
     const int d = h_row_ptr[(size_t)i + 1] - h_row_ptr[(size_t)i];
-    if (d > 1024)
-      return fail(PDHCG_ERR_UNSUPPORTED,
-                  "row " + std::to_string(i) + " has " + std::to_string(d) +
-                      " entries; rows longer than 1024 are not supported yet");
-    int G, E;
-    choose_shape(d, &G, &E);
+    int G = 0, E = 0;  // rows above kLongRow entries: the one-wave-per-row kernels
+    if (d <= kLongRow) choose_shape(d, &G, &E);
     auto key = std::make_pair(G, E);
     auto it = std::find(shapes.begin(), shapes.end(), key);
     int s;
@@ -321,7 +317,7 @@ int32_t build_bins(pdhcg_market mk, const std::vector<int32_t> &h_row_ptr, int w
   const int kWaves = kRowBlock / kWave;
   for (auto &b : mk->bins) {
     b.nrows = (int32_t)b.rows.size();
-    const int per_pass = kWaves * (kWave / b.G);
+    const int per_pass = b.G ? kWaves * (kWave / b.G) : kWaves;
     const int64_t passes = (b.nrows + per_pass - 1) / per_pass;
     int nwg = (int)std::max<int64_t>(
         1, std::min<int64_t>(passes, (int64_t)std::ceil((double)budget * (double)b.nnz /

@@ -114,68 +114,6 @@ __device__ __forceinline__ double block_max(double v, double *red) {
   return t;
 }
 
-// Row root for rows longer than a wave holds in registers: one wave per
-// row, every search round re-reads the row (it stays in cache).  Same
-// search as prox_row (active-set trial points inside the Alg. 3 bracket).
-template <class PGet>
-__device__ double prox_row_long(int beg, int d, double tau, double tw, const float *uh,
-                                const int32_t *col, const float *xin, PGet pget, int max_rounds,
-                                double rtol, int &rounds) {
-  const int lane = threadIdx.x & (kWave - 1);
-  double s0 = 0.0;
-  for (int k = lane; k < d; k += kWave) s0 = fma((double)uh[beg + k], (double)xin[beg + k], s0);
-  s0 = seg_sum_d<kWave>(s0);
-  double s = s0;
-  if (!(s > 0.0)) {
-    double lb = 0.0;
-    for (int k = lane; k < d; k += kWave) {
-      const double u = uh[beg + k];
-      if (u > 0.0) {
-        const double a = fma(-tau, pget(col[beg + k]), (double)xin[beg + k]);
-        lb = fmax(lb, pos_root_d(u * a, tw * u * u));
-      }
-    }
-    lb = seg_max_d<kWave>(lb);
-    s = lb > 0.0 ? lb : 1.0;
-  }
-  double L = 0.0, U = INFINITY, sfin = s;
-  rounds = 0;
-  for (int it = 0; it < max_rounds; ++it) {
-    const double inv = fast_rcp(s), ti = tw * inv;
-    double A = 0.0, Q = 0.0;
-    for (int k = lane; k < d; k += kWave) {
-      const double u = uh[beg + k];
-      const double a = fma(-tau, pget(col[beg + k]), (double)xin[beg + k]);
-      const double on = fma(u, ti, a) > 0.0 ? u : 0.0;
-      A = fma(on, a, A);
-      Q = fma(on, u, Q);
-    }
-    A = seg_sum_d<kWave>(A);
-    Q = seg_sum_d<kWave>(Q);
-    const double B = tw * Q, g = fma(B, inv, A), sA = pos_root_d(A, B);
-    bool same = false;
-    if (sA > 0.0) {
-      const double tA = tw * fast_rcp(sA);
-      bool diff = false;
-      for (int k = lane; k < d; k += kWave) {
-        const double u = uh[beg + k];
-        const double a = fma(-tau, pget(col[beg + k]), (double)xin[beg + k]);
-        diff |= ((fma(u, ti, a) > 0.0) != (fma(u, tA, a) > 0.0));
-      }
-      same = !seg_any<kWave>(diff);
-    }
-    ++rounds;
-    U = fmin(U, fmax(s, g));
-    L = fmax(L, fmin(s, g));
-    if (sA > 0.0) L = fmax(L, sA);
-    if (same || sA == s) return sA;
-    if (U - L <= rtol * U) return 0.5 * (L + U);
-    s = (L > 0.0) ? L : 0.5 * U;
-    sfin = s;
-  }
-  return (U < INFINITY) ? 0.5 * (L + U) : sfin;
-}
-
 // One trial step's row pass over the market for shape (G, E): x_try,
 // lagged fold of x_cur into x_avg, |x_try - x_cur|^2 (returned, this
 // thread's share) and float64 column sums into lc.

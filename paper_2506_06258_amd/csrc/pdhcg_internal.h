@@ -77,7 +77,7 @@ struct MarketDev {
   X(8, 1) X(8, 2) X(8, 4) X(8, 8) \
   X(16, 1) X(16, 2) X(16, 4) X(16, 8) \
   X(32, 1) X(32, 2) X(32, 4) X(32, 8) \
-  X(64, 1) X(64, 2) X(64, 4) X(64, 8) X(64, 16)
+  X(64, 1) X(64, 2) X(64, 4) X(64, 8)
 
 // Rows handled by one kernel variant.
 struct BinDev {
@@ -174,6 +174,15 @@ hipError_t launch_budget_spmv(const int32_t *e_row_ptr, const int32_t *e_col,
                               const float *e_val, const float *p, float *w, int n,
                               hipStream_t st);
 bool row_variant_exists(int G, int E);
+// Rows longer than kLongRow entries: one wave per row (pdhcg_long.hip); a
+// bin of them has G = E = 0.
+constexpr int kLongRow = 512;
+hipError_t launch_row_long(const MarketDev &md, const BinDev &bin, int lds_mode, const RowIO &io,
+                           int nwg, hipStream_t st);
+hipError_t launch_eval_long(const MarketDev &md, const BinDev &bin, int lds_mode,
+                            const EvalIO &io, int nwg, int total_wg, hipStream_t st);
+hipError_t launch_adj_long(const MarketDev &md, const BinDev &bin, int lds, const AdjIO &io,
+                           int nwg, hipStream_t st);
 // Reverse mode (pdhcg_adjoint.hip).
 hipError_t launch_adj_pstep(double *p, const double *c, const double *cprev, double sigma, int m,
                             hipStream_t st);

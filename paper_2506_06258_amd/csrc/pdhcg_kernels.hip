@@ -873,6 +873,7 @@ static hipError_t row_launch_t(const MarketDev &md, const BinDev &bin, const Row
 
 hipError_t launch_row_pass(const MarketDev &md, const BinDev &bin, int G, int E, int lds_mode,
                            const RowIO &io, int nwg, hipStream_t st) {
+  if (G == 0) return launch_row_long(md, bin, lds_mode, io, nwg, st);
   const int mode = io.search;
 #define PDHCG_ROW_LDS(g, e, md_)                                                  \
   switch (lds_mode) {                                                             \
@@ -903,6 +904,7 @@ static hipError_t eval_launch_t(const MarketDev &md, const BinDev &bin, const Ev
 
 hipError_t launch_eval_row(const MarketDev &md, const BinDev &bin, int G, int E, int lds_mode,
                            const EvalIO &io, int nwg, int total_wg, hipStream_t st) {
+  if (G == 0) return launch_eval_long(md, bin, lds_mode, io, nwg, total_wg, st);
 #define PDHCG_EVAL_DISPATCH(g, e)                                                    \
   if (G == g && E == e)                                                              \
     return lds_mode ? eval_launch_t<g, e, 1>(md, bin, io, nwg, total_wg, st)        \

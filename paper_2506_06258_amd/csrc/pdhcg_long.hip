@@ -1,0 +1,362 @@
+// Rows longer than the register-resident shapes hold (more than 512
+// entries): one wave per row, every pass over the row re-reads it (from
+// L2 while it stays there).  Same steps as the register-resident kernels:
+//   k_row_long   row prox (Sec. 2.2) with the active-set search, lagged fold
+//                of the kept allocation into its average (Alg. 2), |dx|^2
+//                and column sums;
+//   k_eval_long  the row part of the relative KKT error (Sec. 5 Criteria);
+//   k_adj_long   the reverse of the row prox (see pdhcg_adjoint.hip).
+// The LDS conventions (bit 1: float64 column partials, bit 2: float64
+// prices; workgroup partials written to their slot of the partial arrays)
+// are those of the register-resident kernels, so a market may mix both.
+#include "pdhcg_internal.h"
+#include "pdhcg_device.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+namespace pdhcg {
+
+template <int LDS_MODE>
+__global__ __launch_bounds__(kRowBlock) void k_row_long(MarketDev md, BinDev bin, RowIO io) {
+  extern __shared__ double lds_d[];
+  const int m = md.m;
+  const float *xin = io.xin;
+  const double *pp = io.p;
+  float *xout = io.xout;
+  float *xavg = io.xavg;
+  double tau = io.tau;
+  float wfold = io.wfold;
+  double *cglob = io.csum;
+  if (io.use_state) {
+    const DevState *S = md.S;
+    xin = pick3<float *>(md.X0, md.X1, md.X2, S->ix[0]);
+    xout = pick3<float *>(md.X0, md.X1, md.X2, S->ix[1]);
+    xavg = pick3<float *>(md.X0, md.X1, md.X2, S->ix[2]);
+    pp = pick3<double *>(md.P0, md.P1, md.P2, S->ip[1]);
+    cglob = pick3<double *>(md.C0, md.C1, md.C2, S->ic[2]);
+    tau = S->tau;
+    wfold = S->fold ? (float)(1.0 / (double)S->k_in) : 0.0f;
+  }
+  double *lp = lds_d;
+  double *lc = (LDS_MODE & 2) ? lds_d + m : lds_d;
+  if (LDS_MODE != 0) {
+    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+      if (LDS_MODE & 2) lp[j] = pp[j];
+      if (LDS_MODE & 1) lc[j] = 0.0;
+    }
+    __syncthreads();
+  }
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  constexpr int kWaves = kRowBlock / kWave;
+  const int wg = blockIdx.x;
+  const int row_lo = wg * bin.rows_per_wg;
+  const int row_hi = min(row_lo + bin.rows_per_wg, bin.nrows);
+  auto pget = [&](int c) { return (LDS_MODE & 2) ? lp[c] : pp[c]; };
+  double dx2 = 0.0;
+  uint32_t rmax = 0, rsum = 0, rcount = 0;
+  for (int slot = row_lo + wave; slot < row_hi; slot += kWaves) {
+    const int i = bin.rows ? bin.rows[slot] : slot;
+    const int beg = md.row_ptr[i];
+    const int d = md.row_ptr[i + 1] - beg;
+    const double tw = tau * (double)md.w[i];
+    int rounds = 0;
+    const double sfin = prox_row_long(beg, d, tau, tw, md.uh, md.col, xin, pget, io.max_rounds,
+                                      io.rtol, rounds);
+    const double tf = tw * fast_rcp(sfin);
+    for (int k = lane; k < d; k += kWave) {
+      const int q = beg + k;
+      const float xk = xin[q];
+      const int c = md.col[q];
+      const double a = fma(-tau, pget(c), (double)xk);
+      const float xn = (float)fmax(fma((double)md.uh[q], tf, a), 0.0);
+      xout[q] = xn;
+      if (wfold != 0.0f) xavg[q] = (wfold == 1.0f) ? xk : fmaf(xk - xavg[q], wfold, xavg[q]);
+      const double df = (double)xn - (double)xk;
+      dx2 = fma(df, df, dx2);
+      if (io.colsum) atomicAdd((LDS_MODE & 1) ? &lc[c] : &cglob[c], (double)xn);
+    }
+    if (lane == 0) {
+      if (io.s_out) io.s_out[i] = (float)sfin;
+      rmax = max(rmax, (uint32_t)rounds);
+      rsum += (uint32_t)rounds;
+      rcount += 1;
+    }
+  }
+  __shared__ double red[kWaves];
+  __shared__ uint32_t red_rmax, red_rsum, red_rcnt;
+  if (threadIdx.x == 0) {
+    red_rmax = 0;
+    red_rsum = 0;
+    red_rcnt = 0;
+  }
+  const double dsum = wave_sum_d(dx2);
+  __syncthreads();
+  if (lane == 0) {
+    red[wave] = dsum;
+    if (rcount) {
+      atomicMax(&red_rmax, rmax);
+      atomicAdd(&red_rsum, rsum);
+      atomicAdd(&red_rcnt, rcount);
+    }
+  }
+  __syncthreads();
+  const int slotw = bin.wg_offset + wg;
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < kWaves; ++q) t += red[q];
+    if (md.rowpart) md.rowpart[(size_t)slotw * kRowStats + 0] = t;
+    if (io.use_state) {
+      atomicMax(&md.S->rounds_max, red_rmax);
+      atomicAdd((unsigned long long *)&md.S->rounds_sum, (unsigned long long)red_rsum);
+      atomicAdd((unsigned long long *)&md.S->rows_searched, (unsigned long long)red_rcnt);
+    }
+  }
+  if ((LDS_MODE & 1) && io.colsum) {
+    double *dst = md.colpart + (size_t)slotw * m;
+    for (int j = threadIdx.x; j < m; j += blockDim.x) dst[j] = lc[j];
+  }
+}
+
+// Row part of the KKT error for long rows; same outputs and partial layout
+// as k_eval_row (statistics 0..9, column maxima, column sums).
+template <int LDS_MODE>
+__global__ __launch_bounds__(kRowBlock) void k_eval_long(MarketDev md, BinDev bin, EvalIO io,
+                                                         int total_wg) {
+  extern __shared__ double lds_e[];
+  const int m = md.m;
+  const bool has_avg = io.xa != nullptr;
+  const bool sum_avg = has_avg && !io.want_cc;
+  double *lcs = lds_e;
+  unsigned int *lMc = reinterpret_cast<unsigned int *>(lds_e + m);
+  unsigned int *lMa = lMc + m;
+  if (LDS_MODE == 1) {
+    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+      lcs[j] = 0.0;
+      lMc[j] = 0u;
+      lMa[j] = 0u;
+    }
+    __syncthreads();
+  }
+  const size_t TW = (LDS_MODE == 1) ? (size_t)total_wg * m : (size_t)m;
+  unsigned int *gMc = reinterpret_cast<unsigned int *>(io.evalpart);
+  unsigned int *gMa = reinterpret_cast<unsigned int *>(io.evalpart + TW);
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  constexpr int kWaves = kRowBlock / kWave;
+  const int wg = blockIdx.x;
+  const int row_lo = wg * bin.rows_per_wg;
+  const int row_hi = min(row_lo + bin.rows_per_wg, bin.nrows);
+  const float wf = io.wfold;
+  double st[10];
+#pragma unroll
+  for (int q = 0; q < 10; ++q) st[q] = 0.0;
+  for (int slot = row_lo + wave; slot < row_hi; slot += kWaves) {
+    const int i = bin.rows ? bin.rows[slot] : slot;
+    const int beg = md.row_ptr[i];
+    const int d = md.row_ptr[i + 1] - beg;
+    const double wi = (double)md.w[i];
+    // pass 1: t = u^T x of both points (folding the average first)
+    double tc = 0.0, ta = 0.0;
+    for (int k = lane; k < d; k += kWave) {
+      const int q = beg + k;
+      const float u = md.uh[q];
+      const float x = io.xc[q];
+      tc = fma((double)u, (double)x, tc);
+      if (has_avg) {
+        float y = io.xa[q];
+        if (wf != 0.0f) {
+          y = (wf == 1.0f) ? x : fmaf(x - y, wf, y);
+          io.xa[q] = y;
+        }
+        ta = fma((double)u, (double)y, ta);
+      }
+      if (io.xanc) {
+        const float z = io.xanc[q];
+        st[8] += (double)(x - z) * (double)(x - z);
+      }
+    }
+    tc = wave_sum_d(tc);
+    ta = wave_sum_d(ta);
+    const double yc = wi / tc;
+    const double ya = has_avg ? wi / ta : 0.0;
+    if (lane == 0) {
+      if (io.tc) io.tc[i] = (float)(tc * (double)io.rowscale[i]);
+      if (io.ta && has_avg) io.ta[i] = (float)(ta * (double)io.rowscale[i]);
+      st[0] = fmax(st[0], yc);
+      st[4] = fmax(st[4], ya);
+    }
+    // pass 2: residual terms, column maxima and sums (the average is folded)
+    for (int k = lane; k < d; k += kWave) {
+      const int q = beg + k;
+      const int c = md.col[q];
+      const double u = (double)md.uh[q];
+      const float xc = io.xc[q];
+      const double p = io.pc[c];
+      const double vc = u * yc;
+      const double rc = p - vc;
+      if (rc > 0.0) {
+        st[2] = fmax(st[2], rc);
+        st[1] = fmax(st[1], (double)xc * rc);
+      }
+      st[3] = fmax(st[3], (double)xc);
+      const unsigned int bc = __float_as_uint((float)vc);
+      if (LDS_MODE == 1) atomicMax(&lMc[c], bc);
+      else atomicMax(&gMc[c], bc);
+      float xa = 0.0f;
+      if (has_avg) {
+        xa = io.xa[q];
+        double pa = io.pa[c];
+        if (wf != 0.0f) pa = (wf == 1.0f) ? p : pa + (p - pa) * (double)wf;
+        const double va = u * ya;
+        const double ra = pa - va;
+        if (ra > 0.0) {
+          st[6] = fmax(st[6], ra);
+          st[5] = fmax(st[5], (double)xa * ra);
+        }
+        st[7] = fmax(st[7], (double)xa);
+        const unsigned int ba = __float_as_uint((float)va);
+        if (LDS_MODE == 1) atomicMax(&lMa[c], ba);
+        else atomicMax(&gMa[c], ba);
+        if (io.xanc) {
+          const float z = io.xanc[q];
+          st[9] += (double)(xa - z) * (double)(xa - z);
+        }
+      }
+      if (sum_avg || io.want_cc) {
+        const double add = io.want_cc ? xc : xa;
+        atomicAdd((LDS_MODE == 1) ? &lcs[c] : &io.cacc[c], add);
+      }
+    }
+  }
+  __shared__ double red[kWaves][10];
+#pragma unroll
+  for (int q = 0; q < 10; ++q) {
+    const double v = (q >= 8) ? wave_sum_d(st[q]) : wave_max_d(st[q]);
+    if (lane == 0) red[wave][q] = v;
+  }
+  __syncthreads();
+  const int slotw = bin.wg_offset + wg;
+  if (threadIdx.x < 10) {
+    const int q = threadIdx.x;
+    double v = red[0][q];
+    for (int w = 1; w < kWaves; ++w) v = (q >= 8) ? v + red[w][q] : fmax(v, red[w][q]);
+    md.rowpart[(size_t)slotw * kEvalRowStats + q] = v;
+  }
+  if (LDS_MODE == 1) {
+    unsigned int *dMc = gMc + (size_t)slotw * m;
+    unsigned int *dMa = gMa + (size_t)slotw * m;
+    double *dcs = io.evalcs + (size_t)slotw * m;
+    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+      dMc[j] = lMc[j];
+      dMa[j] = lMa[j];
+      dcs[j] = lcs[j];
+    }
+  }
+}
+
+// Reverse of the row prox for long rows (same as k_adj_row).
+template <int LDS_MODE>
+__global__ __launch_bounds__(kRowBlock) void k_adj_long(MarketDev md, BinDev bin, AdjIO io) {
+  extern __shared__ double lcs[];
+  const int m = md.m;
+  if (LDS_MODE) {
+    for (int j = threadIdx.x; j < m; j += blockDim.x) lcs[j] = 0.0;
+    __syncthreads();
+  }
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wave = threadIdx.x / kWave;
+  constexpr int kWaves = kRowBlock / kWave;
+  const int wg = blockIdx.x;
+  const int row_lo = wg * bin.rows_per_wg;
+  const int row_hi = min(row_lo + bin.rows_per_wg, bin.nrows);
+  const double tau = io.tau;
+  for (int slot = row_lo + wave; slot < row_hi; slot += kWaves) {
+    const int i = bin.rows ? bin.rows[slot] : slot;
+    const int beg = md.row_ptr[i];
+    const int d = md.row_ptr[i + 1] - beg;
+    const double tw = tau * (double)md.w[i];
+    double s = 0.0, Q = 0.0, Gu = 0.0;
+    for (int k = lane; k < d; k += kWave) {
+      const int q = beg + k;
+      const float xn = io.xn[q];
+      if (xn > 0.0f) {
+        const double u = (double)md.uh[q];
+        const double g = (double)io.r_in[q] + io.b[md.col[q]];
+        s = fma(u, (double)xn, s);
+        Q = fma(u, u, Q);
+        Gu = fma(u, g, Gu);
+      }
+    }
+    s = wave_sum_d(s);
+    Q = wave_sum_d(Q);
+    Gu = wave_sum_d(Gu);
+    const bool live = s > 0.0;
+    const double is = live ? fast_rcp(s) : 0.0;
+    const double tws2 = tw * is * is;
+    const double h = live ? tws2 * Gu / (1.0 + tws2 * Q) : 0.0;
+    double ru = 0.0;
+    for (int k = lane; k < d; k += kWave) {
+      const int q = beg + k;
+      const float xn = io.xn[q];
+      const int c = md.col[q];
+      const double u = (double)md.uh[q];
+      const bool act = live && xn > 0.0f;
+      const double rr = act ? (double)io.r_in[q] + io.b[c] - h * u : 0.0;
+      io.r_out[q] = (float)rr;
+      if (act) io.duh[q] += (float)(rr * tw * is - h * (double)xn);
+      ru = fma(rr, u, ru);
+      if (LDS_MODE)
+        atomicAdd(&lcs[c], rr);
+      else
+        atomicAdd(&io.csum[c], rr);
+    }
+    ru = wave_sum_d(ru);
+    if (live && lane == 0) io.dw[i] += (float)(tau * is * ru);
+  }
+  if (LDS_MODE) {
+    __syncthreads();
+    double *dst = md.colpart + (size_t)(bin.wg_offset + wg) * m;
+    for (int j = threadIdx.x; j < m; j += blockDim.x) dst[j] = lcs[j];
+  }
+}
+
+// ------------------------------------------------------------- launchers --
+
+hipError_t launch_row_long(const MarketDev &md, const BinDev &bin, int lds_mode, const RowIO &io,
+                           int nwg, hipStream_t st) {
+  const size_t shm = (size_t)md.m * (((lds_mode & 2) ? sizeof(double) : 0) +
+                                     ((lds_mode & 1) ? sizeof(double) : 0));
+  switch (lds_mode) {
+    case 0: hipLaunchKernelGGL(k_row_long<0>, dim3(nwg), dim3(kRowBlock), shm, st, md, bin, io); break;
+    case 1: hipLaunchKernelGGL(k_row_long<1>, dim3(nwg), dim3(kRowBlock), shm, st, md, bin, io); break;
+    case 3: hipLaunchKernelGGL(k_row_long<3>, dim3(nwg), dim3(kRowBlock), shm, st, md, bin, io); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_long(const MarketDev &md, const BinDev &bin, int lds_mode,
+                            const EvalIO &io, int nwg, int total_wg, hipStream_t st) {
+  const size_t shm = lds_mode ? (size_t)md.m * (sizeof(double) + 2 * sizeof(uint32_t)) : 0;
+  if (lds_mode)
+    hipLaunchKernelGGL(k_eval_long<1>, dim3(nwg), dim3(kRowBlock), shm, st, md, bin, io, total_wg);
+  else
+    hipLaunchKernelGGL(k_eval_long<0>, dim3(nwg), dim3(kRowBlock), shm, st, md, bin, io, total_wg);
+  return hipGetLastError();
+}
+
+hipError_t launch_adj_long(const MarketDev &md, const BinDev &bin, int lds, const AdjIO &io,
+                           int nwg, hipStream_t st) {
+  const size_t shm = lds ? (size_t)md.m * sizeof(double) : 0;
+  if (lds)
+    hipLaunchKernelGGL(k_adj_long<1>, dim3(nwg), dim3(kRowBlock), shm, st, md, bin, io);
+  else
+    hipLaunchKernelGGL(k_adj_long<0>, dim3(nwg), dim3(kRowBlock), shm, st, md, bin, io);
+  return hipGetLastError();
+}
+
+}  // namespace pdhcg

@@ -154,6 +154,105 @@ def fixed_degree_market(n: int, m: int, d: int, seed: int,
     return Market(n, m, row_ptr, col, u, w, name or f"fixdeg-{n}x{m}-d{d}-s{seed}")
 
 
+def _zipf_rows(args):
+    """Goods of one block of rows of zipf_market (see there)."""
+    seed, block, d, m, ranking = args
+    rng = np.random.default_rng([seed, 7, block])
+    n = d.size
+    logm = np.log(m + 1.0)
+
+    def draw(cnt):
+        # inverse CDF of the density 1/x on [1, m + 1): rank = floor(x) - 1
+        x = np.exp(rng.uniform(0.0, logm, size=cnt))
+        return ranking[np.minimum(np.floor(x).astype(np.int64) - 1, m - 1)]
+
+    rows = np.repeat(np.arange(n, dtype=np.int64), d)
+    keys = np.unique(rows * m + draw(rows.size))
+    for rnd in range(65):
+        short = d - np.bincount(keys // m, minlength=n)
+        if not short.any():
+            break
+        r2 = np.repeat(np.arange(n, dtype=np.int64), short)
+        g2 = draw(r2.size) if rnd < 64 else rng.integers(0, m, size=r2.size)
+        k2 = np.unique(r2 * m + g2)
+        pos = np.minimum(np.searchsorted(keys, k2), keys.size - 1)
+        k2 = k2[keys[pos] != k2]
+        # at most the shortfall of each row, chosen in random order
+        pri = rng.random(k2.size)
+        order = np.lexsort((pri, k2 // m))
+        k2 = k2[order]
+        r = k2 // m
+        first = np.searchsorted(r, np.arange(n))
+        k2 = k2[(np.arange(k2.size) - first[r]) < short[r]]
+        keys = np.union1d(keys, k2)
+    u = np.exp(rng.standard_normal(keys.size))
+    return keys // m, keys % m, u
+
+
+def zipf_market(n: int, m: int, seed: int, a: float = 1.5, dmin: int = 5, dmax: int = 20000,
+                dtype=np.float32, name: str = "", workers: int = 0,
+                block_rows: int = 1 << 16) -> Market:
+    """Skewed buyer degrees and popularity-skewed goods.
+
+    Degrees d = dmin - 1 + K with K ~ Zipf(a), redrawn while d > dmax (the
+    reading of "Zipf(1.5) truncated to [5, 20000]" that gives a mean degree
+    of about 112).  Each buyer's d distinct goods are drawn with probability
+    proportional to 1/(rank + 1) over a random ranking of the goods: draws
+    with replacement, repeated goods dropped and the shortfall drawn again
+    (at most 64 rounds, then uniformly random goods fill what is left).
+    Goods that no buyer drew receive one random buyer (Assumption 1).
+    u ~ LogNormal(0, 1), w ~ U(0.5, 1.5).  Blocks of ``block_rows`` rows
+    have generators of their own, so ``workers`` (processes, 0 = serial)
+    does not change the result."""
+    rng = np.random.default_rng(seed)
+    d = np.empty(n, np.int64)
+    todo = np.arange(n)
+    while todo.size:
+        k = rng.zipf(a, size=todo.size)
+        ok = k <= dmax - dmin + 1
+        d[todo[ok]] = dmin - 1 + k[ok]
+        todo = todo[~ok]
+    d = np.minimum(d, m)
+    ranking = rng.permutation(m).astype(np.int64)  # rank -> good
+    w = rng.uniform(0.5, 1.5, size=n).astype(dtype)
+    jobs = [(seed, b, d[b * block_rows:(b + 1) * block_rows], m, ranking)
+            for b in range((n + block_rows - 1) // block_rows)]
+    if workers > 1 and len(jobs) > 1:
+        from multiprocessing import get_context
+        with get_context("fork").Pool(workers) as pool:
+            parts = pool.map(_zipf_rows, jobs)
+    else:
+        parts = [_zipf_rows(j) for j in jobs]
+    counts = np.zeros(n, np.int64)
+    for b, (r, _, _) in enumerate(parts):
+        counts[b * block_rows:b * block_rows + jobs[b][2].size] = np.bincount(r, minlength=jobs[b][2].size)
+    col = np.concatenate([c for _, c, _ in parts]).astype(np.int32)
+    u = np.concatenate([x for _, _, x in parts]).astype(dtype)
+    row_ptr = np.zeros(n + 1, np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    missing = np.nonzero(np.bincount(col, minlength=m) == 0)[0]
+    if missing.size:
+        # one random buyer for every good nobody drew, inserted in column order
+        rows = np.repeat(np.arange(n, dtype=np.int64), counts)
+        buyers = rng.integers(0, n, size=missing.size)
+        keys = np.concatenate([rows * m + col, buyers * m + missing])
+        vals = np.concatenate([u, np.exp(rng.standard_normal(missing.size)).astype(dtype)])
+        keys, idx = np.unique(keys, return_index=True)
+        u = vals[idx]
+        col = (keys % m).astype(np.int32)
+        np.cumsum(np.bincount(keys // m, minlength=n), out=row_ptr[1:])
+    return Market(n, m, row_ptr.astype(np.int32), col, u, w,
+                  name or f"zipf-{n}x{m}-a{a}-d{dmin}..{dmax}-s{seed}")
+
+
+def fisher_skewed(seed: int = 2, n: int = 4_000_000, m: int = 200_000,
+                  workers: int = 8) -> Market:
+    """The skewed workload: n=4e6 buyers, m=2e5 goods, Zipf(1.5) degrees in
+    [5, 20000], 1/rank popularity of goods (about 4.5e8 edges)."""
+    return zipf_market(n, m, seed, 1.5, 5, 20000, np.float32,
+                       name=f"fisher-skewed-{n}x{m}-s{seed}", workers=workers)
+
+
 # Named workloads.  "small" is the case the oracle finishes in seconds; the
 # "1e8" market is the headline throughput workload.
 def fisher_small(seed: int = 0) -> Market:

@@ -228,6 +228,15 @@ int32_t pdhcg_market_bins(pdhcg_market market, int32_t cap,
                           int32_t *lanes_per_row, int32_t *entries_per_lane,
                           int32_t *rows);
 
+/* Number of goods whose prices and column partial sums the row kernels keep
+ * in LDS: m when all fit, 0 when none is kept there, and in between when the
+ * market's goods were relabelled by degree (most bought first) at creation
+ * and only the first ones fit; the others are read from global memory and
+ * summed with device atomics.  The relabelling is internal: every entry
+ * point takes and returns goods in the caller's order.  Negative status for
+ * a null market. */
+int32_t pdhcg_market_lds_goods(pdhcg_market market);
+
 void pdhcg_market_destroy(pdhcg_market market);
 
 /* ---- Batched markets -------------------------------------------------- */

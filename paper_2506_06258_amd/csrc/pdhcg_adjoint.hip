@@ -38,26 +38,31 @@ __global__ void k_adj_pstep(double *p, const double *c, const double *cprev, dou
   if (j < m) p[j] += sigma * (2.0 * c[j] - cprev[j] - 1.0);
 }
 
-// Per-workgroup column partials [rows][m] summed in kColChunks chunks of
-// rows, each chunk in a fixed order: chunk[q][j].
-__global__ __launch_bounds__(kColBlock) void k_sum_partials(const double *part, int rows, int m,
-                                                            double *chunk) {
+// Per-workgroup column partials [rows][hot] summed in kColChunks chunks of
+// rows, each chunk in a fixed order: chunk[q][j] (j < hot, row stride m).
+__global__ __launch_bounds__(kColBlock) void k_sum_partials(const double *part, int rows, int hot,
+                                                            int m, double *chunk) {
   const int j = blockIdx.x * kColBlock + threadIdx.x;
   const int q = blockIdx.y;
-  if (j >= m) return;
+  if (j >= hot) return;
   const int per = (rows + kColChunks - 1) / kColChunks;
   const int b0 = q * per, b1 = min(rows, b0 + per);
   double c = 0.0;
-  for (int b = b0; b < b1; ++b) c += part[(size_t)b * m + j];
+  for (int b = b0; b < b1; ++b) c += part[(size_t)b * hot + j];
   chunk[(size_t)q * m + j] = c;
 }
 
-// out[j] = sum_q chunk[q][j] in order.
-__global__ void k_finish_colsum(const double *chunk, int m, double *out) {
+// out[j] = sum_q chunk[q][j] in order for j < hot; out[j] = cold[j] above.
+__global__ void k_finish_colsum(const double *chunk, const double *cold, int hot, int m,
+                                double *out) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= m) return;
   double c = 0.0;
-  for (int q = 0; q < kColChunks; ++q) c += chunk[(size_t)q * m + j];
+  if (j < hot) {
+    for (int q = 0; q < kColChunks; ++q) c += chunk[(size_t)q * m + j];
+  } else {
+    c = cold[j];
+  }
   out[j] = c;
 }
 
@@ -84,9 +89,9 @@ __global__ void k_zero_f32(float *a, int64_t len) {
 template <int G, int E, int LDS_MODE>
 __global__ __launch_bounds__(kRowBlock) void k_adj_row(MarketDev md, BinDev bin, AdjIO io) {
   extern __shared__ double lcs[];
-  const int m = md.m;
+  const int hot = LDS_MODE ? md.hot : 0;  // goods [0, hot) have LDS partials
   if (LDS_MODE) {
-    for (int j = threadIdx.x; j < m; j += blockDim.x) lcs[j] = 0.0;
+    for (int j = threadIdx.x; j < hot; j += blockDim.x) lcs[j] = 0.0;
     __syncthreads();
   }
   const int lane = threadIdx.x & (kWave - 1);
@@ -144,10 +149,7 @@ __global__ __launch_bounds__(kRowBlock) void k_adj_row(MarketDev md, BinDev bin,
         if (live && act[e])
           io.duh[k] += (float)(rr * tw * is - h * (double)xn[e]);
         ru = fma(rr, (double)uh[e], ru);
-        if (LDS_MODE)
-          atomicAdd(&lcs[cj[e]], rr);
-        else
-          atomicAdd(&io.csum[cj[e]], rr);
+        atomicAdd(cj[e] < hot ? &lcs[cj[e]] : &io.csum[cj[e]], rr);
       }
     }
     ru = seg_sum_d<G>(ru);
@@ -155,23 +157,23 @@ __global__ __launch_bounds__(kRowBlock) void k_adj_row(MarketDev md, BinDev bin,
   }
   if (LDS_MODE) {
     __syncthreads();
-    double *dst = md.colpart + (size_t)(bin.wg_offset + wg) * m;
-    for (int j = threadIdx.x; j < m; j += blockDim.x) dst[j] = lcs[j];
+    double *dst = md.colpart + (size_t)(bin.wg_offset + wg) * hot;
+    for (int j = threadIdx.x; j < hot; j += blockDim.x) dst[j] = lcs[j];
   }
 }
 
 // Column part of the reverse step: Pt = P - tau colsum(r), B = 2 sigma Pt +
-// Cn, Cn = -sigma Pt, P = Pt.  colsum(r) from chunk sums (chunked != 0) or
-// from the atomic accumulator.
-__global__ void k_adj_col(const double *csrc, int chunked, double *P, double *B, double *Cn,
-                          double tau, double sigma, int m) {
+// Cn, Cn = -sigma Pt, P = Pt.  colsum(r) from chunk sums for goods below hot
+// and from the atomic accumulator cold above.
+__global__ void k_adj_col(const double *chunk, const double *cold, int hot, double *P, double *B,
+                          double *Cn, double tau, double sigma, int m) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= m) return;
   double cr = 0.0;
-  if (chunked) {
-    for (int q = 0; q < kColChunks; ++q) cr += csrc[(size_t)q * m + j];
+  if (j < hot) {
+    for (int q = 0; q < kColChunks; ++q) cr += chunk[(size_t)q * m + j];
   } else {
-    cr = csrc[j];
+    cr = cold[j];
   }
   const double pt = P[j] - tau * cr;
   B[j] = 2.0 * sigma * pt + Cn[j];
@@ -211,15 +213,18 @@ hipError_t launch_adj_pstep(double *p, const double *c, const double *cprev, dou
   return hipGetLastError();
 }
 
-hipError_t launch_sum_partials(const double *part, int rows, int m, double *chunk,
+hipError_t launch_sum_partials(const double *part, int rows, int hot, int m, double *chunk,
                                hipStream_t st) {
-  hipLaunchKernelGGL(k_sum_partials, dim3(grid_1d(m, kColBlock), kColChunks), dim3(kColBlock), 0,
-                     st, part, rows, m, chunk);
+  if (hot <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sum_partials, dim3(grid_1d(hot, kColBlock), kColChunks), dim3(kColBlock),
+                     0, st, part, rows, hot, m, chunk);
   return hipGetLastError();
 }
 
-hipError_t launch_finish_colsum(const double *chunk, int m, double *out, hipStream_t st) {
-  hipLaunchKernelGGL(k_finish_colsum, dim3(grid_1d(m, 256)), dim3(256), 0, st, chunk, m, out);
+hipError_t launch_finish_colsum(const double *chunk, const double *cold, int hot, int m,
+                                double *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_finish_colsum, dim3(grid_1d(m, 256)), dim3(256), 0, st, chunk, cold, hot, m,
+                     out);
   return hipGetLastError();
 }
 
@@ -243,7 +248,7 @@ hipError_t launch_zero_f32(float *a, int64_t len, hipStream_t st) {
 template <int G, int E, int LDSM>
 static hipError_t adj_launch_t(const MarketDev &md, const BinDev &bin, const AdjIO &io, int nwg,
                                hipStream_t st) {
-  const size_t shm = LDSM ? (size_t)md.m * sizeof(double) : 0;
+  const size_t shm = LDSM ? (size_t)md.hot * sizeof(double) : 0;
   hipLaunchKernelGGL((k_adj_row<G, E, LDSM>), dim3(nwg), dim3(kRowBlock), shm, st, md, bin, io);
   return hipGetLastError();
 }
@@ -260,10 +265,10 @@ hipError_t launch_adj_row(const MarketDev &md, const BinDev &bin, int G, int E, 
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_adj_col(const double *csrc, int chunked, double *P, double *B, double *Cn,
-                          double tau, double sigma, int m, hipStream_t st) {
-  hipLaunchKernelGGL(k_adj_col, dim3(grid_1d(m, 256)), dim3(256), 0, st, csrc, chunked, P, B, Cn,
-                     tau, sigma, m);
+hipError_t launch_adj_col(const double *chunk, const double *cold, int hot, double *P, double *B,
+                          double *Cn, double tau, double sigma, int m, hipStream_t st) {
+  hipLaunchKernelGGL(k_adj_col, dim3(grid_1d(m, 256)), dim3(256), 0, st, chunk, cold, hot, P, B,
+                     Cn, tau, sigma, m);
   return hipGetLastError();
 }
 

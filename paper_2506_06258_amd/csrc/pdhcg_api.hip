@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <numeric>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -96,12 +97,21 @@ struct pdhcg_market_s {
   int32_t total_wg = 0;
   int lds_row = 0, lds_eval = 0;
   int col_blocks = 0;
+  // Goods relabelled by degree (most bought first) when their LDS data does
+  // not fit: perm[internal] = caller's id, inv[caller's id] = internal (both
+  // device, null without relabelling); goods [0, hot) use LDS.
+  int32_t hot = 0;
+  int32_t *perm = nullptr, *inv = nullptr;
+  uint32_t *gmax = nullptr;  // [2][m] KKT column maxima of the goods from hot on
+  double *gsum = nullptr;    // [m] KKT column sums of the goods from hot on
 
   MarketDev dev() const {
     MarketDev d;
     d.n = n;
     d.m = m;
     d.nnz = nnz;
+    d.hot = hot;
+    d.pad_hot = 0;
     d.row_ptr = row_ptr;
     d.col = col;
     d.uh = uh;
@@ -227,7 +237,7 @@ void pdhcg_market_destroy(pdhcg_market mk) {
   f(mk->XA); f(mk->PA); f(mk->Pk); f(mk->T[0]); f(mk->T[1]);
   f(mk->colpart); f(mk->evalpart); f(mk->evalcs); f(mk->evalchunk);
   f(mk->rowpart); f(mk->colblk); f(mk->cacc); f(mk->S);
-  f(mk->colchunk); f(mk->tile_ticket);
+  f(mk->colchunk); f(mk->tile_ticket); f(mk->perm); f(mk->inv); f(mk->gmax); f(mk->gsum);
   for (auto &b : mk->bins) {
     f(b.d_rows);
     f(b.d_rbeg);
@@ -422,24 +432,57 @@ extern "C" int32_t pdhcg_market_create(int32_t n, int32_t m, int64_t nnz, const 
   // L1 on most lanes and hold its miss slots, which starves the stream of
   // row data (1e8-edge market: 0.90 ms per pass with global gathers, 0.80
   // ms with prices in LDS).  PDHCG_P_LDS=0 keeps the prices in global memory.
+  //
+  // When 16 bytes per good do not fit, the goods are relabelled by degree
+  // (most bought first) and only the first `hot` of them keep their prices
+  // and partials in LDS (LDS mode 7); the others are gathered from global
+  // memory (the price vector stays in L2) and summed with device atomics.
+  // On popularity-skewed markets the hot goods carry most of the entries.
+  // PDHCG_HOT=k forces the relabelled mode with k LDS goods.
+  const size_t per_good = 2 * sizeof(double);
   mk->lds_row = 0;
+  mk->hot = m;
   if ((size_t)m * sizeof(double) + static_lds <= lds_cap) mk->lds_row = 1;
-  if ((size_t)m * 2 * sizeof(double) + static_lds <= lds_cap) mk->lds_row = 3;
+  if ((size_t)m * per_good + static_lds <= lds_cap) mk->lds_row = 3;
+  int force_hot = -1;
+  if (const char *e = std::getenv("PDHCG_HOT")) force_hot = std::max(0, std::atoi(e));
+  if ((mk->lds_row != 3 || force_hot >= 0) && m > 1) {
+    const int fit = (int)(((lds_cap - static_lds) / per_good - 1) / 64 * 64);
+    mk->hot = std::min(m - 1, force_hot >= 0 ? std::min(force_hot, fit) : fit);
+    mk->hot = std::max(mk->hot, 1);
+    mk->lds_row = 7;
+  }
   if (const char *e = std::getenv("PDHCG_P_LDS")) {
     if (!std::atoi(e) && mk->lds_row == 3) mk->lds_row = 1;
   }
-  mk->lds_eval =
-      ((size_t)m * (sizeof(double) + 2 * sizeof(uint32_t)) + static_lds <= lds_cap) ? 1 : 0;
+  mk->lds_eval = ((size_t)mk->hot * (sizeof(double) + 2 * sizeof(uint32_t)) + static_lds <=
+                  lds_cap) ? 1 : 0;
   if (const char *e = std::getenv("PDHCG_NO_LDS")) {
     if (std::atoi(e)) {
       mk->lds_row = 0;
       mk->lds_eval = 0;
+      mk->hot = m;
     }
+  }
+  std::vector<int32_t> h_perm, h_inv;
+  if (mk->lds_row == 7) {
+    h_perm.resize((size_t)m);
+    std::iota(h_perm.begin(), h_perm.end(), 0);
+    std::stable_sort(h_perm.begin(), h_perm.end(), [&](int32_t a, int32_t b) {
+      return mk->h_deg_col[(size_t)a] > mk->h_deg_col[(size_t)b];
+    });
+    h_inv.resize((size_t)m);
+    for (int32_t j = 0; j < m; ++j) h_inv[(size_t)h_perm[(size_t)j]] = j;
+    for (int64_t k = 0; k < nnz; ++k) h_col[(size_t)k] = h_inv[(size_t)h_col[(size_t)k]];
+    std::vector<int32_t> deg((size_t)m);
+    for (int32_t j = 0; j < m; ++j) deg[(size_t)j] = mk->h_deg_col[(size_t)h_perm[(size_t)j]];
+    mk->h_deg_col.swap(deg);
   }
   mk->col_blocks = (m + kColBlock - 1) / kColBlock;
   {
-    const size_t row_lds = (size_t)m * (((mk->lds_row & 2) ? sizeof(double) : 0) +
-                                        ((mk->lds_row & 1) ? sizeof(double) : 0)) + static_lds;
+    const size_t lh = (mk->lds_row == 7) ? (size_t)mk->hot + 1 : (size_t)m;
+    const size_t row_lds = lh * (((mk->lds_row & 2) ? sizeof(double) : 0) +
+                                 ((mk->lds_row & 1) ? sizeof(double) : 0)) + static_lds;
     rc = build_bins(mk, h_rp, (int)(lds_cu / row_lds));
     if (rc != PDHCG_OK) return cleanup(rc);
   }
@@ -460,9 +503,16 @@ extern "C" int32_t pdhcg_market_create(int32_t n, int32_t m, int64_t nnz, const 
   MK_HIPC(dalloc(&mk->Pk, (size_t)m));
   MK_HIPC(dalloc(&mk->T[0], (size_t)n));
   MK_HIPC(dalloc(&mk->T[1], (size_t)n));
-  MK_HIPC(dalloc(&mk->colpart, (mk->lds_row & 1) ? (size_t)mk->total_wg * m : 1));
-  MK_HIPC(dalloc(&mk->evalpart, mk->lds_eval ? (size_t)2 * mk->total_wg * m : (size_t)2 * m));
-  MK_HIPC(dalloc(&mk->evalcs, mk->lds_eval ? (size_t)mk->total_wg * m : (size_t)1));
+  const size_t hot = (size_t)std::max(mk->hot, 1);
+  MK_HIPC(dalloc(&mk->colpart, (mk->lds_row & 1) ? (size_t)mk->total_wg * hot : 1));
+  MK_HIPC(dalloc(&mk->evalpart, mk->lds_eval ? (size_t)2 * mk->total_wg * hot : (size_t)2 * m));
+  MK_HIPC(dalloc(&mk->evalcs, mk->lds_eval ? (size_t)mk->total_wg * hot : (size_t)1));
+  MK_HIPC(dalloc(&mk->gmax, mk->lds_eval ? (size_t)2 * m : (size_t)1));
+  MK_HIPC(dalloc(&mk->gsum, mk->lds_eval ? (size_t)m : (size_t)1));
+  if (!h_perm.empty()) {
+    MK_HIPC(dalloc(&mk->perm, (size_t)m));
+    MK_HIPC(dalloc(&mk->inv, (size_t)m));
+  }
   MK_HIPC(dalloc(&mk->evalchunk, mk->lds_eval ? (size_t)2 * kColChunks * m : (size_t)1));
   MK_HIPC(dalloc(&mk->cacc, (size_t)kColChunks * m));  // chunk sums in LDS mode
   MK_HIPC(dalloc(&mk->rowpart, (size_t)mk->total_wg * std::max(kRowStats, kEvalRowStats)));
@@ -475,7 +525,13 @@ extern "C" int32_t pdhcg_market_create(int32_t n, int32_t m, int64_t nnz, const 
   std::memset(mk->hS, 0, sizeof(DevState));
 
   MK_HIPC(hipMemcpyAsync(mk->row_ptr, row_ptr, ((size_t)n + 1) * 4, hipMemcpyDeviceToDevice, st));
-  MK_HIPC(hipMemcpyAsync(mk->col, col, (size_t)nnz * 4, hipMemcpyDeviceToDevice, st));
+  if (h_perm.empty()) {
+    MK_HIPC(hipMemcpyAsync(mk->col, col, (size_t)nnz * 4, hipMemcpyDeviceToDevice, st));
+  } else {
+    MK_HIPC(hipMemcpyAsync(mk->col, h_col.data(), (size_t)nnz * 4, hipMemcpyHostToDevice, st));
+    MK_HIPC(hipMemcpyAsync(mk->perm, h_perm.data(), (size_t)m * 4, hipMemcpyHostToDevice, st));
+    MK_HIPC(hipMemcpyAsync(mk->inv, h_inv.data(), (size_t)m * 4, hipMemcpyHostToDevice, st));
+  }
   MK_HIPC(hipMemcpyAsync(mk->w, w, (size_t)n * 4, hipMemcpyDeviceToDevice, st));
   MK_HIPC(hipMemcpyAsync(mk->deg, mk->h_deg_col.data(), (size_t)m * 4, hipMemcpyHostToDevice, st));
   MK_HIPC(launch_normalize(mk->row_ptr, u, mk->uh, mk->rowmax, n, st));
@@ -501,6 +557,11 @@ extern "C" int32_t pdhcg_set_budgets(pdhcg_market mk, const float *w) {
   HIPC(hipMemcpyAsync(mk->w, w, (size_t)mk->n * 4, hipMemcpyDeviceToDevice, mk->stream));
   HIPC(hipStreamSynchronize(mk->stream));
   return PDHCG_OK;
+}
+
+extern "C" int32_t pdhcg_market_lds_goods(pdhcg_market mk) {
+  if (!mk) return fail(PDHCG_ERR_ARG, "null market");
+  return (mk->lds_row & 1) ? mk->hot : 0;
 }
 
 extern "C" int32_t pdhcg_market_bins(pdhcg_market mk, int32_t cap, int32_t *lanes,
@@ -551,7 +612,8 @@ RowIO row_io_state(const pdhcg_params *p) {
 int32_t enqueue_step(pdhcg_market mk, const RowIO &io, hipEvent_t ev0 = nullptr,
                      hipEvent_t ev1 = nullptr) {
   const MarketDev md = mk->dev();
-  HIPC(launch_pstep(md, (mk->lds_row & 1) ? 0 : 1, mk->stream));
+  // c_try is zeroed when some of its goods are summed by device atomics
+  HIPC(launch_pstep(md, (mk->lds_row == 1 || mk->lds_row == 3) ? 0 : 1, mk->stream));
   if (ev0) HIPC(hipEventRecord(ev0, mk->stream));
   for (const Bin &b : mk->bins)
     HIPC(launch_row_pass(md, mk->bindev(b), b.G, b.E, mk->lds_row, io, b.nwg, mk->stream));
@@ -579,6 +641,12 @@ int32_t enqueue_eval(pdhcg_market mk, EvalIO io) {
   }
   io.evalcs = mk->evalcs;
   io.evalchunk = mk->evalchunk;
+  io.gmax = mk->gmax;
+  io.gsum = mk->gsum;
+  if (mk->lds_eval && mk->hot < mk->m) {
+    HIPC(launch_zero_f32(reinterpret_cast<float *>(mk->gmax), (int64_t)2 * mk->m, mk->stream));
+    HIPC(launch_zero_f64(mk->gsum, mk->m, mk->stream));
+  }
   for (const Bin &b : mk->bins)
     HIPC(launch_eval_row(md, mk->bindev(b), b.G, b.E, mk->lds_eval, io, b.nwg, mk->total_wg,
                          mk->stream));
@@ -604,7 +672,7 @@ double kkt_max(const double *k) { return std::max(k[0], std::max(k[1], k[2])); }
 
 extern "C" int32_t pdhcg_kkt(pdhcg_market mk, const float *p, const float *x, pdhcg_info *info) {
   if (!mk || !p || !x) return fail(PDHCG_ERR_ARG, "null argument");
-  HIPC(launch_f32_to_f64(p, mk->Pk, mk->m, mk->stream));
+  HIPC(launch_gather_f32_to_f64(p, mk->perm, mk->Pk, mk->m, mk->stream));
   EvalIO io;
   std::memset(&io, 0, sizeof(io));
   io.xc = x;
@@ -638,7 +706,7 @@ extern "C" int32_t pdhcg_row_prox(pdhcg_market mk, const float *x_in, const floa
   RowIO io = row_io_state(prm);
   io.use_state = 0;
   io.colsum = 0;
-  HIPC(launch_f32_to_f64(p, mk->Pk, mk->m, mk->stream));
+  HIPC(launch_gather_f32_to_f64(p, mk->perm, mk->Pk, mk->m, mk->stream));
   io.xin = x_in;
   io.p = mk->Pk;
   io.xout = x_out;
@@ -669,7 +737,7 @@ extern "C" int32_t pdhcg_solve(pdhcg_market mk, const pdhcg_params *params, int3
   // sum to the budgets).  A warm start copies the caller's point.
   if (warm) {
     HIPC(hipMemcpyAsync(mk->X[0], x, (size_t)nnz * 4, hipMemcpyDeviceToDevice, st));
-    HIPC(launch_f32_to_f64(p, mk->P[0], m, st));
+    HIPC(launch_gather_f32_to_f64(p, mk->perm, mk->P[0], m, st));
   } else {
     HIPC(launch_init_point(mk->col, mk->deg, nnz, mk->X[0], mk->P[0], m,
                            mk->sumw / (double)m, st));
@@ -854,7 +922,7 @@ extern "C" int32_t pdhcg_solve(pdhcg_market mk, const pdhcg_params *params, int3
   const float *xs = mk->X[out_avg ? S.ix[2] : S.ix[0]];
   const double *ps = mk->P[out_avg ? S.ip[2] : S.ip[0]];
   HIPC(hipMemcpyAsync(x, xs, (size_t)nnz * 4, hipMemcpyDeviceToDevice, st));
-  HIPC(launch_f64_to_f32(ps, p, m, st));
+  HIPC(launch_gather_f64_to_f32(ps, mk->inv, p, m, st));
   if (t) HIPC(hipMemcpyAsync(t, mk->T[out_avg ? 1 : 0], (size_t)mk->n * 4, hipMemcpyDeviceToDevice, st));
   if (prm->output != PDHCG_OUTPUT_CANDIDATE) {
     const int z = out_avg ? 1 : 0;
@@ -992,15 +1060,15 @@ struct AdjBuffers {
   }
 };
 
+// Goods whose column sums come from LDS partials ([0, hot)); the others are
+// summed by device atomics.
+int lds_goods(pdhcg_market mk) { return (mk->lds_row & 1) ? mk->hot : 0; }
+
 // Column sums of the row pass just launched (explicit mode) into out.
 int32_t finish_colsum(pdhcg_market mk, double *chunk, double *atomic_sum, double *out) {
-  if (mk->lds_row & 1) {
-    HIPC(launch_sum_partials(mk->colpart, mk->total_wg, mk->m, chunk, mk->stream));
-    HIPC(launch_finish_colsum(chunk, mk->m, out, mk->stream));
-  } else {
-    HIPC(hipMemcpyAsync(out, atomic_sum, (size_t)mk->m * sizeof(double),
-                        hipMemcpyDeviceToDevice, mk->stream));
-  }
+  const int h = lds_goods(mk);
+  HIPC(launch_sum_partials(mk->colpart, mk->total_wg, h, mk->m, chunk, mk->stream));
+  HIPC(launch_finish_colsum(chunk, atomic_sum, h, mk->m, out, mk->stream));
   return PDHCG_OK;
 }
 
@@ -1063,7 +1131,7 @@ extern "C" int32_t pdhcg_backward(pdhcg_market mk, const float *x, const float *
   auto forward = [&](const float *xin, float *xout) -> int32_t {
     HIPC(launch_adj_pstep(pw, c, cp, sigma, m, st));
     HIPC(hipMemcpyAsync(cp, c, (size_t)m * sizeof(double), hipMemcpyDeviceToDevice, st));
-    if (!(mk->lds_row & 1)) HIPC(launch_zero_f64(asum, m, st));
+    if (lds_goods(mk) < m) HIPC(launch_zero_f64(asum, m, st));
     io.xin = xin;
     io.xout = xout;
     for (const Bin &b : mk->bins)
@@ -1072,7 +1140,7 @@ extern "C" int32_t pdhcg_backward(pdhcg_market mk, const float *x, const float *
   };
 
   // forward sweep from the given point, one checkpoint every L steps
-  HIPC(launch_f32_to_f64(p, pw, m, st));
+  HIPC(launch_gather_f32_to_f64(p, mk->perm, pw, m, st));
   HIPC(launch_colsum_atomic(mk->col, x, nnz, c, m, st));
   HIPC(hipMemcpyAsync(cp, c, (size_t)m * sizeof(double), hipMemcpyDeviceToDevice, st));
   const float *xcur = x;
@@ -1100,7 +1168,7 @@ extern "C" int32_t pdhcg_backward(pdhcg_market mk, const float *x, const float *
   HIPC(launch_zero_f32(dw, n, st));
   HIPC(launch_zero_f64(B, m, st));
   HIPC(launch_zero_f64(Cn, m, st));
-  HIPC(launch_f32_to_f64(dL_dp, P, m, st));
+  HIPC(launch_gather_f32_to_f64(dL_dp, mk->perm, P, m, st));
   float *rin = R0, *rout = R1;
   for (int q = nck - 1; q >= 0; --q) {
     const int j0 = q * L, j1 = std::min(K, j0 + L);
@@ -1127,15 +1195,12 @@ extern "C" int32_t pdhcg_backward(pdhcg_market mk, const float *x, const float *
       aio.dw = dw;
       aio.csum = asum;
       aio.tau = tau;
-      if (!(mk->lds_row & 1)) HIPC(launch_zero_f64(asum, m, st));
+      const int h = lds_goods(mk);
+      if (h < m) HIPC(launch_zero_f64(asum, m, st));
       for (const Bin &b : mk->bins)
         HIPC(launch_adj_row(md, mk->bindev(b), b.G, b.E, mk->lds_row & 1, aio, b.nwg, st));
-      if (mk->lds_row & 1) {
-        HIPC(launch_sum_partials(mk->colpart, mk->total_wg, m, chunk, st));
-        HIPC(launch_adj_col(chunk, 1, P, B, Cn, tau, sigma, m, st));
-      } else {
-        HIPC(launch_adj_col(asum, 0, P, B, Cn, tau, sigma, m, st));
-      }
+      HIPC(launch_sum_partials(mk->colpart, mk->total_wg, h, m, chunk, st));
+      HIPC(launch_adj_col(chunk, asum, h, P, B, Cn, tau, sigma, m, st));
       std::swap(rin, rout);
     }
   }

@@ -54,6 +54,10 @@ struct DevState {
 struct MarketDev {
   int32_t n, m;
   int64_t nnz;
+  int32_t hot;       // goods [0, hot) have prices and column partials in LDS;
+                     // goods from hot on (the less bought ones after the
+                     // relabelling by degree) use global memory and atomics
+  int32_t pad_hot;
   const int32_t *row_ptr;
   const int32_t *col;
   const float *uh;   // row-normalised utilities
@@ -132,9 +136,11 @@ struct EvalIO {
   float *tc;         // per-row utility of the current point (nullable)
   float *ta;         // per-row utility of the averaged point (nullable)
   const float *rowscale; // multiply t by this (original units)
-  float *evalpart;   // column maxima (float bits): [2][total_wg][m] (LDS mode) or [2][m]
-  double *evalcs;    // [total_wg][m] float64 column-sum partials (LDS mode)
+  float *evalpart;   // column maxima (float bits): [2][total_wg][hot] (LDS mode) or [2][m]
+  double *evalcs;    // [total_wg][hot] float64 column-sum partials (LDS mode)
   uint32_t *evalchunk; // [2][kColChunks][m] chunk maxima (LDS mode)
+  uint32_t *gmax;    // [2][m] device-wide maxima of the goods from hot on (LDS mode)
+  double *gsum;      // [m] device-wide sums of the goods from hot on (LDS mode)
   double *cacc;      // [m] float64 column sums: accumulator (non-LDS mode), else
                      // [kColChunks][m] chunk sums
   int32_t want_cc;   // sum the columns of xc (no average; ccur unused)
@@ -164,6 +170,12 @@ hipError_t launch_degrees(const int32_t *col, int64_t nnz, int32_t *deg, hipStre
 hipError_t launch_init_point(const int32_t *col, const int32_t *deg, int64_t nnz,
                              float *x, double *p, int m, double p0, hipStream_t st);
 hipError_t launch_f32_to_f64(const float *src, double *dst, int64_t len, hipStream_t st);
+// dst[i] = src[map[i]] (map may be null: dst[i] = src[i]); goods vectors
+// between the caller's order and the relabelled one.
+hipError_t launch_gather_f32_to_f64(const float *src, const int32_t *map, double *dst, int m,
+                                    hipStream_t st);
+hipError_t launch_gather_f64_to_f32(const double *src, const int32_t *map, float *dst, int m,
+                                    hipStream_t st);
 hipError_t launch_f64_to_f32(const double *src, float *dst, int64_t len, hipStream_t st);
 hipError_t launch_copy_f32(const float *src, float *dst, int64_t len, hipStream_t st);
 hipError_t launch_copy_f64(const double *src, double *dst, int64_t len, hipStream_t st);
@@ -186,17 +198,18 @@ hipError_t launch_adj_long(const MarketDev &md, const BinDev &bin, int lds, cons
 // Reverse mode (pdhcg_adjoint.hip).
 hipError_t launch_adj_pstep(double *p, const double *c, const double *cprev, double sigma, int m,
                             hipStream_t st);
-hipError_t launch_sum_partials(const double *part, int rows, int m, double *chunk,
+hipError_t launch_sum_partials(const double *part, int rows, int hot, int m, double *chunk,
                                hipStream_t st);
-hipError_t launch_finish_colsum(const double *chunk, int m, double *out, hipStream_t st);
+hipError_t launch_finish_colsum(const double *chunk, const double *cold, int hot, int m,
+                                double *out, hipStream_t st);
 hipError_t launch_colsum_atomic(const int32_t *col, const float *x, int64_t nnz, double *out,
                                 int m, hipStream_t st);
 hipError_t launch_zero_f64(double *a, int64_t len, hipStream_t st);
 hipError_t launch_zero_f32(float *a, int64_t len, hipStream_t st);
 hipError_t launch_adj_row(const MarketDev &md, const BinDev &bin, int G, int E, int lds,
                           const AdjIO &io, int nwg, hipStream_t st);
-hipError_t launch_adj_col(const double *csrc, int chunked, double *P, double *B, double *Cn,
-                          double tau, double sigma, int m, hipStream_t st);
+hipError_t launch_adj_col(const double *chunk, const double *cold, int hot, double *P, double *B,
+                          double *Cn, double tau, double sigma, int m, hipStream_t st);
 hipError_t launch_adj_unnormalize(const int32_t *row_ptr, const float *uh, const float *rowmax,
                                   const float *duh, int n, float *du, hipStream_t st);
 

@@ -124,11 +124,16 @@ __global__ __launch_bounds__(kRowBlock) void k_row_pass(MarketDev md, BinDev bin
     tau = S->tau;
     wfold = S->fold ? (float)(1.0 / (double)S->k_in) : 0.0f;
   }
-  double *lp = lds_d;  // [m] prices (LDS_MODE & 2)
-  double *lc = (LDS_MODE & 2) ? lds_d + m : lds_d;  // [m] column partials
+  // LDS holds lh goods: all of them, or with LDS_MODE & 4 the goods [0, hot)
+  // plus one idle slot (the goods from hot on use global memory)
+  constexpr bool kHybrid = (LDS_MODE & 4) != 0;
+  const int hot = kHybrid ? md.hot : m;
+  const int lh = kHybrid ? hot + 1 : m;
+  double *lp = lds_d;  // [lh] prices (LDS_MODE & 2)
+  double *lc = (LDS_MODE & 2) ? lds_d + lh : lds_d;  // [lh] column partials
   if (LDS_MODE != 0) {
-    for (int j = threadIdx.x; j < m; j += blockDim.x) {
-      if (LDS_MODE & 2) lp[j] = pp[j];
+    for (int j = threadIdx.x; j < lh; j += blockDim.x) {
+      if (LDS_MODE & 2) lp[j] = j < hot ? pp[j] : 0.0;
       if (LDS_MODE & 1) lc[j] = 0.0;
     }
     __syncthreads();
@@ -186,8 +191,22 @@ __global__ __launch_bounds__(kRowBlock) void k_row_pass(MarketDev md, BinDev bin
   double a[E];
   float y[E];
   auto head = [&](const RowRegs<E> &Rc, const RowBounds &bc) {
+    if (kHybrid) {
+      // both loads for every entry (no branch around a memory instruction):
+      // LDS for the hot goods, global for the others (hot entries read the
+      // price of good 0, one cached line)
 #pragma unroll
-    for (int e = 0; e < E; ++e) a[e] = (LDS_MODE & 2) ? lp[Rc.c[e]] : pp[Rc.c[e]];
+      for (int e = 0; e < E; ++e) {
+        const int c = Rc.c[e];
+        const bool hc = c < hot;
+        const double vg = pp[hc ? 0 : c];
+        const double vl = lp[hc ? c : hot];
+        a[e] = hc ? vl : vg;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) a[e] = (LDS_MODE & 2) ? lp[Rc.c[e]] : pp[Rc.c[e]];
+    }
     const uint32_t off = lane_off(bc);
 #pragma unroll
     for (int e = 0; e < E; ++e) y[e] = bload_f(ry, off + 4u * G * e);
@@ -234,7 +253,14 @@ __global__ __launch_bounds__(kRowBlock) void k_row_pass(MarketDev md, BinDev bin
       const float df = ok[e] ? xn - xk : 0.0f;
       dx2 = fmaf(df, df, dx2);
       if (io.colsum) {
-        atomicAdd((LDS_MODE & 1) ? &lc[Rc.c[e]] : &cglob[Rc.c[e]], ok[e] ? (double)xn : 0.0);
+        if (kHybrid) {
+          const int c = Rc.c[e];
+          const bool hc = c < hot;
+          atomicAdd(&lc[hc ? c : hot], (ok[e] && hc) ? (double)xn : 0.0);
+          if (ok[e] && !hc) atomicAdd(&cglob[c], (double)xn);
+        } else {
+          atomicAdd((LDS_MODE & 1) ? &lc[Rc.c[e]] : &cglob[Rc.c[e]], ok[e] ? (double)xn : 0.0);
+        }
       }
     }
     bstore_f(rs, (rv && r == 0) ? 4u * (uint32_t)rid : kOutOfRange, (float)sfin);
@@ -285,8 +311,8 @@ __global__ __launch_bounds__(kRowBlock) void k_row_pass(MarketDev md, BinDev bin
     }
   }
   if ((LDS_MODE & 1) && io.colsum) {
-    double *dst = md.colpart + (size_t)slot * m;
-    for (int j = threadIdx.x; j < m; j += blockDim.x) dst[j] = lc[j];
+    double *dst = md.colpart + (size_t)slot * hot;
+    for (int j = threadIdx.x; j < hot; j += blockDim.x) dst[j] = lc[j];
   }
 }
 
@@ -332,19 +358,22 @@ __global__ __launch_bounds__(kColBlock) void k_col_decide(MarketDev md, int tota
   double *ctry = pick3<double *>(md.C0, md.C1, md.C2, S->ic[2]);
   __shared__ bool last_chunk, last_tile;
   if (from_partials) {
+    // partial rows cover the goods [0, hot) (all goods unless the market
+    // is hybrid, where the others are summed by device atomics in c_try)
+    const int hot = md.hot;
     const int per = (total_wg + nq - 1) / nq;
     const int b0 = q * per, b1 = min(total_wg, b0 + per);
-    if (j < m) {
+    if (j < hot) {
       double c = 0.0;
       const double *src = md.colpart + j;
       int b = b0;
       for (; b + 8 <= b1; b += 8) {  // eight loads in flight per thread
         double v[8];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) v[t] = src[(size_t)(b + t) * m];
+        for (int t = 0; t < 8; ++t) v[t] = src[(size_t)(b + t) * hot];
         c += ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
       }
-      for (; b < b1; ++b) c += src[(size_t)b * m];
+      for (; b < b1; ++b) c += src[(size_t)b * hot];
       md.colchunk[(size_t)q * m + j] = c;
     }
     __syncthreads();
@@ -356,7 +385,7 @@ __global__ __launch_bounds__(kColBlock) void k_col_decide(MarketDev md, int tota
     __syncthreads();
     if (!last_chunk) return;
     __threadfence();
-    if (j < m) {
+    if (j < hot) {
       double c = 0.0;
       for (int k = 0; k < nq; ++k) c += md.colchunk[(size_t)k * m + j];
       ctry[j] = c;
@@ -473,20 +502,26 @@ __global__ __launch_bounds__(kRowBlock) void k_eval_row(MarketDev md, BinDev bin
   const int m = md.m;
   const bool has_avg = io.xa != nullptr;
   const bool sum_avg = has_avg && !io.want_cc;
+  // LDS mode: goods [0, hot) in LDS, the others in the device-wide
+  // accumulators io.gmax / io.gsum
+  const int hot = (LDS_MODE == 1) ? md.hot : 0;
   double *lcs = lds_e;
-  unsigned int *lMc = reinterpret_cast<unsigned int *>(lds_e + m);
-  unsigned int *lMa = lMc + m;
+  unsigned int *lMc = reinterpret_cast<unsigned int *>(lds_e + hot);
+  unsigned int *lMa = lMc + hot;
   if (LDS_MODE == 1) {
-    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    for (int j = threadIdx.x; j < hot; j += blockDim.x) {
       lcs[j] = 0.0;
       lMc[j] = 0u;
       lMa[j] = 0u;
     }
     __syncthreads();
   }
-  const size_t TW = (LDS_MODE == 1) ? (size_t)total_wg * m : (size_t)m;
+  const size_t TW = (LDS_MODE == 1) ? (size_t)total_wg * hot : (size_t)m;
   unsigned int *gMc = reinterpret_cast<unsigned int *>(io.evalpart);
   unsigned int *gMa = reinterpret_cast<unsigned int *>(io.evalpart + TW);
+  unsigned int *xMc = (LDS_MODE == 1) ? io.gmax : gMc;
+  unsigned int *xMa = (LDS_MODE == 1) ? io.gmax + m : gMa;
+  double *xcs = (LDS_MODE == 1) ? io.gsum : io.cacc;
 
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
@@ -574,8 +609,8 @@ __global__ __launch_bounds__(kRowBlock) void k_eval_row(MarketDev md, BinDev bin
         }
         st[3] = fmax(st[3], (double)xc[e]);
         const unsigned int bc = __float_as_uint((float)vc);
-        if (LDS_MODE == 1) atomicMax(&lMc[c], bc);
-        else atomicMax(&gMc[c], bc);
+        if (c < hot) atomicMax(&lMc[c], bc);
+        else atomicMax(&xMc[c], bc);
         if (has_avg) {
           const double va = (double)uh[e] * ya;
           const double ra = paj[e] - va;
@@ -585,12 +620,12 @@ __global__ __launch_bounds__(kRowBlock) void k_eval_row(MarketDev md, BinDev bin
           }
           st[7] = fmax(st[7], (double)xa[e]);
           const unsigned int ba = __float_as_uint((float)va);
-          if (LDS_MODE == 1) atomicMax(&lMa[c], ba);
-          else atomicMax(&gMa[c], ba);
+          if (c < hot) atomicMax(&lMa[c], ba);
+          else atomicMax(&xMa[c], ba);
         }
         if (sum_avg || io.want_cc) {
           const double add = io.want_cc ? xc[e] : xa[e];
-          atomicAdd((LDS_MODE == 1) ? &lcs[c] : &io.cacc[c], add);
+          atomicAdd(c < hot ? &lcs[c] : &xcs[c], add);
         }
       }
     }
@@ -610,10 +645,10 @@ __global__ __launch_bounds__(kRowBlock) void k_eval_row(MarketDev md, BinDev bin
     md.rowpart[(size_t)slot * kEvalRowStats + q] = v;
   }
   if (LDS_MODE == 1) {
-    unsigned int *dMc = gMc + (size_t)slot * m;
-    unsigned int *dMa = gMa + (size_t)slot * m;
-    double *dcs = io.evalcs + (size_t)slot * m;
-    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    unsigned int *dMc = gMc + (size_t)slot * hot;
+    unsigned int *dMa = gMa + (size_t)slot * hot;
+    double *dcs = io.evalcs + (size_t)slot * hot;
+    for (int j = threadIdx.x; j < hot; j += blockDim.x) {
       dMc[j] = lMc[j];
       dMa[j] = lMa[j];
       dcs[j] = lcs[j];
@@ -629,13 +664,13 @@ __global__ __launch_bounds__(kRowBlock) void k_eval_row(MarketDev md, BinDev bin
 // cacc [kColChunks][m].
 __global__ __launch_bounds__(kColBlock) void k_eval_chunks(MarketDev md, EvalIO io,
                                                            int total_wg) {
-  const int m = md.m;
+  const int m = md.m, hot = md.hot;
   const int j = blockIdx.x * kColBlock + threadIdx.x;
   const int q = blockIdx.y;
-  if (j >= m) return;
+  if (j >= hot) return;
   const bool has_avg = io.xa != nullptr;
   const bool want_sum = (has_avg && !io.want_cc) || io.want_cc;
-  const size_t TW = (size_t)total_wg * m;
+  const size_t TW = (size_t)total_wg * hot;
   const int per = (total_wg + kColChunks - 1) / kColChunks;
   const int b0 = q * per, b1 = min(total_wg, b0 + per);
   const unsigned int *sMc = reinterpret_cast<const unsigned int *>(io.evalpart) + j;
@@ -643,9 +678,9 @@ __global__ __launch_bounds__(kColBlock) void k_eval_chunks(MarketDev md, EvalIO 
   unsigned int bMc = 0u, bMa = 0u;
   double cs = 0.0;
   for (int b = b0; b < b1; ++b) {
-    bMc = max(bMc, sMc[(size_t)b * m]);
-    if (has_avg) bMa = max(bMa, sMa[(size_t)b * m]);
-    if (want_sum) cs += io.evalcs[(size_t)b * m + j];
+    bMc = max(bMc, sMc[(size_t)b * hot]);
+    if (has_avg) bMa = max(bMa, sMa[(size_t)b * hot]);
+    if (want_sum) cs += io.evalcs[(size_t)b * hot + j];
   }
   io.evalchunk[(size_t)q * m + j] = bMc;
   io.evalchunk[(size_t)(kColChunks + q) * m + j] = bMa;
@@ -675,13 +710,18 @@ __global__ __launch_bounds__(kColBlock) void k_eval_col(MarketDev md, EvalIO io,
     double cs = 0.0;
     const unsigned int *sMc = reinterpret_cast<const unsigned int *>(io.evalpart) + j;
     const unsigned int *sMa = reinterpret_cast<const unsigned int *>(io.evalpart + TW) + j;
-    if (partials) {
+    if (partials && j < md.hot) {
       // chunk results of k_eval_chunks, combined in a fixed order
       for (int q = 0; q < kColChunks; ++q) {
         bMc = max(bMc, io.evalchunk[(size_t)q * m + j]);
         if (has_avg) bMa = max(bMa, io.evalchunk[(size_t)(kColChunks + q) * m + j]);
         if (sum_avg || io.want_cc) cs += io.cacc[(size_t)q * m + j];
       }
+    } else if (partials) {
+      // goods from hot on: device-wide accumulators
+      bMc = io.gmax[j];
+      if (has_avg) bMa = io.gmax[m + j];
+      if (sum_avg || io.want_cc) cs = io.gsum[j];
     } else {
       bMc = sMc[0];
       if (has_avg) bMa = sMa[0];
@@ -814,6 +854,16 @@ __global__ void k_f32_to_f64(const float *src, double *dst, int64_t len) {
     dst[k] = (double)src[k];
 }
 
+__global__ void k_gather_f32_to_f64(const float *src, const int32_t *map, double *dst, int m) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) dst[i] = (double)src[map ? map[i] : i];
+}
+
+__global__ void k_gather_f64_to_f32(const double *src, const int32_t *map, float *dst, int m) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < m) dst[i] = (float)src[map ? map[i] : i];
+}
+
 __global__ void k_f64_to_f32(const double *src, float *dst, int64_t len) {
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < len;
        k += (int64_t)gridDim.x * blockDim.x)
@@ -864,8 +914,8 @@ bool row_variant_exists(int G, int E) {
 template <int G, int E, int MODE, int LDSM>
 static hipError_t row_launch_t(const MarketDev &md, const BinDev &bin, const RowIO &io, int nwg,
                                hipStream_t st) {
-  const size_t shm = (size_t)md.m * (((LDSM & 2) ? sizeof(double) : 0) +
-                                      ((LDSM & 1) ? sizeof(double) : 0));
+  const size_t lh = (LDSM & 4) ? (size_t)md.hot + 1 : (size_t)md.m;
+  const size_t shm = lh * (((LDSM & 2) ? sizeof(double) : 0) + ((LDSM & 1) ? sizeof(double) : 0));
   hipLaunchKernelGGL((k_row_pass<G, E, MODE, LDSM>), dim3(nwg), dim3(kRowBlock), shm, st, md,
                      bin, io);
   return hipGetLastError();
@@ -877,6 +927,7 @@ hipError_t launch_row_pass(const MarketDev &md, const BinDev &bin, int G, int E,
   const int mode = io.search;
 #define PDHCG_ROW_LDS(g, e, md_)                                                  \
   switch (lds_mode) {                                                             \
+    case 7: return row_launch_t<g, e, md_, 7>(md, bin, io, nwg, st);              \
     case 3: return row_launch_t<g, e, md_, 3>(md, bin, io, nwg, st);              \
     case 1: return row_launch_t<g, e, md_, 1>(md, bin, io, nwg, st);              \
     case 0: return row_launch_t<g, e, md_, 0>(md, bin, io, nwg, st);              \
@@ -896,7 +947,7 @@ hipError_t launch_row_pass(const MarketDev &md, const BinDev &bin, int G, int E,
 template <int G, int E, int LDSM>
 static hipError_t eval_launch_t(const MarketDev &md, const BinDev &bin, const EvalIO &io,
                                 int nwg, int total_wg, hipStream_t st) {
-  const size_t shm = LDSM == 1 ? (size_t)md.m * (sizeof(double) + 2 * sizeof(uint32_t)) : 0;
+  const size_t shm = LDSM == 1 ? (size_t)md.hot * (sizeof(double) + 2 * sizeof(uint32_t)) : 0;
   hipLaunchKernelGGL((k_eval_row<G, E, LDSM>), dim3(nwg), dim3(kRowBlock), shm, st, md, bin,
                      io, total_wg);
   return hipGetLastError();
@@ -931,7 +982,8 @@ hipError_t launch_col_decide(const MarketDev &md, int total_wg, int from_partial
 
 hipError_t launch_eval_chunks(const MarketDev &md, const EvalIO &io, int total_wg,
                               hipStream_t st) {
-  hipLaunchKernelGGL(k_eval_chunks, dim3((md.m + kColBlock - 1) / kColBlock, kColChunks),
+  if (md.hot <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_eval_chunks, dim3((md.hot + kColBlock - 1) / kColBlock, kColChunks),
                      dim3(kColBlock), 0, st, md, io, total_wg);
   return hipGetLastError();
 }
@@ -975,6 +1027,20 @@ hipError_t launch_copy_f64(const double *src, double *dst, int64_t len, hipStrea
 
 hipError_t launch_f32_to_f64(const float *src, double *dst, int64_t len, hipStream_t st) {
   hipLaunchKernelGGL(k_f32_to_f64, dim3(grid_for(len, 256)), dim3(256), 0, st, src, dst, len);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_f32_to_f64(const float *src, const int32_t *map, double *dst, int m,
+                                    hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_f32_to_f64, dim3(grid_for(m, 256)), dim3(256), 0, st, src, map, dst,
+                     m);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_f64_to_f32(const double *src, const int32_t *map, float *dst, int m,
+                                    hipStream_t st) {
+  hipLaunchKernelGGL(k_gather_f64_to_f32, dim3(grid_for(m, 256)), dim3(256), 0, st, src, map, dst,
+                     m);
   return hipGetLastError();
 }
 

@@ -40,10 +40,12 @@ __global__ __launch_bounds__(kRowBlock) void k_row_long(MarketDev md, BinDev bin
     tau = S->tau;
     wfold = S->fold ? (float)(1.0 / (double)S->k_in) : 0.0f;
   }
+  // goods [0, hot) in LDS (all of them unless LDS_MODE & 4)
+  const int hot = (LDS_MODE & 4) ? md.hot : ((LDS_MODE & 3) ? m : 0);
   double *lp = lds_d;
-  double *lc = (LDS_MODE & 2) ? lds_d + m : lds_d;
+  double *lc = (LDS_MODE & 2) ? lds_d + hot : lds_d;
   if (LDS_MODE != 0) {
-    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    for (int j = threadIdx.x; j < hot; j += blockDim.x) {
       if (LDS_MODE & 2) lp[j] = pp[j];
       if (LDS_MODE & 1) lc[j] = 0.0;
     }
@@ -55,7 +57,7 @@ __global__ __launch_bounds__(kRowBlock) void k_row_long(MarketDev md, BinDev bin
   const int wg = blockIdx.x;
   const int row_lo = wg * bin.rows_per_wg;
   const int row_hi = min(row_lo + bin.rows_per_wg, bin.nrows);
-  auto pget = [&](int c) { return (LDS_MODE & 2) ? lp[c] : pp[c]; };
+  auto pget = [&](int c) { return ((LDS_MODE & 2) && c < hot) ? lp[c] : pp[c]; };
   double dx2 = 0.0;
   uint32_t rmax = 0, rsum = 0, rcount = 0;
   for (int slot = row_lo + wave; slot < row_hi; slot += kWaves) {
@@ -77,7 +79,7 @@ __global__ __launch_bounds__(kRowBlock) void k_row_long(MarketDev md, BinDev bin
       if (wfold != 0.0f) xavg[q] = (wfold == 1.0f) ? xk : fmaf(xk - xavg[q], wfold, xavg[q]);
       const double df = (double)xn - (double)xk;
       dx2 = fma(df, df, dx2);
-      if (io.colsum) atomicAdd((LDS_MODE & 1) ? &lc[c] : &cglob[c], (double)xn);
+      if (io.colsum) atomicAdd(((LDS_MODE & 1) && c < hot) ? &lc[c] : &cglob[c], (double)xn);
     }
     if (lane == 0) {
       if (io.s_out) io.s_out[i] = (float)sfin;
@@ -116,8 +118,8 @@ __global__ __launch_bounds__(kRowBlock) void k_row_long(MarketDev md, BinDev bin
     }
   }
   if ((LDS_MODE & 1) && io.colsum) {
-    double *dst = md.colpart + (size_t)slotw * m;
-    for (int j = threadIdx.x; j < m; j += blockDim.x) dst[j] = lc[j];
+    double *dst = md.colpart + (size_t)slotw * hot;
+    for (int j = threadIdx.x; j < hot; j += blockDim.x) dst[j] = lc[j];
   }
 }
 
@@ -130,20 +132,24 @@ __global__ __launch_bounds__(kRowBlock) void k_eval_long(MarketDev md, BinDev bi
   const int m = md.m;
   const bool has_avg = io.xa != nullptr;
   const bool sum_avg = has_avg && !io.want_cc;
+  const int hot = (LDS_MODE == 1) ? md.hot : 0;
   double *lcs = lds_e;
-  unsigned int *lMc = reinterpret_cast<unsigned int *>(lds_e + m);
-  unsigned int *lMa = lMc + m;
+  unsigned int *lMc = reinterpret_cast<unsigned int *>(lds_e + hot);
+  unsigned int *lMa = lMc + hot;
   if (LDS_MODE == 1) {
-    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    for (int j = threadIdx.x; j < hot; j += blockDim.x) {
       lcs[j] = 0.0;
       lMc[j] = 0u;
       lMa[j] = 0u;
     }
     __syncthreads();
   }
-  const size_t TW = (LDS_MODE == 1) ? (size_t)total_wg * m : (size_t)m;
+  const size_t TW = (LDS_MODE == 1) ? (size_t)total_wg * hot : (size_t)m;
   unsigned int *gMc = reinterpret_cast<unsigned int *>(io.evalpart);
   unsigned int *gMa = reinterpret_cast<unsigned int *>(io.evalpart + TW);
+  unsigned int *xMc = (LDS_MODE == 1) ? io.gmax : gMc;
+  unsigned int *xMa = (LDS_MODE == 1) ? io.gmax + m : gMa;
+  double *xcs = (LDS_MODE == 1) ? io.gsum : io.cacc;
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
   constexpr int kWaves = kRowBlock / kWave;
@@ -204,8 +210,8 @@ __global__ __launch_bounds__(kRowBlock) void k_eval_long(MarketDev md, BinDev bi
       }
       st[3] = fmax(st[3], (double)xc);
       const unsigned int bc = __float_as_uint((float)vc);
-      if (LDS_MODE == 1) atomicMax(&lMc[c], bc);
-      else atomicMax(&gMc[c], bc);
+      if (c < hot) atomicMax(&lMc[c], bc);
+      else atomicMax(&xMc[c], bc);
       float xa = 0.0f;
       if (has_avg) {
         xa = io.xa[q];
@@ -219,8 +225,8 @@ __global__ __launch_bounds__(kRowBlock) void k_eval_long(MarketDev md, BinDev bi
         }
         st[7] = fmax(st[7], (double)xa);
         const unsigned int ba = __float_as_uint((float)va);
-        if (LDS_MODE == 1) atomicMax(&lMa[c], ba);
-        else atomicMax(&gMa[c], ba);
+        if (c < hot) atomicMax(&lMa[c], ba);
+        else atomicMax(&xMa[c], ba);
         if (io.xanc) {
           const float z = io.xanc[q];
           st[9] += (double)(xa - z) * (double)(xa - z);
@@ -228,7 +234,7 @@ __global__ __launch_bounds__(kRowBlock) void k_eval_long(MarketDev md, BinDev bi
       }
       if (sum_avg || io.want_cc) {
         const double add = io.want_cc ? xc : xa;
-        atomicAdd((LDS_MODE == 1) ? &lcs[c] : &io.cacc[c], add);
+        atomicAdd(c < hot ? &lcs[c] : &xcs[c], add);
       }
     }
   }
@@ -247,10 +253,10 @@ __global__ __launch_bounds__(kRowBlock) void k_eval_long(MarketDev md, BinDev bi
     md.rowpart[(size_t)slotw * kEvalRowStats + q] = v;
   }
   if (LDS_MODE == 1) {
-    unsigned int *dMc = gMc + (size_t)slotw * m;
-    unsigned int *dMa = gMa + (size_t)slotw * m;
-    double *dcs = io.evalcs + (size_t)slotw * m;
-    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+    unsigned int *dMc = gMc + (size_t)slotw * hot;
+    unsigned int *dMa = gMa + (size_t)slotw * hot;
+    double *dcs = io.evalcs + (size_t)slotw * hot;
+    for (int j = threadIdx.x; j < hot; j += blockDim.x) {
       dMc[j] = lMc[j];
       dMa[j] = lMa[j];
       dcs[j] = lcs[j];
@@ -262,9 +268,9 @@ __global__ __launch_bounds__(kRowBlock) void k_eval_long(MarketDev md, BinDev bi
 template <int LDS_MODE>
 __global__ __launch_bounds__(kRowBlock) void k_adj_long(MarketDev md, BinDev bin, AdjIO io) {
   extern __shared__ double lcs[];
-  const int m = md.m;
+  const int hot = LDS_MODE ? md.hot : 0;
   if (LDS_MODE) {
-    for (int j = threadIdx.x; j < m; j += blockDim.x) lcs[j] = 0.0;
+    for (int j = threadIdx.x; j < hot; j += blockDim.x) lcs[j] = 0.0;
     __syncthreads();
   }
   const int lane = threadIdx.x & (kWave - 1);
@@ -309,18 +315,15 @@ __global__ __launch_bounds__(kRowBlock) void k_adj_long(MarketDev md, BinDev bin
       io.r_out[q] = (float)rr;
       if (act) io.duh[q] += (float)(rr * tw * is - h * (double)xn);
       ru = fma(rr, u, ru);
-      if (LDS_MODE)
-        atomicAdd(&lcs[c], rr);
-      else
-        atomicAdd(&io.csum[c], rr);
+      atomicAdd(c < hot ? &lcs[c] : &io.csum[c], rr);
     }
     ru = wave_sum_d(ru);
     if (live && lane == 0) io.dw[i] += (float)(tau * is * ru);
   }
   if (LDS_MODE) {
     __syncthreads();
-    double *dst = md.colpart + (size_t)(bin.wg_offset + wg) * m;
-    for (int j = threadIdx.x; j < m; j += blockDim.x) dst[j] = lcs[j];
+    double *dst = md.colpart + (size_t)(bin.wg_offset + wg) * hot;
+    for (int j = threadIdx.x; j < hot; j += blockDim.x) dst[j] = lcs[j];
   }
 }
 
@@ -328,12 +331,14 @@ __global__ __launch_bounds__(kRowBlock) void k_adj_long(MarketDev md, BinDev bin
 
 hipError_t launch_row_long(const MarketDev &md, const BinDev &bin, int lds_mode, const RowIO &io,
                            int nwg, hipStream_t st) {
-  const size_t shm = (size_t)md.m * (((lds_mode & 2) ? sizeof(double) : 0) +
-                                     ((lds_mode & 1) ? sizeof(double) : 0));
+  const size_t lh = (lds_mode & 4) ? (size_t)md.hot : (size_t)md.m;
+  const size_t shm = lh * (((lds_mode & 2) ? sizeof(double) : 0) +
+                           ((lds_mode & 1) ? sizeof(double) : 0));
   switch (lds_mode) {
     case 0: hipLaunchKernelGGL(k_row_long<0>, dim3(nwg), dim3(kRowBlock), shm, st, md, bin, io); break;
     case 1: hipLaunchKernelGGL(k_row_long<1>, dim3(nwg), dim3(kRowBlock), shm, st, md, bin, io); break;
     case 3: hipLaunchKernelGGL(k_row_long<3>, dim3(nwg), dim3(kRowBlock), shm, st, md, bin, io); break;
+    case 7: hipLaunchKernelGGL(k_row_long<7>, dim3(nwg), dim3(kRowBlock), shm, st, md, bin, io); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -341,7 +346,7 @@ hipError_t launch_row_long(const MarketDev &md, const BinDev &bin, int lds_mode,
 
 hipError_t launch_eval_long(const MarketDev &md, const BinDev &bin, int lds_mode,
                             const EvalIO &io, int nwg, int total_wg, hipStream_t st) {
-  const size_t shm = lds_mode ? (size_t)md.m * (sizeof(double) + 2 * sizeof(uint32_t)) : 0;
+  const size_t shm = lds_mode ? (size_t)md.hot * (sizeof(double) + 2 * sizeof(uint32_t)) : 0;
   if (lds_mode)
     hipLaunchKernelGGL(k_eval_long<1>, dim3(nwg), dim3(kRowBlock), shm, st, md, bin, io, total_wg);
   else
@@ -351,7 +356,7 @@ hipError_t launch_eval_long(const MarketDev &md, const BinDev &bin, int lds_mode
 
 hipError_t launch_adj_long(const MarketDev &md, const BinDev &bin, int lds, const AdjIO &io,
                            int nwg, hipStream_t st) {
-  const size_t shm = lds ? (size_t)md.m * sizeof(double) : 0;
+  const size_t shm = lds ? (size_t)md.hot * sizeof(double) : 0;
   if (lds)
     hipLaunchKernelGGL(k_adj_long<1>, dim3(nwg), dim3(kRowBlock), shm, st, md, bin, io);
   else

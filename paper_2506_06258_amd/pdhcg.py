@@ -33,7 +33,8 @@ EXPORTS = (
     "pdhcg_abi_version", "pdhcg_status_string", "pdhcg_last_error",
     "pdhcg_default_params", "pdhcg_validate_host", "pdhcg_market_create",
     "pdhcg_set_budgets", "pdhcg_solve", "pdhcg_kkt", "pdhcg_row_prox",
-    "pdhcg_arrow_debreu", "pdhcg_backward", "pdhcg_market_bins", "pdhcg_market_destroy",
+    "pdhcg_arrow_debreu", "pdhcg_backward", "pdhcg_market_bins", "pdhcg_market_lds_goods",
+    "pdhcg_market_destroy",
     "pdhcg_batch_create", "pdhcg_batch_solve", "pdhcg_batch_layout", "pdhcg_batch_destroy",
 )
 
@@ -94,6 +95,7 @@ def lib() -> C.CDLL:
                                      C.POINTER(pdhcg_info)]),
         "pdhcg_backward": (i32, [vp, vp, vp, dbl, i32, i32, vp, vp, vp]),
         "pdhcg_market_bins": (i32, [vp, i32, vp, vp, vp]),
+        "pdhcg_market_lds_goods": (i32, [vp]),
         "pdhcg_market_destroy": (None, [vp]),
         "pdhcg_batch_create": (i32, [i32, vp, vp, vp, vp, vp, vp, vp, C.POINTER(vp)]),
         "pdhcg_batch_solve": (i32, [vp, C.POINTER(pdhcg_params), vp, vp, vp]),
@@ -262,6 +264,13 @@ def pdhcg_market_bins(h, cap: int = 64):
     return list(zip(G[:k].tolist(), E[:k].tolist(), R[:k].tolist()))
 
 
+def pdhcg_market_lds_goods(h) -> int:
+    r = lib().pdhcg_market_lds_goods(h)
+    if r < 0:
+        _check(r, "pdhcg_market_lds_goods")
+    return r
+
+
 @dataclass
 class Solution:
     p: torch.Tensor
@@ -332,6 +341,10 @@ class Market:
 
     def bins(self):
         return pdhcg_market_bins(self._h)
+
+    def lds_goods(self) -> int:
+        """Goods whose column data the row kernels keep in LDS (m: all)."""
+        return pdhcg_market_lds_goods(self._h)
 
     def backward(self, x, p, omega: float, dL_dp, unroll: int = 1024, ckpt_every: int = 32):
         """(dL/du, dL/dw) by reverse mode through `unroll` fixed-step

@@ -150,10 +150,12 @@ def kkt(n, m, row_ptr, col, u, w, x, p):
 def normalize_rows(row_ptr, u):
     """u_hat = u / max_j u_ij per row (the preprocessing of Sec. 5)."""
     u = _d(u)
-    rows = np.repeat(np.arange(len(row_ptr) - 1), np.diff(row_ptr))
-    mx = np.zeros(len(row_ptr) - 1)
-    np.maximum.at(mx, rows, u)
-    return u / mx[rows], mx
+    rp = np.asarray(row_ptr, dtype=np.int64)
+    lens = np.diff(rp)
+    mx = np.zeros(len(rp) - 1)
+    nz = lens > 0
+    mx[nz] = np.maximum.reduceat(u, rp[:-1][nz])
+    return u / np.repeat(mx, lens), mx
 
 
 def row_prox_exact(u, xk, pg, w, tau):

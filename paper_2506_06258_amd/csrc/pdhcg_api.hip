@@ -317,7 +317,9 @@ int32_t build_bins(pdhcg_market mk, const std::vector<int32_t> &h_row_ptr, int w
     b.nnz += h_row_ptr[(size_t)i + 1] - h_row_ptr[(size_t)i];
   }
   // workgroup budget: the resident workgroups per CU (at most two), so that
-  // the row pass runs in one round and writes as few partial rows as it can
+  // each bin's launch fills the chip in one round.  The bins are launched one
+  // after the other, so every bin gets the whole budget; each workgroup
+  // writes one partial row, reduced by the column kernels.
   int cus = 256;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, mk->device) == hipSuccess && prop.multiProcessorCount > 0)
@@ -329,9 +331,7 @@ int32_t build_bins(pdhcg_market mk, const std::vector<int32_t> &h_row_ptr, int w
     b.nrows = (int32_t)b.rows.size();
     const int per_pass = b.G ? kWaves * (kWave / b.G) : kWaves;
     const int64_t passes = (b.nrows + per_pass - 1) / per_pass;
-    int nwg = (int)std::max<int64_t>(
-        1, std::min<int64_t>(passes, (int64_t)std::ceil((double)budget * (double)b.nnz /
-                                                       (double)std::max<int64_t>(mk->nnz, 1))));
+    int nwg = (int)std::max<int64_t>(1, std::min<int64_t>(passes, budget));
     const int64_t passes_per_wg = (passes + nwg - 1) / nwg;
     b.rows_per_wg = (int32_t)(passes_per_wg * per_pass);
     b.nwg = (int32_t)((b.nrows + b.rows_per_wg - 1) / b.rows_per_wg);

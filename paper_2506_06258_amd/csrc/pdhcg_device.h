@@ -311,6 +311,40 @@ __device__ __forceinline__ double prox_row(bool rv, int beg, int d, int r, doubl
   return prox_solve<G, E, MODE>(rv, tw, max_rounds, rtol, K, ok, a, uh, xk, rounds);
 }
 
+// Entries of a long row in chunks of kWave * U: lane l takes entries
+// l, l + kWave, ..., l + (U-1) kWave of the chunk.  Every load of a chunk is
+// issued before any is used (indices past the row end are clamped to its
+// last entry and flagged invalid), so a pass over the row waits for memory
+// once per chunk rather than once per entry.  body(valid, k, u, a, x, c)
+// gets u = 0 for invalid entries; a = x^k - tau p.
+constexpr int kLongUnroll = 8;
+template <class PGet, class Body>
+__device__ __forceinline__ void long_row_chunks(int beg, int d, double tau, const float *uh,
+                                                const int32_t *col, const float *xin, PGet pget,
+                                                Body body) {
+  const int lane = threadIdx.x & (kWave - 1);
+  for (int base = 0; base < d; base += kWave * kLongUnroll) {
+    float u[kLongUnroll], x[kLongUnroll];
+    int c[kLongUnroll];
+    double pj[kLongUnroll];
+#pragma unroll
+    for (int e = 0; e < kLongUnroll; ++e) {
+      const int k = beg + min(base + lane + kWave * e, d - 1);
+      u[e] = uh[k];
+      c[e] = col[k];
+      x[e] = xin[k];
+    }
+#pragma unroll
+    for (int e = 0; e < kLongUnroll; ++e) pj[e] = pget(c[e]);
+#pragma unroll
+    for (int e = 0; e < kLongUnroll; ++e) {
+      const int k = base + lane + kWave * e;
+      const bool v = k < d;
+      body(v, beg + k, v ? (double)u[e] : 0.0, fma(-tau, pj[e], (double)x[e]), x[e], c[e]);
+    }
+  }
+}
+
 // Row root for rows longer than a wave holds in registers: one wave per
 // row, every search round re-reads the row (it stays in cache).  Same
 // search as prox_row (active-set trial points inside the Alg. 3 bracket).
@@ -318,20 +352,16 @@ template <class PGet>
 __device__ __forceinline__ double prox_row_long(int beg, int d, double tau, double tw, const float *uh,
                                 const int32_t *col, const float *xin, PGet pget, int max_rounds,
                                 double rtol, int &rounds) {
-  const int lane = threadIdx.x & (kWave - 1);
   double s0 = 0.0;
-  for (int k = lane; k < d; k += kWave) s0 = fma((double)uh[beg + k], (double)xin[beg + k], s0);
+  long_row_chunks(beg, d, tau, uh, col, xin, pget,
+                  [&](bool, int, double u, double, float x, int) { s0 = fma(u, (double)x, s0); });
   s0 = seg_sum_d<kWave>(s0);
   double s = s0;
   if (!(s > 0.0)) {
     double lb = 0.0;
-    for (int k = lane; k < d; k += kWave) {
-      const double u = uh[beg + k];
-      if (u > 0.0) {
-        const double a = fma(-tau, pget(col[beg + k]), (double)xin[beg + k]);
-        lb = fmax(lb, pos_root_d(u * a, tw * u * u));
-      }
-    }
+    long_row_chunks(beg, d, tau, uh, col, xin, pget, [&](bool, int, double u, double a, float, int) {
+      if (u > 0.0) lb = fmax(lb, pos_root_d(u * a, tw * u * u));
+    });
     lb = seg_max_d<kWave>(lb);
     s = lb > 0.0 ? lb : 1.0;
   }
@@ -340,13 +370,11 @@ __device__ __forceinline__ double prox_row_long(int beg, int d, double tau, doub
   for (int it = 0; it < max_rounds; ++it) {
     const double inv = fast_rcp(s), ti = tw * inv;
     double A = 0.0, Q = 0.0;
-    for (int k = lane; k < d; k += kWave) {
-      const double u = uh[beg + k];
-      const double a = fma(-tau, pget(col[beg + k]), (double)xin[beg + k]);
+    long_row_chunks(beg, d, tau, uh, col, xin, pget, [&](bool, int, double u, double a, float, int) {
       const double on = fma(u, ti, a) > 0.0 ? u : 0.0;
       A = fma(on, a, A);
       Q = fma(on, u, Q);
-    }
+    });
     A = seg_sum_d<kWave>(A);
     Q = seg_sum_d<kWave>(Q);
     const double B = tw * Q, g = fma(B, inv, A), sA = pos_root_d(A, B);
@@ -354,11 +382,10 @@ __device__ __forceinline__ double prox_row_long(int beg, int d, double tau, doub
     if (sA > 0.0) {
       const double tA = tw * fast_rcp(sA);
       bool diff = false;
-      for (int k = lane; k < d; k += kWave) {
-        const double u = uh[beg + k];
-        const double a = fma(-tau, pget(col[beg + k]), (double)xin[beg + k]);
-        diff |= ((fma(u, ti, a) > 0.0) != (fma(u, tA, a) > 0.0));
-      }
+      long_row_chunks(beg, d, tau, uh, col, xin, pget,
+                      [&](bool, int, double u, double a, float, int) {
+                        diff |= ((fma(u, ti, a) > 0.0) != (fma(u, tA, a) > 0.0));
+                      });
       same = !seg_any<kWave>(diff);
     }
     ++rounds;

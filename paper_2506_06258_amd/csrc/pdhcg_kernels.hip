@@ -771,22 +771,42 @@ __global__ __launch_bounds__(kColBlock) void k_eval_col(MarketDev md, EvalIO io,
   __syncthreads();
   if (!last) return;
   __threadfence();
-  if (threadIdx.x != 0) return;
+  // Every thread of the last block combines a strided share of the block
+  // and workgroup statistics, then a fixed-order block reduction.
   double c[10], rw[10];
   for (int q = 0; q < 10; ++q) {
     c[q] = (q == 3 || q == 7) ? -INFINITY : 0.0;
     rw[q] = 0.0;
   }
-  for (int b = 0; b < (int)gridDim.x; ++b)
+  for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x)
     for (int q = 0; q < 10; ++q) {
       const double v = md.colblk[(size_t)b * kEvalColStats + q];
       c[q] = (q >= 8) ? c[q] + v : fmax(c[q], v);
     }
-  for (int b = 0; b < total_wg; ++b)
+  for (int b = threadIdx.x; b < total_wg; b += blockDim.x)
     for (int q = 0; q < 10; ++q) {
       const double v = md.rowpart[(size_t)b * kEvalRowStats + q];
       rw[q] = (q >= 8) ? rw[q] + v : fmax(rw[q], v);
     }
+  __shared__ double fin[2][kColBlock / kWave][10];
+  for (int q = 0; q < 10; ++q) {
+    const double cv = (q >= 8) ? wave_sum_d(c[q]) : wave_max_d(c[q]);
+    const double rv = (q >= 8) ? wave_sum_d(rw[q]) : wave_max_d(rw[q]);
+    if (lane == 0) {
+      fin[0][wave][q] = cv;
+      fin[1][wave][q] = rv;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int q = 0; q < 10; ++q) {
+    c[q] = fin[0][0][q];
+    rw[q] = fin[1][0][q];
+    for (int w = 1; w < kColBlock / kWave; ++w) {
+      c[q] = (q >= 8) ? c[q] + fin[0][w][q] : fmax(c[q], fin[0][w][q]);
+      rw[q] = (q >= 8) ? rw[q] + fin[1][w][q] : fmax(rw[q], fin[1][w][q]);
+    }
+  }
   // Relative KKT error (Sec. 5 Criteria) with t = Ux, y = w / t:
   //   r_primal = max|c - 1| / (1 + max(max|c|, 1))
   //   r_dual   = max (M - p)_+ / (1 + max(max y, max (p - M)))

@@ -57,7 +57,18 @@ __global__ __launch_bounds__(kRowBlock) void k_row_long(MarketDev md, BinDev bin
   const int wg = blockIdx.x;
   const int row_lo = wg * bin.rows_per_wg;
   const int row_hi = min(row_lo + bin.rows_per_wg, bin.nrows);
-  auto pget = [&](int c) { return ((LDS_MODE & 2) && c < hot) ? lp[c] : pp[c]; };
+  // price of good c: LDS for the goods below hot, global memory above (both
+  // loads issued, so that a chunk's gathers are not split by a branch)
+  auto pget = [&](int c) {
+    if (!(LDS_MODE & 2)) return pp[c];
+    if (!(LDS_MODE & 4)) return lp[c];
+    const bool h = c < hot;
+    const double vl = lp[h ? c : 0];
+    const double vg = pp[h ? 0 : c];
+    return h ? vl : vg;
+  };
+  const bool fold = wfold != 0.0f;
+  const bool fold_read = fold && wfold != 1.0f;  // weight 1 replaces the average
   double dx2 = 0.0;
   uint32_t rmax = 0, rsum = 0, rcount = 0;
   for (int slot = row_lo + wave; slot < row_hi; slot += kWaves) {
@@ -69,17 +80,36 @@ __global__ __launch_bounds__(kRowBlock) void k_row_long(MarketDev md, BinDev bin
     const double sfin = prox_row_long(beg, d, tau, tw, md.uh, md.col, xin, pget, io.max_rounds,
                                       io.rtol, rounds);
     const double tf = tw * fast_rcp(sfin);
-    for (int k = lane; k < d; k += kWave) {
-      const int q = beg + k;
-      const float xk = xin[q];
-      const int c = md.col[q];
-      const double a = fma(-tau, pget(c), (double)xk);
-      const float xn = (float)fmax(fma((double)md.uh[q], tf, a), 0.0);
-      xout[q] = xn;
-      if (wfold != 0.0f) xavg[q] = (wfold == 1.0f) ? xk : fmaf(xk - xavg[q], wfold, xavg[q]);
-      const double df = (double)xn - (double)xk;
-      dx2 = fma(df, df, dx2);
-      if (io.colsum) atomicAdd(((LDS_MODE & 1) && c < hot) ? &lc[c] : &cglob[c], (double)xn);
+    // final sweep in chunks, every load of a chunk issued first
+    for (int base = 0; base < d; base += kWave * kLongUnroll) {
+      float u[kLongUnroll], xk[kLongUnroll], y[kLongUnroll];
+      int c[kLongUnroll];
+      double pj[kLongUnroll];
+#pragma unroll
+      for (int e = 0; e < kLongUnroll; ++e) {
+        const int q = beg + min(base + lane + kWave * e, d - 1);
+        u[e] = md.uh[q];
+        c[e] = md.col[q];
+        xk[e] = xin[q];
+        y[e] = fold_read ? xavg[q] : 0.0f;
+      }
+#pragma unroll
+      for (int e = 0; e < kLongUnroll; ++e) pj[e] = pget(c[e]);
+#pragma unroll
+      for (int e = 0; e < kLongUnroll; ++e) {
+        const int k = base + lane + kWave * e;
+        if (k < d) {
+          const int q = beg + k;
+          const double a = fma(-tau, pj[e], (double)xk[e]);
+          const float xn = (float)fmax(fma((double)u[e], tf, a), 0.0);
+          xout[q] = xn;
+          if (fold) xavg[q] = fold_read ? fmaf(xk[e] - y[e], wfold, y[e]) : xk[e];
+          const double df = (double)xn - (double)xk[e];
+          dx2 = fma(df, df, dx2);
+          if (io.colsum)
+            atomicAdd(((LDS_MODE & 1) && c[e] < hot) ? &lc[c[e]] : &cglob[c[e]], (double)xn);
+        }
+      }
     }
     if (lane == 0) {
       if (io.s_out) io.s_out[i] = (float)sfin;
@@ -165,24 +195,34 @@ __global__ __launch_bounds__(kRowBlock) void k_eval_long(MarketDev md, BinDev bi
     const int beg = md.row_ptr[i];
     const int d = md.row_ptr[i + 1] - beg;
     const double wi = (double)md.w[i];
-    // pass 1: t = u^T x of both points (folding the average first)
+    // pass 1: t = u^T x of both points (folding the average first); chunks
+    // of kWave * kLongUnroll entries, every load of a chunk issued first
     double tc = 0.0, ta = 0.0;
-    for (int k = lane; k < d; k += kWave) {
-      const int q = beg + k;
-      const float u = md.uh[q];
-      const float x = io.xc[q];
-      tc = fma((double)u, (double)x, tc);
-      if (has_avg) {
-        float y = io.xa[q];
-        if (wf != 0.0f) {
-          y = (wf == 1.0f) ? x : fmaf(x - y, wf, y);
-          io.xa[q] = y;
-        }
-        ta = fma((double)u, (double)y, ta);
+    for (int base = 0; base < d; base += kWave * kLongUnroll) {
+      float u[kLongUnroll], x[kLongUnroll], y[kLongUnroll], z[kLongUnroll];
+#pragma unroll
+      for (int e = 0; e < kLongUnroll; ++e) {
+        const int q = beg + min(base + lane + kWave * e, d - 1);
+        u[e] = md.uh[q];
+        x[e] = io.xc[q];
+        y[e] = has_avg ? io.xa[q] : 0.0f;
+        z[e] = io.xanc ? io.xanc[q] : 0.0f;
       }
-      if (io.xanc) {
-        const float z = io.xanc[q];
-        st[8] += (double)(x - z) * (double)(x - z);
+#pragma unroll
+      for (int e = 0; e < kLongUnroll; ++e) {
+        const int k = base + lane + kWave * e;
+        if (k < d) {
+          tc = fma((double)u[e], (double)x[e], tc);
+          if (has_avg) {
+            float yy = y[e];
+            if (wf != 0.0f) {
+              yy = (wf == 1.0f) ? x[e] : fmaf(x[e] - yy, wf, yy);
+              io.xa[beg + k] = yy;
+            }
+            ta = fma((double)u[e], (double)yy, ta);
+          }
+          if (io.xanc) st[8] += (double)(x[e] - z[e]) * (double)(x[e] - z[e]);
+        }
       }
     }
     tc = wave_sum_d(tc);
@@ -196,45 +236,63 @@ __global__ __launch_bounds__(kRowBlock) void k_eval_long(MarketDev md, BinDev bi
       st[4] = fmax(st[4], ya);
     }
     // pass 2: residual terms, column maxima and sums (the average is folded)
-    for (int k = lane; k < d; k += kWave) {
-      const int q = beg + k;
-      const int c = md.col[q];
-      const double u = (double)md.uh[q];
-      const float xc = io.xc[q];
-      const double p = io.pc[c];
-      const double vc = u * yc;
-      const double rc = p - vc;
-      if (rc > 0.0) {
-        st[2] = fmax(st[2], rc);
-        st[1] = fmax(st[1], (double)xc * rc);
+    for (int base = 0; base < d; base += kWave * kLongUnroll) {
+      float u[kLongUnroll], xcv[kLongUnroll], xav[kLongUnroll], z[kLongUnroll];
+      int cv[kLongUnroll];
+      double pcv[kLongUnroll], pav[kLongUnroll];
+#pragma unroll
+      for (int e = 0; e < kLongUnroll; ++e) {
+        const int q = beg + min(base + lane + kWave * e, d - 1);
+        cv[e] = md.col[q];
+        u[e] = md.uh[q];
+        xcv[e] = io.xc[q];
+        xav[e] = has_avg ? io.xa[q] : 0.0f;
+        z[e] = (has_avg && io.xanc) ? io.xanc[q] : 0.0f;
       }
-      st[3] = fmax(st[3], (double)xc);
-      const unsigned int bc = __float_as_uint((float)vc);
-      if (c < hot) atomicMax(&lMc[c], bc);
-      else atomicMax(&xMc[c], bc);
-      float xa = 0.0f;
-      if (has_avg) {
-        xa = io.xa[q];
-        double pa = io.pa[c];
-        if (wf != 0.0f) pa = (wf == 1.0f) ? p : pa + (p - pa) * (double)wf;
-        const double va = u * ya;
-        const double ra = pa - va;
-        if (ra > 0.0) {
-          st[6] = fmax(st[6], ra);
-          st[5] = fmax(st[5], (double)xa * ra);
-        }
-        st[7] = fmax(st[7], (double)xa);
-        const unsigned int ba = __float_as_uint((float)va);
-        if (c < hot) atomicMax(&lMa[c], ba);
-        else atomicMax(&xMa[c], ba);
-        if (io.xanc) {
-          const float z = io.xanc[q];
-          st[9] += (double)(xa - z) * (double)(xa - z);
-        }
+#pragma unroll
+      for (int e = 0; e < kLongUnroll; ++e) {
+        pcv[e] = io.pc[cv[e]];
+        pav[e] = has_avg ? io.pa[cv[e]] : 0.0;
       }
-      if (sum_avg || io.want_cc) {
-        const double add = io.want_cc ? xc : xa;
-        atomicAdd(c < hot ? &lcs[c] : &xcs[c], add);
+#pragma unroll
+      for (int e = 0; e < kLongUnroll; ++e) {
+        const int k = base + lane + kWave * e;
+        if (k < d) {
+          const int c = cv[e];
+          const double uu = (double)u[e];
+          const float xc = xcv[e];
+          const double p = pcv[e];
+          const double vc = uu * yc;
+          const double rc = p - vc;
+          if (rc > 0.0) {
+            st[2] = fmax(st[2], rc);
+            st[1] = fmax(st[1], (double)xc * rc);
+          }
+          st[3] = fmax(st[3], (double)xc);
+          const unsigned int bc = __float_as_uint((float)vc);
+          if (c < hot) atomicMax(&lMc[c], bc);
+          else atomicMax(&xMc[c], bc);
+          const float xa = xav[e];
+          if (has_avg) {
+            double pa = pav[e];
+            if (wf != 0.0f) pa = (wf == 1.0f) ? p : pa + (p - pa) * (double)wf;
+            const double va = uu * ya;
+            const double ra = pa - va;
+            if (ra > 0.0) {
+              st[6] = fmax(st[6], ra);
+              st[5] = fmax(st[5], (double)xa * ra);
+            }
+            st[7] = fmax(st[7], (double)xa);
+            const unsigned int ba = __float_as_uint((float)va);
+            if (c < hot) atomicMax(&lMa[c], ba);
+            else atomicMax(&xMa[c], ba);
+            if (io.xanc) st[9] += (double)(xa - z[e]) * (double)(xa - z[e]);
+          }
+          if (sum_avg || io.want_cc) {
+            const double add = io.want_cc ? xc : xa;
+            atomicAdd(c < hot ? &lcs[c] : &xcs[c], add);
+          }
+        }
       }
     }
   }

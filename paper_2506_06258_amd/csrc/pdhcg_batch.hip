@@ -180,8 +180,8 @@ __device__ double wg_rows_step(const MView &v, const double *lp, double *lc, con
 // KKT row pass (Sec. 5 Criteria) over the current point and, if xa is not
 // NULL, the averaged point (folded in place with weight wf).  G lanes per
 // row, entries visited with stride G.  Row statistics go to st[0..9]
-// (same layout as the single-market KKT pass); column maxima of u y go to
-// lMc/lMa (float bits), column sums of the averaged point (or of the
+// (same layout as the single-market KKT pass); column maxima of u y - p go
+// to lMc/lMa (ord_key keys), column sums of the averaged point (or of the
 // current point when sum_cur) to lcs.
 template <int G>
 __device__ void wg_rows_eval(const MView &v, const float *xc, const double *pc, float *xa,
@@ -241,7 +241,7 @@ __device__ void wg_rows_eval(const MView &v, const float *xc, const double *pc, 
         st[1] = fmax(st[1], x * rc);
       }
       st[3] = fmax(st[3], x);
-      atomicMax(&lMc[c], __float_as_uint((float)vc));
+      atomicMax(&lMc[c], ord_key((float)(vc - pc[c])));
       if (has_avg) {
         const double y = xa[q];
         const double va = u * ya, ra = pa_folded[c] - va;
@@ -250,7 +250,7 @@ __device__ void wg_rows_eval(const MView &v, const float *xc, const double *pc, 
           st[5] = fmax(st[5], y * ra);
         }
         st[7] = fmax(st[7], y);
-        atomicMax(&lMa[c], __float_as_uint((float)va));
+        atomicMax(&lMa[c], ord_key((float)(va - pa_folded[c])));
         if (!sum_cur) atomicAdd(&lcs[c], y);
       }
       if (sum_cur) atomicAdd(&lcs[c], x);
@@ -325,22 +325,22 @@ __device__ void wg_eval(const MView &v, int shape, WGState &S, bool has_avg, flo
   const double *cc = v.C(uni(S.ic[1]));
   double *cavg = v.C(uni(S.ic[2]));
   for (int j = threadIdx.x; j < v.m; j += blockDim.x) {
-    const double Mc = __uint_as_float(lMc[j]);
+    const double Dc = ord_dec(lMc[j]);  // column max of u y - p
     const double p = pc[j];
     cs[0] = fmax(cs[0], fabs(cc[j] - 1.0));
     cs[1] = fmax(cs[1], fabs(cc[j]));
-    cs[2] = fmax(cs[2], Mc - p);
-    cs[3] = fmax(cs[3], p - Mc);
+    cs[2] = fmax(cs[2], Dc);
+    cs[3] = fmax(cs[3], -Dc);
     cs[8] += (p - v.PA[j]) * (p - v.PA[j]);
     if (has_avg) {
-      const double Ma = __uint_as_float(lMa[j]);
+      const double Da = ord_dec(lMa[j]);
       const double ca = lc[j];
       const double q = lp[j];
       cavg[j] = ca;
       cs[4] = fmax(cs[4], fabs(ca - 1.0));
       cs[5] = fmax(cs[5], fabs(ca));
-      cs[6] = fmax(cs[6], Ma - q);
-      cs[7] = fmax(cs[7], q - Ma);
+      cs[6] = fmax(cs[6], Da);
+      cs[7] = fmax(cs[7], -Da);
       cs[9] += (q - v.PA[j]) * (q - v.PA[j]);
     }
   }

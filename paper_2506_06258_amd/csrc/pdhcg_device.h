@@ -100,6 +100,20 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   return v;
 }
 
+// Order-preserving 32-bit key of a float of any sign: unsigned comparison
+// of keys matches the comparison of the floats, and key 0 lies below every
+// float.  The KKT column maxima are taken over D = u y - p (the column max of
+// u y shifted by the column's price), so that near equilibrium, where M and
+// p almost cancel, the float32 key rounds the small difference rather than
+// M itself.
+__device__ __forceinline__ unsigned int ord_key(float f) {
+  const unsigned int b = __float_as_uint(f);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float ord_dec(unsigned int k) {
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+
 __device__ __forceinline__ double wave_max_d(double v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o));

@@ -487,9 +487,9 @@ __global__ __launch_bounds__(kColBlock) void k_col_decide(MarketDev md, int tota
 //  0 max y_c, 1 max gap_c, 2 max (p - u y)_+ c, 3 max x_c,
 //  4 max y_a, 5 max gap_a, 6 max (p - u y)_+ a, 7 max x_a,
 //  8 |x_c - anchor|^2, 9 |x_a - anchor|^2
-// Column quantities: M_c, M_a (column maxima of u_ij y_i, as float bits,
-// max-reduced as unsigned because they are non-negative) and the column
-// sums of the averaged point (or of the current point when want_cc).
+// Column quantities: the column maxima of u_ij y_i - p_j for both points
+// (as ord_key keys, max-reduced as unsigned) and the column sums of the
+// averaged point (or of the current point when want_cc).
 // LDS_MODE 1: per-workgroup partials in LDS (float64 sums: float32 LDS
 // atomic adds are slow on gfx950), written to evalpart [2][total_wg][m]
 // (maxima) and evalcs [total_wg][m] (sums).  LDS_MODE 0: device-wide atomics
@@ -608,7 +608,7 @@ __global__ __launch_bounds__(kRowBlock) void k_eval_row(MarketDev md, BinDev bin
           st[1] = fmax(st[1], (double)xc[e] * rc);
         }
         st[3] = fmax(st[3], (double)xc[e]);
-        const unsigned int bc = __float_as_uint((float)vc);
+        const unsigned int bc = ord_key((float)(vc - pcj[e]));
         if (c < hot) atomicMax(&lMc[c], bc);
         else atomicMax(&xMc[c], bc);
         if (has_avg) {
@@ -619,7 +619,7 @@ __global__ __launch_bounds__(kRowBlock) void k_eval_row(MarketDev md, BinDev bin
             st[5] = fmax(st[5], (double)xa[e] * ra);
           }
           st[7] = fmax(st[7], (double)xa[e]);
-          const unsigned int ba = __float_as_uint((float)va);
+          const unsigned int ba = ord_key((float)(va - paj[e]));
           if (c < hot) atomicMax(&lMa[c], ba);
           else atomicMax(&xMa[c], ba);
         }
@@ -727,14 +727,15 @@ __global__ __launch_bounds__(kColBlock) void k_eval_col(MarketDev md, EvalIO io,
       if (has_avg) bMa = sMa[0];
       if (sum_avg || io.want_cc) cs = io.cacc[j];
     }
-    const double Mc = (double)__uint_as_float(bMc);
-    const double Ma = (double)__uint_as_float(bMa);
+    // column maxima of u y - p (keys of ord_key)
+    const double Dc = (double)ord_dec(bMc);
+    const double Da = (double)ord_dec(bMa);
     const double cc = io.want_cc ? cs : io.ccur[j];
     const double pc = io.pc[j];
     st[0] = fabs(cc - 1.0);
     st[1] = fabs(cc);
-    st[2] = fmax(0.0, Mc - pc);
-    st[3] = pc - Mc;
+    st[2] = fmax(0.0, Dc);
+    st[3] = -Dc;
     if (io.panc) st[8] = (pc - io.panc[j]) * (pc - io.panc[j]);
     if ((sum_avg || io.want_cc) && io.cavg_out) io.cavg_out[j] = cs;
     if (has_avg) {
@@ -744,8 +745,8 @@ __global__ __launch_bounds__(kColBlock) void k_eval_col(MarketDev md, EvalIO io,
       const double pa = q;
       st[4] = fabs(cs - 1.0);
       st[5] = fabs(cs);
-      st[6] = fmax(0.0, Ma - pa);
-      st[7] = pa - Ma;
+      st[6] = fmax(0.0, Da);
+      st[7] = -Da;
       if (io.panc) st[9] = (pa - io.panc[j]) * (pa - io.panc[j]);
     }
   }

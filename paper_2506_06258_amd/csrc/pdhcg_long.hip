@@ -269,7 +269,7 @@ __global__ __launch_bounds__(kRowBlock) void k_eval_long(MarketDev md, BinDev bi
             st[1] = fmax(st[1], (double)xc * rc);
           }
           st[3] = fmax(st[3], (double)xc);
-          const unsigned int bc = __float_as_uint((float)vc);
+          const unsigned int bc = ord_key((float)(vc - p));
           if (c < hot) atomicMax(&lMc[c], bc);
           else atomicMax(&xMc[c], bc);
           const float xa = xav[e];
@@ -283,7 +283,7 @@ __global__ __launch_bounds__(kRowBlock) void k_eval_long(MarketDev md, BinDev bi
               st[5] = fmax(st[5], (double)xa * ra);
             }
             st[7] = fmax(st[7], (double)xa);
-            const unsigned int ba = __float_as_uint((float)va);
+            const unsigned int ba = ord_key((float)(va - pa));
             if (c < hot) atomicMax(&lMa[c], ba);
             else atomicMax(&xMa[c], ba);
             if (io.xanc) st[9] += (double)(xa - z[e]) * (double)(xa - z[e]);

@@ -306,6 +306,13 @@ def arrow_debreu_market(n: int, m: int, deg_u: int, deg_e: int, seed: int,
     return mk
 
 
+def arrow_debreu_1e5(seed: int = 4) -> Market:
+    """The exchange workload: n = m = 1e5 agents and goods, 50 utility
+    edges per agent (5e6), 5 endowed goods per agent, columns of E
+    normalised to one (Sec. 4)."""
+    return arrow_debreu_market(100_000, 100_000, 50, 5, seed)
+
+
 @dataclass
 class MarketBatch:
     """Independent Fisher markets concatenated: market b owns rows

@@ -1,0 +1,212 @@
+"""The full-size workloads on the GPU, in the launch configuration the
+benchmark times (default parameters, relative KKT 1e-4), against the FP64
+oracle on sampled outputs and through properties that hold at any size.
+
+* 1e8-edge market (n = 1e6 buyers, m = 1e4 goods, 100 goods per buyer);
+* skewed market (n = 4e6, m = 2e5, Zipf(1.5) buyer degrees in [5, 20000],
+  1/rank popularity of goods, about 4.5e8 edges): rows longer than 512
+  entries and goods outside LDS (relabelled by degree) on the same path;
+* 4096 independent markets in one batched launch;
+* the Arrow-Debreu exchange market (n = m = 1e5, 50 utility edges and 5
+  endowed goods per agent).
+
+Checks:
+* the relative KKT error of the returned point, recomputed by the oracle
+  in FP64 over every edge, is within the tolerance and agrees with the
+  device's own FP64 evaluation (Sec. 5 Criteria);
+* row prox (Sec. 2.2) of sampled rows, element by element, against the
+  oracle's exact prox of the same rows, with the bar of the small-market
+  parity tests (64 eps32 of the entry's two terms; 1e-5 relative on s);
+* Arrow-Debreu (Sec. 4): budgets equal E p and sum to n.
+Each test prints the case it is running before it touches the GPU.
+"""
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2506_06258_amd import pdhcg, synth
+from test_gpu_parity import EPS32
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+def say(msg):
+    print(f"[fullsize] {msg}", flush=True)
+
+
+def sampled_rows(mk, rng, short, long_, long_from=513):
+    d = np.diff(mk.row_ptr)
+    lr = np.nonzero(d >= long_from)[0]
+    sr = np.nonzero(d < long_from)[0]
+    pick = [rng.choice(sr, size=min(short, sr.size), replace=False)]
+    if lr.size and long_:
+        pick.append(rng.choice(lr, size=min(long_, lr.size), replace=False))
+    return np.sort(np.concatenate(pick))
+
+
+def check_rows(mk, rows, xg, sg, x_in, p, tau):
+    """Device prox of `rows` against the oracle's exact prox of each row."""
+    worst = 0.0
+    for i in rows:
+        a0, a1 = int(mk.row_ptr[i]), int(mk.row_ptr[i + 1])
+        u = mk.u[a0:a1].astype(np.float64)
+        uh = u / u.max()
+        pj = p[mk.col[a0:a1]].astype(np.float64)
+        xk = x_in[a0:a1].astype(np.float64)
+        x_ref, s_ref = oracle.row_prox_exact(uh, xk, pj, float(mk.w[i]), tau)
+        a = xk - tau * pj
+        b = tau * float(mk.w[i]) * uh
+        scale = np.abs(a) + b / s_ref
+        err = np.abs(xg[a0:a1] - x_ref)
+        ratio = float(np.max(err / (scale + 1e-300)))
+        worst = max(worst, ratio)
+        assert np.all(err <= 64 * EPS32 * scale + 1e-30), (i, a1 - a0, ratio / EPS32)
+        assert abs(sg[i] - s_ref) <= 1e-5 * s_ref, (i, sg[i], s_ref)
+    return worst / EPS32
+
+
+def uhat32(mk):
+    """u / max_j u_ij rounded to float32, as the device stores it: the
+    device solves this float32 instance, so its own FP64 KKT evaluation is
+    compared with the oracle's on the same numbers."""
+    u = np.asarray(mk.u, np.float32)
+    rp = np.asarray(mk.row_ptr, np.int64)
+    mx = np.maximum.reduceat(u, rp[:-1])
+    return u / np.repeat(mx, np.diff(rp))
+
+
+def random_state(mk, rng):
+    deg = np.bincount(mk.col, minlength=mk.m)
+    x = (rng.uniform(0, 2.0, mk.nnz) / deg[mk.col]).astype(np.float32)
+    p = (float(mk.w.sum() / mk.m) * rng.uniform(0.5, 1.5, mk.m)).astype(np.float32)
+    return x, p
+
+
+def solve_and_check(mk, M, cuda, label):
+    say(f"{label}: solve to rel. KKT {TOL:g} (default parameters)")
+    prm = pdhcg.pdhcg_default_params(tol=TOL, max_iter=20000, timing=1)
+    sol = M.solve(prm)
+    torch.cuda.synchronize()
+    info = sol.info
+    say(f"{label}: status {info.status}, {info.iters} iterations, {info.seconds:.2f} s, "
+        f"rel. KKT {info.rel_kkt:.3e}")
+    assert info.status == pdhcg.PDHCG_OK, pdhcg.pdhcg_last_error()
+    assert info.rel_kkt <= TOL
+    t = time.time()
+    x, p = sol.x.cpu().numpy(), sol.p.cpu().numpy()
+    r, parts = oracle.kkt(mk.n, mk.m, mk.row_ptr, mk.col, uhat32(mk), mk.w, x, p)
+    say(f"{label}: oracle KKT {r:.3e} {parts} in {time.time() - t:.1f} s")
+    # the solver evaluates its float64 prices; the returned prices are
+    # rounded to float32, which moves the dual and gap terms by O(eps32 p)
+    assert r <= TOL * 1.05
+    assert abs(r - info.rel_kkt) <= 0.05 * r + 4 * EPS32
+    # the KKT entry point evaluates exactly the returned point
+    ik = M.kkt(sol.p, sol.x)
+    got = np.array([ik.rel_primal, ik.rel_dual, ik.rel_gap])
+    say(f"{label}: KKT entry point {got}")
+    assert np.all(np.abs(got - parts) <= 1e-5 * parts + 1e-13), (got, parts)
+    # and on the exact normalisation (float64 u / max u)
+    uh, _ = oracle.normalize_rows(mk.row_ptr, mk.u)
+    r64, parts64 = oracle.kkt(mk.n, mk.m, mk.row_ptr, mk.col, uh, mk.w, x, p)
+    say(f"{label}: oracle KKT on float64 u/max u {r64:.3e} {parts64}")
+    assert r64 <= TOL * (1 + 1e-2)
+    return sol
+
+
+def prox_and_check(mk, M, cuda, label, rows, x_in, p, tau):
+    say(f"{label}: row prox of every row, {rows.size} rows compared (tau {tau:.3g})")
+    xg, sg = M.row_prox(torch.as_tensor(x_in, device=cuda), torch.as_tensor(p, device=cuda), tau)
+    torch.cuda.synchronize()
+    xg, sg = xg.cpu().numpy().astype(np.float64), sg.cpu().numpy().astype(np.float64)
+    worst = check_rows(mk, rows, xg, sg, x_in, p, tau)
+    say(f"{label}: worst entry error {worst:.2f} eps32 of its scale")
+
+
+def test_fisher_1e8(cuda):
+    say("1e8-edge market: generate")
+    mk = synth.fisher_1e8(1)
+    M = pdhcg.Market.from_synth(mk, device=cuda)
+    assert M.lds_goods() == mk.m
+    sol = solve_and_check(mk, M, cuda, "1e8")
+    rng = np.random.default_rng(21)
+    rows = sampled_rows(mk, rng, 4000, 0)
+    tau = sol.info.eta / sol.info.omega
+    prox_and_check(mk, M, cuda, "1e8 at the solution", rows, sol.x.cpu().numpy(),
+                   sol.p.cpu().numpy(), tau)
+    x_in, p = random_state(mk, rng)
+    prox_and_check(mk, M, cuda, "1e8 random state", rows, x_in, p, 0.3 * mk.m / mk.w.sum())
+    M.close()
+
+
+def test_fisher_skewed(cuda):
+    say("skewed market: generate")
+    mk = synth.fisher_skewed(workers=12)
+    M = pdhcg.Market.from_synth(mk, device=cuda)
+    hot = M.lds_goods()
+    say(f"skewed: n={mk.n} m={mk.m} nnz={mk.nnz}, {hot} goods in LDS, bins {M.bins()}")
+    assert 0 < hot < mk.m
+    assert any(g == 0 for g, _, _ in M.bins())
+    sol = solve_and_check(mk, M, cuda, "skewed")
+    rng = np.random.default_rng(22)
+    rows = sampled_rows(mk, rng, 3000, 300)
+    x_in, p = random_state(mk, rng)
+    prox_and_check(mk, M, cuda, "skewed random state", rows, x_in, p, 0.3 * mk.m / mk.w.sum())
+    del sol
+    M.close()
+
+
+def test_batch_4096(cuda):
+    say("4096-market batch: generate")
+    bt = synth.batch_markets(4096, 1001)
+    B = pdhcg.Batch(bt, device=cuda)
+    say("4096-market batch: solve")
+    st, p, x, infos = B.solve(pdhcg.pdhcg_default_params(tol=TOL, max_iter=200000))
+    torch.cuda.synchronize()
+    assert st == pdhcg.PDHCG_OK
+    assert all(i.status == pdhcg.PDHCG_OK and i.rel_kkt <= TOL for i in infos)
+    p, x = p.cpu().numpy(), x.cpu().numpy()
+    B.close()
+    _, _, good_off, edge_off = bt.offsets()
+    say("4096-market batch: oracle KKT of every market")
+    worst = 0.0
+    for b in range(bt.count):
+        mk = bt.market(b)
+        r, _ = oracle.kkt(mk.n, mk.m, mk.row_ptr, mk.col, uhat32(mk), mk.w,
+                          x[edge_off[b]:edge_off[b + 1]], p[good_off[b]:good_off[b + 1]])
+        # float64 prices evaluated on the device, float32 prices returned
+        assert r <= TOL * 1.05, (b, r)
+        assert abs(r - infos[b].rel_kkt) <= 0.05 * r + 4 * EPS32, (b, r, infos[b].rel_kkt)
+        worst = max(worst, r)
+    say(f"4096-market batch: worst oracle KKT {worst:.3e}")
+
+
+def test_arrow_debreu_1e5(cuda):
+    say("Arrow-Debreu 1e5 x 1e5: generate")
+    mk = synth.arrow_debreu_1e5()
+    M = pdhcg.Market.from_synth(mk, device=cuda)
+    inner = pdhcg.pdhcg_default_params(tol=1e-7, max_iter=200000)
+    say(f"Arrow-Debreu: fixed point ({M.lds_goods()} goods in LDS)")
+    t = time.time()
+    res = M.arrow_debreu(mk.e_row_ptr, mk.e_col, mk.e_val, np.ones(mk.n, np.float32), inner,
+                         outer_tol=1e-6, outer_max=400)
+    torch.cuda.synchronize()
+    say(f"Arrow-Debreu: status {res['status']}, {res['outer']} outer / {res['inner']} inner "
+        f"iterations in {time.time() - t:.1f} s")
+    assert res["status"] == pdhcg.PDHCG_OK, pdhcg.pdhcg_last_error()
+    p = res["p"].double().cpu().numpy()
+    w = res["w"].double().cpu().numpy()
+    assert abs(p.sum() - mk.n) / mk.n < 1e-5
+    assert abs(w.sum() - mk.n) / mk.n < 1e-5
+    rows_e = np.repeat(np.arange(mk.n), np.diff(mk.e_row_ptr))
+    Ep = np.bincount(rows_e, weights=mk.e_val.astype(np.float64) * p[mk.e_col], minlength=mk.n)
+    assert np.max(np.abs(Ep - w) / w) < 1e-5
+    # the last inner solve: a Fisher equilibrium for the budgets E p
+    uh, _ = oracle.normalize_rows(mk.row_ptr, mk.u)
+    r, parts = oracle.kkt(mk.n, mk.m, mk.row_ptr, mk.col, uh, w, res["x"].cpu().numpy(), p)
+    say(f"Arrow-Debreu: oracle KKT of the last inner point {r:.3e} {parts}")
+    assert r <= 1e-5
+    M.close()

@@ -175,7 +175,11 @@ def main():
     launches = sum(i.row_pass_launches for i in infos)
     row_sec = sum(i.row_pass_seconds for i in infos)
     avg_launch = row_sec / max(launches, 1)
-    alg_bytes = 24 * mk.nnz + 8 * mk.n + 4 * mk.m
+    # per edge: u, x read, x written, average read and written (4 B each) and
+    # the good id (2 B when every good sits in LDS, else 4 B); per buyer the
+    # row pointer and budget; per good its price
+    id_bytes = 2 if M.lds_goods() == mk.m else 4
+    alg_bytes = (20 + id_bytes) * mk.nnz + 8 * mk.n + 4 * mk.m
     achieved = alg_bytes / avg_launch / 1e9
     traffic = traffic_from_profile()
 

@@ -102,6 +102,7 @@ struct pdhcg_market_s {
   // device, null without relabelling); goods [0, hot) use LDS.
   int32_t hot = 0;
   int32_t *perm = nullptr, *inv = nullptr;
+  uint16_t *col16 = nullptr;  // 2-byte good ids (LDS modes 1 and 3)
   uint32_t *gmax = nullptr;  // [2][m] KKT column maxima of the goods from hot on
   double *gsum = nullptr;    // [m] KKT column sums of the goods from hot on
 
@@ -112,6 +113,7 @@ struct pdhcg_market_s {
     d.nnz = nnz;
     d.hot = hot;
     d.pad_hot = 0;
+    d.col16 = col16;
     d.row_ptr = row_ptr;
     d.col = col;
     d.uh = uh;
@@ -237,7 +239,7 @@ void pdhcg_market_destroy(pdhcg_market mk) {
   f(mk->XA); f(mk->PA); f(mk->Pk); f(mk->T[0]); f(mk->T[1]);
   f(mk->colpart); f(mk->evalpart); f(mk->evalcs); f(mk->evalchunk);
   f(mk->rowpart); f(mk->colblk); f(mk->cacc); f(mk->S);
-  f(mk->colchunk); f(mk->tile_ticket); f(mk->perm); f(mk->inv); f(mk->gmax); f(mk->gsum);
+  f(mk->colchunk); f(mk->tile_ticket); f(mk->perm); f(mk->inv); f(mk->col16); f(mk->gmax); f(mk->gsum);
   for (auto &b : mk->bins) {
     f(b.d_rows);
     f(b.d_rbeg);
@@ -513,6 +515,13 @@ extern "C" int32_t pdhcg_market_create(int32_t n, int32_t m, int64_t nnz, const 
     MK_HIPC(dalloc(&mk->perm, (size_t)m));
     MK_HIPC(dalloc(&mk->inv, (size_t)m));
   }
+  std::vector<uint16_t> h_col16;
+  if (mk->lds_row == 1 || mk->lds_row == 3) {
+    if (m > 65536) return cleanup(fail(PDHCG_ERR_ARG, "internal: 16-bit good ids need m <= 65536"));
+    h_col16.resize((size_t)nnz);
+    for (int64_t k = 0; k < nnz; ++k) h_col16[(size_t)k] = (uint16_t)h_col[(size_t)k];
+    MK_HIPC(dalloc(&mk->col16, (size_t)nnz));
+  }
   MK_HIPC(dalloc(&mk->evalchunk, mk->lds_eval ? (size_t)2 * kColChunks * m : (size_t)1));
   MK_HIPC(dalloc(&mk->cacc, (size_t)kColChunks * m));  // chunk sums in LDS mode
   MK_HIPC(dalloc(&mk->rowpart, (size_t)mk->total_wg * std::max(kRowStats, kEvalRowStats)));
@@ -525,6 +534,8 @@ extern "C" int32_t pdhcg_market_create(int32_t n, int32_t m, int64_t nnz, const 
   std::memset(mk->hS, 0, sizeof(DevState));
 
   MK_HIPC(hipMemcpyAsync(mk->row_ptr, row_ptr, ((size_t)n + 1) * 4, hipMemcpyDeviceToDevice, st));
+  if (!h_col16.empty())
+    MK_HIPC(hipMemcpyAsync(mk->col16, h_col16.data(), (size_t)nnz * 2, hipMemcpyHostToDevice, st));
   if (h_perm.empty()) {
     MK_HIPC(hipMemcpyAsync(mk->col, col, (size_t)nnz * 4, hipMemcpyDeviceToDevice, st));
   } else {

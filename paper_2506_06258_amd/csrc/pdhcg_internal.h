@@ -60,6 +60,8 @@ struct MarketDev {
   int32_t pad_hot;
   const int32_t *row_ptr;
   const int32_t *col;
+  const uint16_t *col16;  // the same good ids in 16 bits, for markets whose
+                          // goods all sit in LDS (m < 65536); else null
   const float *uh;   // row-normalised utilities
   const float *w;    // budgets
   float *X0, *X1, *X2;
@@ -90,7 +92,7 @@ struct BinDev {
   const int32_t *rhi;   // per slot: one past its last entry (row_ptr + 1 without rows)
   int32_t nrows;
   int32_t wg_offset;    // first partial slot of this bin
-  int32_t rows_per_wg;
+  int32_t rows_per_wg;  // rows per workgroup (the row kernel interleaves passes instead)
 };
 
 // Inputs/outputs of a row pass.  With use_state = 1 the kernel takes the

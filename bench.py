@@ -61,6 +61,9 @@ def batched_leg(args, pdhcg, synth, torch):
     log(f"batch of {bt.count} markets generated in {time.time() - t0:.1f}s, nnz={nnz}")
     B = pdhcg.Batch(bt, device=torch.device("cuda:0"))
     prm = pdhcg.pdhcg_default_params(tol=args.tol, max_iter=200000)
+    t0 = time.time()
+    sch = B.autotune(prm, trial_iters=64)  # schedule choice, outside the timed region
+    log(f"batch schedule {sch.as_dict()} tuned in {time.time() - t0:.2f}s")
     st, _, _, infos = B.solve(prm)  # warmup
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -103,6 +106,8 @@ def batched_leg(args, pdhcg, synth, torch):
         "batched_max_rel_kkt": kkt_b,
         "batched_iters_median": float(np.median(iters_b)),
         "batched_iters_max": int(iters_b.max()),
+        "batched_schedule": sch.as_dict(),
+        "batched_longest_market_s": float(max(i.seconds for i in infos)),
         "looped_markets_per_s": mps_l,
         "looped_sample": f"{k} markets evenly spaced through the batch, one pdhcg_solve call each",
         "looped_seconds": dt_l,

@@ -262,13 +262,37 @@ int32_t pdhcg_batch_create(int32_t count, const int32_t *n, const int32_t *m,
  * Sec. 5 enhancements, active-set search) in ONE persistent launch: each
  * workgroup takes markets from a work queue (largest first) and runs a
  * market's whole solve with workgroup barriers only, so markets converge
- * and retire independently.
+ * and retire independently.  The launch (queue reset, persistent kernel)
+ * is a HIP graph built at the first call and replayed; the parameters and
+ * output pointers are read by the kernel from device memory.
  *   p_cat [sum m] and x_cat [sum nnz]: device outputs, concatenated like
- *   the inputs; infos [count]: host, per-market results (may be NULL).
+ *   the inputs; infos [count]: host, per-market results (may be NULL);
+ *   infos[b].seconds is market b's solve time on its workgroup and
+ *   infos[b].row_pass_seconds the whole launch.
  * Returns PDHCG_OK when every market reached tol, PDHCG_MAX_ITER when some
  * market ran out of iterations, or the most negative error status. */
 int32_t pdhcg_batch_solve(pdhcg_batch batch, const pdhcg_params *params,
                           float *p_cat, float *x_cat, pdhcg_info *infos);
+
+/* Schedule of the batched launch: resident workgroups per CU and the row
+ * shape policy (0: fewest lanes per row that hold the market's longest row,
+ * 1: one size wider). */
+typedef struct {
+  int32_t wg_per_cu;
+  int32_t shape_policy;
+  int32_t trials;             /* configurations timed */
+  double best_trial_seconds;  /* time of the chosen one */
+} pdhcg_batch_schedule;
+
+/* Pick the batch's schedule by timing it: every (wg_per_cu, shape_policy)
+ * candidate solves the whole batch for trial_iters iterations per market
+ * (tolerance ignored, outputs discarded; the markets' results are not
+ * kept), and the fastest is kept for later pdhcg_batch_solve calls.  It
+ * changes the schedule only, not what is computed.  out (host) may be NULL.
+ * Errors: PDHCG_ERR_ARG for a null batch or trial_iters < 1; device
+ * failures restore the previous schedule. */
+int32_t pdhcg_batch_autotune(pdhcg_batch batch, const pdhcg_params *params,
+                             int32_t trial_iters, pdhcg_batch_schedule *out);
 
 /* Offsets of market b's goods and edges in the concatenated arrays (host
  * arrays of count + 1 entries, either may be NULL). */

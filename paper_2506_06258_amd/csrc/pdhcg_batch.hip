@@ -19,6 +19,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -43,6 +44,15 @@ struct BatchInfoDev {
   double rel_kkt, eta, omega;
   int64_t iters, accepted;
   int32_t restarts, status, evals, pad;
+  int64_t ticks;  // the market's solve time in device wall-clock ticks
+};
+
+// Per-solve arguments, read by the kernel from device memory (so that one
+// graph of the solve serves every call): parameters and the caller's
+// outputs (null outputs are not written, as in the tuning runs).
+struct BatchArgs {
+  BatchParamsDev prm;
+  float *p_out, *x_out;
 };
 
 struct BatchDev {
@@ -54,7 +64,6 @@ struct BatchDev {
   const float *uh, *w, *rowmax;
   float *X0, *X1, *X2, *XA;
   double *P0, *P1, *P2, *PA, *C0, *C1, *C2;
-  float *p_out, *x_out;
   BatchInfoDev *info;
   uint32_t *queue;
 };
@@ -75,7 +84,7 @@ struct MView {
 struct WGState {
   int ix[3], ip[3], ic[3];
   int fold, done, status, restarts, evals, cand_avg, do_restart, market;
-  int64_t total, since, k_in, accepted;
+  int64_t total, since, k_in, accepted, t0;
   double eta, omega, eta0, omega0, tau, sigma, kkt0, kkt_prev, kbest;
   double kout[3];
   double kc[3], ka[3];
@@ -373,7 +382,14 @@ __device__ void wg_eval(const MView &v, int shape, WGState &S, bool has_avg, flo
   out.dpa2[1] = c[9];
 }
 
-__global__ __launch_bounds__(kBatchBlock) void k_batch_solve(BatchDev bd, BatchParamsDev prm) {
+__global__ void k_batch_reset(uint32_t *queue) {
+  if (threadIdx.x == 0) *queue = 0u;
+}
+
+__global__ __launch_bounds__(kBatchBlock) void k_batch_solve(BatchDev bd, const BatchArgs *args) {
+  const BatchParamsDev prm = args->prm;
+  float *const p_out = args->p_out;
+  float *const x_out = args->x_out;
   __shared__ double lp[kBatchMaxGoods];
   __shared__ double lc[kBatchMaxGoods];
   __shared__ unsigned int lMc[kBatchMaxGoods];
@@ -426,6 +442,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(BatchDev bd, BatchP
       S.ic[0] = 0; S.ic[1] = 1; S.ic[2] = 2;
       S.fold = 0; S.done = 0; S.status = PDHCG_MAX_ITER; S.restarts = 0; S.evals = 0;
       S.cand_avg = 0; S.do_restart = 0;
+      S.t0 = (int64_t)wall_clock64();
       S.total = 0; S.since = 0; S.k_in = 0; S.accepted = 0;
       const bool adaptive = prm.step_mode == 1;
       double kmax = 0.0;
@@ -616,8 +633,10 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(BatchDev bd, BatchP
     if (prm.output == PDHCG_OUTPUT_AVERAGE) out_avg = S.k_in > 0;
     const float *xs = v.X(uni(out_avg ? S.ix[2] : S.ix[0]));
     const double *ps = v.P(uni(out_avg ? S.ip[2] : S.ip[0]));
-    for (int k = threadIdx.x; k < nnz; k += blockDim.x) bd.x_out[eo + k] = xs[k];
-    for (int j = threadIdx.x; j < v.m; j += blockDim.x) bd.p_out[go + j] = (float)ps[j];
+    if (x_out)
+      for (int k = threadIdx.x; k < nnz; k += blockDim.x) x_out[eo + k] = xs[k];
+    if (p_out)
+      for (int j = threadIdx.x; j < v.m; j += blockDim.x) p_out[go + j] = (float)ps[j];
     if (threadIdx.x == 0) {
       BatchInfoDev &I = bd.info[b];
       for (int q = 0; q < 3; ++q) I.kkt[q] = S.kout[q];
@@ -629,6 +648,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(BatchDev bd, BatchP
       I.restarts = S.restarts;
       I.status = S.status;
       I.evals = S.evals;
+      I.ticks = (int64_t)wall_clock64() - S.t0;
     }
     __syncthreads();
   }
@@ -657,6 +677,17 @@ struct pdhcg_batch_s {
   double *C[3] = {nullptr, nullptr, nullptr};
   BatchInfoDev *info = nullptr;
   uint32_t *queue = nullptr;
+  BatchArgs *args = nullptr;  // device copy of the per-solve arguments
+  // schedule: resident workgroups per CU (0: as many as fit) and the row
+  // shape policy (0: fewest lanes per row, 1: one size wider); set by
+  // pdhcg_batch_autotune
+  int32_t wg_per_cu = 0, shape_policy = 0;
+  std::vector<int32_t> h_dmax;  // largest row degree of each market
+  // the solve as a graph (queue reset, persistent kernel), rebuilt when the
+  // grid changes
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int32_t graph_grid = 0;
 };
 
 namespace {
@@ -687,6 +718,18 @@ int32_t bfail(int32_t st, const std::string &msg) {
                    std::string(#call) + ": " + hipGetErrorString(e_));               \
   } while (0)
 
+namespace {
+
+// Row shape of a market from its largest row degree: 8x4, 16x4, 32x4,
+// 64x4, 64x8 lanes x entries (rows beyond 512 entries take the whole-wave
+// path of the 64x8 shape); policy 1 takes the next wider shape.
+int32_t batch_shape(int dmax, int policy) {
+  const int s = dmax <= 32 ? 0 : dmax <= 64 ? 1 : dmax <= 128 ? 2 : dmax <= 256 ? 3 : 4;
+  return policy == 1 ? std::min(s + 1, 4) : s;
+}
+
+}  // namespace
+
 extern "C" void pdhcg_batch_destroy(pdhcg_batch bt) {
   if (!bt) return;
   auto f = [](void *p) {
@@ -695,8 +738,10 @@ extern "C" void pdhcg_batch_destroy(pdhcg_batch bt) {
   f(bt->order); f(bt->n); f(bt->m); f(bt->shape); f(bt->rp_off); f(bt->row_off);
   f(bt->good_off); f(bt->edge_off); f(bt->sumw); f(bt->row_ptr); f(bt->col); f(bt->deg);
   f(bt->uh); f(bt->w); f(bt->rowmax); f(bt->XA); f(bt->PA); f(bt->info);
-  f(bt->queue);
+  f(bt->queue); f(bt->args);
   for (int q = 0; q < 3; ++q) { f(bt->X[q]); f(bt->P[q]); f(bt->C[q]); }
+  if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+  if (bt->graph) (void)hipGraphDestroy(bt->graph);
   delete bt;
 }
 
@@ -735,7 +780,7 @@ extern "C" int32_t pdhcg_batch_create(int32_t count, const int32_t *n, const int
   BHIPC(hipMemcpyAsync(h_w.data(), w_cat, h_w.size() * 4, hipMemcpyDeviceToHost, st));
   BHIPC(hipStreamSynchronize(st));
   std::vector<double> sumw(count);
-  std::vector<int32_t> shape(count), deg(good_off[count], 0);
+  std::vector<int32_t> shape(count), deg(good_off[count], 0), dmaxv(count);
   for (int b = 0; b < count; ++b) {
     const int32_t rc = pdhcg_validate_host(n[b], m[b], h_rp[rp_off[b] + n[b]], h_rp.data() + rp_off[b],
                                            h_col.data() + edge_off[b], h_u.data() + edge_off[b],
@@ -751,8 +796,8 @@ extern "C" int32_t pdhcg_batch_create(int32_t count, const int32_t *n, const int
     }
     for (int64_t k = edge_off[b]; k < edge_off[b + 1]; ++k) deg[good_off[b] + h_col[k]] += 1;
     sumw[b] = s;
-    // row shape: 8x4, 16x4, 32x4, 64x4, 64x8 (+ whole-wave path beyond 512)
-    shape[b] = dmax <= 32 ? 0 : dmax <= 64 ? 1 : dmax <= 128 ? 2 : dmax <= 256 ? 3 : 4;
+    dmaxv[b] = dmax;
+    shape[b] = batch_shape(dmax, 0);
   }
   std::vector<int32_t> order(count);
   std::iota(order.begin(), order.end(), 0);
@@ -773,6 +818,7 @@ extern "C" int32_t pdhcg_batch_create(int32_t count, const int32_t *n, const int
   bt->total_rows = row_off[count];
   bt->total_goods = good_off[count];
   bt->total_edges = E;
+  bt->h_dmax = dmaxv;
   auto cleanup = [&](int32_t code) {
     pdhcg_batch_destroy(bt);
     return code;
@@ -798,7 +844,7 @@ extern "C" int32_t pdhcg_batch_create(int32_t count, const int32_t *n, const int
     BK(balloc(&bt->C[q], good_off[count]));
   }
   BK(balloc(&bt->XA, E)); BK(balloc(&bt->PA, good_off[count]));
-  BK(balloc(&bt->info, count)); BK(balloc(&bt->queue, 1));
+  BK(balloc(&bt->info, count)); BK(balloc(&bt->queue, 1)); BK(balloc(&bt->args, 1));
   // normalised utilities (Sec. 5 preprocessing), on the host copy
   std::vector<float> h_uh(E), h_rowmax(row_off[count]);
   for (int b = 0; b < count; ++b)
@@ -830,16 +876,9 @@ extern "C" int32_t pdhcg_batch_create(int32_t count, const int32_t *n, const int
   return PDHCG_OK;
 }
 
-extern "C" int32_t pdhcg_batch_solve(pdhcg_batch bt, const pdhcg_params *params, float *p_cat,
-                                     float *x_cat, pdhcg_info *infos) {
-  if (!bt || !p_cat || !x_cat) return bfail(PDHCG_ERR_ARG, "null argument");
-  pdhcg_params dflt;
-  pdhcg_default_params(&dflt);
-  const pdhcg_params *p = params ? params : &dflt;
-  if (!(p->tol >= 0.0) || p->max_iter < 0 || p->eval_every <= 0 || p->max_search_rounds < 1)
-    return bfail(PDHCG_ERR_ARG, "invalid parameters");
-  if (p->search != PDHCG_SEARCH_ACTIVESET)
-    return bfail(PDHCG_ERR_UNSUPPORTED, "the batched solver uses the active-set search");
+namespace {
+
+BatchParamsDev batch_params(const pdhcg_params *p) {
   BatchParamsDev d;
   d.tol = p->tol;
   d.max_iter = p->max_iter;
@@ -857,6 +896,10 @@ extern "C" int32_t pdhcg_batch_solve(pdhcg_batch bt, const pdhcg_params *params,
   d.omega0 = p->omega0;
   d.omega_check_every = p->omega_check_every;
   d.output = p->output;
+  return d;
+}
+
+BatchDev batch_view(pdhcg_batch bt) {
   BatchDev bd;
   bd.count = bt->count;
   bd.order = bt->order; bd.n = bt->n; bd.m = bt->m; bd.shape = bt->shape;
@@ -867,27 +910,143 @@ extern "C" int32_t pdhcg_batch_solve(pdhcg_batch bt, const pdhcg_params *params,
   bd.X0 = bt->X[0]; bd.X1 = bt->X[1]; bd.X2 = bt->X[2]; bd.XA = bt->XA;
   bd.P0 = bt->P[0]; bd.P1 = bt->P[1]; bd.P2 = bt->P[2]; bd.PA = bt->PA;
   bd.C0 = bt->C[0]; bd.C1 = bt->C[1]; bd.C2 = bt->C[2];
-  bd.p_out = p_cat; bd.x_out = x_cat;
   bd.info = bt->info; bd.queue = bt->queue;
+  return bd;
+}
+
+int32_t check_params(const pdhcg_params *p) {
+  if (!(p->tol >= 0.0) || p->max_iter < 0 || p->eval_every <= 0 || p->max_search_rounds < 1)
+    return bfail(PDHCG_ERR_ARG, "invalid parameters");
+  if (p->search != PDHCG_SEARCH_ACTIVESET)
+    return bfail(PDHCG_ERR_UNSUPPORTED, "the batched solver uses the active-set search");
+  return PDHCG_OK;
+}
+
+// Resident workgroups of the persistent kernel: wg_per_cu per CU (0: as
+// many as fit), at most one per market.
+int32_t batch_grid(pdhcg_batch bt, int wg_per_cu, int *grid) {
   int dev = 0, cus = 256;
   (void)hipGetDevice(&dev);
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
     cus = prop.multiProcessorCount;
-  int per_cu = 0;
-  BHIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_solve, kBatchBlock, 0));
-  if (per_cu < 1) per_cu = 1;
-  const int grid = std::min<int64_t>((int64_t)cus * per_cu, bt->count);
-  BHIPC(hipMemsetAsync(bt->queue, 0, sizeof(uint32_t), bt->stream));
+  int fit = 0;
+  BHIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, k_batch_solve, kBatchBlock, 0));
+  fit = std::max(fit, 1);
+  const int per_cu = wg_per_cu > 0 ? std::min(wg_per_cu, fit) : fit;
+  *grid = (int)std::min<int64_t>((int64_t)cus * per_cu, bt->count);
+  return PDHCG_OK;
+}
+
+// (Re)build the solve graph for `grid` workgroups: a queue reset kernel,
+// then the persistent kernel (no memset node: the queue is cleared by a
+// kernel).
+int32_t batch_graph(pdhcg_batch bt, int grid) {
+  if (bt->exec && bt->graph_grid == grid) return PDHCG_OK;
+  if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+  if (bt->graph) (void)hipGraphDestroy(bt->graph);
+  bt->exec = nullptr;
+  bt->graph = nullptr;
+  BHIPC(hipGraphCreate(&bt->graph, 0));
+  uint32_t *queue = bt->queue;
+  void *a0[] = {&queue};
+  hipKernelNodeParams k0 = {};
+  k0.func = reinterpret_cast<void *>(k_batch_reset);
+  k0.gridDim = dim3(1);
+  k0.blockDim = dim3(64);
+  k0.sharedMemBytes = 0;
+  k0.kernelParams = a0;
+  k0.extra = nullptr;
+  hipGraphNode_t n0, n1;
+  BHIPC(hipGraphAddKernelNode(&n0, bt->graph, nullptr, 0, &k0));
+  BatchDev bd = batch_view(bt);
+  const BatchArgs *args = bt->args;
+  void *a1[] = {&bd, &args};
+  hipKernelNodeParams k1 = {};
+  k1.func = reinterpret_cast<void *>(k_batch_solve);
+  k1.gridDim = dim3(grid);
+  k1.blockDim = dim3(kBatchBlock);
+  k1.sharedMemBytes = 0;
+  k1.kernelParams = a1;
+  k1.extra = nullptr;
+  BHIPC(hipGraphAddKernelNode(&n1, bt->graph, &n0, 1, &k1));
+  BHIPC(hipGraphInstantiate(&bt->exec, bt->graph, nullptr, nullptr, 0));
+  bt->graph_grid = grid;
+  return PDHCG_OK;
+}
+
+// One solve of the whole batch with the current schedule; per-market
+// results into hi.  PDHCG_BATCH_EAGER=1 launches the two kernels directly
+// instead of the graph.
+int32_t batch_run(pdhcg_batch bt, const pdhcg_params *p, float *p_cat, float *x_cat,
+                  std::vector<BatchInfoDev> &hi, double *secs) {
+  BatchArgs ha;
+  ha.prm = batch_params(p);
+  ha.p_out = p_cat;
+  ha.x_out = x_cat;
+  int grid = 0;
+  int32_t rc = batch_grid(bt, bt->wg_per_cu, &grid);
+  if (rc != PDHCG_OK) return rc;
+  const char *eg = std::getenv("PDHCG_BATCH_EAGER");
+  const bool eager = eg && std::atoi(eg) != 0;
+  if (!eager) {
+    rc = batch_graph(bt, grid);
+    if (rc != PDHCG_OK) return rc;
+  }
+  BHIPC(hipMemcpyAsync(bt->args, &ha, sizeof(ha), hipMemcpyHostToDevice, bt->stream));
   const auto t0 = std::chrono::steady_clock::now();
-  hipLaunchKernelGGL(k_batch_solve, dim3(grid), dim3(kBatchBlock), 0, bt->stream, bd, d);
-  BHIPC(hipGetLastError());
-  std::vector<BatchInfoDev> hi(bt->count);
+  if (eager) {
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, bt->stream, bt->queue);
+    BHIPC(hipGetLastError());
+    const BatchArgs *args = bt->args;
+    hipLaunchKernelGGL(k_batch_solve, dim3(grid), dim3(kBatchBlock), 0, bt->stream, batch_view(bt),
+                       args);
+    BHIPC(hipGetLastError());
+  } else {
+    BHIPC(hipGraphLaunch(bt->exec, bt->stream));
+  }
+  hi.resize(bt->count);
   BHIPC(hipMemcpyAsync(hi.data(), bt->info, hi.size() * sizeof(BatchInfoDev),
                        hipMemcpyDeviceToHost, bt->stream));
   BHIPC(hipStreamSynchronize(bt->stream));
-  const double secs =
-      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  *secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return PDHCG_OK;
+}
+
+double tick_seconds() {
+  int dev = 0, khz = 0;
+  (void)hipGetDevice(&dev);
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+    khz = 100000;
+  return 1.0 / (1e3 * (double)khz);
+}
+
+int32_t set_shape_policy(pdhcg_batch bt, int policy) {
+  if (policy == bt->shape_policy) return PDHCG_OK;
+  std::vector<int32_t> shape(bt->count);
+  for (int b = 0; b < bt->count; ++b) shape[b] = batch_shape(bt->h_dmax[b], policy);
+  BHIPC(hipMemcpyAsync(bt->shape, shape.data(), shape.size() * 4, hipMemcpyHostToDevice,
+                       bt->stream));
+  BHIPC(hipStreamSynchronize(bt->stream));
+  bt->shape_policy = policy;
+  return PDHCG_OK;
+}
+
+}  // namespace
+
+extern "C" int32_t pdhcg_batch_solve(pdhcg_batch bt, const pdhcg_params *params, float *p_cat,
+                                     float *x_cat, pdhcg_info *infos) {
+  if (!bt || !p_cat || !x_cat) return bfail(PDHCG_ERR_ARG, "null argument");
+  pdhcg_params dflt;
+  pdhcg_default_params(&dflt);
+  const pdhcg_params *p = params ? params : &dflt;
+  int32_t rc = check_params(p);
+  if (rc != PDHCG_OK) return rc;
+  std::vector<BatchInfoDev> hi;
+  double secs = 0.0;
+  rc = batch_run(bt, p, p_cat, x_cat, hi, &secs);
+  if (rc != PDHCG_OK) return rc;
+  const double tick = tick_seconds();
   int32_t worst = PDHCG_OK;
   for (int b = 0; b < bt->count; ++b) {
     if (hi[b].status < 0) worst = std::min(worst, hi[b].status);
@@ -906,10 +1065,63 @@ extern "C" int32_t pdhcg_batch_solve(pdhcg_batch bt, const pdhcg_params *params,
       I.restarts = hi[b].restarts;
       I.status = hi[b].status;
       I.evals = hi[b].evals;
-      I.seconds = secs;
+      I.seconds = (double)hi[b].ticks * tick;  // this market's solve on its workgroup
+      I.row_pass_seconds = secs;               // the whole launch
     }
   }
   return worst;
+}
+
+extern "C" int32_t pdhcg_batch_autotune(pdhcg_batch bt, const pdhcg_params *params,
+                                        int32_t trial_iters, pdhcg_batch_schedule *out) {
+  if (!bt) return bfail(PDHCG_ERR_ARG, "null batch");
+  if (trial_iters < 1) return bfail(PDHCG_ERR_ARG, "trial_iters must be >= 1");
+  pdhcg_params p;
+  if (params) p = *params;
+  else pdhcg_default_params(&p);
+  p.tol = 0.0;  // every market runs trial_iters iterations
+  p.max_iter = trial_iters;
+  int32_t rc = check_params(&p);
+  if (rc != PDHCG_OK) return rc;
+  int fit = 0;
+  BHIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, k_batch_solve, kBatchBlock, 0));
+  fit = std::max(fit, 1);
+  const int old_wg = bt->wg_per_cu, old_policy = bt->shape_policy;
+  double best = INFINITY;
+  int best_wg = fit, best_policy = 0, trials = 0;
+  std::vector<BatchInfoDev> hi;
+  for (int policy = 0; policy < 2; ++policy) {
+    rc = set_shape_policy(bt, policy);
+    if (rc != PDHCG_OK) break;
+    for (int wg = 1; wg <= fit; ++wg) {
+      bt->wg_per_cu = wg;
+      double secs = 0.0;
+      rc = batch_run(bt, &p, nullptr, nullptr, hi, &secs);
+      if (rc != PDHCG_OK) break;
+      ++trials;
+      if (secs < best) {
+        best = secs;
+        best_wg = wg;
+        best_policy = policy;
+      }
+    }
+    if (rc != PDHCG_OK) break;
+  }
+  if (rc != PDHCG_OK) {
+    bt->wg_per_cu = old_wg;
+    (void)set_shape_policy(bt, old_policy);
+    return rc;
+  }
+  bt->wg_per_cu = best_wg;
+  rc = set_shape_policy(bt, best_policy);
+  if (rc != PDHCG_OK) return rc;
+  if (out) {
+    out->wg_per_cu = best_wg;
+    out->shape_policy = best_policy;
+    out->trials = trials;
+    out->best_trial_seconds = best;
+  }
+  return PDHCG_OK;
 }
 
 extern "C" int32_t pdhcg_batch_layout(pdhcg_batch bt, int64_t *good_off, int64_t *edge_off) {

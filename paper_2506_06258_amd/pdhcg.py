@@ -35,7 +35,8 @@ EXPORTS = (
     "pdhcg_set_budgets", "pdhcg_solve", "pdhcg_kkt", "pdhcg_row_prox",
     "pdhcg_arrow_debreu", "pdhcg_backward", "pdhcg_market_bins", "pdhcg_market_lds_goods",
     "pdhcg_market_destroy",
-    "pdhcg_batch_create", "pdhcg_batch_solve", "pdhcg_batch_layout", "pdhcg_batch_destroy",
+    "pdhcg_batch_create", "pdhcg_batch_solve", "pdhcg_batch_autotune", "pdhcg_batch_layout",
+    "pdhcg_batch_destroy",
 )
 
 
@@ -61,6 +62,14 @@ class pdhcg_info(C.Structure):
         ("search_rounds_max", C.c_int32), ("search_rounds_mean", C.c_double),
         ("row_pass_seconds", C.c_double), ("row_pass_launches", C.c_int64),
     ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class pdhcg_batch_schedule(C.Structure):
+    _fields_ = [("wg_per_cu", C.c_int32), ("shape_policy", C.c_int32), ("trials", C.c_int32),
+                ("best_trial_seconds", C.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -99,6 +108,8 @@ def lib() -> C.CDLL:
         "pdhcg_market_destroy": (None, [vp]),
         "pdhcg_batch_create": (i32, [i32, vp, vp, vp, vp, vp, vp, vp, C.POINTER(vp)]),
         "pdhcg_batch_solve": (i32, [vp, C.POINTER(pdhcg_params), vp, vp, vp]),
+        "pdhcg_batch_autotune": (i32, [vp, C.POINTER(pdhcg_params), i32,
+                                       C.POINTER(pdhcg_batch_schedule)]),
         "pdhcg_batch_layout": (i32, [vp, vp, vp]),
         "pdhcg_batch_destroy": (None, [vp]),
     }
@@ -393,6 +404,14 @@ def pdhcg_batch_solve(h, params: pdhcg_params, p_cat, x_cat, count: int):
     return st, list(infos)
 
 
+def pdhcg_batch_autotune(h, params: Optional[pdhcg_params], trial_iters: int
+                         ) -> pdhcg_batch_schedule:
+    out = pdhcg_batch_schedule()
+    _check(lib().pdhcg_batch_autotune(h, C.byref(params) if params is not None else None,
+                                      int(trial_iters), C.byref(out)), "pdhcg_batch_autotune")
+    return out
+
+
 def pdhcg_batch_layout(h, count: int):
     import numpy as np
     g = np.zeros(count + 1, np.int64)
@@ -438,6 +457,10 @@ class Batch:
         x = torch.empty(int(self.edge_off[-1]), dtype=torch.float32, device=self.device)
         st, infos = pdhcg_batch_solve(self._h, prm, p, x, self.count)
         return st, p, x, infos
+
+    def autotune(self, params: Optional[pdhcg_params] = None, trial_iters: int = 64):
+        """Time the schedule candidates and keep the fastest (pdhcg_batch_autotune)."""
+        return pdhcg_batch_autotune(self._h, params, trial_iters)
 
 
 class FisherPrices(torch.autograd.Function):

@@ -79,3 +79,52 @@ def test_batch_max_iter_and_rejects_oversized(cuda):
     with pytest.raises(pdhcg.PDHCGError) as e:
         pdhcg.Batch(big, device=cuda)
     assert e.value.status == pdhcg.PDHCG_ERR_UNSUPPORTED
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def test_graph_replays_match_eager_launch(cuda, monkeypatch, small_batch):
+    """The solve runs as a replayed HIP graph; each replay, with eager device
+    work and synchronisations in between, reaches the prices of a directly
+    launched solve (column sums are float64 LDS atomics in no fixed order,
+    so runs agree to the solve tolerance, not bit for bit)."""
+    B = pdhcg.Batch(small_batch, device=cuda)
+    monkeypatch.setenv("PDHCG_BATCH_EAGER", "1")
+    st, p_e, _, _ = B.solve(tol=1e-7, max_iter=200000)
+    assert st == pdhcg.PDHCG_OK
+    p_e = p_e.double().cpu().numpy()
+    monkeypatch.delenv("PDHCG_BATCH_EAGER")
+    for rep in range(3):
+        junk = torch.randn(1 << 20, device=cuda)
+        (junk * 2.0).sum().item()
+        torch.cuda.synchronize()
+        st, p_g, _, infos = B.solve(tol=1e-7, max_iter=200000)
+        assert st == pdhcg.PDHCG_OK, rep
+        assert all(i.rel_kkt <= 1e-7 for i in infos)
+        for b in range(small_batch.count):
+            sl = slice(B.good_off[b], B.good_off[b + 1])
+            assert _rel(p_g.double().cpu().numpy()[sl], p_e[sl]) <= 2e-5, (rep, b)
+        # per-market times are reported and bounded by the launch
+        assert all(0.0 < i.seconds <= i.row_pass_seconds * 1.01 + 1e-3 for i in infos)
+    B.close()
+
+
+def test_autotune_keeps_results(cuda, small_batch):
+    B = pdhcg.Batch(small_batch, device=cuda)
+    sch = B.autotune(trial_iters=32)
+    assert sch.trials >= 2 and sch.wg_per_cu >= 1 and sch.shape_policy in (0, 1)
+    assert sch.best_trial_seconds > 0.0
+    st, p, _, infos = B.solve(tol=1e-7, max_iter=200000)
+    assert st == pdhcg.PDHCG_OK
+    p = p.double().cpu().numpy()
+    for b in (0, 5, 11, 24):
+        mk = small_batch.market(b)
+        ref = oracle.solve(mk.n, mk.m, mk.row_ptr, mk.col, mk.u.astype(np.float64),
+                           mk.w.astype(np.float64), tol=1e-11, max_iter=400000)
+        assert _rel(p[B.good_off[b]:B.good_off[b + 1]], ref.p) <= 1e-5, b
+    with pytest.raises(pdhcg.PDHCGError) as e:
+        B.autotune(trial_iters=0)
+    assert e.value.status == pdhcg.PDHCG_ERR_ARG
+    B.close()

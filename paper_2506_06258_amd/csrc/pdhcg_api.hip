@@ -86,7 +86,6 @@ struct pdhcg_market_s {
   double *evalcs = nullptr;
   uint32_t *evalchunk = nullptr;
   double *rowpart = nullptr, *colblk = nullptr, *cacc = nullptr, *colchunk = nullptr;
-  uint32_t *tile_ticket = nullptr;
   DevState *S = nullptr;   // device
   DevState *hS = nullptr;  // pinned host shadow
   // host data
@@ -133,7 +132,6 @@ struct pdhcg_market_s {
     d.rowpart = rowpart;
     d.colblk = colblk;
     d.colchunk = colchunk;
-    d.tile_ticket = tile_ticket;
     d.S = S;
     return d;
   }
@@ -239,7 +237,7 @@ void pdhcg_market_destroy(pdhcg_market mk) {
   f(mk->XA); f(mk->PA); f(mk->Pk); f(mk->T[0]); f(mk->T[1]);
   f(mk->colpart); f(mk->evalpart); f(mk->evalcs); f(mk->evalchunk);
   f(mk->rowpart); f(mk->colblk); f(mk->cacc); f(mk->S);
-  f(mk->colchunk); f(mk->tile_ticket); f(mk->perm); f(mk->inv); f(mk->col16); f(mk->gmax); f(mk->gsum);
+  f(mk->colchunk); f(mk->perm); f(mk->inv); f(mk->col16); f(mk->gmax); f(mk->gsum);
   for (auto &b : mk->bins) {
     f(b.d_rows);
     f(b.d_rbeg);
@@ -527,8 +525,6 @@ extern "C" int32_t pdhcg_market_create(int32_t n, int32_t m, int64_t nnz, const 
   MK_HIPC(dalloc(&mk->rowpart, (size_t)mk->total_wg * std::max(kRowStats, kEvalRowStats)));
   MK_HIPC(dalloc(&mk->colblk, (size_t)mk->col_blocks * std::max(kColStats, kEvalColStats)));
   MK_HIPC(dalloc(&mk->colchunk, (size_t)kColChunks * m));
-  MK_HIPC(dalloc(&mk->tile_ticket, (size_t)mk->col_blocks));
-  MK_HIPC(hipMemsetAsync(mk->tile_ticket, 0, (size_t)mk->col_blocks * sizeof(uint32_t), st));
   MK_HIPC(dalloc(&mk->S, 1));
   MK_HIPC(hipHostMalloc((void **)&mk->hS, sizeof(DevState), hipHostMallocDefault));
   std::memset(mk->hS, 0, sizeof(DevState));

@@ -73,7 +73,6 @@ struct MarketDev {
   double *rowpart;   // [total_wg][kRowStats]
   double *colblk;    // [col blocks][kColStats or kEvalColStats]
   double *colchunk;  // [kColChunks][m] chunk sums of the column partials
-  uint32_t *tile_ticket; // [col blocks] arrival counters (zero between launches)
   DevState *S;
 };
 

@@ -360,51 +360,48 @@ __global__ __launch_bounds__(kColBlock) void k_pstep(MarketDev md, int zero_ctry
 // dp^T (c_try - c) and |dp|^2, and the last tile to arrive applies the
 // step-size rule of Sec. 5 and updates DevState.  Without partials (global
 // atomics) there is one chunk and c_try is already complete.
-__global__ __launch_bounds__(kColBlock) void k_col_decide(MarketDev md, int total_wg,
-                                                          int from_partials) {
+// Chunk sums of the per-workgroup column partials: block (t, q) adds the
+// partial rows of chunk q for tile t's goods (partial rows cover the goods
+// [0, hot): all goods unless the market is hybrid, where the others are
+// summed by device atomics in c_try).  A kernel of its own, so that the sums
+// reach k_col_decide through the kernel boundary rather than a device-scope
+// fence per block (on gfx950 a fence writes back and invalidates the L2).
+__global__ __launch_bounds__(kColBlock) void k_col_chunks(MarketDev md, int total_wg) {
+  const int hot = md.hot;
+  const int q = blockIdx.y, nq = gridDim.y;
+  const int j = blockIdx.x * kColBlock + threadIdx.x;
+  if (j >= hot) return;
+  const int per = (total_wg + nq - 1) / nq;
+  const int b0 = q * per, b1 = min(total_wg, b0 + per);
+  double c = 0.0;
+  const double *src = md.colpart + j;
+  int b = b0;
+  for (; b + 8 <= b1; b += 8) {  // eight loads in flight per thread
+    double v[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) v[t] = src[(size_t)(b + t) * hot];
+    c += ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+  }
+  for (; b < b1; ++b) c += src[(size_t)b * hot];
+  md.colchunk[(size_t)q * md.m + j] = c;
+}
+
+// c_try from the chunk sums (nq chunks, fixed order), dp^T (c_try - c) and
+// |dp|^2 per block, and the last block to arrive applies the step rule.
+__global__ __launch_bounds__(kColBlock) void k_col_decide(MarketDev md, int total_wg, int nq) {
   DevState *S = md.S;
   const int m = md.m;
-  const int tile = blockIdx.x, q = blockIdx.y, nq = gridDim.y;
+  const int tile = blockIdx.x;
   const int j = tile * kColBlock + threadIdx.x;
   const double *pc = pick3<double *>(md.P0, md.P1, md.P2, S->ip[0]);
   const double *pt = pick3<double *>(md.P0, md.P1, md.P2, S->ip[1]);
   const double *ccur = pick3<double *>(md.C0, md.C1, md.C2, S->ic[1]);
   double *ctry = pick3<double *>(md.C0, md.C1, md.C2, S->ic[2]);
-  __shared__ bool last_chunk, last_tile;
-  if (from_partials) {
-    // partial rows cover the goods [0, hot) (all goods unless the market
-    // is hybrid, where the others are summed by device atomics in c_try)
-    const int hot = md.hot;
-    const int per = (total_wg + nq - 1) / nq;
-    const int b0 = q * per, b1 = min(total_wg, b0 + per);
-    if (j < hot) {
-      double c = 0.0;
-      const double *src = md.colpart + j;
-      int b = b0;
-      for (; b + 8 <= b1; b += 8) {  // eight loads in flight per thread
-        double v[8];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) v[t] = src[(size_t)(b + t) * hot];
-        c += ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
-      }
-      for (; b < b1; ++b) c += src[(size_t)b * hot];
-      md.colchunk[(size_t)q * m + j] = c;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      __threadfence();
-      const uint32_t t = atomicAdd(&md.tile_ticket[tile], 1u);
-      last_chunk = (t == (uint32_t)nq - 1);
-    }
-    __syncthreads();
-    if (!last_chunk) return;
-    __threadfence();
-    if (j < hot) {
-      double c = 0.0;
-      for (int k = 0; k < nq; ++k) c += md.colchunk[(size_t)k * m + j];
-      ctry[j] = c;
-    }
-    if (threadIdx.x == 0) md.tile_ticket[tile] = 0u;
+  __shared__ bool last_tile;
+  if (nq > 0 && j < md.hot) {
+    double c = 0.0;
+    for (int k = 0; k < nq; ++k) c += md.colchunk[(size_t)k * m + j];
+    ctry[j] = c;
   }
   double inter = 0.0, dp2 = 0.0;
   if (j < m) {
@@ -1009,9 +1006,15 @@ hipError_t launch_pstep(const MarketDev &md, int zero_ctry, hipStream_t st) {
 hipError_t launch_col_decide(const MarketDev &md, int total_wg, int from_partials,
                              hipStream_t st) {
   const int tiles = (md.m + kColBlock - 1) / kColBlock;
-  const int chunks = from_partials ? (total_wg < kColChunks ? total_wg : kColChunks) : 1;
-  hipLaunchKernelGGL(k_col_decide, dim3(tiles, chunks), dim3(kColBlock), 0, st, md, total_wg,
-                     from_partials);
+  const int chunks = from_partials ? (total_wg < kColChunks ? total_wg : kColChunks) : 0;
+  if (chunks > 0 && md.hot > 0) {
+    hipLaunchKernelGGL(k_col_chunks, dim3((md.hot + kColBlock - 1) / kColBlock, chunks),
+                       dim3(kColBlock), 0, st, md, total_wg);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_col_decide, dim3(tiles), dim3(kColBlock), 0, st, md, total_wg,
+                     md.hot > 0 ? chunks : 0);
   return hipGetLastError();
 }
 

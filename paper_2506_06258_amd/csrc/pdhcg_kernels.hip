@@ -397,7 +397,6 @@ __global__ __launch_bounds__(kColBlock) void k_col_decide(MarketDev md, int tota
   const double *pt = pick3<double *>(md.P0, md.P1, md.P2, S->ip[1]);
   const double *ccur = pick3<double *>(md.C0, md.C1, md.C2, S->ic[1]);
   double *ctry = pick3<double *>(md.C0, md.C1, md.C2, S->ic[2]);
-  __shared__ bool last_tile;
   if (nq > 0 && j < md.hot) {
     double c = 0.0;
     for (int k = 0; k < nq; ++k) c += md.colchunk[(size_t)k * m + j];
@@ -411,7 +410,6 @@ __global__ __launch_bounds__(kColBlock) void k_col_decide(MarketDev md, int tota
     dp2 = dp * dp;
   }
   __shared__ double sh[2][kColBlock / kWave];
-  __shared__ double shx[kColBlock / kWave];
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   inter = wave_sum_d(inter);
   dp2 = wave_sum_d(dp2);
@@ -428,16 +426,18 @@ __global__ __launch_bounds__(kColBlock) void k_col_decide(MarketDev md, int tota
     }
     md.colblk[(size_t)tile * kColStats + 0] = a;
     md.colblk[(size_t)tile * kColStats + 1] = qq;
-    __threadfence();
-    const uint32_t t = atomicAdd(&S->ticket, 1u);
-    last_tile = (t == gridDim.x - 1);
   }
-  __syncthreads();
-  if (!last_tile) return;
-  __threadfence();
-  // Last tile: global sums and the step-size rule.
+}
+
+// Global sums and the step-size rule, in one block after k_col_decide (the
+// block statistics arrive through the kernel boundary).
+__global__ __launch_bounds__(kColBlock) void k_step_rule(MarketDev md, int total_wg, int tiles) {
+  DevState *S = md.S;
+  __shared__ double sh[2][kColBlock / kWave];
+  __shared__ double shx[kColBlock / kWave];
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   double a = 0.0, qq = 0.0, x2 = 0.0;
-  for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x) {
+  for (int b = threadIdx.x; b < tiles; b += blockDim.x) {
     a += md.colblk[(size_t)b * kColStats + 0];
     qq += md.colblk[(size_t)b * kColStats + 1];
   }
@@ -459,7 +459,6 @@ __global__ __launch_bounds__(kColBlock) void k_col_decide(MarketDev md, int tota
     qq += sh[1][w];
     x2 += shx[w];
   }
-  S->ticket = 0u;
   S->total += 1;
   S->since += 1;
   bool accept = true;
@@ -489,7 +488,6 @@ __global__ __launch_bounds__(kColBlock) void k_col_decide(MarketDev md, int tota
     S->fold = 0;
   }
   S->accept_last = accept ? 1 : 0;
-  __threadfence();
 }
 
 // ---------------------------------------------------------- KKT row pass ---
@@ -706,7 +704,6 @@ __global__ __launch_bounds__(kColBlock) void k_eval_chunks(MarketDev md, EvalIO 
 // KKT error of Sec. 5 and writes it, with the anchor distances, to DevState.
 __global__ __launch_bounds__(kColBlock) void k_eval_col(MarketDev md, EvalIO io, int total_wg,
                                                         int partials) {
-  DevState *S = md.S;
   const int m = md.m;
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   const bool has_avg = io.xa != nullptr;
@@ -762,7 +759,6 @@ __global__ __launch_bounds__(kColBlock) void k_eval_col(MarketDev md, EvalIO io,
     }
   }
   __shared__ double red[kColBlock / kWave][10];
-  __shared__ bool last;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   for (int q = 0; q < 10; ++q) {
     const double v = (q >= 8) ? wave_sum_d(st[q]) : wave_max_d(st[q]);
@@ -776,21 +772,22 @@ __global__ __launch_bounds__(kColBlock) void k_eval_col(MarketDev md, EvalIO io,
         v = (q >= 8) ? v + red[w][q] : fmax(v, red[w][q]);
       md.colblk[(size_t)blockIdx.x * kEvalColStats + q] = v;
     }
-    __threadfence();
-    const uint32_t t = atomicAdd(&S->ticket_eval, 1u);
-    last = (t == gridDim.x - 1);
   }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  // Every thread of the last block combines a strided share of the block
-  // and workgroup statistics, then a fixed-order block reduction.
+}
+
+// The relative KKT errors from the block statistics of k_eval_col and the
+// workgroup statistics of the row kernels, in one block (both arrive
+// through the kernel boundary).  Every thread combines a strided share,
+// then a fixed-order block reduction.
+__global__ __launch_bounds__(kColBlock) void k_eval_final(MarketDev md, int total_wg, int tiles) {
+  DevState *S = md.S;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   double c[10], rw[10];
   for (int q = 0; q < 10; ++q) {
     c[q] = (q == 3 || q == 7) ? -INFINITY : 0.0;
     rw[q] = 0.0;
   }
-  for (int b = threadIdx.x; b < (int)gridDim.x; b += blockDim.x)
+  for (int b = threadIdx.x; b < tiles; b += blockDim.x)
     for (int q = 0; q < 10; ++q) {
       const double v = md.colblk[(size_t)b * kEvalColStats + q];
       c[q] = (q >= 8) ? c[q] + v : fmax(c[q], v);
@@ -833,8 +830,6 @@ __global__ __launch_bounds__(kColBlock) void k_eval_col(MarketDev md, EvalIO io,
   S->dxa2[1] = rw[9];
   S->dpa2[0] = c[8];
   S->dpa2[1] = c[9];
-  S->ticket_eval = 0u;
-  __threadfence();
 }
 
 // ------------------------------------------------------------ utilities ----
@@ -1015,6 +1010,9 @@ hipError_t launch_col_decide(const MarketDev &md, int total_wg, int from_partial
   }
   hipLaunchKernelGGL(k_col_decide, dim3(tiles), dim3(kColBlock), 0, st, md, total_wg,
                      md.hot > 0 ? chunks : 0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_step_rule, dim3(1), dim3(kColBlock), 0, st, md, total_wg, tiles);
   return hipGetLastError();
 }
 
@@ -1028,8 +1026,11 @@ hipError_t launch_eval_chunks(const MarketDev &md, const EvalIO &io, int total_w
 
 hipError_t launch_eval_col(const MarketDev &md, const EvalIO &io, int total_wg,
                            int partials, hipStream_t st) {
-  hipLaunchKernelGGL(k_eval_col, dim3((md.m + kColBlock - 1) / kColBlock), dim3(kColBlock), 0,
-                     st, md, io, total_wg, partials);
+  const int tiles = (md.m + kColBlock - 1) / kColBlock;
+  hipLaunchKernelGGL(k_eval_col, dim3(tiles), dim3(kColBlock), 0, st, md, io, total_wg, partials);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_eval_final, dim3(1), dim3(kColBlock), 0, st, md, total_wg, tiles);
   return hipGetLastError();
 }
 

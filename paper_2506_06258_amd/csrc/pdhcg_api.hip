@@ -256,7 +256,7 @@ namespace {
 // each load of a segment at least 32 contiguous bytes).
 void choose_shape(int d, int *G, int *E) {
   static const int Gs[] = {8, 16, 32, 64};
-  static const int Es[] = {1, 2, 4, 8};
+  static const int Es[] = {1, 2, 4, 6, 7, 8};
   int bestG = 64, bestE = 16, best = 1 << 30;
   for (int g : Gs)
     for (int e : Es) {
@@ -264,7 +264,7 @@ void choose_shape(int d, int *G, int *E) {
       // fewest slots; among those the fewest lanes per row (fewer
       // reduction steps per row; measured faster on 100-entry rows:
       // G=16,E=8 0.80 ms, 32,4 0.83 ms, 64,2 1.01 ms per pass)
-      if (slots >= d && slots < best) {
+      if (row_variant_exists(g, e) && slots >= d && slots < best) {
         best = slots;
         bestG = g;
         bestE = e;

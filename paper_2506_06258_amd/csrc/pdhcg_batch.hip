@@ -30,6 +30,7 @@ namespace pdhcg {
 constexpr int kBatchBlock = 512;
 constexpr int kBatchWaves = kBatchBlock / kWave;
 constexpr int kBatchMaxGoods = 2048;
+constexpr int kEvalUnroll = 4;  // entries per lane loaded together in the KKT passes
 
 struct BatchParamsDev {
   double tol;
@@ -147,15 +148,32 @@ __device__ double wg_rows_step(const MView &v, const double *lp, double *lc, con
       const double sfin =
           prox_row_long(beg, d, tau, tw, v.uh, v.col, xin, pget, max_rounds, rtol, rounds);
       const double tf = tw * fast_rcp(sfin);
-      for (int k = lane; k < d; k += kWave) {
-        const int q = beg + k;
-        const float xk = xin[q];
-        const double a = fma(-tau, lp[v.col[q]], (double)xk);
-        const float xn = (float)fmax(fma((double)v.uh[q], tf, a), 0.0);
-        xout[q] = xn;
-        if (wfold != 0.0f) xavg[q] = (wfold == 1.0f) ? xk : fmaf(xk - xavg[q], wfold, xavg[q]);
-        dx2 += (double)(xn - xk) * (double)(xn - xk);
-        atomicAdd(&lc[v.col[q]], (double)xn);
+      const bool fold_read = wfold != 0.0f && wfold != 1.0f;
+      // final sweep in chunks, every load of a chunk issued first
+      for (int base2 = 0; base2 < d; base2 += kWave * kLongUnroll) {
+        float uu[kLongUnroll], xk[kLongUnroll], y[kLongUnroll];
+        int c[kLongUnroll];
+#pragma unroll
+        for (int e = 0; e < kLongUnroll; ++e) {
+          const int q = beg + min(base2 + lane + kWave * e, d - 1);
+          uu[e] = v.uh[q];
+          c[e] = v.col[q];
+          xk[e] = xin[q];
+          y[e] = fold_read ? xavg[q] : 0.0f;
+        }
+#pragma unroll
+        for (int e = 0; e < kLongUnroll; ++e) {
+          const int k = base2 + lane + kWave * e;
+          if (k < d) {
+            const int q = beg + k;
+            const double a = fma(-tau, lp[c[e]], (double)xk[e]);
+            const float xn = (float)fmax(fma((double)uu[e], tf, a), 0.0);
+            xout[q] = xn;
+            if (wfold != 0.0f) xavg[q] = fold_read ? fmaf(xk[e] - y[e], wfold, y[e]) : xk[e];
+            dx2 += (double)(xn - xk[e]) * (double)(xn - xk[e]);
+            atomicAdd(&lc[c[e]], (double)xn);
+          }
+        }
       }
       continue;
     }
@@ -206,26 +224,37 @@ __device__ void wg_rows_eval(const MView &v, const float *xc, const double *pc, 
     const bool rv = i < v.n;
     const int beg = rv ? v.rp[i] : 0;
     const int d = rv ? v.rp[i + 1] - beg : 0;
+    // entries in chunks of G * kEvalUnroll per segment, every load of a
+    // chunk issued before any is used (indices past the row end clamped to
+    // its last entry and skipped)
+    constexpr int U = kEvalUnroll;
     double tc = 0.0, ta = 0.0;
-    for (int k = r; k < d; k += G) {
-      const int q = beg + k;
-      const float x = xc[q];
-      tc = fma((double)v.uh[q], (double)x, tc);
-      if (has_avg) {
-        float y = xa[q];
-        if (wf != 0.0f) {
-          y = (wf == 1.0f) ? x : fmaf(x - y, wf, y);
-          xa[q] = y;
-        }
-        ta = fma((double)v.uh[q], (double)y, ta);
-        if (xanc) {
-          const double z = xanc[q];
-          st[9] += ((double)y - z) * ((double)y - z);
-        }
+    for (int k0 = r; k0 < d; k0 += G * U) {
+      float x[U], uu[U], y[U], z[U];
+#pragma unroll
+      for (int e = 0; e < U; ++e) {
+        const int q = beg + min(k0 + G * e, d - 1);
+        x[e] = xc[q];
+        uu[e] = v.uh[q];
+        y[e] = has_avg ? xa[q] : 0.0f;
+        z[e] = xanc ? xanc[q] : 0.0f;
       }
-      if (xanc) {
-        const double z = xanc[q];
-        st[8] += ((double)x - z) * ((double)x - z);
+#pragma unroll
+      for (int e = 0; e < U; ++e) {
+        const int k = k0 + G * e;
+        if (k < d) {
+          tc = fma((double)uu[e], (double)x[e], tc);
+          if (has_avg) {
+            float yy = y[e];
+            if (wf != 0.0f) {
+              yy = (wf == 1.0f) ? x[e] : fmaf(x[e] - yy, wf, yy);
+              xa[beg + k] = yy;
+            }
+            ta = fma((double)uu[e], (double)yy, ta);
+            if (xanc) st[9] += ((double)yy - (double)z[e]) * ((double)yy - (double)z[e]);
+          }
+          if (xanc) st[8] += ((double)x[e] - (double)z[e]) * ((double)x[e] - (double)z[e]);
+        }
       }
     }
     tc = seg_sum_d<G>(tc);
@@ -239,30 +268,47 @@ __device__ void wg_rows_eval(const MView &v, const float *xc, const double *pc, 
       if (tc_out) tc_out[i] = (float)(tc * (double)v.rowmax[i]);
       if (ta_out && has_avg) ta_out[i] = (float)(ta * (double)v.rowmax[i]);
     }
-    for (int k = r; k < d; k += G) {
-      const int q = beg + k;
-      const int c = v.col[q];
-      const double u = v.uh[q];
-      const double x = xc[q];
-      const double vc = u * yc, rc = pc[c] - vc;
-      if (rc > 0.0) {
-        st[2] = fmax(st[2], rc);
-        st[1] = fmax(st[1], x * rc);
+    for (int k0 = r; k0 < d; k0 += G * U) {
+      int c[U];
+      float uu[U], x[U], y[U];
+      double pcj[U], paj[U];
+#pragma unroll
+      for (int e = 0; e < U; ++e) {
+        const int q = beg + min(k0 + G * e, d - 1);
+        c[e] = v.col[q];
+        uu[e] = v.uh[q];
+        x[e] = xc[q];
+        y[e] = has_avg ? xa[q] : 0.0f;
       }
-      st[3] = fmax(st[3], x);
-      atomicMax(&lMc[c], ord_key((float)(vc - pc[c])));
-      if (has_avg) {
-        const double y = xa[q];
-        const double va = u * ya, ra = pa_folded[c] - va;
-        if (ra > 0.0) {
-          st[6] = fmax(st[6], ra);
-          st[5] = fmax(st[5], y * ra);
+#pragma unroll
+      for (int e = 0; e < U; ++e) {
+        pcj[e] = pc[c[e]];
+        paj[e] = has_avg ? pa_folded[c[e]] : 0.0;
+      }
+#pragma unroll
+      for (int e = 0; e < U; ++e) {
+        if (k0 + G * e < d) {
+          const double u = uu[e];
+          const double vc = u * yc, rc = pcj[e] - vc;
+          if (rc > 0.0) {
+            st[2] = fmax(st[2], rc);
+            st[1] = fmax(st[1], (double)x[e] * rc);
+          }
+          st[3] = fmax(st[3], (double)x[e]);
+          atomicMax(&lMc[c[e]], ord_key((float)(vc - pcj[e])));
+          if (has_avg) {
+            const double va = u * ya, ra = paj[e] - va;
+            if (ra > 0.0) {
+              st[6] = fmax(st[6], ra);
+              st[5] = fmax(st[5], (double)y[e] * ra);
+            }
+            st[7] = fmax(st[7], (double)y[e]);
+            atomicMax(&lMa[c[e]], ord_key((float)(va - paj[e])));
+            if (!sum_cur) atomicAdd(&lcs[c[e]], (double)y[e]);
+          }
+          if (sum_cur) atomicAdd(&lcs[c[e]], (double)x[e]);
         }
-        st[7] = fmax(st[7], y);
-        atomicMax(&lMa[c], ord_key((float)(va - pa_folded[c])));
-        if (!sum_cur) atomicAdd(&lcs[c], y);
       }
-      if (sum_cur) atomicAdd(&lcs[c], x);
     }
   }
 }

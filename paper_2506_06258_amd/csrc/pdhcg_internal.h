@@ -80,7 +80,7 @@ struct MarketDev {
 #define PDHCG_ROW_VARIANTS(X) \
   X(4, 1) X(4, 2) X(4, 4) X(4, 8) \
   X(8, 1) X(8, 2) X(8, 4) X(8, 8) \
-  X(16, 1) X(16, 2) X(16, 4) X(16, 8) \
+  X(16, 1) X(16, 2) X(16, 4) X(16, 6) X(16, 7) X(16, 8) \
   X(32, 1) X(32, 2) X(32, 4) X(32, 8) \
   X(64, 1) X(64, 2) X(64, 4) X(64, 8)
 

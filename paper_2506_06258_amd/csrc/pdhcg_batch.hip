@@ -128,76 +128,111 @@ __device__ __forceinline__ double block_max(double v, double *red) {
 // lagged fold of x_cur into x_avg, |x_try - x_cur|^2 (returned, this
 // thread's share) and float64 column sums into lc.
 template <int G, int E>
-__device__ double wg_rows_step(const MView &v, const double *lp, double *lc, const float *xin,
+__device__ __attribute__((noinline)) double wg_rows_step(const MView &v, const double *lp, double *lc, const float *xin,
                                float *xout, float *xavg, double tau, float wfold, int max_rounds,
                                double rtol) {
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int r = lane & (G - 1), seg = lane / G;
   constexpr int kSeg = kWave / G;
+  constexpr int kStride = kBatchWaves * kSeg;  // rows per workgroup pass
+  const bool fold_read = wfold != 0.0f && wfold != 1.0f;
   double dx2 = 0.0;
   auto pget = [&](int c) { return lp[c]; };
-  for (int base = wave * kSeg; base < v.n; base += kBatchWaves * kSeg) {
-    const int i = base + seg;
-    const bool rv = i < v.n;
-    const int beg = rv ? v.rp[i] : 0;
-    const int d = rv ? v.rp[i + 1] - beg : 0;
-    const double tw = rv ? tau * (double)v.w[i] : 0.0;
-    // rows beyond the register capacity: whole-wave path (only G = 64)
-    if (G == kWave && E * G < d) {
-      int rounds = 0;
-      const double sfin =
-          prox_row_long(beg, d, tau, tw, v.uh, v.col, xin, pget, max_rounds, rtol, rounds);
-      const double tf = tw * fast_rcp(sfin);
-      const bool fold_read = wfold != 0.0f && wfold != 1.0f;
-      // final sweep in chunks, every load of a chunk issued first
-      for (int base2 = 0; base2 < d; base2 += kWave * kLongUnroll) {
-        float uu[kLongUnroll], xk[kLongUnroll], y[kLongUnroll];
-        int c[kLongUnroll];
+  // rows beyond the register capacity (only G = 64): whole-wave path
+  auto long_row = [&](int beg, int d, double tw) {
+    int rounds = 0;
+    const double sfin =
+        prox_row_long(beg, d, tau, tw, v.uh, v.col, xin, pget, max_rounds, rtol, rounds);
+    const double tf = tw * fast_rcp(sfin);
+    // final sweep in chunks, every load of a chunk issued first
+    for (int base2 = 0; base2 < d; base2 += kWave * kLongUnroll) {
+      float uu[kLongUnroll], xk[kLongUnroll], y[kLongUnroll];
+      int c[kLongUnroll];
 #pragma unroll
-        for (int e = 0; e < kLongUnroll; ++e) {
-          const int q = beg + min(base2 + lane + kWave * e, d - 1);
-          uu[e] = v.uh[q];
-          c[e] = v.col[q];
-          xk[e] = xin[q];
-          y[e] = fold_read ? xavg[q] : 0.0f;
-        }
+      for (int e = 0; e < kLongUnroll; ++e) {
+        const int q = beg + min(base2 + lane + kWave * e, d - 1);
+        uu[e] = v.uh[q];
+        c[e] = v.col[q];
+        xk[e] = xin[q];
+        y[e] = fold_read ? xavg[q] : 0.0f;
+      }
 #pragma unroll
-        for (int e = 0; e < kLongUnroll; ++e) {
-          const int k = base2 + lane + kWave * e;
-          if (k < d) {
-            const int q = beg + k;
-            const double a = fma(-tau, lp[c[e]], (double)xk[e]);
-            const float xn = (float)fmax(fma((double)uu[e], tf, a), 0.0);
-            xout[q] = xn;
-            if (wfold != 0.0f) xavg[q] = fold_read ? fmaf(xk[e] - y[e], wfold, y[e]) : xk[e];
-            dx2 += (double)(xn - xk[e]) * (double)(xn - xk[e]);
-            atomicAdd(&lc[c[e]], (double)xn);
-          }
+      for (int e = 0; e < kLongUnroll; ++e) {
+        const int k = base2 + lane + kWave * e;
+        if (k < d) {
+          const int q = beg + k;
+          const double a = fma(-tau, lp[c[e]], (double)xk[e]);
+          const float xn = (float)fmax(fma((double)uu[e], tf, a), 0.0);
+          xout[q] = xn;
+          if (wfold != 0.0f) xavg[q] = fold_read ? fmaf(xk[e] - y[e], wfold, y[e]) : xk[e];
+          dx2 += (double)(xn - xk[e]) * (double)(xn - xk[e]);
+          atomicAdd(&lc[c[e]], (double)xn);
         }
       }
-      continue;
     }
-    double a[E];
-    float uh[E], xk[E];
-    int cj[E];
-    int rounds = 0;
-    const double sfin = prox_row<G, E, 0>(rv, beg, d, r, tau, tw, v.uh, v.col, xin, pget,
-                                          max_rounds, rtol, 0, a, uh, xk, cj, rounds);
-    const double tf = tw * fast_rcp(sfin);
+  };
+  // Register path, NP workgroup passes per trip (two when the registers
+  // allow it): the entries and averaged allocations of the passes are loaded
+  // before any is solved, so each wave keeps NP passes of reads in flight.
+  // Loads use indices clamped into the row (every slot loads; slots past the
+  // row end are masked).
+  constexpr int NP = E <= 4 ? 2 : 1;
+  for (int base = wave * kSeg; base < v.n; base += NP * kStride) {
+    int beg[NP], d[NP];
+    double tw[NP];
+    bool rv[NP];
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int idx = r + G * e;
-      if (idx < d) {
-        const int q = beg + idx;
-        const float xn = (float)fmax(fma((double)uh[e], tf, a[e]), 0.0);
-        xout[q] = xn;
-        if (wfold != 0.0f) {
-          const float xb = xavg[q];
-          xavg[q] = (wfold == 1.0f) ? xk[e] : fmaf(xk[e] - xb, wfold, xb);
+    for (int h = 0; h < NP; ++h) {
+      const int i = base + h * kStride + seg;
+      rv[h] = i < v.n;
+      beg[h] = rv[h] ? v.rp[i] : 0;
+      d[h] = rv[h] ? v.rp[i + 1] - beg[h] : 0;
+      tw[h] = rv[h] ? tau * (double)v.w[i] : 0.0;
+    }
+    float uh[NP][E], xk[NP][E], y[NP][E];
+    int cj[NP][E];
+    bool ok[NP][E];
+#pragma unroll
+    for (int h = 0; h < NP; ++h)
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int idx = r + G * e;
+        ok[h][e] = idx < d[h];
+        const int q = beg[h] + (ok[h][e] ? idx : 0);  // row start: in bounds (nnz >= 1)
+        uh[h][e] = v.uh[q];
+        xk[h][e] = xin[q];
+        cj[h][e] = v.col[q];
+        y[h][e] = fold_read ? xavg[q] : 0.0f;
+      }
+#pragma unroll
+    for (int h = 0; h < NP; ++h) {
+      if (G == kWave && E * G < d[h]) {
+        long_row(beg[h], d[h], tw[h]);
+        continue;
+      }
+      double a[E];
+      float u[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        u[e] = ok[h][e] ? uh[h][e] : 0.0f;
+        a[e] = fma(-tau, lp[cj[h][e]], (double)xk[h][e]);  // x^k - tau p
+      }
+      int rounds = 0;
+      const double sfin =
+          prox_solve<G, E, 0>(rv[h], tw[h], max_rounds, rtol, 0, ok[h], a, u, xk[h], rounds);
+      const double tf = tw[h] * fast_rcp(sfin);
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        if (ok[h][e]) {
+          const int q = beg[h] + r + G * e;
+          const float xn = (float)fmax(fma((double)u[e], tf, a[e]), 0.0);
+          xout[q] = xn;
+          if (wfold != 0.0f)
+            xavg[q] = fold_read ? fmaf(xk[h][e] - y[h][e], wfold, y[h][e]) : xk[h][e];
+          const double df = (double)xn - (double)xk[h][e];
+          dx2 = fma(df, df, dx2);
+          atomicAdd(&lc[cj[h][e]], (double)xn);
         }
-        const double df = (double)xn - (double)xk[e];
-        dx2 = fma(df, df, dx2);
-        atomicAdd(&lc[cj[e]], (double)xn);
       }
     }
   }
@@ -211,7 +246,7 @@ __device__ double wg_rows_step(const MView &v, const double *lp, double *lc, con
 // to lMc/lMa (ord_key keys), column sums of the averaged point (or of the
 // current point when sum_cur) to lcs.
 template <int G>
-__device__ void wg_rows_eval(const MView &v, const float *xc, const double *pc, float *xa,
+__device__ __attribute__((noinline)) void wg_rows_eval(const MView &v, const float *xc, const double *pc, float *xa,
                              const double *pa_folded, float wf, const float *xanc, bool sum_cur,
                              unsigned int *lMc, unsigned int *lMa, double *lcs, double *st,
                              float *tc_out, float *ta_out) {

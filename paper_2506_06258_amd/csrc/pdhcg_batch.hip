@@ -587,7 +587,8 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(BatchDev bd, const 
         case 1: dx2 = wg_rows_step<16, 4>(v, lp, lc, xin, xout, xavg, tau, wfold, prm.max_rounds, prm.rtol); break;
         case 2: dx2 = wg_rows_step<32, 4>(v, lp, lc, xin, xout, xavg, tau, wfold, prm.max_rounds, prm.rtol); break;
         case 3: dx2 = wg_rows_step<64, 4>(v, lp, lc, xin, xout, xavg, tau, wfold, prm.max_rounds, prm.rtol); break;
-        default: dx2 = wg_rows_step<64, 8>(v, lp, lc, xin, xout, xavg, tau, wfold, prm.max_rounds, prm.rtol); break;
+        case 4: dx2 = wg_rows_step<64, 8>(v, lp, lc, xin, xout, xavg, tau, wfold, prm.max_rounds, prm.rtol); break;
+        default: dx2 = wg_rows_step<64, 16>(v, lp, lc, xin, xout, xavg, tau, wfold, prm.max_rounds, prm.rtol); break;
       }
       dx2 = block_sum(dx2, red);  // contains the barrier after the row pass
       // ---- column sums, dp^T K dx and |dp|^2
@@ -802,11 +803,12 @@ int32_t bfail(int32_t st, const std::string &msg) {
 namespace {
 
 // Row shape of a market from its largest row degree: 8x4, 16x4, 32x4,
-// 64x4, 64x8 lanes x entries (rows beyond 512 entries take the whole-wave
-// path of the 64x8 shape); policy 1 takes the next wider shape.
+// 64x4, 64x8, 64x16 lanes x entries (rows beyond 1024 entries take the
+// whole-wave path of the 64x16 shape); policy 1 takes the next wider shape.
 int32_t batch_shape(int dmax, int policy) {
-  const int s = dmax <= 32 ? 0 : dmax <= 64 ? 1 : dmax <= 128 ? 2 : dmax <= 256 ? 3 : 4;
-  return policy == 1 ? std::min(s + 1, 4) : s;
+  const int s = dmax <= 32 ? 0 : dmax <= 64 ? 1 : dmax <= 128 ? 2 : dmax <= 256 ? 3
+              : dmax <= 512 ? 4 : 5;
+  return policy == 1 ? std::min(s + 1, 5) : s;
 }
 
 }  // namespace

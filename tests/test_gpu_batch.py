@@ -128,3 +128,30 @@ def test_autotune_keeps_results(cuda, small_batch):
         B.autotune(trial_iters=0)
     assert e.value.status == pdhcg.PDHCG_ERR_ARG
     B.close()
+
+
+def test_rows_beyond_register_capacity(cuda):
+    """Rows of 513-1024 entries take the 64x16 register shape, longer rows
+    the whole-wave path: both against the single-market solver and the
+    oracle's KKT of the batch output."""
+    markets = [synth.bernoulli_market(40, 1100, 0.55, 5, w_mode="uniform", dtype=np.float32),
+               synth.bernoulli_market(24, 2000, 0.6, 9, w_mode="uniform", dtype=np.float32),
+               synth.bernoulli_market(300, 200, 0.2, 4, w_mode="uniform", dtype=np.float32)]
+    dmax = [int(np.diff(mk.row_ptr).max()) for mk in markets]
+    assert 512 < dmax[0] <= 1024 and dmax[1] > 1024
+    bt = synth.batch_from_markets(markets)
+    B = pdhcg.Batch(bt, device=cuda)
+    st, p, x, infos = B.solve(tol=1e-7, max_iter=400000)
+    assert st == pdhcg.PDHCG_OK, [i.status for i in infos]
+    p, x = p.double().cpu().numpy(), x.double().cpu().numpy()
+    for b, mk in enumerate(markets):
+        pb = p[B.good_off[b]:B.good_off[b + 1]]
+        xb = x[B.edge_off[b]:B.edge_off[b + 1]]
+        uh, _ = oracle.normalize_rows(mk.row_ptr, mk.u.astype(np.float64))
+        r, _ = oracle.kkt(mk.n, mk.m, mk.row_ptr, mk.col, uh, mk.w, xb, pb)
+        assert r <= 1e-6, (b, r)
+        M = pdhcg.Market.from_synth(mk, device=cuda)
+        q = M.solve(tol=1e-7, max_iter=400000).p.double().cpu().numpy()
+        M.close()
+        assert _rel(pb, q) <= 2e-5, b
+    B.close()

@@ -102,6 +102,7 @@ struct pdhcg_market_s {
   int32_t hot = 0;
   int32_t *perm = nullptr, *inv = nullptr;
   uint16_t *col16 = nullptr;  // 2-byte good ids (LDS modes 1 and 3)
+  int32_t *cold_ptr = nullptr, *cold_idx = nullptr;  // goods beyond LDS by column (mode 7)
   uint32_t *gmax = nullptr;  // [2][m] KKT column maxima of the goods from hot on
   double *gsum = nullptr;    // [m] KKT column sums of the goods from hot on
 
@@ -113,6 +114,8 @@ struct pdhcg_market_s {
     d.hot = hot;
     d.pad_hot = 0;
     d.col16 = col16;
+    d.cold_ptr = cold_ptr;
+    d.cold_idx = cold_idx;
     d.row_ptr = row_ptr;
     d.col = col;
     d.uh = uh;
@@ -237,7 +240,7 @@ void pdhcg_market_destroy(pdhcg_market mk) {
   f(mk->XA); f(mk->PA); f(mk->Pk); f(mk->T[0]); f(mk->T[1]);
   f(mk->colpart); f(mk->evalpart); f(mk->evalcs); f(mk->evalchunk);
   f(mk->rowpart); f(mk->colblk); f(mk->cacc); f(mk->S);
-  f(mk->colchunk); f(mk->perm); f(mk->inv); f(mk->col16); f(mk->gmax); f(mk->gsum);
+  f(mk->colchunk); f(mk->perm); f(mk->inv); f(mk->col16); f(mk->cold_ptr); f(mk->cold_idx); f(mk->gmax); f(mk->gsum);
   for (auto &b : mk->bins) {
     f(b.d_rows);
     f(b.d_rbeg);
@@ -513,6 +516,21 @@ extern "C" int32_t pdhcg_market_create(int32_t n, int32_t m, int64_t nnz, const 
     MK_HIPC(dalloc(&mk->perm, (size_t)m));
     MK_HIPC(dalloc(&mk->inv, (size_t)m));
   }
+  // entries of the goods beyond LDS, column by column in row order
+  std::vector<int32_t> h_cold_ptr, h_cold_idx;
+  if (mk->lds_row == 7) {
+    const int32_t hot = mk->hot, ncold = m - hot;
+    h_cold_ptr.assign((size_t)ncold + 1, 0);
+    for (int64_t k = 0; k < nnz; ++k)
+      if (h_col[(size_t)k] >= hot) h_cold_ptr[(size_t)(h_col[(size_t)k] - hot) + 1] += 1;
+    for (int32_t g = 0; g < ncold; ++g) h_cold_ptr[(size_t)g + 1] += h_cold_ptr[(size_t)g];
+    h_cold_idx.resize((size_t)h_cold_ptr[(size_t)ncold]);
+    std::vector<int32_t> fill(h_cold_ptr.begin(), h_cold_ptr.end() - 1);
+    for (int64_t k = 0; k < nnz; ++k)
+      if (h_col[(size_t)k] >= hot) h_cold_idx[(size_t)fill[(size_t)(h_col[(size_t)k] - hot)]++] = (int32_t)k;
+    MK_HIPC(dalloc(&mk->cold_ptr, h_cold_ptr.size()));
+    MK_HIPC(dalloc(&mk->cold_idx, std::max<size_t>(h_cold_idx.size(), 1)));
+  }
   std::vector<uint16_t> h_col16;
   if (mk->lds_row == 1 || mk->lds_row == 3) {
     if (m > 65536) return cleanup(fail(PDHCG_ERR_ARG, "internal: 16-bit good ids need m <= 65536"));
@@ -530,6 +548,13 @@ extern "C" int32_t pdhcg_market_create(int32_t n, int32_t m, int64_t nnz, const 
   std::memset(mk->hS, 0, sizeof(DevState));
 
   MK_HIPC(hipMemcpyAsync(mk->row_ptr, row_ptr, ((size_t)n + 1) * 4, hipMemcpyDeviceToDevice, st));
+  if (!h_cold_ptr.empty()) {
+    MK_HIPC(hipMemcpyAsync(mk->cold_ptr, h_cold_ptr.data(), h_cold_ptr.size() * 4,
+                           hipMemcpyHostToDevice, st));
+    if (!h_cold_idx.empty())
+      MK_HIPC(hipMemcpyAsync(mk->cold_idx, h_cold_idx.data(), h_cold_idx.size() * 4,
+                             hipMemcpyHostToDevice, st));
+  }
   if (!h_col16.empty())
     MK_HIPC(hipMemcpyAsync(mk->col16, h_col16.data(), (size_t)nnz * 2, hipMemcpyHostToDevice, st));
   if (h_perm.empty()) {
@@ -619,11 +644,12 @@ RowIO row_io_state(const pdhcg_params *p) {
 int32_t enqueue_step(pdhcg_market mk, const RowIO &io, hipEvent_t ev0 = nullptr,
                      hipEvent_t ev1 = nullptr) {
   const MarketDev md = mk->dev();
-  // c_try is zeroed when some of its goods are summed by device atomics
-  HIPC(launch_pstep(md, (mk->lds_row == 1 || mk->lds_row == 3) ? 0 : 1, mk->stream));
+  // c_try is zeroed when its goods are summed by device atomics (no LDS)
+  HIPC(launch_pstep(md, mk->lds_row == 0 ? 1 : 0, mk->stream));
   if (ev0) HIPC(hipEventRecord(ev0, mk->stream));
   for (const Bin &b : mk->bins)
     HIPC(launch_row_pass(md, mk->bindev(b), b.G, b.E, mk->lds_row, io, b.nwg, mk->stream));
+  if (mk->lds_row == 7) HIPC(launch_cold_sums(md, 1, nullptr, nullptr, mk->stream));
   if (ev1) HIPC(hipEventRecord(ev1, mk->stream));
   HIPC(launch_col_decide(md, mk->total_wg, mk->lds_row & 1, mk->stream));
   return PDHCG_OK;
@@ -1143,6 +1169,7 @@ extern "C" int32_t pdhcg_backward(pdhcg_market mk, const float *x, const float *
     io.xout = xout;
     for (const Bin &b : mk->bins)
       HIPC(launch_row_pass(md, mk->bindev(b), b.G, b.E, mk->lds_row, io, b.nwg, st));
+    if (mk->lds_row == 7) HIPC(launch_cold_sums(md, 0, xout, asum, st));
     return finish_colsum(mk, chunk, asum, c);
   };
 

@@ -58,6 +58,10 @@ struct MarketDev {
                      // goods from hot on (the less bought ones after the
                      // relabelling by degree) use global memory and atomics
   int32_t pad_hot;
+  // goods from hot on, column by column (relabelled markets): entries of
+  // good hot + g are cold_idx[cold_ptr[g] .. cold_ptr[g + 1]) in row order
+  const int32_t *cold_ptr;
+  const int32_t *cold_idx;
   const int32_t *row_ptr;
   const int32_t *col;
   const uint16_t *col16;  // the same good ids in 16 bits, for markets whose
@@ -156,6 +160,11 @@ struct EvalIO {
 hipError_t launch_row_pass(const MarketDev &md, const BinDev &bin, int G, int E,
                            int lds_mode, const RowIO &io, int nwg, hipStream_t st);
 hipError_t launch_pstep(const MarketDev &md, int zero_ctry, hipStream_t st);
+// Column sums of the goods from hot on (relabelled markets), gathered from
+// the new allocation in a fixed order: with use_state the trial allocation
+// and trial column sums of DevState, else x / out.
+hipError_t launch_cold_sums(const MarketDev &md, int use_state, const float *x, double *out,
+                            hipStream_t st);
 hipError_t launch_col_decide(const MarketDev &md, int total_wg, int from_partials,
                              hipStream_t st);
 hipError_t launch_eval_row(const MarketDev &md, const BinDev &bin, int G, int E,

@@ -24,6 +24,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 #include <cstdint>
@@ -268,10 +269,10 @@ __global__ __launch_bounds__(kRowBlock) void k_row_pass(MarketDev md, BinDev bin
       dx2 = fmaf(df, df, dx2);
       if (io.colsum) {
         if (kHybrid) {
+          // goods from hot on are summed afterwards by k_cold_sums
           const int c = Rc.c[e];
           const bool hc = c < hot;
           atomicAdd(&lc[hc ? c : hot], (ok[e] && hc) ? (double)xn : 0.0);
-          if (ok[e] && !hc) atomicAdd(&cglob[c], (double)xn);
         } else {
           atomicAdd((LDS_MODE & 1) ? &lc[Rc.c[e]] : &cglob[Rc.c[e]], ok[e] ? (double)xn : 0.0);
         }
@@ -360,6 +361,38 @@ __global__ __launch_bounds__(kColBlock) void k_pstep(MarketDev md, int zero_ctry
 // dp^T (c_try - c) and |dp|^2, and the last tile to arrive applies the
 // step-size rule of Sec. 5 and updates DevState.  Without partials (global
 // atomics) there is one chunk and c_try is already complete.
+// Column sums of the goods from hot on: one wave per good, its entries
+// (in row order) gathered from the allocation in chunks of 4 per lane and
+// added in float64 in a fixed order.  Replaces device atomics for these
+// goods, whose scattered read-modify-writes ran at about 22 G/s.
+__global__ __launch_bounds__(256) void k_cold_sums(MarketDev md, int use_state, const float *x,
+                                                   double *out) {
+  if (use_state) {
+    const DevState *S = md.S;
+    x = pick3<float *>(md.X0, md.X1, md.X2, S->ix[1]);
+    out = pick3<double *>(md.C0, md.C1, md.C2, S->ic[2]);
+  }
+  const int lane = threadIdx.x & (kWave - 1);
+  const int ncold = md.m - md.hot;
+  const int waves = (int)(gridDim.x * (blockDim.x / kWave));
+  for (int g = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; g < ncold; g += waves) {
+    const int b = md.cold_ptr[g], e = md.cold_ptr[g + 1];
+    double acc = 0.0;
+    for (int k0 = b + lane; k0 < e; k0 += 4 * kWave) {
+      int q[4];
+      float v[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) q[t] = md.cold_idx[min(k0 + t * kWave, e - 1)];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) v[t] = x[q[t]];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) acc += (k0 + t * kWave < e) ? (double)v[t] : 0.0;
+    }
+    acc = wave_sum_d(acc);
+    if (lane == 0) out[md.hot + g] = acc;
+  }
+}
+
 // Chunk sums of the per-workgroup column partials: block (t, q) adds the
 // partial rows of chunk q for tile t's goods (partial rows cover the goods
 // [0, hot): all goods unless the market is hybrid, where the others are
@@ -995,6 +1028,15 @@ hipError_t launch_eval_row(const MarketDev &md, const BinDev &bin, int G, int E,
 hipError_t launch_pstep(const MarketDev &md, int zero_ctry, hipStream_t st) {
   hipLaunchKernelGGL(k_pstep, dim3((md.m + kColBlock - 1) / kColBlock), dim3(kColBlock), 0, st,
                      md, zero_ctry);
+  return hipGetLastError();
+}
+
+hipError_t launch_cold_sums(const MarketDev &md, int use_state, const float *x, double *out,
+                            hipStream_t st) {
+  const int ncold = md.m - md.hot;
+  if (ncold <= 0 || !md.cold_ptr) return hipSuccess;
+  const int blocks = (int)std::min<int64_t>(((int64_t)ncold + 3) / 4, 2048);
+  hipLaunchKernelGGL(k_cold_sums, dim3(blocks), dim3(256), 0, st, md, use_state, x, out);
   return hipGetLastError();
 }
 

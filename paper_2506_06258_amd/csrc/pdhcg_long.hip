@@ -106,7 +106,8 @@ __global__ __launch_bounds__(kRowBlock) void k_row_long(MarketDev md, BinDev bin
           if (fold) xavg[q] = fold_read ? fmaf(xk[e] - y[e], wfold, y[e]) : xk[e];
           const double df = (double)xn - (double)xk[e];
           dx2 = fma(df, df, dx2);
-          if (io.colsum)
+          // with LDS_MODE & 4 the goods from hot on are summed by k_cold_sums
+          if (io.colsum && (!(LDS_MODE & 4) || c[e] < hot))
             atomicAdd(((LDS_MODE & 1) && c[e] < hot) ? &lc[c[e]] : &cglob[c[e]], (double)xn);
         }
       }

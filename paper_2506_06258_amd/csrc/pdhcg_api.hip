@@ -103,6 +103,7 @@ struct pdhcg_market_s {
   int32_t *perm = nullptr, *inv = nullptr;
   uint16_t *col16 = nullptr;  // 2-byte good ids (LDS modes 1 and 3)
   int32_t *cold_ptr = nullptr, *cold_idx = nullptr;  // goods beyond LDS by column (mode 7)
+  float *srow = nullptr;  // [n] roots of long rows between solver passes (markets with long rows)
   uint32_t *gmax = nullptr;  // [2][m] KKT column maxima of the goods from hot on
   double *gsum = nullptr;    // [m] KKT column sums of the goods from hot on
 
@@ -116,6 +117,7 @@ struct pdhcg_market_s {
     d.col16 = col16;
     d.cold_ptr = cold_ptr;
     d.cold_idx = cold_idx;
+    d.srow = srow;
     d.row_ptr = row_ptr;
     d.col = col;
     d.uh = uh;
@@ -240,7 +242,7 @@ void pdhcg_market_destroy(pdhcg_market mk) {
   f(mk->XA); f(mk->PA); f(mk->Pk); f(mk->T[0]); f(mk->T[1]);
   f(mk->colpart); f(mk->evalpart); f(mk->evalcs); f(mk->evalchunk);
   f(mk->rowpart); f(mk->colblk); f(mk->cacc); f(mk->S);
-  f(mk->colchunk); f(mk->perm); f(mk->inv); f(mk->col16); f(mk->cold_ptr); f(mk->cold_idx); f(mk->gmax); f(mk->gsum);
+  f(mk->colchunk); f(mk->perm); f(mk->inv); f(mk->col16); f(mk->cold_ptr); f(mk->cold_idx); f(mk->srow); f(mk->gmax); f(mk->gsum);
   for (auto &b : mk->bins) {
     f(b.d_rows);
     f(b.d_rbeg);
@@ -531,6 +533,9 @@ extern "C" int32_t pdhcg_market_create(int32_t n, int32_t m, int64_t nnz, const 
     MK_HIPC(dalloc(&mk->cold_ptr, h_cold_ptr.size()));
     MK_HIPC(dalloc(&mk->cold_idx, std::max<size_t>(h_cold_idx.size(), 1)));
   }
+  // roots of long rows between solver passes (start of each search)
+  if (std::any_of(mk->bins.begin(), mk->bins.end(), [](const Bin &b) { return b.G == 0; }))
+    MK_HIPC(dalloc(&mk->srow, (size_t)n));
   std::vector<uint16_t> h_col16;
   if (mk->lds_row == 1 || mk->lds_row == 3) {
     if (m > 65536) return cleanup(fail(PDHCG_ERR_ARG, "internal: 16-bit good ids need m <= 65536"));
@@ -775,6 +780,7 @@ extern "C" int32_t pdhcg_solve(pdhcg_market mk, const pdhcg_params *params, int3
     HIPC(launch_init_point(mk->col, mk->deg, nnz, mk->X[0], mk->P[0], m,
                            mk->sumw / (double)m, st));
   }
+  if (mk->srow) HIPC(launch_zero_f32(mk->srow, mk->n, st));  // no previous roots
   DevState &S = *mk->hS;
   std::memset(&S, 0, sizeof(S));
   S.ix[0] = 0; S.ix[1] = 1; S.ix[2] = 2;

@@ -62,6 +62,7 @@ struct MarketDev {
   // good hot + g are cold_idx[cold_ptr[g] .. cold_ptr[g + 1]) in row order
   const int32_t *cold_ptr;
   const int32_t *cold_idx;
+  float *srow;       // [n] root of each long row at the last solver pass (0: none)
   const int32_t *row_ptr;
   const int32_t *col;
   const uint16_t *col16;  // the same good ids in 16 bits, for markets whose

@@ -77,8 +77,11 @@ __global__ __launch_bounds__(kRowBlock) void k_row_long(MarketDev md, BinDev bin
     const int d = md.row_ptr[i + 1] - beg;
     const double tw = tau * (double)md.w[i];
     int rounds = 0;
+    // solver passes start the search at the row's previous root
+    const double s_start = (io.use_state && md.srow) ? (double)md.srow[i] : 0.0;
     const double sfin = prox_row_long(beg, d, tau, tw, md.uh, md.col, xin, pget, io.max_rounds,
-                                      io.rtol, rounds);
+                                      io.rtol, rounds, s_start);
+    if (io.use_state && md.srow && lane == 0) md.srow[i] = (float)sfin;
     const double tf = tw * fast_rcp(sfin);
     // final sweep in chunks, every load of a chunk issued first
     for (int base = 0; base < d; base += kWave * kLongUnroll) {

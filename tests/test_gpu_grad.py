@@ -6,7 +6,7 @@ active support (oracle.implicit_grad, pinned by closed forms and finite
 differences in test_oracle_grad.py).  The GPU unrolls 1024 fixed-step
 iterations from its own solution; the unrolled derivative converges to the
 implicit one geometrically (the oracle pins that too), so the bar is the
-north-star's 1e-4, relative to the largest gradient entry.  The oracle's
+gradient accuracy target, 1e-4 relative to the largest gradient entry.  The oracle's
 own unrolled reverse mode from its own solution is a second reference with
 the same bar.
 """

@@ -587,46 +587,56 @@ __global__ __launch_bounds__(kRowBlock) void k_eval_row(MarketDev md, BinDev bin
     const int beg = rv ? md.row_ptr[i] : 0;
     const int d = rv ? md.row_ptr[i + 1] - beg : 0;
     const double wi = rv ? (double)md.w[i] : 0.0;
-    float uh[E], xc[E], xa[E];
+    float uh[E], xc[E], xa[E], xz[E];
     double pcj[E], paj[E];
     int cj[E];
+    bool ok[E];
     double tc = 0.0, ta = 0.0;
+    // every load of the pass first (indices clamped to the row start, slots
+    // past the row end masked), then the price gathers, then the fold and
+    // its stores: a store between loads would order every later load after
+    // it
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int idx = r + G * e;
-      const bool v = idx < d;
-      const int k = beg + idx;
-      float u = 0.0f, x = 0.0f, y = 0.0f;
-      double p = 0.0, q = 0.0;
-      int c = 0;
-      if (v) {
-        u = md.uh[k];
-        x = io.xc[k];
-        c = md.col[k];
-        p = io.pc[c];
-        if (has_avg) {
-          y = io.xa[k];
-          if (wf != 0.0f) {
-            y = (wf == 1.0f) ? x : fmaf(x - y, wf, y);
-            io.xa[k] = y;
-          }
-          q = io.pa[c];
-          if (wf != 0.0f) q = (wf == 1.0f) ? p : q + (p - q) * (double)wf;
-        }
-        if (io.xanc) {
-          const float z = io.xanc[k];
-          st[8] += (double)(x - z) * (double)(x - z);
-          if (has_avg) st[9] += (double)(y - z) * (double)(y - z);
-        }
+      ok[e] = idx < d;
+      const int k = beg + (ok[e] ? idx : 0);
+      uh[e] = md.uh[k];
+      xc[e] = io.xc[k];
+      cj[e] = md.col[k];
+      xa[e] = has_avg ? io.xa[k] : 0.0f;
+      xz[e] = io.xanc ? io.xanc[k] : 0.0f;
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      pcj[e] = io.pc[cj[e]];
+      paj[e] = has_avg ? io.pa[cj[e]] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if (!ok[e]) {
+        uh[e] = 0.0f;
+        xc[e] = 0.0f;
+        xa[e] = 0.0f;
+        continue;
       }
-      uh[e] = u;
-      xc[e] = x;
+      const float x = xc[e];
+      float y = xa[e];
+      double q = paj[e];
+      if (has_avg && wf != 0.0f) {
+        y = (wf == 1.0f) ? x : fmaf(x - y, wf, y);
+        io.xa[beg + r + G * e] = y;
+        q = (wf == 1.0f) ? pcj[e] : q + (pcj[e] - q) * (double)wf;
+      }
       xa[e] = y;
-      pcj[e] = p;
       paj[e] = q;
-      cj[e] = c;
-      tc += (double)u * (double)x;
-      ta += (double)u * (double)y;
+      if (io.xanc) {
+        const float z = xz[e];
+        st[8] += (double)(x - z) * (double)(x - z);
+        if (has_avg) st[9] += (double)(y - z) * (double)(y - z);
+      }
+      tc += (double)uh[e] * (double)x;
+      ta += (double)uh[e] * (double)y;
     }
     tc = seg_sum_d<G>(tc);
     ta = seg_sum_d<G>(ta);

@@ -104,6 +104,7 @@ struct pdhcg_market_s {
   uint16_t *col16 = nullptr;  // 2-byte good ids (LDS modes 1 and 3)
   int32_t *cold_ptr = nullptr, *cold_idx = nullptr;  // goods beyond LDS by column (mode 7)
   float *srow = nullptr;  // [n] roots of long rows between solver passes (markets with long rows)
+  int32_t cold_mean_degree = 0;  // mean degree of the goods beyond LDS
   uint32_t *gmax = nullptr;  // [2][m] KKT column maxima of the goods from hot on
   double *gsum = nullptr;    // [m] KKT column sums of the goods from hot on
 
@@ -530,6 +531,7 @@ extern "C" int32_t pdhcg_market_create(int32_t n, int32_t m, int64_t nnz, const 
     std::vector<int32_t> fill(h_cold_ptr.begin(), h_cold_ptr.end() - 1);
     for (int64_t k = 0; k < nnz; ++k)
       if (h_col[(size_t)k] >= hot) h_cold_idx[(size_t)fill[(size_t)(h_col[(size_t)k] - hot)]++] = (int32_t)k;
+    mk->cold_mean_degree = (int32_t)(h_cold_idx.size() / (size_t)std::max(ncold, 1));
     MK_HIPC(dalloc(&mk->cold_ptr, h_cold_ptr.size()));
     MK_HIPC(dalloc(&mk->cold_idx, std::max<size_t>(h_cold_idx.size(), 1)));
   }
@@ -654,7 +656,8 @@ int32_t enqueue_step(pdhcg_market mk, const RowIO &io, hipEvent_t ev0 = nullptr,
   if (ev0) HIPC(hipEventRecord(ev0, mk->stream));
   for (const Bin &b : mk->bins)
     HIPC(launch_row_pass(md, mk->bindev(b), b.G, b.E, mk->lds_row, io, b.nwg, mk->stream));
-  if (mk->lds_row == 7) HIPC(launch_cold_sums(md, 1, nullptr, nullptr, mk->stream));
+  if (mk->lds_row == 7)
+    HIPC(launch_cold_sums(md, 1, nullptr, nullptr, mk->cold_mean_degree, mk->stream));
   if (ev1) HIPC(hipEventRecord(ev1, mk->stream));
   HIPC(launch_col_decide(md, mk->total_wg, mk->lds_row & 1, mk->stream));
   return PDHCG_OK;
@@ -1175,7 +1178,7 @@ extern "C" int32_t pdhcg_backward(pdhcg_market mk, const float *x, const float *
     io.xout = xout;
     for (const Bin &b : mk->bins)
       HIPC(launch_row_pass(md, mk->bindev(b), b.G, b.E, mk->lds_row, io, b.nwg, st));
-    if (mk->lds_row == 7) HIPC(launch_cold_sums(md, 0, xout, asum, st));
+    if (mk->lds_row == 7) HIPC(launch_cold_sums(md, 0, xout, asum, mk->cold_mean_degree, st));
     return finish_colsum(mk, chunk, asum, c);
   };
 

@@ -165,7 +165,7 @@ hipError_t launch_pstep(const MarketDev &md, int zero_ctry, hipStream_t st);
 // the new allocation in a fixed order: with use_state the trial allocation
 // and trial column sums of DevState, else x / out.
 hipError_t launch_cold_sums(const MarketDev &md, int use_state, const float *x, double *out,
-                            hipStream_t st);
+                            int mean_degree, hipStream_t st);
 hipError_t launch_col_decide(const MarketDev &md, int total_wg, int from_partials,
                              hipStream_t st);
 hipError_t launch_eval_row(const MarketDev &md, const BinDev &bin, int G, int E,

@@ -361,10 +361,12 @@ __global__ __launch_bounds__(kColBlock) void k_pstep(MarketDev md, int zero_ctry
 // dp^T (c_try - c) and |dp|^2, and the last tile to arrive applies the
 // step-size rule of Sec. 5 and updates DevState.  Without partials (global
 // atomics) there is one chunk and c_try is already complete.
-// Column sums of the goods from hot on: one wave per good, its entries
-// (in row order) gathered from the allocation in chunks of 4 per lane and
-// added in float64 in a fixed order.  Replaces device atomics for these
-// goods, whose scattered read-modify-writes ran at about 22 G/s.
+// Column sums of the goods from hot on: a segment of GC lanes per good
+// (GC picked from the goods' mean degree), its entries (in row order)
+// gathered from the allocation in chunks of 4 per lane and added in float64
+// in a fixed order.  Replaces device atomics for these goods, whose
+// scattered read-modify-writes ran at about 22 G/s.
+template <int GC>
 __global__ __launch_bounds__(256) void k_cold_sums(MarketDev md, int use_state, const float *x,
                                                    double *out) {
   if (use_state) {
@@ -373,23 +375,33 @@ __global__ __launch_bounds__(256) void k_cold_sums(MarketDev md, int use_state, 
     out = pick3<double *>(md.C0, md.C1, md.C2, S->ic[2]);
   }
   const int lane = threadIdx.x & (kWave - 1);
+  const int r = lane & (GC - 1);
   const int ncold = md.m - md.hot;
-  const int waves = (int)(gridDim.x * (blockDim.x / kWave));
-  for (int g = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; g < ncold; g += waves) {
-    const int b = md.cold_ptr[g], e = md.cold_ptr[g + 1];
+  const int segs = (int)(gridDim.x * (blockDim.x / GC));
+  // goods of a wave's segments are consecutive, so every segment of a wave
+  // runs the same number of trips as long as degrees are alike; the trip
+  // count is the wave's maximum (segments past their good add nothing)
+  for (int g0 = (blockIdx.x * blockDim.x + threadIdx.x - r) / GC; g0 - (lane / GC) < ncold;
+       g0 += segs) {
+    const int g = g0;
+    const bool gv = g < ncold;
+    const int b = gv ? md.cold_ptr[g] : 0, e = gv ? md.cold_ptr[g + 1] : 0;
     double acc = 0.0;
-    for (int k0 = b + lane; k0 < e; k0 += 4 * kWave) {
+    int trips = (e - b + 4 * GC - 1) / (4 * GC);
+    for (int o = 1; o < kWave / GC; o <<= 1) trips = max(trips, __shfl_xor(trips, o * GC));
+    for (int t0 = 0; t0 < trips; ++t0) {
+      const int k0 = b + r + t0 * 4 * GC;
       int q[4];
       float v[4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) q[t] = md.cold_idx[min(k0 + t * kWave, e - 1)];
+      for (int t = 0; t < 4; ++t) q[t] = (k0 + t * GC < e) ? md.cold_idx[k0 + t * GC] : -1;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) v[t] = x[q[t]];
+      for (int t = 0; t < 4; ++t) v[t] = q[t] >= 0 ? x[q[t]] : 0.0f;
 #pragma unroll
-      for (int t = 0; t < 4; ++t) acc += (k0 + t * kWave < e) ? (double)v[t] : 0.0;
+      for (int t = 0; t < 4; ++t) acc += (double)v[t];
     }
-    acc = wave_sum_d(acc);
-    if (lane == 0) out[md.hot + g] = acc;
+    acc = seg_sum_d<GC>(acc);
+    if (gv && r == 0) out[md.hot + g] = acc;
   }
 }
 
@@ -1042,11 +1054,19 @@ hipError_t launch_pstep(const MarketDev &md, int zero_ctry, hipStream_t st) {
 }
 
 hipError_t launch_cold_sums(const MarketDev &md, int use_state, const float *x, double *out,
-                            hipStream_t st) {
+                            int mean_degree, hipStream_t st) {
   const int ncold = md.m - md.hot;
   if (ncold <= 0 || !md.cold_ptr) return hipSuccess;
-  const int blocks = (int)std::min<int64_t>(((int64_t)ncold + 3) / 4, 2048);
-  hipLaunchKernelGGL(k_cold_sums, dim3(blocks), dim3(256), 0, st, md, use_state, x, out);
+  // lanes per good: about a quarter of the mean degree (4 loads in flight per lane)
+  const int gc = mean_degree >= 192 ? 64 : mean_degree >= 96 ? 32 : mean_degree >= 48 ? 16 : 8;
+  const int per_block = 256 / gc;
+  const int blocks = (int)std::min<int64_t>(((int64_t)ncold + per_block - 1) / per_block, 4096);
+  switch (gc) {
+    case 8: hipLaunchKernelGGL(k_cold_sums<8>, dim3(blocks), dim3(256), 0, st, md, use_state, x, out); break;
+    case 16: hipLaunchKernelGGL(k_cold_sums<16>, dim3(blocks), dim3(256), 0, st, md, use_state, x, out); break;
+    case 32: hipLaunchKernelGGL(k_cold_sums<32>, dim3(blocks), dim3(256), 0, st, md, use_state, x, out); break;
+    default: hipLaunchKernelGGL(k_cold_sums<64>, dim3(blocks), dim3(256), 0, st, md, use_state, x, out); break;
+  }
   return hipGetLastError();
 }
 

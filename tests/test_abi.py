@@ -52,7 +52,8 @@ def _c_layout(struct_name, fields):
 
 
 @pytest.mark.parametrize("cls,name", [(pdhcg.pdhcg_params, "pdhcg_params"),
-                                      (pdhcg.pdhcg_info, "pdhcg_info")])
+                                      (pdhcg.pdhcg_info, "pdhcg_info"),
+                                      (pdhcg.pdhcg_batch_schedule, "pdhcg_batch_schedule")])
 def test_struct_layout_matches_header(cls, name):
     fields = [f for f, _ in cls._fields_]
     size, offs = _c_layout(name, fields)
@@ -134,4 +135,13 @@ def test_null_handles_are_rejected_without_gpu():
     assert L.pdhcg_solve(None, C.byref(prm), 0, None, None, None, None) == pdhcg.PDHCG_ERR_ARG
     assert L.pdhcg_kkt(None, None, None, None) == pdhcg.PDHCG_ERR_ARG
     assert L.pdhcg_set_budgets(None, None) == pdhcg.PDHCG_ERR_ARG
+    assert L.pdhcg_market_lds_goods(None) == pdhcg.PDHCG_ERR_ARG
+    assert L.pdhcg_row_prox(None, None, None, 1.0, None, None, None) == pdhcg.PDHCG_ERR_ARG
+    assert L.pdhcg_backward(None, None, None, 1.0, 8, 4, None, None, None) == pdhcg.PDHCG_ERR_ARG
+    assert L.pdhcg_market_bins(None, 0, None, None, None) == pdhcg.PDHCG_ERR_ARG
+    sch = pdhcg.pdhcg_batch_schedule()
+    assert L.pdhcg_batch_autotune(None, C.byref(prm), 8, C.byref(sch)) == pdhcg.PDHCG_ERR_ARG
+    assert L.pdhcg_batch_solve(None, C.byref(prm), None, None, None) == pdhcg.PDHCG_ERR_ARG
+    assert L.pdhcg_batch_layout(None, None, None) == pdhcg.PDHCG_ERR_ARG
     L.pdhcg_market_destroy(None)
+    L.pdhcg_batch_destroy(None)

@@ -77,43 +77,127 @@ __global__ __launch_bounds__(kRowBlock) void k_row_long(MarketDev md, BinDev bin
     const int d = md.row_ptr[i + 1] - beg;
     const double tw = tau * (double)md.w[i];
     int rounds = 0;
-    // solver passes start the search at the row's previous root
-    const double s_start = (io.use_state && md.srow) ? (double)md.srow[i] : 0.0;
-    const double sfin = prox_row_long(beg, d, tau, tw, md.uh, md.col, xin, pget, io.max_rounds,
-                                      io.rtol, rounds, s_start);
-    if (io.use_state && md.srow && lane == 0) md.srow[i] = (float)sfin;
-    const double tf = tw * fast_rcp(sfin);
-    // final sweep in chunks, every load of a chunk issued first
-    for (int base = 0; base < d; base += kWave * kLongUnroll) {
-      float u[kLongUnroll], xk[kLongUnroll], y[kLongUnroll];
-      int c[kLongUnroll];
-      double pj[kLongUnroll];
+    // One pass writing the allocation at tf = tw / s: x^{k+1} = [a + u tf]_+,
+    // the fold of x^k into the average (unless an earlier pass of this row
+    // did it), |dx|^2 and the column sums; with undo, the contributions of a
+    // pass already written at tf_undo are taken back.  With check, the pass
+    // also compares the active sets at ti and tf (the search's verification).
+    auto sweep = [&](double tf, bool do_fold, bool undo, double tf_undo, bool check, double ti,
+                     bool &diff) {
+      for (int base = 0; base < d; base += kWave * kLongUnroll) {
+        float u[kLongUnroll], xk[kLongUnroll], y[kLongUnroll];
+        int c[kLongUnroll];
+        double pj[kLongUnroll];
 #pragma unroll
-      for (int e = 0; e < kLongUnroll; ++e) {
-        const int q = beg + min(base + lane + kWave * e, d - 1);
-        u[e] = md.uh[q];
-        c[e] = md.col[q];
-        xk[e] = xin[q];
-        y[e] = fold_read ? xavg[q] : 0.0f;
-      }
+        for (int e = 0; e < kLongUnroll; ++e) {
+          const int q = beg + min(base + lane + kWave * e, d - 1);
+          u[e] = md.uh[q];
+          c[e] = md.col[q];
+          xk[e] = xin[q];
+          y[e] = (do_fold && fold_read) ? xavg[q] : 0.0f;
+        }
 #pragma unroll
-      for (int e = 0; e < kLongUnroll; ++e) pj[e] = pget(c[e]);
+        for (int e = 0; e < kLongUnroll; ++e) pj[e] = pget(c[e]);
 #pragma unroll
-      for (int e = 0; e < kLongUnroll; ++e) {
-        const int k = base + lane + kWave * e;
-        if (k < d) {
-          const int q = beg + k;
-          const double a = fma(-tau, pj[e], (double)xk[e]);
-          const float xn = (float)fmax(fma((double)u[e], tf, a), 0.0);
-          xout[q] = xn;
-          if (fold) xavg[q] = fold_read ? fmaf(xk[e] - y[e], wfold, y[e]) : xk[e];
-          const double df = (double)xn - (double)xk[e];
-          dx2 = fma(df, df, dx2);
-          // with LDS_MODE & 4 the goods from hot on are summed by k_cold_sums
-          if (io.colsum && (!(LDS_MODE & 4) || c[e] < hot))
-            atomicAdd(((LDS_MODE & 1) && c[e] < hot) ? &lc[c[e]] : &cglob[c[e]], (double)xn);
+        for (int e = 0; e < kLongUnroll; ++e) {
+          const int k = base + lane + kWave * e;
+          if (k < d) {
+            const int q = beg + k;
+            const double uu = (double)u[e];
+            const double a = fma(-tau, pj[e], (double)xk[e]);
+            if (check) diff |= ((fma(uu, ti, a) > 0.0) != (fma(uu, tf, a) > 0.0));
+            const float xn = (float)fmax(fma(uu, tf, a), 0.0);
+            xout[q] = xn;
+            if (do_fold) xavg[q] = fold_read ? fmaf(xk[e] - y[e], wfold, y[e]) : xk[e];
+            const double df = (double)xn - (double)xk[e];
+            dx2 = fma(df, df, dx2);
+            double add = (double)xn;
+            if (undo) {
+              const float xs = (float)fmax(fma(uu, tf_undo, a), 0.0);
+              const double ds = (double)xs - (double)xk[e];
+              dx2 = fma(-ds, ds, dx2);
+              add -= (double)xs;
+            }
+            // with LDS_MODE & 4 the goods from hot on are summed by k_cold_sums
+            if (io.colsum && (!(LDS_MODE & 4) || c[e] < hot))
+              atomicAdd(((LDS_MODE & 1) && c[e] < hot) ? &lc[c[e]] : &cglob[c[e]], add);
+          }
         }
       }
+    };
+    // Root search (prox_row_long's rounds, started at the row's previous root
+    // in solver passes) whose first verification pass also writes the
+    // allocation at its trial root: when that root is accepted (the common
+    // case near convergence) the row needs no separate final pass.
+    double s = (io.use_state && md.srow) ? (double)md.srow[i] : 0.0;
+    if (!(s > 0.0)) {
+      double s0 = 0.0;
+      long_row_chunks(beg, d, tau, md.uh, md.col, xin, pget,
+                      [&](bool, int, double uu, double, float x, int) { s0 = fma(uu, (double)x, s0); });
+      s = seg_sum_d<kWave>(s0);
+    }
+    if (!(s > 0.0)) {
+      double lb = 0.0;
+      long_row_chunks(beg, d, tau, md.uh, md.col, xin, pget, [&](bool, int, double uu, double a, float, int) {
+        if (uu > 0.0) lb = fmax(lb, pos_root_d(uu * a, tw * uu * uu));
+      });
+      lb = seg_max_d<kWave>(lb);
+      s = lb > 0.0 ? lb : 1.0;
+    }
+    double L = 0.0, U = INFINITY, sfin = s, tf_spec = 0.0, s_spec = 0.0;
+    bool spec = false, found = false;
+    for (int it = 0; it < io.max_rounds; ++it) {
+      const double inv = fast_rcp(s), ti = tw * inv;
+      double A = 0.0, Q = 0.0;
+      long_row_chunks(beg, d, tau, md.uh, md.col, xin, pget,
+                      [&](bool, int, double uu, double a, float, int) {
+                        const double on = fma(uu, ti, a) > 0.0 ? uu : 0.0;
+                        A = fma(on, a, A);
+                        Q = fma(on, uu, Q);
+                      });
+      A = seg_sum_d<kWave>(A);
+      Q = seg_sum_d<kWave>(Q);
+      const double B = tw * Q, g = fma(B, inv, A), sA = pos_root_d(A, B);
+      bool same = false;
+      if (sA > 0.0) {
+        const double tA = tw * fast_rcp(sA);
+        bool diff = false;
+        if (!spec) {
+          sweep(tA, fold, false, 0.0, true, ti, diff);
+          spec = true;
+          tf_spec = tA;
+          s_spec = sA;
+        } else {
+          long_row_chunks(beg, d, tau, md.uh, md.col, xin, pget,
+                          [&](bool, int, double uu, double a, float, int) {
+                            diff |= ((fma(uu, ti, a) > 0.0) != (fma(uu, tA, a) > 0.0));
+                          });
+        }
+        same = !seg_any<kWave>(diff);
+      }
+      ++rounds;
+      U = fmin(U, fmax(s, g));
+      L = fmax(L, fmin(s, g));
+      if (sA > 0.0) L = fmax(L, sA);
+      if (same || sA == s) {
+        sfin = sA;
+        found = true;
+        break;
+      }
+      if (U - L <= io.rtol * U) {
+        sfin = 0.5 * (L + U);
+        found = true;
+        break;
+      }
+      s = (L > 0.0) ? L : 0.5 * U;
+      sfin = s;
+    }
+    if (!found && U < INFINITY) sfin = 0.5 * (L + U);
+    if (io.use_state && md.srow && lane == 0) md.srow[i] = (float)sfin;
+    // the allocation at the root, unless the verification pass wrote it
+    if (!(spec && sfin == s_spec)) {
+      bool unused = false;
+      sweep(tw * fast_rcp(sfin), fold && !spec, spec, tf_spec, false, 0.0, unused);
     }
     if (lane == 0) {
       if (io.s_out) io.s_out[i] = (float)sfin;

@@ -362,20 +362,14 @@ __device__ __forceinline__ void long_row_chunks(int beg, int d, double tau, cons
 // Row root for rows longer than a wave holds in registers: one wave per
 // row, every search round re-reads the row (it stays in cache).  Same
 // search as prox_row (active-set trial points inside the Alg. 3 bracket).
-// s_start > 0 is taken as the first trial point instead of u^T x^k (the
-// caller's root of the previous iteration: any positive start gives the
-// same root, a close one saves the pass that sums u^T x^k and most rounds).
 template <class PGet>
 __device__ __forceinline__ double prox_row_long(int beg, int d, double tau, double tw, const float *uh,
                                 const int32_t *col, const float *xin, PGet pget, int max_rounds,
-                                double rtol, int &rounds, double s_start = 0.0) {
-  double s0 = s_start;
-  if (!(s0 > 0.0)) {
-    s0 = 0.0;
-    long_row_chunks(beg, d, tau, uh, col, xin, pget,
-                    [&](bool, int, double u, double, float x, int) { s0 = fma(u, (double)x, s0); });
-    s0 = seg_sum_d<kWave>(s0);
-  }
+                                double rtol, int &rounds) {
+  double s0 = 0.0;
+  long_row_chunks(beg, d, tau, uh, col, xin, pget,
+                  [&](bool, int, double u, double, float x, int) { s0 = fma(u, (double)x, s0); });
+  s0 = seg_sum_d<kWave>(s0);
   double s = s0;
   if (!(s > 0.0)) {
     double lb = 0.0;

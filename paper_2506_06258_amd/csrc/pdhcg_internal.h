@@ -38,8 +38,6 @@ struct DevState {
   int64_t accepted;  // kept steps overall
   double eta, omega, eta0, eta_lo, eta_hi, tau, sigma;
   double emax_last;
-  uint32_t ticket;      // arrival counter of the column kernel
-  uint32_t ticket_eval; // arrival counter of the KKT column kernel
   uint32_t rounds_max;
   uint32_t pad1;
   uint64_t rounds_sum;

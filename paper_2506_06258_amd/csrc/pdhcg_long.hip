@@ -3,12 +3,16 @@
 // L2 while it stays there).  Same steps as the register-resident kernels:
 //   k_row_long   row prox (Sec. 2.2) with the active-set search, lagged fold
 //                of the kept allocation into its average (Alg. 2), |dx|^2
-//                and column sums;
+//                and column sums; solver passes start each row's search at
+//                its previous root, and the first verification pass also
+//                writes the allocation at its trial root (no final pass
+//                when that root is accepted);
 //   k_eval_long  the row part of the relative KKT error (Sec. 5 Criteria);
 //   k_adj_long   the reverse of the row prox (see pdhcg_adjoint.hip).
 // The LDS conventions (bit 1: float64 column partials, bit 2: float64
-// prices; workgroup partials written to their slot of the partial arrays)
-// are those of the register-resident kernels, so a market may mix both.
+// prices, bit 4: only the goods below hot in LDS; workgroup partials
+// written to their slot of the partial arrays) are those of the
+// register-resident kernels, so a market may mix both.
 #include "pdhcg_internal.h"
 #include "pdhcg_device.h"
 

@@ -117,6 +117,73 @@ def batched_leg(args, pdhcg, synth, torch):
     }
 
 
+def backward_leg(args, M, mk, s, pdhcg, torch):
+    """Reverse mode (pdhcg_backward) through `backward_unroll` fixed-step
+    iterations from the solution, checkpoints every 16: one forward sweep,
+    one recomputed forward pass and one adjoint pass per step."""
+    K = args.backward_unroll
+    g = torch.randn(mk.m, device=M.device, generator=torch.Generator(device=M.device).manual_seed(7))
+    M.backward(s.x, s.p, s.info.omega, g, unroll=4, ckpt_every=2)  # warmup
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    M.backward(s.x, s.p, s.info.omega, g, unroll=K, ckpt_every=16)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    # per step: two forward passes without the average (u 4, id 2, x read 4,
+    # x write 4 B/edge) and one adjoint pass (u 4, id 2, x 4, R in 4, R out 4,
+    # dL/du read and write 8 B/edge)
+    per_edge = 2 * 14 + 26
+    log(f"backward: {K} unrolled steps in {dt:.3f}s")
+    return {"workload": f"pdhcg_backward on the same market, {K} unrolled fixed steps, "
+                        "checkpoints every 16, from the timed solve's point",
+            "seconds": dt, "ms_per_step": 1e3 * dt / K,
+            "alg_bytes_per_step": per_edge * mk.nnz,
+            "achieved_GBs": per_edge * mk.nnz * K / dt / 1e9}
+
+
+def exchange_leg(pdhcg, synth, torch):
+    """Arrow-Debreu fixed point (Sec. 4) on n = m = 1e5 (5e6 utility edges),
+    warm-started inner solves to rel. KKT 1e-7, outer tolerance 1e-6."""
+    mk = synth.arrow_debreu_1e5()
+    M = pdhcg.Market.from_synth(mk, device=torch.device("cuda:0"))
+    inner = pdhcg.pdhcg_default_params(tol=1e-7, max_iter=200000)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    res = M.arrow_debreu(mk.e_row_ptr, mk.e_col, mk.e_val, np.ones(mk.n, np.float32), inner,
+                         outer_tol=1e-6, outer_max=400)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    M.close()
+    log(f"exchange: {dt:.3f}s, {res['outer']} outer / {res['inner']} inner iterations")
+    return {"workload": "Arrow-Debreu fixed point, n = m = 1e5, 50 utility edges and 5 endowed goods "
+                        "per agent; inner rel. KKT 1e-7, outer rel. price change 1e-6",
+            "seconds": dt, "status": int(res["status"]), "outer_iterations": int(res["outer"]),
+            "inner_iterations": int(res["inner"]),
+            "ms_per_inner_iteration": 1e3 * dt / max(int(res["inner"]), 1)}
+
+
+def skewed_leg(args, pdhcg, synth, torch):
+    """The skewed market (n = 4e6, m = 2e5, Zipf(1.5) degrees, 1/rank
+    popularity) to rel. KKT 1e-4."""
+    t0 = time.time()
+    mk = synth.fisher_skewed(workers=12)
+    log(f"skewed market generated in {time.time() - t0:.1f}s, nnz={mk.nnz}")
+    M = pdhcg.Market.from_synth(mk, device=torch.device("cuda:0"))
+    prm = pdhcg.pdhcg_default_params(tol=args.tol, max_iter=20000, timing=1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s = M.solve(prm)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    info = s.info
+    M.close()
+    log(f"skewed: {dt:.3f}s, {info.iters} iterations, kkt {info.rel_kkt:.2e}")
+    return {"workload": f"skewed linear Fisher market, n={mk.n}, m={mk.m}, nnz={mk.nnz}; "
+                        f"rel. KKT <= {args.tol:g}",
+            "seconds": dt, "iterations": int(info.iters), "final_rel_kkt": float(info.rel_kkt),
+            "row_pass_ms": 1e3 * info.row_pass_seconds / max(info.row_pass_launches, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +198,12 @@ def main():
                     help="oracle iterations timed for the CPU baseline (0: skip)")
     ap.add_argument("--batch-markets", type=int, default=4096,
                     help="markets of the batched leg (0: skip)")
+    ap.add_argument("--backward-unroll", type=int, default=64,
+                    help="unrolled steps of the reverse-mode leg on the same market (0: skip)")
+    ap.add_argument("--exchange", type=int, default=1,
+                    help="run the Arrow-Debreu leg (1e5 agents and goods; 0: skip)")
+    ap.add_argument("--skewed", type=int, default=0,
+                    help="run the skewed-market leg (4e6 x 2e5, 4.5e8 edges; about a minute)")
     ap.add_argument("--loop-markets", type=int, default=32,
                     help="markets of the batch solved one call at a time for the looped rate")
     args = ap.parse_args()
@@ -206,9 +279,15 @@ def main():
                           f"{args.tol:g}")}
         log(f"cpu oracle: {per_it:.3f}s/iter on {oracle.num_threads()} threads")
 
+    backward = None
+    if args.backward_unroll > 0:
+        backward = backward_leg(args, M, mk, s, pdhcg, torch)
+
     batched = None
     if args.batch_markets > 0:
         batched = batched_leg(args, pdhcg, synth, torch)
+    exchange = exchange_leg(pdhcg, synth, torch) if args.exchange else None
+    skewed = skewed_leg(args, pdhcg, synth, torch) if args.skewed else None
 
     out = {
         "metric": "time-to-1e-4 KKT & HBM GB/s (1e8-nnz Fisher); batched vs looped markets/s",
@@ -240,6 +319,9 @@ def main():
                      "avg_launch_ms": 1e3 * avg_launch, "launches_timed": launches},
         "cpu_baseline": cpu,
         "batched": batched,
+        "backward": backward,
+        "exchange": exchange,
+        "skewed": skewed,
     }
     print(json.dumps(out), flush=True)
     M.close()

@@ -2,6 +2,8 @@
 
   python -m paper_2506_06258_amd.profile_run copy  [--mib 1024] [--reps 4]
   python -m paper_2506_06258_amd.profile_run solve [--iters 64]
+  python -m paper_2506_06258_amd.profile_run skewed [--iters 40]
+  python -m paper_2506_06258_amd.profile_run exchange
   python -m paper_2506_06258_amd.profile_run summarize --stats DIR
   python -m paper_2506_06258_amd.profile_run counters --copy-fetch DIR --copy-write DIR \
         --fetch DIR --write DIR [--mib 1024] [--out FILE]
@@ -10,7 +12,9 @@
 size: the calibration kernel for the HBM byte counters.  ``solve`` runs a
 fixed number of PDHCG iterations (fixed step, no restarts, so every
 iteration launches the same kernels) on the 1e8-edge market (n = 1e6
-buyers, m = 1e4 goods, 100 goods per buyer).  ``summarize`` prints the
+buyers, m = 1e4 goods, 100 goods per buyer); ``skewed`` the same on the
+skewed market (n = 4e6, m = 2e5, 4.5e8 edges); ``exchange`` the
+Arrow-Debreu fixed point on n = m = 1e5 (inner rel. KKT 1e-7, outer 1e-6).  ``summarize`` prints the
 per-kernel table of a ``--kernel-trace --stats`` run; ``counters`` turns
 FETCH_SIZE / WRITE_SIZE runs (KiB per dispatch) into HBM bytes per row-pass
 launch, scaled by what the same counters read for the copy of known size.
@@ -67,6 +71,43 @@ def run_solve(iters: int) -> None:
     s = M.solve(prm)
     torch.cuda.synchronize()
     print(f"solve: {s.info.iters} iterations, rel. KKT {s.info.rel_kkt:.3e}", flush=True)
+    M.close()
+
+
+def run_skewed(iters: int) -> None:
+    import torch
+
+    sys.path.insert(0, ROOT)
+    from paper_2506_06258_amd import pdhcg, synth
+
+    mk = synth.fisher_skewed(workers=12)
+    print(f"skewed market: nnz={mk.nnz}", flush=True)
+    M = pdhcg.Market.from_synth(mk, device=torch.device("cuda:0"))
+    prm = pdhcg.pdhcg_default_params(tol=0.0, max_iter=iters, step_mode=pdhcg.PDHCG_STEP_FIXED,
+                                     restart=pdhcg.PDHCG_RESTART_NONE, eval_every=iters, timing=1)
+    s = M.solve(prm)
+    torch.cuda.synchronize()
+    i = s.info
+    print(f"skewed: {i.iters} iterations, row pass "
+          f"{1e3 * i.row_pass_seconds / max(i.row_pass_launches, 1):.3f} ms", flush=True)
+    M.close()
+
+
+def run_exchange() -> None:
+    import numpy as np
+    import torch
+
+    sys.path.insert(0, ROOT)
+    from paper_2506_06258_amd import pdhcg, synth
+
+    mk = synth.arrow_debreu_1e5()
+    M = pdhcg.Market.from_synth(mk, device=torch.device("cuda:0"))
+    inner = pdhcg.pdhcg_default_params(tol=1e-7, max_iter=200000)
+    res = M.arrow_debreu(mk.e_row_ptr, mk.e_col, mk.e_val, np.ones(mk.n, np.float32), inner,
+                         outer_tol=1e-6, outer_max=400)
+    torch.cuda.synchronize()
+    print(f"exchange: status {res['status']}, {res['outer']} outer / {res['inner']} inner "
+          "iterations", flush=True)
     M.close()
 
 
@@ -154,6 +195,9 @@ def main() -> None:
     c.add_argument("--reps", type=int, default=4)
     s = sub.add_parser("solve")
     s.add_argument("--iters", type=int, default=64)
+    k2 = sub.add_parser("skewed")
+    k2.add_argument("--iters", type=int, default=40)
+    sub.add_parser("exchange")
     m = sub.add_parser("summarize")
     m.add_argument("--stats", required=True)
     k = sub.add_parser("counters")
@@ -169,6 +213,10 @@ def main() -> None:
         run_copy(a.mib, a.reps)
     elif a.cmd == "solve":
         run_solve(a.iters)
+    elif a.cmd == "skewed":
+        run_skewed(a.iters)
+    elif a.cmd == "exchange":
+        run_exchange()
     elif a.cmd == "summarize":
         print(summarize(a.stats))
     else:

@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kRowBlock) void k_adj_row(MarketDev md, BinDev bin,
     const int beg = rv ? md.row_ptr[i] : 0;
     const int d = rv ? md.row_ptr[i + 1] - beg : 0;
     const double tw = rv ? tau * (double)md.w[i] : 0.0;
-    float uh[E], xn[E];
+    float uh[E], xn[E], du[E];
     double g[E];
     int cj[E];
     bool act[E];
@@ -124,6 +124,7 @@ __global__ __launch_bounds__(kRowBlock) void k_adj_row(MarketDev md, BinDev bin,
       uh[e] = v ? md.uh[k] : 0.0f;
       xn[e] = v ? io.xn[k] : 0.0f;
       cj[e] = v ? md.col[k] : 0;
+      du[e] = v ? io.duh[k] : 0.0f;  // loaded before any store of the pass
       g[e] = v ? (double)io.r_in[k] + io.b[cj[e]] : 0.0;
       act[e] = v && xn[e] > 0.0f;
       const double u = act[e] ? (double)uh[e] : 0.0;
@@ -146,8 +147,7 @@ __global__ __launch_bounds__(kRowBlock) void k_adj_row(MarketDev md, BinDev bin,
         const int k = beg + idx;
         const double rr = (live && act[e]) ? g[e] - h * (double)uh[e] : 0.0;
         io.r_out[k] = (float)rr;
-        if (live && act[e])
-          io.duh[k] += (float)(rr * tw * is - h * (double)xn[e]);
+        if (live && act[e]) io.duh[k] = du[e] + (float)(rr * tw * is - h * (double)xn[e]);
         ru = fma(rr, (double)uh[e], ru);
         atomicAdd(cj[e] < hot ? &lcs[cj[e]] : &io.csum[cj[e]], rr);
       }

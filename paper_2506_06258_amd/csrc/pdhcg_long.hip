@@ -435,16 +435,33 @@ __global__ __launch_bounds__(kRowBlock) void k_adj_long(MarketDev md, BinDev bin
     const int beg = md.row_ptr[i];
     const int d = md.row_ptr[i + 1] - beg;
     const double tw = tau * (double)md.w[i];
+    // entries in chunks of kWave * kLongUnroll, every load of a chunk issued
+    // before any is used or any store of the chunk
+    constexpr int U = kLongUnroll;
     double s = 0.0, Q = 0.0, Gu = 0.0;
-    for (int k = lane; k < d; k += kWave) {
-      const int q = beg + k;
-      const float xn = io.xn[q];
-      if (xn > 0.0f) {
-        const double u = (double)md.uh[q];
-        const double g = (double)io.r_in[q] + io.b[md.col[q]];
-        s = fma(u, (double)xn, s);
-        Q = fma(u, u, Q);
-        Gu = fma(u, g, Gu);
+    for (int base = 0; base < d; base += kWave * U) {
+      float xn[U], uu[U], rin[U];
+      int c[U];
+      double bj[U];
+#pragma unroll
+      for (int e = 0; e < U; ++e) {
+        const int q = beg + min(base + lane + kWave * e, d - 1);
+        xn[e] = io.xn[q];
+        uu[e] = md.uh[q];
+        rin[e] = io.r_in[q];
+        c[e] = md.col[q];
+      }
+#pragma unroll
+      for (int e = 0; e < U; ++e) bj[e] = io.b[c[e]];
+#pragma unroll
+      for (int e = 0; e < U; ++e) {
+        if (base + lane + kWave * e < d && xn[e] > 0.0f) {
+          const double u = (double)uu[e];
+          const double g = (double)rin[e] + bj[e];
+          s = fma(u, (double)xn[e], s);
+          Q = fma(u, u, Q);
+          Gu = fma(u, g, Gu);
+        }
       }
     }
     s = wave_sum_d(s);
@@ -455,17 +472,35 @@ __global__ __launch_bounds__(kRowBlock) void k_adj_long(MarketDev md, BinDev bin
     const double tws2 = tw * is * is;
     const double h = live ? tws2 * Gu / (1.0 + tws2 * Q) : 0.0;
     double ru = 0.0;
-    for (int k = lane; k < d; k += kWave) {
-      const int q = beg + k;
-      const float xn = io.xn[q];
-      const int c = md.col[q];
-      const double u = (double)md.uh[q];
-      const bool act = live && xn > 0.0f;
-      const double rr = act ? (double)io.r_in[q] + io.b[c] - h * u : 0.0;
-      io.r_out[q] = (float)rr;
-      if (act) io.duh[q] += (float)(rr * tw * is - h * (double)xn);
-      ru = fma(rr, u, ru);
-      atomicAdd(c < hot ? &lcs[c] : &io.csum[c], rr);
+    for (int base = 0; base < d; base += kWave * U) {
+      float xn[U], uu[U], rin[U], du[U];
+      int c[U];
+      double bj[U];
+#pragma unroll
+      for (int e = 0; e < U; ++e) {
+        const int q = beg + min(base + lane + kWave * e, d - 1);
+        xn[e] = io.xn[q];
+        uu[e] = md.uh[q];
+        rin[e] = io.r_in[q];
+        c[e] = md.col[q];
+        du[e] = io.duh[q];
+      }
+#pragma unroll
+      for (int e = 0; e < U; ++e) bj[e] = io.b[c[e]];
+#pragma unroll
+      for (int e = 0; e < U; ++e) {
+        const int k = base + lane + kWave * e;
+        if (k < d) {
+          const int q = beg + k;
+          const double u = (double)uu[e];
+          const bool act = live && xn[e] > 0.0f;
+          const double rr = act ? (double)rin[e] + bj[e] - h * u : 0.0;
+          io.r_out[q] = (float)rr;
+          if (act) io.duh[q] = du[e] + (float)(rr * tw * is - h * (double)xn[e]);
+          ru = fma(rr, u, ru);
+          atomicAdd(c[e] < hot ? &lcs[c[e]] : &io.csum[c[e]], rr);
+        }
+      }
     }
     ru = wave_sum_d(ru);
     if (live && lane == 0) io.dw[i] += (float)(tau * is * ru);

@@ -88,72 +88,104 @@ __global__ void k_zero_f32(float *a, int64_t len) {
 // io.csum by device atomics (LDS_MODE 0).
 template <int G, int E, int LDS_MODE>
 __global__ __launch_bounds__(kRowBlock) void k_adj_row(MarketDev md, BinDev bin, AdjIO io) {
+  // LDS_MODE bit 1: column partials of r for goods [0, hot); bit 2: the
+  // goods' b values as well (gathered from LDS instead of global memory)
   extern __shared__ double lcs[];
-  const int hot = LDS_MODE ? md.hot : 0;  // goods [0, hot) have LDS partials
+  const int hot = LDS_MODE ? md.hot : 0;
+  double *lb = lcs + hot;
   if (LDS_MODE) {
-    for (int j = threadIdx.x; j < hot; j += blockDim.x) lcs[j] = 0.0;
+    for (int j = threadIdx.x; j < hot; j += blockDim.x) {
+      lcs[j] = 0.0;
+      if (LDS_MODE & 2) lb[j] = io.b[j];
+    }
     __syncthreads();
   }
+  auto bget = [&](int c) {
+    if (!(LDS_MODE & 2)) return io.b[c];
+    const bool h = c < hot;
+    const double vl = lb[h ? c : 0];
+    const double vg = io.b[h ? 0 : c];
+    return h ? vl : vg;
+  };
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
   const int r = lane & (G - 1);
   const int seg = lane / G;
   constexpr int kSeg = kWave / G;
   constexpr int kWaves = kRowBlock / kWave;
+  constexpr int kStep = kWaves * kSeg;  // rows per workgroup pass
+  // passes interleaved over the workgroups (as in the forward row kernel);
+  // NP passes per trip, all their loads issued before any is used
+  constexpr int NP = 2;
   const int wg = blockIdx.x;
-  const int row_lo = wg * bin.rows_per_wg;
-  const int row_hi = min(row_lo + bin.rows_per_wg, bin.nrows);
+  const int stride = (int)gridDim.x * kStep;
   const double tau = io.tau;
-  for (int base = row_lo + wave * kSeg; base < row_hi; base += kWaves * kSeg) {
-    const int slot = base + seg;
-    const bool rv = slot < row_hi;
-    const int i = rv ? (bin.rows ? bin.rows[slot] : slot) : 0;
-    const int beg = rv ? md.row_ptr[i] : 0;
-    const int d = rv ? md.row_ptr[i + 1] - beg : 0;
-    const double tw = rv ? tau * (double)md.w[i] : 0.0;
-    float uh[E], xn[E], du[E];
-    double g[E];
-    int cj[E];
-    bool act[E];
-    double s = 0.0, Q = 0.0, Gu = 0.0;
+  for (int base = wg * kStep + wave * kSeg; base < bin.nrows; base += NP * stride) {
+    int i[NP], beg[NP], d[NP];
+    double tw[NP];
+    bool rv[NP];
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int idx = r + G * e;
-      const bool v = idx < d;
-      const int k = beg + (v ? idx : 0);
-      uh[e] = v ? md.uh[k] : 0.0f;
-      xn[e] = v ? io.xn[k] : 0.0f;
-      cj[e] = v ? md.col[k] : 0;
-      du[e] = v ? io.duh[k] : 0.0f;  // loaded before any store of the pass
-      g[e] = v ? (double)io.r_in[k] + io.b[cj[e]] : 0.0;
-      act[e] = v && xn[e] > 0.0f;
-      const double u = act[e] ? (double)uh[e] : 0.0;
-      s = fma(u, (double)xn[e], s);
-      Q = fma(u, u, Q);
-      Gu = fma(u, g[e], Gu);
+    for (int h = 0; h < NP; ++h) {
+      const int slot = base + h * stride + seg;
+      rv[h] = slot < bin.nrows;
+      i[h] = rv[h] ? (bin.rows ? bin.rows[slot] : slot) : 0;
+      beg[h] = rv[h] ? md.row_ptr[i[h]] : 0;
+      d[h] = rv[h] ? md.row_ptr[i[h] + 1] - beg[h] : 0;
+      tw[h] = rv[h] ? tau * (double)md.w[i[h]] : 0.0;
     }
-    s = seg_sum_d<G>(s);
-    Q = seg_sum_d<G>(Q);
-    Gu = seg_sum_d<G>(Gu);
-    const bool live = rv && s > 0.0;
-    const double is = live ? fast_rcp(s) : 0.0;
-    const double tws2 = tw * is * is;
-    const double h = live ? tws2 * Gu / (1.0 + tws2 * Q) : 0.0;
-    double ru = 0.0;
+    float uh[NP][E], xn[NP][E], du[NP][E], rin[NP][E];
+    int cj[NP][E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int idx = r + G * e;
-      if (idx < d) {
-        const int k = beg + idx;
-        const double rr = (live && act[e]) ? g[e] - h * (double)uh[e] : 0.0;
-        io.r_out[k] = (float)rr;
-        if (live && act[e]) io.duh[k] = du[e] + (float)(rr * tw * is - h * (double)xn[e]);
-        ru = fma(rr, (double)uh[e], ru);
-        atomicAdd(cj[e] < hot ? &lcs[cj[e]] : &io.csum[cj[e]], rr);
+    for (int h = 0; h < NP; ++h)
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int idx = r + G * e;
+        const int k = beg[h] + (idx < d[h] ? idx : 0);  // row start: in bounds
+        uh[h][e] = md.uh[k];
+        xn[h][e] = io.xn[k];
+        cj[h][e] = md.col[k];
+        du[h][e] = io.duh[k];
+        rin[h][e] = io.r_in[k];
       }
+#pragma unroll
+    for (int h = 0; h < NP; ++h) {
+      double g[E];
+      bool act[E];
+      double s = 0.0, Q = 0.0, Gu = 0.0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const bool v = r + G * e < d[h];
+        g[e] = v ? (double)rin[h][e] + bget(cj[h][e]) : 0.0;
+        act[e] = v && xn[h][e] > 0.0f;
+        const double u = act[e] ? (double)uh[h][e] : 0.0;
+        s = fma(u, (double)xn[h][e], s);
+        Q = fma(u, u, Q);
+        Gu = fma(u, g[e], Gu);
+      }
+      s = seg_sum_d<G>(s);
+      Q = seg_sum_d<G>(Q);
+      Gu = seg_sum_d<G>(Gu);
+      const bool live = rv[h] && s > 0.0;
+      const double is = live ? fast_rcp(s) : 0.0;
+      const double tws2 = tw[h] * is * is;
+      const double hh = live ? tws2 * Gu / (1.0 + tws2 * Q) : 0.0;
+      double ru = 0.0;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int idx = r + G * e;
+        if (idx < d[h]) {
+          const int k = beg[h] + idx;
+          const double rr = (live && act[e]) ? g[e] - hh * (double)uh[h][e] : 0.0;
+          io.r_out[k] = (float)rr;
+          if (live && act[e])
+            io.duh[k] = du[h][e] + (float)(rr * tw[h] * is - hh * (double)xn[h][e]);
+          ru = fma(rr, (double)uh[h][e], ru);
+          atomicAdd(cj[h][e] < hot ? &lcs[cj[h][e]] : &io.csum[cj[h][e]], rr);
+        }
+      }
+      ru = seg_sum_d<G>(ru);
+      if (live && r == 0) io.dw[i[h]] += (float)(tau * is * ru);
     }
-    ru = seg_sum_d<G>(ru);
-    if (live && r == 0) io.dw[i] += (float)(tau * is * ru);
   }
   if (LDS_MODE) {
     __syncthreads();
@@ -248,18 +280,21 @@ hipError_t launch_zero_f32(float *a, int64_t len, hipStream_t st) {
 template <int G, int E, int LDSM>
 static hipError_t adj_launch_t(const MarketDev &md, const BinDev &bin, const AdjIO &io, int nwg,
                                hipStream_t st) {
-  const size_t shm = LDSM ? (size_t)md.hot * sizeof(double) : 0;
+  const size_t shm = (size_t)md.hot * (((LDSM & 1) ? sizeof(double) : 0) +
+                                       ((LDSM & 2) ? sizeof(double) : 0));
   hipLaunchKernelGGL((k_adj_row<G, E, LDSM>), dim3(nwg), dim3(kRowBlock), shm, st, md, bin, io);
   return hipGetLastError();
 }
 
 hipError_t launch_adj_row(const MarketDev &md, const BinDev &bin, int G, int E, int lds,
                           const AdjIO &io, int nwg, hipStream_t st) {
-  if (G == 0) return launch_adj_long(md, bin, lds, io, nwg, st);
+  // lds: the market's LDS mode (bit 1 partials, bit 2 prices: then b too)
+  if (G == 0) return launch_adj_long(md, bin, lds & 1, io, nwg, st);
 #define PDHCG_ADJ_DISPATCH(g, e)                                              \
   if (G == g && E == e)                                                       \
-    return lds ? adj_launch_t<g, e, 1>(md, bin, io, nwg, st)                  \
-               : adj_launch_t<g, e, 0>(md, bin, io, nwg, st);
+    return (lds & 2) ? adj_launch_t<g, e, 3>(md, bin, io, nwg, st)            \
+         : (lds & 1) ? adj_launch_t<g, e, 1>(md, bin, io, nwg, st)            \
+                     : adj_launch_t<g, e, 0>(md, bin, io, nwg, st);
   PDHCG_ROW_VARIANTS(PDHCG_ADJ_DISPATCH)
 #undef PDHCG_ADJ_DISPATCH
   return hipErrorInvalidValue;

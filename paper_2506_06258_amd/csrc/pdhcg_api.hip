@@ -1241,7 +1241,7 @@ extern "C" int32_t pdhcg_backward(pdhcg_market mk, const float *x, const float *
       const int h = lds_goods(mk);
       if (h < m) HIPC(launch_zero_f64(asum, m, st));
       for (const Bin &b : mk->bins)
-        HIPC(launch_adj_row(md, mk->bindev(b), b.G, b.E, mk->lds_row & 1, aio, b.nwg, st));
+        HIPC(launch_adj_row(md, mk->bindev(b), b.G, b.E, mk->lds_row, aio, b.nwg, st));
       HIPC(launch_sum_partials(mk->colpart, mk->total_wg, h, m, chunk, st));
       HIPC(launch_adj_col(chunk, asum, h, P, B, Cn, tau, sigma, m, st));
       std::swap(rin, rout);

@@ -4,6 +4,7 @@
   python -m paper_2506_06258_amd.profile_run solve [--iters 64]
   python -m paper_2506_06258_amd.profile_run skewed [--iters 40]
   python -m paper_2506_06258_amd.profile_run exchange
+  python -m paper_2506_06258_amd.profile_run backward [--unroll 64]
   python -m paper_2506_06258_amd.profile_run summarize --stats DIR
   python -m paper_2506_06258_amd.profile_run counters --copy-fetch DIR --copy-write DIR \
         --fetch DIR --write DIR [--mib 1024] [--out FILE]
@@ -111,6 +112,23 @@ def run_exchange() -> None:
     M.close()
 
 
+def run_backward(unroll: int) -> None:
+    import torch
+
+    sys.path.insert(0, ROOT)
+    from paper_2506_06258_amd import pdhcg, synth
+
+    mk = synth.fisher_1e8(1)
+    dev = torch.device("cuda:0")
+    M = pdhcg.Market.from_synth(mk, device=dev)
+    s = M.solve(tol=1e-4, max_iter=20000)
+    g = torch.randn(mk.m, device=dev, generator=torch.Generator(device=dev).manual_seed(7))
+    M.backward(s.x, s.p, s.info.omega, g, unroll=unroll, ckpt_every=16)
+    torch.cuda.synchronize()
+    print(f"backward: {unroll} unrolled steps", flush=True)
+    M.close()
+
+
 def _rows(path_glob: str):
     files = sorted(glob.glob(path_glob, recursive=True))
     if not files:
@@ -198,6 +216,8 @@ def main() -> None:
     k2 = sub.add_parser("skewed")
     k2.add_argument("--iters", type=int, default=40)
     sub.add_parser("exchange")
+    bw = sub.add_parser("backward")
+    bw.add_argument("--unroll", type=int, default=64)
     m = sub.add_parser("summarize")
     m.add_argument("--stats", required=True)
     k = sub.add_parser("counters")
@@ -217,6 +237,8 @@ def main() -> None:
         run_skewed(a.iters)
     elif a.cmd == "exchange":
         run_exchange()
+    elif a.cmd == "backward":
+        run_backward(a.unroll)
     elif a.cmd == "summarize":
         print(summarize(a.stats))
     else:

@@ -294,6 +294,20 @@ typedef struct {
 int32_t pdhcg_batch_autotune(pdhcg_batch batch, const pdhcg_params *params,
                              int32_t trial_iters, pdhcg_batch_schedule *out);
 
+/* Reverse mode for every market of the batch (as pdhcg_backward, market by
+ * market on the batch's stream): from the batch solve's outputs x_cat,
+ * p_cat and each market's primal weight omega[count] (host, infos[b].omega
+ * of pdhcg_batch_solve), unroll fixed steps with checkpoints every
+ * ckpt_every, dL_dp_cat [sum m] -> dL_du_cat [sum nnz], dL_dw_cat [sum n]
+ * (device, concatenated like the inputs).  Errors: PDHCG_ERR_ARG for null
+ * arguments, unroll or ckpt_every < 1 or a non-positive omega; the status
+ * of the first market that fails otherwise. */
+int32_t pdhcg_batch_backward(pdhcg_batch batch, const float *x_cat,
+                             const float *p_cat, const double *omega,
+                             int32_t unroll, int32_t ckpt_every,
+                             const float *dL_dp_cat, float *dL_du_cat,
+                             float *dL_dw_cat);
+
 /* Offsets of market b's goods and edges in the concatenated arrays (host
  * arrays of count + 1 entries, either may be NULL). */
 int32_t pdhcg_batch_layout(pdhcg_batch batch, int64_t *good_off,

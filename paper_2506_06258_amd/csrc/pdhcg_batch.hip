@@ -754,6 +754,7 @@ struct pdhcg_batch_s {
   double *sumw = nullptr;
   int32_t *row_ptr = nullptr, *col = nullptr, *deg = nullptr;
   float *uh = nullptr, *w = nullptr, *rowmax = nullptr;
+  float *u = nullptr;  // the caller's utilities (for the reverse mode)
   float *X[3] = {nullptr, nullptr, nullptr}, *XA = nullptr;
   double *P[3] = {nullptr, nullptr, nullptr}, *PA = nullptr;
   double *C[3] = {nullptr, nullptr, nullptr};
@@ -820,7 +821,7 @@ extern "C" void pdhcg_batch_destroy(pdhcg_batch bt) {
   };
   f(bt->order); f(bt->n); f(bt->m); f(bt->shape); f(bt->rp_off); f(bt->row_off);
   f(bt->good_off); f(bt->edge_off); f(bt->sumw); f(bt->row_ptr); f(bt->col); f(bt->deg);
-  f(bt->uh); f(bt->w); f(bt->rowmax); f(bt->XA); f(bt->PA); f(bt->info);
+  f(bt->uh); f(bt->u); f(bt->w); f(bt->rowmax); f(bt->XA); f(bt->PA); f(bt->info);
   f(bt->queue); f(bt->args);
   for (int q = 0; q < 3; ++q) { f(bt->X[q]); f(bt->P[q]); f(bt->C[q]); }
   if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
@@ -921,6 +922,7 @@ extern "C" int32_t pdhcg_batch_create(int32_t count, const int32_t *n, const int
   BK(balloc(&bt->edge_off, count + 1)); BK(balloc(&bt->sumw, count));
   BK(balloc(&bt->row_ptr, rp_off[count])); BK(balloc(&bt->col, E)); BK(balloc(&bt->deg, good_off[count]));
   BK(balloc(&bt->uh, E)); BK(balloc(&bt->w, row_off[count])); BK(balloc(&bt->rowmax, row_off[count]));
+  BK(balloc(&bt->u, E));
   for (int q = 0; q < 3; ++q) {
     BK(balloc(&bt->X[q], E));
     BK(balloc(&bt->P[q], good_off[count]));
@@ -951,6 +953,7 @@ extern "C" int32_t pdhcg_batch_create(int32_t count, const int32_t *n, const int
   BK(hipMemcpyAsync(bt->col, col_cat, E * 4, hipMemcpyDeviceToDevice, st));
   BK(hipMemcpyAsync(bt->deg, deg.data(), deg.size() * 4, hipMemcpyHostToDevice, st));
   BK(hipMemcpyAsync(bt->uh, h_uh.data(), E * 4, hipMemcpyHostToDevice, st));
+  BK(hipMemcpyAsync(bt->u, u_cat, E * 4, hipMemcpyDeviceToDevice, st));
   BK(hipMemcpyAsync(bt->w, w_cat, row_off[count] * 4, hipMemcpyDeviceToDevice, st));
   BK(hipMemcpyAsync(bt->rowmax, h_rowmax.data(), row_off[count] * 4, hipMemcpyHostToDevice, st));
   BK(hipStreamSynchronize(st));
@@ -1203,6 +1206,32 @@ extern "C" int32_t pdhcg_batch_autotune(pdhcg_batch bt, const pdhcg_params *para
     out->shape_policy = best_policy;
     out->trials = trials;
     out->best_trial_seconds = best;
+  }
+  return PDHCG_OK;
+}
+
+extern "C" int32_t pdhcg_batch_backward(pdhcg_batch bt, const float *x_cat, const float *p_cat,
+                                        const double *omega, int32_t unroll, int32_t ckpt_every,
+                                        const float *dL_dp_cat, float *dL_du_cat,
+                                        float *dL_dw_cat) {
+  if (!bt || !x_cat || !p_cat || !omega || !dL_dp_cat || !dL_du_cat || !dL_dw_cat)
+    return bfail(PDHCG_ERR_ARG, "null argument");
+  if (unroll < 1 || ckpt_every < 1) return bfail(PDHCG_ERR_ARG, "unroll and ckpt_every must be >= 1");
+  for (int b = 0; b < bt->count; ++b)
+    if (!(omega[b] > 0.0) || !std::isfinite(omega[b]))
+      return bfail(PDHCG_ERR_ARG, "omega of market " + std::to_string(b) + " must be finite and > 0");
+  // each market through the single-market reverse mode, on the batch's stream
+  for (int b = 0; b < bt->count; ++b) {
+    const int64_t ro = bt->h_row_off[b], go = bt->h_good_off[b], eo = bt->h_edge_off[b];
+    const int64_t nnz = bt->h_edge_off[b + 1] - eo;
+    pdhcg_market mk = nullptr;
+    int32_t rc = pdhcg_market_create(bt->h_n[b], bt->h_m[b], nnz, bt->row_ptr + bt->h_rp_off[b],
+                                     bt->col + eo, bt->u + eo, bt->w + ro, bt->stream, &mk);
+    if (rc != PDHCG_OK) return rc;
+    rc = pdhcg_backward(mk, x_cat + eo, p_cat + go, omega[b], unroll, ckpt_every, dL_dp_cat + go,
+                        dL_du_cat + eo, dL_dw_cat + ro);
+    pdhcg_market_destroy(mk);
+    if (rc != PDHCG_OK) return rc;
   }
   return PDHCG_OK;
 }

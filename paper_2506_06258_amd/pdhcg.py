@@ -35,7 +35,8 @@ EXPORTS = (
     "pdhcg_set_budgets", "pdhcg_solve", "pdhcg_kkt", "pdhcg_row_prox",
     "pdhcg_arrow_debreu", "pdhcg_backward", "pdhcg_market_bins", "pdhcg_market_lds_goods",
     "pdhcg_market_destroy",
-    "pdhcg_batch_create", "pdhcg_batch_solve", "pdhcg_batch_autotune", "pdhcg_batch_layout",
+    "pdhcg_batch_create", "pdhcg_batch_solve", "pdhcg_batch_autotune", "pdhcg_batch_backward",
+    "pdhcg_batch_layout",
     "pdhcg_batch_destroy",
 )
 
@@ -110,6 +111,7 @@ def lib() -> C.CDLL:
         "pdhcg_batch_solve": (i32, [vp, C.POINTER(pdhcg_params), vp, vp, vp]),
         "pdhcg_batch_autotune": (i32, [vp, C.POINTER(pdhcg_params), i32,
                                        C.POINTER(pdhcg_batch_schedule)]),
+        "pdhcg_batch_backward": (i32, [vp, vp, vp, vp, i32, i32, vp, vp, vp]),
         "pdhcg_batch_layout": (i32, [vp, vp, vp]),
         "pdhcg_batch_destroy": (None, [vp]),
     }
@@ -412,6 +414,19 @@ def pdhcg_batch_autotune(h, params: Optional[pdhcg_params], trial_iters: int
     return out
 
 
+def pdhcg_batch_backward(h, x_cat, p_cat, omega, unroll: int, ckpt_every: int, dL_dp_cat,
+                         dL_du_cat, dL_dw_cat) -> None:
+    import numpy as np
+    om = np.ascontiguousarray(omega, dtype=np.float64)
+    _check(lib().pdhcg_batch_backward(h, _dev_ptr(x_cat, torch.float32, "x_cat"),
+                                      _dev_ptr(p_cat, torch.float32, "p_cat"), _host_ptr(om, "omega"),
+                                      int(unroll), int(ckpt_every),
+                                      _dev_ptr(dL_dp_cat, torch.float32, "dL_dp_cat"),
+                                      _dev_ptr(dL_du_cat, torch.float32, "dL_du_cat"),
+                                      _dev_ptr(dL_dw_cat, torch.float32, "dL_dw_cat")),
+           "pdhcg_batch_backward")
+
+
 def pdhcg_batch_layout(h, count: int):
     import numpy as np
     g = np.zeros(count + 1, np.int64)
@@ -438,6 +453,7 @@ class Batch:
         u = torch.as_tensor(batch.u).to(dev, torch.float32).contiguous()
         w = torch.as_tensor(batch.w).to(dev, torch.float32).contiguous()
         self._h = pdhcg_batch_create(self.count, batch.n, batch.m, rp, col, u, w, stream)
+        self.n_total = int(w.numel())
         self.good_off, self.edge_off = pdhcg_batch_layout(self._h, self.count)
 
     def close(self):
@@ -457,6 +473,16 @@ class Batch:
         x = torch.empty(int(self.edge_off[-1]), dtype=torch.float32, device=self.device)
         st, infos = pdhcg_batch_solve(self._h, prm, p, x, self.count)
         return st, p, x, infos
+
+    def backward(self, x, p, omega, dL_dp, unroll: int = 1024, ckpt_every: int = 32):
+        """(dL/du, dL/dw), concatenated like the inputs, for every market
+        (pdhcg_batch_backward); omega: each market's primal weight."""
+        du = torch.empty(int(self.edge_off[-1]), dtype=torch.float32, device=self.device)
+        dw = torch.empty(self.n_total, dtype=torch.float32, device=self.device)
+        g = torch.as_tensor(dL_dp).to(self.device, torch.float32).contiguous()
+        pdhcg_batch_backward(self._h, x.contiguous(), p.contiguous(), omega, unroll, ckpt_every, g,
+                             du, dw)
+        return du, dw
 
     def autotune(self, params: Optional[pdhcg_params] = None, trial_iters: int = 64):
         """Time the schedule candidates and keep the fastest (pdhcg_batch_autotune)."""

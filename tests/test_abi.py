@@ -143,5 +143,6 @@ def test_null_handles_are_rejected_without_gpu():
     assert L.pdhcg_batch_autotune(None, C.byref(prm), 8, C.byref(sch)) == pdhcg.PDHCG_ERR_ARG
     assert L.pdhcg_batch_solve(None, C.byref(prm), None, None, None) == pdhcg.PDHCG_ERR_ARG
     assert L.pdhcg_batch_layout(None, None, None) == pdhcg.PDHCG_ERR_ARG
+    assert L.pdhcg_batch_backward(None, None, None, None, 8, 4, None, None, None) == pdhcg.PDHCG_ERR_ARG
     L.pdhcg_market_destroy(None)
     L.pdhcg_batch_destroy(None)

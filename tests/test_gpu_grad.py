@@ -150,3 +150,40 @@ def test_backward_rejects_bad_arguments(cuda):
         M.backward(sol.x, sol.p, 1.0, g, unroll=0)
     assert e.value.status == pdhcg.PDHCG_ERR_ARG
     M.close()
+
+
+def test_batch_backward_matches_oracle(cuda):
+    """pdhcg_batch_backward: every market of a batch against the oracle's
+    implicit derivative at its equilibrium (same bar as above)."""
+    from paper_2506_06258_amd import synth
+    specs = [(3, 30, 10), (5, 60, 20), (8, 40, 12), (13, 50, 15)]
+    markets, refs, gs = [], [], []
+    for seed, n, m in specs:
+        rp, col, u, w, rng = _market(seed, n, m, 0.5)
+        mk = synth.Market(n, m, rp.astype(np.int32), col, u, w, f"grad-{seed}")
+        ref = oracle.solve(n, m, rp, col, u.astype(np.float64), w.astype(np.float64), tol=1e-13,
+                           max_iter=2000000)
+        assert ref.status == oracle.OK
+        g = rng.normal(size=m)
+        st, du_i, dw_i, _ = oracle.implicit_grad(n, m, rp, col, u, w, ref.x, ref.p, g)
+        assert st == oracle.OK
+        markets.append(mk)
+        refs.append((du_i, dw_i))
+        gs.append(g)
+    bt = synth.batch_from_markets(markets)
+    B = pdhcg.Batch(bt, device=cuda)
+    st, p, x, infos = B.solve(tol=1e-7, max_iter=200000)
+    assert st == pdhcg.PDHCG_OK
+    du, dw = B.backward(x, p, [i.omega for i in infos], torch.tensor(np.concatenate(gs)),
+                        unroll=1024, ckpt_every=32)
+    du, dw = du.double().cpu().numpy(), dw.double().cpu().numpy()
+    row_off = np.concatenate([[0], np.cumsum([mk.n for mk in markets])])
+    for b, (du_i, dw_i) in enumerate(refs):
+        dub = du[B.edge_off[b]:B.edge_off[b + 1]]
+        dwb = dw[row_off[b]:row_off[b + 1]]
+        assert _rel(dub, du_i) <= 1e-4, (b, _rel(dub, du_i))
+        assert _rel(dwb, dw_i) <= 1e-4, (b, _rel(dwb, dw_i))
+    with pytest.raises(pdhcg.PDHCGError) as e:
+        B.backward(x, p, [0.0] * len(markets), torch.tensor(np.concatenate(gs)))
+    assert e.value.status == pdhcg.PDHCG_ERR_ARG
+    B.close()

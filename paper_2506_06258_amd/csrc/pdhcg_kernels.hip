@@ -1,24 +1,30 @@
 // HIP kernels (gfx950) of restarted PDHCG for linear Fisher markets.
 //
-// One iteration of Alg. 2 is three launches that read the device-resident
+// One iteration of Alg. 2 is a few launches that read the device-resident
 // solver state (DevState):
 //   k_pstep      price step p_try = p + sigma (2 c - c_prev - 1)  (eq. update:py)
 //                and the lagged fold of the kept price into its average;
 //   k_row_pass   every buyer's prox subproblem (Sec. 2.2) on its CSR row,
 //                the lagged fold of the kept allocation into its average,
-//                |x_try - x|^2 and per-workgroup column sums of x_try;
-//   k_col_decide float64 column sums, dp^T K dx and |dp|^2, and in its last
-//                block the step-size rule (Sec. 5): keep or reject the trial,
+//                |x_try - x|^2 and per-workgroup column sums of x_try (one
+//                launch per row-shape bin; rows above 512 entries in
+//                pdhcg_long.hip);
+//   k_cold_sums  column sums of the goods beyond the LDS (relabelled markets);
+//   k_col_chunks, k_col_decide
+//                float64 column sums from the workgroup partials, dp^T K dx
+//                and |dp|^2 per column tile;
+//   k_step_rule  the step-size rule (Sec. 5): keep or reject the trial,
 //                rotate buffer roles, next eta.
-// Every eval_every iterations k_eval_row / k_eval_col compute the relative
-// KKT error (Sec. 5 Criteria) of the current and averaged points in float64.
+// Every eval_every iterations k_eval_row / k_eval_chunks / k_eval_col /
+// k_eval_final compute the relative KKT error (Sec. 5 Criteria) of the
+// current and averaged points in float64.
 //
 // Memory layout: CSR row_ptr/col int32, values float32 aligned with col.
 // A row is owned by a segment of G lanes of one wave (G in 4..64); lane r of
 // the segment holds the row entries r, r+G, ..., r+(E-1)G in registers for
 // the whole search, so the row is read from HBM once per iteration.  Loads
 // of a segment are contiguous.  Column sums are privatised per workgroup in
-// LDS and reduced in float64 by the column kernel.
+// LDS and reduced in float64 by the column kernels.
 #include "pdhcg_internal.h"
 #include "pdhcg_device.h"
 
@@ -354,13 +360,9 @@ __global__ __launch_bounds__(kColBlock) void k_pstep(MarketDev md, int zero_ctry
 
 // ---------------------------------------------- column sums + step rule ----
 
-// Grid (column tiles, chunks).  With per-workgroup partials, block (t, q)
-// sums partial rows [q*per, (q+1)*per) of tile t's columns into
-// colchunk[q][j]; the last chunk block of a tile to arrive adds the chunks
-// in a fixed order (deterministic float64 column sums), forms the tile's
-// dp^T (c_try - c) and |dp|^2, and the last tile to arrive applies the
-// step-size rule of Sec. 5 and updates DevState.  Without partials (global
-// atomics) there is one chunk and c_try is already complete.
+// Column sums (deterministic float64: partial rows in chunks, chunks in a
+// fixed order), the tiles' dp^T (c_try - c) and |dp|^2, and the step rule,
+// in kernels of their own so that results pass through kernel boundaries.
 // Column sums of the goods from hot on: a segment of GC lanes per good
 // (GC picked from the goods' mean degree), its entries (in row order)
 // gathered from the allocation in chunks of 4 per lane and added in float64

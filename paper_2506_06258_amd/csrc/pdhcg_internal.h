@@ -72,7 +72,7 @@ struct MarketDev {
   double *C0, *C1, *C2;
   float *XA;         // restart anchor x^{n,0}
   double *PA;        // restart anchor p^{n,0}
-  double *colpart;   // [total_wg][m] per-workgroup column partials
+  double *colpart;   // [total_wg][hot] per-workgroup column partials of the LDS goods
   double *rowpart;   // [total_wg][kRowStats]
   double *colblk;    // [col blocks][kColStats or kEvalColStats]
   double *colchunk;  // [kColChunks][m] chunk sums of the column partials
@@ -140,7 +140,7 @@ struct EvalIO {
   float *tc;         // per-row utility of the current point (nullable)
   float *ta;         // per-row utility of the averaged point (nullable)
   const float *rowscale; // multiply t by this (original units)
-  float *evalpart;   // column maxima (float bits): [2][total_wg][hot] (LDS mode) or [2][m]
+  float *evalpart;   // column maxima (ord_key keys): [2][total_wg][hot] (LDS mode) or [2][m]
   double *evalcs;    // [total_wg][hot] float64 column-sum partials (LDS mode)
   uint32_t *evalchunk; // [2][kColChunks][m] chunk maxima (LDS mode)
   uint32_t *gmax;    // [2][m] device-wide maxima of the goods from hot on (LDS mode)

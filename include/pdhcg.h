@@ -28,6 +28,16 @@
  *  - Synchronisation: pdhcg_market_create, pdhcg_solve, pdhcg_kkt and
  *    pdhcg_arrow_debreu return after their device work on the handle's
  *    stream has finished.  pdhcg_row_prox only enqueues.
+ *  - Environment overrides, read at pdhcg_market_create (for tests and
+ *    parameter sweeps; results stay those of the method):
+ *      PDHCG_ROW_G, PDHCG_ROW_E   force the row shape (lanes, entries per
+ *                                 lane) of every bin that it can hold;
+ *      PDHCG_HOT=k                relabel the goods by degree and keep only
+ *                                 the first k in LDS (as for large m);
+ *      PDHCG_P_LDS=0              prices from global memory, partials in LDS;
+ *      PDHCG_NO_LDS=1             no LDS: device atomics for column sums;
+ *    and at pdhcg_batch_solve: PDHCG_BATCH_EAGER=1 launches the batch's
+ *    kernels directly instead of replaying its graph.
  */
 #ifndef PDHCG_H
 #define PDHCG_H

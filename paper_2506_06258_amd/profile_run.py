@@ -5,6 +5,8 @@
   python -m paper_2506_06258_amd.profile_run skewed [--iters 40]
   python -m paper_2506_06258_amd.profile_run exchange
   python -m paper_2506_06258_amd.profile_run backward [--unroll 64]
+  python -m paper_2506_06258_amd.profile_run ksweep
+  python -m paper_2506_06258_amd.profile_run jd
   python -m paper_2506_06258_amd.profile_run summarize --stats DIR
   python -m paper_2506_06258_amd.profile_run counters --copy-fetch DIR --copy-write DIR \
         --fetch DIR --write DIR [--mib 1024] [--out FILE]
@@ -129,6 +131,55 @@ def run_backward(unroll: int) -> None:
     M.close()
 
 
+def run_ksweep() -> None:
+    """The 1e8-edge market to rel. KKT 1e-4 with the paper's k-section row
+    search for k = 2 ... 32 (Sec. 2.2.1, Table 1) and with the active-set
+    search: iterations, row-pass time and search rounds."""
+    import torch
+
+    sys.path.insert(0, ROOT)
+    from paper_2506_06258_amd import pdhcg, synth
+
+    mk = synth.fisher_1e8(1)
+    M = pdhcg.Market.from_synth(mk, device=torch.device("cuda:0"))
+    cases = [("active set", pdhcg.PDHCG_SEARCH_ACTIVESET, 32)]
+    cases += [(f"{k}-section", pdhcg.PDHCG_SEARCH_KSECTION, k) for k in (2, 4, 8, 16, 32)]
+    print("| search | iterations | solve s | row pass ms | mean rounds | max rounds | rel. KKT |")
+    print("|---|---|---|---|---|---|---|")
+    for name, search, k in cases:
+        prm = pdhcg.pdhcg_default_params(tol=1e-4, max_iter=20000, timing=1, search=search,
+                                         sections=k)
+        M.solve(prm)  # warmup
+        s = M.solve(prm)
+        torch.cuda.synchronize()
+        i = s.info
+        print(f"| {name} | {i.iters} | {i.seconds:.4f} | "
+              f"{1e3 * i.row_pass_seconds / max(i.row_pass_launches, 1):.3f} | "
+              f"{i.search_rounds_mean:.2f} | {i.search_rounds_max} | {i.rel_kkt:.2e} |", flush=True)
+    M.close()
+
+
+def run_jd() -> None:
+    import torch
+
+    sys.path.insert(0, ROOT)
+    from paper_2506_06258_amd import pdhcg, synth
+
+    mk = synth.jd_shaped(workers=12)
+    print(f"jd-shaped market: n={mk.n} m={mk.m} nnz={mk.nnz}", flush=True)
+    M = pdhcg.Market.from_synth(mk, device=torch.device("cuda:0"))
+    print(f"bins {M.bins()}, {M.lds_goods()} goods in LDS", flush=True)
+    prm = pdhcg.pdhcg_default_params(tol=1e-4, max_iter=20000, timing=1)
+    M.solve(prm)  # warmup
+    s = M.solve(prm)
+    torch.cuda.synchronize()
+    i = s.info
+    print(f"jd-shaped: {i.iters} iterations in {i.seconds:.3f} s, row pass "
+          f"{1e3 * i.row_pass_seconds / max(i.row_pass_launches, 1):.3f} ms, rel. KKT {i.rel_kkt:.2e}",
+          flush=True)
+    M.close()
+
+
 def _rows(path_glob: str):
     files = sorted(glob.glob(path_glob, recursive=True))
     if not files:
@@ -216,6 +267,8 @@ def main() -> None:
     k2 = sub.add_parser("skewed")
     k2.add_argument("--iters", type=int, default=40)
     sub.add_parser("exchange")
+    sub.add_parser("ksweep")
+    sub.add_parser("jd")
     bw = sub.add_parser("backward")
     bw.add_argument("--unroll", type=int, default=64)
     m = sub.add_parser("summarize")
@@ -239,6 +292,10 @@ def main() -> None:
         run_exchange()
     elif a.cmd == "backward":
         run_backward(a.unroll)
+    elif a.cmd == "ksweep":
+        run_ksweep()
+    elif a.cmd == "jd":
+        run_jd()
     elif a.cmd == "summarize":
         print(summarize(a.stats))
     else:

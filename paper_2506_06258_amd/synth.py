@@ -191,7 +191,7 @@ def _zipf_rows(args):
 
 def zipf_market(n: int, m: int, seed: int, a: float = 1.5, dmin: int = 5, dmax: int = 20000,
                 dtype=np.float32, name: str = "", workers: int = 0,
-                block_rows: int = 1 << 16) -> Market:
+                block_rows: int = 1 << 16, uniform_degrees: bool = False) -> Market:
     """Skewed buyer degrees and popularity-skewed goods.
 
     Degrees d = dmin - 1 + K with K ~ Zipf(a), redrawn while d > dmax (the
@@ -206,7 +206,9 @@ def zipf_market(n: int, m: int, seed: int, a: float = 1.5, dmin: int = 5, dmax: 
     does not change the result."""
     rng = np.random.default_rng(seed)
     d = np.empty(n, np.int64)
-    todo = np.arange(n)
+    if uniform_degrees:  # degrees uniform on [dmin, dmax] instead
+        d[:] = rng.integers(dmin, dmax + 1, size=n)
+    todo = np.arange(0 if uniform_degrees else n)
     while todo.size:
         k = rng.zipf(a, size=todo.size)
         ok = k <= dmax - dmin + 1
@@ -251,6 +253,15 @@ def fisher_skewed(seed: int = 2, n: int = 4_000_000, m: int = 200_000,
     [5, 20000], 1/rank popularity of goods (about 4.5e8 edges)."""
     return zipf_market(n, m, seed, 1.5, 5, 20000, np.float32,
                        name=f"fisher-skewed-{n}x{m}-s{seed}", workers=workers)
+
+
+def jd_shaped(seed: int = 5, n: int = 2_560_000, m: int = 27_000, workers: int = 8) -> Market:
+    """A market of the shape of the e-commerce data of Sec. 5.2 (shape only,
+    no data): n = 2.56e6 buyers, m = 27,000 goods, 3-70 goods per buyer
+    (uniform), goods drawn with probability proportional to 1/rank,
+    u ~ LogNormal(0, 1), w ~ U(0.5, 1.5)."""
+    return zipf_market(n, m, seed, 1.5, 3, 70, np.float32, name=f"jd-shaped-{n}x{m}-s{seed}",
+                       workers=workers, uniform_degrees=True)
 
 
 # Named workloads.  "small" is the case the oracle finishes in seconds; the

@@ -71,7 +71,9 @@ enum {
    * such root is a lower bound on s* and is exact once the active set
    * settles.  Default on gfx950. */
   PDHCG_SEARCH_ACTIVESET = 0,
-  /* k-section search of Sec. 2.2.1 (sections = k, 32 in the paper). */
+  /* k-section search of Sec. 2.2.1 (sections = k, 32 in the paper).
+   * pdhcg_solve and pdhcg_row_prox return PDHCG_ERR_UNSUPPORTED for it on
+   * markets with rows of more than 512 entries. */
   PDHCG_SEARCH_KSECTION = 1
 };
 
@@ -199,7 +201,10 @@ int32_t pdhcg_row_prox(pdhcg_market market, const float *x_in,
  * (Sec. 4, Alg. 4).  E: device CSR (e_row_ptr[n+1], e_col[e_nnz],
  * e_val[e_nnz]) with column sums one (Sec. 4).  Each Fisher solve uses
  * `inner` and is warm-started from the previous prices and allocation.
- * Stops when ||p^k - p^{k-1}||_inf / ||p^{k-1}||_inf <= outer_tol.
+ * Stops when ||p^k - p^{k-1}||_inf / ||p^{k-1}||_inf <= outer_tol; returns
+ * PDHCG_OK then if the inner solve that produced p^k reached inner->tol,
+ * else PDHCG_MAX_ITER (the small change may only reflect a solve cut off by
+ * inner->max_iter), and PDHCG_MAX_ITER when outer_max ran out.
  *   w  [n] device: initial budgets on entry, final budgets E p on exit.
  *   p  [m], x [nnz] device: outputs.
  *   outer_iters, inner_iters: host, may be NULL. */

@@ -727,7 +727,9 @@ int ora_arrow_debreu(int n, int m, const int64_t *row_ptr, const int32_t *col,
       for (int64_t q = e_row_ptr[i]; q < e_row_ptr[i + 1]; ++q) s += e_val[q] * p[e_col[q]];
       w[i] = s;
     }
-    if (k > 0 && change <= outer_tol) { rc = ORA_OK; ++k; break; }
+    /* p^k = p(E p^{k-1}) close to p^{k-1} certifies a fixed point only when
+     * the solve that produced p^k reached its tolerance */
+    if (k > 0 && change <= outer_tol) { rc = (r == ORA_OK) ? ORA_OK : ORA_MAX_ITER; ++k; break; }
   }
   if (outer_iters) *outer_iters = k;
   if (inner_iters) *inner_iters = tot_inner;

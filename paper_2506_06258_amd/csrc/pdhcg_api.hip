@@ -634,6 +634,16 @@ int32_t check_params(const pdhcg_params *p) {
   return PDHCG_OK;
 }
 
+// The k-section search is built for the register-resident row shapes only.
+int32_t check_search(pdhcg_market mk, const pdhcg_params *p) {
+  if (p->search == PDHCG_SEARCH_KSECTION)
+    for (const Bin &b : mk->bins)
+      if (b.G == 0)
+        return fail(PDHCG_ERR_UNSUPPORTED, "the k-section search is not built for rows of more "
+                                           "than 512 entries");
+  return PDHCG_OK;
+}
+
 RowIO row_io_state(const pdhcg_params *p) {
   RowIO io;
   std::memset(&io, 0, sizeof(io));
@@ -743,6 +753,7 @@ extern "C" int32_t pdhcg_row_prox(pdhcg_market mk, const float *x_in, const floa
   pdhcg_default_params(&dflt);
   const pdhcg_params *prm = params ? params : &dflt;
   int32_t rc = check_params(prm);
+  if (rc == PDHCG_OK) rc = check_search(mk, prm);
   if (rc != PDHCG_OK) return rc;
   RowIO io = row_io_state(prm);
   io.use_state = 0;
@@ -767,6 +778,7 @@ extern "C" int32_t pdhcg_solve(pdhcg_market mk, const pdhcg_params *params, int3
   pdhcg_default_params(&dflt);
   const pdhcg_params *prm = params ? params : &dflt;
   int32_t rc = check_params(prm);
+  if (rc == PDHCG_OK) rc = check_search(mk, prm);
   if (rc != PDHCG_OK) return rc;
   hipStream_t st = mk->stream;
   const auto t0 = std::chrono::steady_clock::now();
@@ -1067,7 +1079,13 @@ extern "C" int32_t pdhcg_arrow_debreu(pdhcg_market mk, const int32_t *e_row_ptr,
       std::fprintf(stderr, "[pdhcg-ad] outer=%d inner_iters=%lld kkt=%.3e change=%.3e\n", k,
                    (long long)last.iters, last.rel_kkt, change);
     if (k > 0 && change <= outer_tol) {
-      rc = PDHCG_OK;
+      // the stop compares p^k = p(E p^{k-1}) with p^{k-1}: it certifies a
+      // fixed point only when the solve that produced p^k reached its
+      // tolerance (an inner solve cut off by max_iter may barely move the
+      // warm-started prices)
+      rc = (r == PDHCG_OK) ? PDHCG_OK : PDHCG_MAX_ITER;
+      if (rc != PDHCG_OK)
+        fail(rc, "outer change below tolerance but the last inner solve stopped at max_iter");
       ++k;
       break;
     }

@@ -186,7 +186,7 @@ __global__ __launch_bounds__(kRowBlock) void k_row_pass(MarketDev md, BinDev bin
   const __amdgpu_buffer_rsrc_t ryw = make_rsrc(xavg, fold ? ebytes : 0u);
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(io.s_out, io.s_out ? (uint32_t)md.n * 4u : 0u);
 
-  float dx2 = 0.0f;
+  double dx2 = 0.0;  // |x_try - x|^2 of the lane's entries (float64, like the global sum)
   uint32_t rmax = 0;
   uint32_t rsum = 0, rcount = 0;
 
@@ -271,8 +271,8 @@ __global__ __launch_bounds__(kRowBlock) void k_row_pass(MarketDev md, BinDev bin
       const float xn = (float)fmax(fma((double)uh[e], tf, a[e]), 0.0);
       bstore_f(ro, o, xn);
       bstore_f(ryw, o, fold_read ? fmaf(xk - y[e], wfold, y[e]) : xk);
-      const float df = ok[e] ? xn - xk : 0.0f;
-      dx2 = fmaf(df, df, dx2);
+      const double df = ok[e] ? (double)xn - (double)xk : 0.0;
+      dx2 = fma(df, df, dx2);
       if (io.colsum) {
         if (kHybrid) {
           // goods from hot on are summed afterwards by k_cold_sums
@@ -309,7 +309,7 @@ __global__ __launch_bounds__(kRowBlock) void k_row_pass(MarketDev md, BinDev bin
     red_rsum = 0;
     red_rcnt = 0;
   }
-  double dsum = wave_sum_d((double)dx2);
+  double dsum = wave_sum_d(dx2);
   __syncthreads();
   if (lane == 0) red[wave] = dsum;
   if (rcount) {

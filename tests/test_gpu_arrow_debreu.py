@@ -48,3 +48,17 @@ def test_arrow_debreu_rejects_bad_endowments(cuda):
         M.arrow_debreu(mk.e_row_ptr, mk.e_col, bad, np.ones(mk.n, np.float32))
     assert e.value.status == pdhcg.PDHCG_ERR_ARG
     M.close()
+
+
+def test_arrow_debreu_reports_unconverged_inner_solve(cuda):
+    """With inner solves cut off after two iterations the warm-started prices
+    barely move, so the outer change test passes without a fixed point
+    (Alg. 4): the call reports MAX_ITER, not OK."""
+    mk = synth.arrow_debreu_market(60, 50, 10, 3, 2)
+    M = pdhcg.Market.from_synth(mk, device=cuda)
+    inner = pdhcg.pdhcg_default_params(tol=1e-12, max_iter=2)
+    res = M.arrow_debreu(mk.e_row_ptr, mk.e_col, mk.e_val, np.ones(mk.n, np.float32), inner,
+                         outer_tol=0.5, outer_max=50)
+    assert res["status"] == pdhcg.PDHCG_MAX_ITER
+    assert res["outer"] < 50
+    M.close()

@@ -109,3 +109,21 @@ def test_backward_with_long_rows(cuda):
     assert rel_err(du, du_i) <= 1e-4, rel_err(du, du_i)
     assert rel_err(dw, dw_i) <= 1e-4, rel_err(dw, dw_i)
     M.close()
+
+
+def test_ksection_rejected_on_long_rows(cuda):
+    """The k-section search is built for the register-resident shapes: on a
+    market with rows above 512 entries the solve and the row prox say so
+    instead of silently using another search."""
+    mk = synth.fixed_degree_market(40, 700, 520, 9, "uniform").as_float32()
+    M = pdhcg.Market.from_synth(mk, device=cuda)
+    prm = pdhcg.pdhcg_default_params(search=pdhcg.PDHCG_SEARCH_KSECTION, sections=32)
+    with pytest.raises(pdhcg.PDHCGError) as e:
+        M.solve(prm)
+    assert e.value.status == pdhcg.PDHCG_ERR_UNSUPPORTED
+    x_in = torch.full((mk.nnz,), 0.01, device=cuda)
+    p = torch.ones(mk.m, device=cuda)
+    with pytest.raises(pdhcg.PDHCGError) as e:
+        M.row_prox(x_in, p, 0.1, prm)
+    assert e.value.status == pdhcg.PDHCG_ERR_UNSUPPORTED
+    M.close()

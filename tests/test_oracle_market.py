@@ -255,3 +255,15 @@ def test_arrow_debreu_fixed_point():
     # ... and (nearly) a fixed point: E p(w) reproduces w
     Ep2 = np.bincount(rows_e, weights=mk.e_val * fis.p[mk.e_col], minlength=mk.n)
     assert np.max(np.abs(Ep2 - res["w"]) / res["w"]) < 1e-6
+
+
+def test_arrow_debreu_reports_unconverged_inner_solve():
+    """Alg. 4 stops on a small price change; with inner solves cut off after
+    a few iterations the warm-started prices barely move, so the change test
+    passes without a fixed point: the status says MAX_ITER, not OK."""
+    mk = synth.arrow_debreu_market(60, 50, 10, 3, 2, dtype=np.float64)
+    inner = oracle.default_params(tol=1e-12, max_iter=2)
+    res = oracle.arrow_debreu(mk.n, mk.m, mk.row_ptr, mk.col, mk.u, mk.e_row_ptr, mk.e_col,
+                              mk.e_val, np.ones(mk.n), inner, outer_tol=0.5, outer_max=50)
+    assert res["change"] <= 0.5
+    assert res["status"] == oracle.MAX_ITER, res

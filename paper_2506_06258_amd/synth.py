@@ -220,8 +220,10 @@ def zipf_market(n: int, m: int, seed: int, a: float = 1.5, dmin: int = 5, dmax: 
     jobs = [(seed, b, d[b * block_rows:(b + 1) * block_rows], m, ranking)
             for b in range((n + block_rows - 1) // block_rows)]
     if workers > 1 and len(jobs) > 1:
+        # fresh interpreters, not forks: callers may already hold a GPU
+        # context, which a forked child must not inherit
         from multiprocessing import get_context
-        with get_context("fork").Pool(workers) as pool:
+        with get_context("spawn").Pool(workers) as pool:
             parts = pool.map(_zipf_rows, jobs)
     else:
         parts = [_zipf_rows(j) for j in jobs]

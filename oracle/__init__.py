@@ -1,4 +1,5 @@
-"""FP64 CPU oracle for restarted PDHCG on linear Fisher markets.
+"""FP64 CPU oracle for restarted PDHCG (Alg. 2) and restarted PDHG (Alg. 1)
+on linear Fisher markets.
 
 TEST INFRASTRUCTURE.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 CPU-baseline leg of ``bench.py`` may import this package.  The GPU solver
@@ -53,6 +54,7 @@ class OraInfo(C.Structure):
         ("rel_kkt", C.c_double), ("rel_primal", C.c_double), ("rel_dual", C.c_double),
         ("rel_gap", C.c_double), ("eta", C.c_double), ("omega", C.c_double),
         ("iters", C.c_int64), ("restarts", C.c_int32), ("status", C.c_int32),
+        ("accepted", C.c_int64),
     ]
 
 
@@ -98,6 +100,14 @@ def lib():
         L.ora_unrolled_grad.argtypes = [C.c_int, C.c_int, ip64, ip32, dp, dp, dp, dp, C.c_double,
                                         C.c_double, C.c_int, dp, dp, dp, dp]
         L.ora_unrolled_grad.restype = C.c_int
+        L.ora_kkt_ty.argtypes = [C.c_int, C.c_int, ip64, ip32, dp, dp, dp, dp, dp, dp, dp]
+        L.ora_kkt_ty.restype = C.c_double
+        L.ora_pdhg_step.argtypes = [C.c_int, C.c_int, ip64, ip32, dp, dp, dp, dp, dp, dp, dp, dp,
+                                    C.c_double, C.c_double, dp, dp, dp, dp]
+        L.ora_pdhg_step.restype = None
+        L.ora_pdhg_solve.argtypes = [C.c_int, C.c_int, ip64, ip32, dp, dp, C.POINTER(OraParams),
+                                     dp, dp, dp, dp, C.POINTER(OraInfo)]
+        L.ora_pdhg_solve.restype = C.c_int
         _lib = L
     return _lib
 
@@ -145,6 +155,73 @@ def kkt(n, m, row_ptr, col, u, w, x, p):
                       _ptr(w, C.c_double), _ptr(x, C.c_double), _ptr(p, C.c_double),
                       _ptr(out, C.c_double))
     return float(r), out
+
+
+def kkt_ty(n, m, row_ptr, col, u, w, x, t, p, y):
+    """Relative KKT error (r_primal, r_dual, r_gap) of a point (x, t, p, y) of
+    the reformulated program (Sec. 2.1), on utilities u."""
+    rp, cl = _csr(row_ptr, col)
+    u, w, x, t, p, y = _d(u), _d(w), _d(x), _d(t), _d(p), _d(y)
+    out = np.zeros(3)
+    r = lib().ora_kkt_ty(n, m, _ptr(rp, C.c_int64), _ptr(cl, C.c_int32), _ptr(u, C.c_double),
+                         _ptr(w, C.c_double), _ptr(x, C.c_double), _ptr(t, C.c_double),
+                         _ptr(p, C.c_double), _ptr(y, C.c_double), _ptr(out, C.c_double))
+    return float(r), out
+
+
+def pdhg_step(n, m, row_ptr, col, u, w, x, t, p, y, c_prev, g_prev, tau, sigma):
+    """One PDHG iteration of Alg. 1 (eqs. update:py, update:t, update:x) on
+    utilities u from (x, t, p, y) with the previous column sums c_prev and
+    utility residuals g_prev = t - Ux; returns (x', t', p', y')."""
+    rp, cl = _csr(row_ptr, col)
+    u, w, x, t, p, y = _d(u), _d(w), _d(x), _d(t), _d(p), _d(y)
+    c_prev, g_prev = _d(c_prev), _d(g_prev)
+    x2, t2, p2, y2 = np.zeros_like(x), np.zeros(n), np.zeros(m), np.zeros(n)
+    lib().ora_pdhg_step(n, m, _ptr(rp, C.c_int64), _ptr(cl, C.c_int32), _ptr(u, C.c_double),
+                        _ptr(w, C.c_double), _ptr(x, C.c_double), _ptr(t, C.c_double),
+                        _ptr(p, C.c_double), _ptr(y, C.c_double), _ptr(c_prev, C.c_double),
+                        _ptr(g_prev, C.c_double), float(tau), float(sigma),
+                        _ptr(x2, C.c_double), _ptr(t2, C.c_double), _ptr(p2, C.c_double),
+                        _ptr(y2, C.c_double))
+    return x2, t2, p2, y2
+
+
+@dataclass
+class PdhgSolution:
+    p: np.ndarray
+    x: np.ndarray
+    t: np.ndarray  # normalised units (u_i / max_j u_ij)
+    y: np.ndarray  # normalised units
+    status: int
+    rel_kkt: float
+    rel_primal: float
+    rel_dual: float
+    rel_gap: float
+    iters: int
+    restarts: int
+    eta: float
+    omega: float
+    accepted: int
+
+
+def pdhg_solve(n, m, row_ptr, col, u, w, params: OraParams | None = None,
+               **kw) -> PdhgSolution:
+    """Restarted PDHG in FP64 (Alg. 1 with the Sec. 5 enhancements)."""
+    rp, cl = _csr(row_ptr, col)
+    u, w = _d(u), _d(w)
+    prm = params if params is not None else default_params(**kw)
+    if params is not None:
+        for k, v in kw.items():
+            setattr(prm, k, v)
+    p, x, t, y = np.zeros(m), np.zeros(int(rp[-1])), np.zeros(n), np.zeros(n)
+    info = OraInfo()
+    st = lib().ora_pdhg_solve(n, m, _ptr(rp, C.c_int64), _ptr(cl, C.c_int32), _ptr(u, C.c_double),
+                              _ptr(w, C.c_double), C.byref(prm), _ptr(p, C.c_double),
+                              _ptr(x, C.c_double), _ptr(t, C.c_double), _ptr(y, C.c_double),
+                              C.byref(info))
+    return PdhgSolution(p, x, t, y, int(st), info.rel_kkt, info.rel_primal, info.rel_dual,
+                        info.rel_gap, int(info.iters), int(info.restarts), info.eta, info.omega,
+                        int(info.accepted))
 
 
 def normalize_rows(row_ptr, u):
@@ -228,6 +305,7 @@ class Solution:
     restarts: int
     eta: float
     omega: float
+    accepted: int = 0
 
 
 def solve(n, m, row_ptr, col, u, w, params: OraParams | None = None, p0=None, x0=None,
@@ -248,7 +326,8 @@ def solve(n, m, row_ptr, col, u, w, params: OraParams | None = None, p0=None, x0
                          _ptr(w, C.c_double), C.byref(prm), int(warm), _ptr(p, C.c_double),
                          _ptr(x, C.c_double), _ptr(t, C.c_double), C.byref(info))
     return Solution(p, x, t, int(st), info.rel_kkt, info.rel_primal, info.rel_dual,
-                    info.rel_gap, int(info.iters), int(info.restarts), info.eta, info.omega)
+                    info.rel_gap, int(info.iters), int(info.restarts), info.eta, info.omega,
+                    int(info.accepted))
 
 
 def solve_market(mk, **kw) -> Solution:

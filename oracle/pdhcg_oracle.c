@@ -336,6 +336,7 @@ typedef struct {
   int64_t iters;
   int32_t restarts;
   int32_t status;
+  int64_t accepted;    /* steps kept by the adaptive step rule (all when fixed) */
 } ora_info;
 
 void ora_default_params(ora_params *prm) {
@@ -476,6 +477,9 @@ static int prox_sweep(int n, const int64_t *row_ptr, const int32_t *col,
  *    omega_check_every restarts omega is reset to omega0 when it left
  *    [omega0/omega_bound, omega0*omega_bound];
  *  - stop when the candidate's error <= tol; the output is the candidate.
+ *    When max_iter runs out, the last check's candidate is the output, with
+ *    no restart decision at that check (Sec. 5 gives no rule there; a run
+ *    cut at k iterations is then the first k iterations of a longer run).
  *
  * p[m], x[nnz]: if warm != 0 they hold the starting point on entry.  On exit
  * they hold the solution; t[n] (if non-NULL) receives u_i^T x_i in the
@@ -549,7 +553,7 @@ int ora_solve(int n, int m, const int64_t *row_ptr, const int32_t *col,
 
   double kkt0 = ora_kkt(n, m, row_ptr, col, uh, w, x, p, NULL);
   double kkt_prev = INFINITY;
-  int64_t k_in = 0, total = 0;
+  int64_t k_in = 0, total = 0, accepted = 0;
   int restarts = 0;
   double kout[3] = {NAN, NAN, NAN}, kbest = INFINITY;
   int status = ORA_MAX_ITER;
@@ -590,6 +594,7 @@ int ora_solve(int n, int m, const int64_t *row_ptr, const int32_t *col,
       memcpy(cp, c, (size_t)m * sizeof(double));
       memcpy(c, cn, (size_t)m * sizeof(double));
       ++k_in;
+      ++accepted;
       /* running averages over the iterates since the last restart (Alg. 2) */
       for (int64_t k = 0; k < nnz; ++k) xb[k] += (x[k] - xb[k]) / (double)k_in;
       for (int j = 0; j < m; ++j) pb[j] += (p[j] - pb[j]) / (double)k_in;
@@ -619,6 +624,7 @@ int ora_solve(int n, int m, const int64_t *row_ptr, const int32_t *col,
       status = ORA_OK;
       break;
     }
+    if (total >= prm->max_iter) break;
     if (prm->restart) {
       int do_restart = (kcand <= prm->beta_sufficient * kkt0) ||
                        (kcand <= prm->beta_necessary * kkt0 && kcand > kkt_prev) ||
@@ -674,6 +680,7 @@ int ora_solve(int n, int m, const int64_t *row_ptr, const int32_t *col,
     info->iters = total;
     info->restarts = restarts;
     info->status = status;
+    info->accepted = accepted;
   }
   rc = status;
 
@@ -983,5 +990,344 @@ int ora_unrolled_grad(int n, int m, const int64_t *row_ptr, const int32_t *col,
 done:
   free(uh); free(rs); free(xs); free(p); free(c); free(cprev); free(R); free(r); free(duh);
   free(B); free(P); free(Cn); free(rc_col);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Restarted PDHG on the reformulated program (Sec. 2.1, Alg. 1) with the    */
+/* enhancements of Sec. 5.  Primal (x, t), dual (p, y) of                    */
+/*   L = -sum_i w_i log t_i + p^T (1^T x - 1) + y^T (t - U x)               */
+/* (eq. primal-dual-formulation), u normalised per row as in ora_solve.      */
+/* ------------------------------------------------------------------------ */
+
+/* Relative KKT error (Sec. 5, "Criteria") of a point (x, t, p, y) of the
+ * reformulated program, with r_i = u_i^T x_i and M_j = max_i u_ij y_i over
+ * the stored entries:
+ *   r_primal = max(||1^T x - 1||_inf, max_i |t_i - r_i|)
+ *              / (1 + max(||1^T x||_inf, max_i |t_i - r_i|, 1))
+ *   r_dual   = max(||w/t - y||_inf, max_j (p_j - M_j)_-)
+ *              / (1 + max(||w/t||_inf, ||y||_inf, max_j (p_j - M_j)))
+ *   r_gap    = max_ij x_ij (p_j - u_ij y_i)_+
+ *              / (1 + max(||x||_inf, max_ij (p_j - u_ij y_i)_+))
+ * out[0..2] = r_primal, r_dual, r_gap; returns the largest. */
+double ora_kkt_ty(int n, int m, const int64_t *row_ptr, const int32_t *col,
+                  const double *u, const double *w, const double *x, const double *t,
+                  const double *p, const double *y, double *out) {
+  double *c = (double *)calloc((size_t)m, sizeof(double));
+  double *M = (double *)malloc((size_t)m * sizeof(double));
+  if (!c || !M) {
+    free(c); free(M);
+    return NAN;
+  }
+  for (int j = 0; j < m; ++j) M[j] = -INFINITY;
+  double tr = 0.0, wty = 0.0, wt = 0.0, ya = 0.0, xmax = 0.0;
+  for (int i = 0; i < n; ++i) {
+    double r = 0.0;
+    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+      int j = col[k];
+      r += u[k] * x[k];
+      c[j] += x[k];
+      double v = u[k] * y[i];
+      if (v > M[j]) M[j] = v;
+      if (fabs(x[k]) > xmax) xmax = fabs(x[k]);
+    }
+    if (fabs(t[i] - r) > tr) tr = fabs(t[i] - r);
+    double q = w[i] / t[i];
+    if (fabs(q - y[i]) > wty) wty = fabs(q - y[i]);
+    if (fabs(q) > wt) wt = fabs(q);
+    if (fabs(y[i]) > ya) ya = fabs(y[i]);
+  }
+  double cres = 0.0, cmax = 0.0, dneg = 0.0, dmax = -INFINITY;
+  for (int j = 0; j < m; ++j) {
+    if (fabs(c[j] - 1.0) > cres) cres = fabs(c[j] - 1.0);
+    if (fabs(c[j]) > cmax) cmax = fabs(c[j]);
+    double d = p[j] - M[j];
+    if (-d > dneg) dneg = -d;
+    if (d > dmax) dmax = d;
+  }
+  double gnum = 0.0, gpos = 0.0;
+  for (int i = 0; i < n; ++i)
+    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+      double r = p[col[k]] - u[k] * y[i];
+      if (r > 0.0) {
+        if (r > gpos) gpos = r;
+        if (x[k] * r > gnum) gnum = x[k] * r;
+      }
+    }
+  double pn = cres > tr ? cres : tr;
+  double pd = cmax;
+  if (tr > pd) pd = tr;
+  if (1.0 > pd) pd = 1.0;
+  double rp = pn / (1.0 + pd);
+  double dn = wty > dneg ? wty : dneg;
+  double dd = wt > ya ? wt : ya;
+  if (dmax > dd) dd = dmax;
+  double rd = dn / (1.0 + dd);
+  double gd = xmax > gpos ? xmax : gpos;
+  double rg = gnum / (1.0 + gd);
+  free(c); free(M);
+  if (out) { out[0] = rp; out[1] = rd; out[2] = rg; }
+  double r = rp > rd ? rp : rd;
+  return r > rg ? r : rg;
+}
+
+/* Row sums r_i = u_i^T x_i. */
+static void rowsum(int n, const int64_t *row_ptr, const double *u, const double *x, double *r) {
+  for (int i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) s += u[k] * x[k];
+    r[i] = s;
+  }
+}
+
+/* One PDHG iteration (Alg. 1) on the normalised market u:
+ *   p' = p + sigma (2 c - c_prev - 1),  c = 1^T x            (eq. update:py)
+ *   y' = y + sigma (2 g - g_prev),      g = t - U x          (eq. update:py)
+ *   t' = (t - tau y' + sqrt((tau y' - t)^2 + 4 tau w)) / 2   (eq. update:t)
+ *   x' = max(0, x - tau (p'_j - u_ij y'_i))                  (eq. update:x)
+ * c_prev, g_prev are the column sums and utility residuals of the previous
+ * iterate.  Outputs x2[nnz], t2[n], p2[m], y2[n]. */
+void ora_pdhg_step(int n, int m, const int64_t *row_ptr, const int32_t *col,
+                   const double *u, const double *w, const double *x, const double *t,
+                   const double *p, const double *y, const double *c_prev,
+                   const double *g_prev, double tau, double sigma, double *x2, double *t2,
+                   double *p2, double *y2) {
+  double *c = (double *)malloc((size_t)m * sizeof(double));
+  double *r = (double *)malloc((size_t)n * sizeof(double));
+  colsum(n, m, row_ptr, col, x, c);
+  rowsum(n, row_ptr, u, x, r);
+  for (int j = 0; j < m; ++j) p2[j] = p[j] + sigma * (2.0 * c[j] - c_prev[j] - 1.0);
+  for (int i = 0; i < n; ++i) {
+    double g = t[i] - r[i];
+    y2[i] = y[i] + sigma * (2.0 * g - g_prev[i]);
+    double b = tau * y2[i] - t[i];
+    t2[i] = (-b + sqrt(b * b + 4.0 * tau * w[i])) / 2.0;
+    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+      double v = x[k] - tau * (p2[col[k]] - u[k] * y2[i]);
+      x2[k] = v > 0.0 ? v : 0.0;
+    }
+  }
+  free(c); free(r);
+}
+
+/*
+ * Solve the Fisher market by restarted PDHG (Alg. 1) with the Sec. 5
+ * enhancements, which the paper applies to both PDHG and PDHCG.  Readings
+ * (shared with ora_solve where they apply):
+ *  - initial point: x0_ij = 1/deg_j, p0_j = sum(w)/m, t0 = U x0 (the utility
+ *    constraint holds), y0 = w / t0 (the dual residual w/t - y is zero);
+ *  - steps tau = eta/omega, sigma = eta*omega.  Adaptive mode: eta0 = 1 =
+ *    max |K_ij| (|u_ij| <= 1 after normalisation, the t column is 1) and
+ *    the rule of ora_solve with primal norm |dx|^2 + |dt|^2, dual norm
+ *    |dp|^2 + |dy|^2 and interaction dp^T (1^T dx) + dy^T (dt - U dx).
+ *    Fixed mode: eta = 0.9 / B with
+ *    B = sqrt(max_j deg_j) + 1 + sqrt(max_j deg_j * max_i deg_i) >= ||K||
+ *    (K = [1^T 0; -U I], |u_ij| <= 1), so sigma tau ||K||^2 < 1;
+ *  - restarts, primal weight and stop test as in ora_solve, with the KKT
+ *    error of ora_kkt_ty and primal/dual distances over (x, t) / (p, y);
+ *    after a restart c_prev := c, g_prev := g.
+ * p[m], x[nnz], t[n], y[n]: outputs (t, y in the normalised units). */
+int ora_pdhg_solve(int n, int m, const int64_t *row_ptr, const int32_t *col,
+                   const double *u_in, const double *w, const ora_params *prm,
+                   double *p, double *x, double *t, double *y, ora_info *info) {
+  int rc = ora_validate(n, m, row_ptr, col, u_in, w);
+  if (rc != ORA_OK) {
+    if (info) info->status = rc;
+    return rc;
+  }
+  int64_t nnz = row_ptr[n];
+  double *u = (double *)malloc((size_t)nnz * sizeof(double));
+  double *X[4], *T[4], *P[4], *Y[4];  /* 0 current, 1 trial, 2 average, 3 anchor */
+  for (int q = 0; q < 4; ++q) {
+    X[q] = (double *)malloc((size_t)nnz * sizeof(double));
+    T[q] = (double *)malloc((size_t)n * sizeof(double));
+    P[q] = (double *)malloc((size_t)m * sizeof(double));
+    Y[q] = (double *)malloc((size_t)n * sizeof(double));
+  }
+  double *c = (double *)malloc((size_t)m * sizeof(double));
+  double *cp = (double *)malloc((size_t)m * sizeof(double));
+  double *cn = (double *)malloc((size_t)m * sizeof(double));
+  double *g = (double *)malloc((size_t)n * sizeof(double));
+  double *gp = (double *)malloc((size_t)n * sizeof(double));
+  double *gn = (double *)malloc((size_t)n * sizeof(double));
+  double *r = (double *)malloc((size_t)n * sizeof(double));
+  double *deg = (double *)calloc((size_t)m, sizeof(double));
+
+  /* preprocessing (Sec. 5) */
+  int maxrow = 0;
+  for (int i = 0; i < n; ++i) {
+    double mx = 0.0;
+    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+      if (u_in[k] > mx) mx = u_in[k];
+    if (!prm->normalize_rows) mx = 1.0;
+    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) u[k] = u_in[k] / mx;
+    if ((int)(row_ptr[i + 1] - row_ptr[i]) > maxrow) maxrow = (int)(row_ptr[i + 1] - row_ptr[i]);
+  }
+  for (int64_t k = 0; k < nnz; ++k) deg[col[k]] += 1.0;
+  double maxcol = 0.0, sumw = 0.0;
+  for (int j = 0; j < m; ++j)
+    if (deg[j] > maxcol) maxcol = deg[j];
+  for (int i = 0; i < n; ++i) sumw += w[i];
+  double Kbound = sqrt(maxcol) + 1.0 + sqrt(maxcol * (double)maxrow);
+
+  /* initial point */
+  for (int i = 0; i < n; ++i)
+    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) X[0][k] = 1.0 / deg[col[k]];
+  for (int j = 0; j < m; ++j) P[0][j] = sumw / m;
+  rowsum(n, row_ptr, u, X[0], T[0]);
+  for (int i = 0; i < n; ++i) Y[0][i] = w[i] / T[0][i];
+  colsum(n, m, row_ptr, col, X[0], c);
+  memcpy(cp, c, (size_t)m * sizeof(double));
+  for (int i = 0; i < n; ++i) g[i] = 0.0;
+  memcpy(gp, g, (size_t)n * sizeof(double));
+  memcpy(X[2], X[0], (size_t)nnz * sizeof(double));
+  memcpy(T[2], T[0], (size_t)n * sizeof(double));
+  memcpy(P[2], P[0], (size_t)m * sizeof(double));
+  memcpy(Y[2], Y[0], (size_t)n * sizeof(double));
+  memcpy(X[3], X[0], (size_t)nnz * sizeof(double));
+  memcpy(T[3], T[0], (size_t)n * sizeof(double));
+  memcpy(P[3], P[0], (size_t)m * sizeof(double));
+  memcpy(Y[3], Y[0], (size_t)n * sizeof(double));
+
+  double eta0 = prm->eta0 > 0.0 ? prm->eta0 : (prm->step_mode == 1 ? 1.0 : 0.9 / Kbound);
+  double omega0 = prm->omega0 > 0.0 ? prm->omega0 : 0.05 * sumw / (double)m;
+  double eta = eta0, omega = omega0;
+  double kkt0 = ora_kkt_ty(n, m, row_ptr, col, u, w, X[0], T[0], P[0], Y[0], NULL);
+  double kkt_prev = INFINITY, kout[3] = {NAN, NAN, NAN}, kbest = INFINITY;
+  int64_t k_in = 0, total = 0, since = 0, accepted = 0;
+  int restarts = 0, status = ORA_MAX_ITER, cand_avg = 0;
+
+  while (total < prm->max_iter) {
+    double tau = eta / omega, sigma = eta * omega;
+    ora_pdhg_step(n, m, row_ptr, col, u, w, X[0], T[0], P[0], Y[0], cp, gp, tau, sigma,
+                  X[1], T[1], P[1], Y[1]);
+    colsum(n, m, row_ptr, col, X[1], cn);
+    rowsum(n, row_ptr, u, X[1], r);
+    for (int i = 0; i < n; ++i) gn[i] = T[1][i] - r[i];
+    ++total;
+    ++since;
+    int accept = 1;
+    if (prm->step_mode == 1) {
+      double pz = dist2(nnz, X[1], X[0]) + dist2(n, T[1], T[0]);
+      double dz = dist2(m, P[1], P[0]) + dist2(n, Y[1], Y[0]);
+      double inter = 0.0;
+      for (int j = 0; j < m; ++j) inter += (P[1][j] - P[0][j]) * (cn[j] - c[j]);
+      for (int i = 0; i < n; ++i) inter += (Y[1][i] - Y[0][i]) * (gn[i] - g[i]);
+      double emax = fabs(inter) > 0.0 ? (omega * pz + dz / omega) / (2.0 * fabs(inter)) : INFINITY;
+      double kk = (double)(total + 1);
+      double enew = fmin((1.0 - pow(kk, -0.3)) * emax, (1.0 + pow(kk, -0.6)) * eta);
+      if (enew > 3.0 * eta0) enew = 3.0 * eta0;
+      if (enew < 0.01 * eta0) enew = 0.01 * eta0;
+      accept = (eta <= emax) || (eta <= 0.01 * eta0);
+      eta = enew;
+    }
+    if (accept) {
+      memcpy(X[0], X[1], (size_t)nnz * sizeof(double));
+      memcpy(T[0], T[1], (size_t)n * sizeof(double));
+      memcpy(P[0], P[1], (size_t)m * sizeof(double));
+      memcpy(Y[0], Y[1], (size_t)n * sizeof(double));
+      memcpy(cp, c, (size_t)m * sizeof(double));
+      memcpy(c, cn, (size_t)m * sizeof(double));
+      memcpy(gp, g, (size_t)n * sizeof(double));
+      memcpy(g, gn, (size_t)n * sizeof(double));
+      ++k_in;
+      ++accepted;
+      /* running averages since the last restart (Alg. 1) */
+      for (int64_t k = 0; k < nnz; ++k) X[2][k] += (X[0][k] - X[2][k]) / (double)k_in;
+      for (int i = 0; i < n; ++i) T[2][i] += (T[0][i] - T[2][i]) / (double)k_in;
+      for (int j = 0; j < m; ++j) P[2][j] += (P[0][j] - P[2][j]) / (double)k_in;
+      for (int i = 0; i < n; ++i) Y[2][i] += (Y[0][i] - Y[2][i]) / (double)k_in;
+    }
+    int eval = (total % prm->eval_every == 0) || total == prm->max_iter;
+    if (!eval) continue;
+    if (k_in == 0) {
+      memcpy(X[2], X[0], (size_t)nnz * sizeof(double));
+      memcpy(T[2], T[0], (size_t)n * sizeof(double));
+      memcpy(P[2], P[0], (size_t)m * sizeof(double));
+      memcpy(Y[2], Y[0], (size_t)n * sizeof(double));
+    }
+    double kc[3], ka[3];
+    double ec = ora_kkt_ty(n, m, row_ptr, col, u, w, X[0], T[0], P[0], Y[0], kc);
+    double ea = ora_kkt_ty(n, m, row_ptr, col, u, w, X[2], T[2], P[2], Y[2], ka);
+    if (!isfinite(ec) || !isfinite(ea)) {
+      rc = ORA_ERR_NUMERIC;
+      goto done;
+    }
+    cand_avg = ea < ec;
+    double kcand = cand_avg ? ea : ec;
+    memcpy(kout, cand_avg ? ka : kc, sizeof(kout));
+    kbest = kcand;
+    if (prm->verbose)
+      fprintf(stderr, "[oracle-pdhg] it=%lld cur=%.3e avg=%.3e eta=%.3e omega=%.3e\n",
+              (long long)total, ec, ea, eta, omega);
+    if (kcand <= prm->tol) {
+      status = ORA_OK;
+      break;
+    }
+    if (total >= prm->max_iter) break;
+    if (prm->restart) {
+      int do_restart = (kcand <= prm->beta_sufficient * kkt0) ||
+                       (kcand <= prm->beta_necessary * kkt0 && kcand > kkt_prev) ||
+                       ((double)since >= prm->beta_artificial * (double)total);
+      if (do_restart) {
+        if (cand_avg) {
+          memcpy(X[0], X[2], (size_t)nnz * sizeof(double));
+          memcpy(T[0], T[2], (size_t)n * sizeof(double));
+          memcpy(P[0], P[2], (size_t)m * sizeof(double));
+          memcpy(Y[0], Y[2], (size_t)n * sizeof(double));
+          colsum(n, m, row_ptr, col, X[0], c);
+          rowsum(n, row_ptr, u, X[0], r);
+          for (int i = 0; i < n; ++i) g[i] = T[0][i] - r[i];
+        }
+        memcpy(cp, c, (size_t)m * sizeof(double));
+        memcpy(gp, g, (size_t)n * sizeof(double));
+        double dx = sqrt(dist2(nnz, X[0], X[3]) + dist2(n, T[0], T[3]));
+        double dp = sqrt(dist2(m, P[0], P[3]) + dist2(n, Y[0], Y[3]));
+        if (dx > 1e-10 && dp > 1e-10)
+          omega = exp(prm->theta * log(dp / dx) + (1.0 - prm->theta) * log(omega));
+        ++restarts;
+        if (prm->omega_check_every > 0 && restarts % prm->omega_check_every == 0 &&
+            (omega < omega0 / prm->omega_bound || omega > omega0 * prm->omega_bound))
+          omega = omega0;
+        memcpy(X[3], X[0], (size_t)nnz * sizeof(double));
+        memcpy(T[3], T[0], (size_t)n * sizeof(double));
+        memcpy(P[3], P[0], (size_t)m * sizeof(double));
+        memcpy(Y[3], Y[0], (size_t)n * sizeof(double));
+        kkt0 = kcand;
+        kkt_prev = INFINITY;
+        k_in = 0;
+        since = 0;
+        cand_avg = 0;
+      } else {
+        kkt_prev = kcand;
+      }
+    }
+  }
+  {
+    int z = (prm->output == 2 || (prm->output == 0 && cand_avg)) ? 2 : 0;
+    memcpy(x, X[z], (size_t)nnz * sizeof(double));
+    memcpy(p, P[z], (size_t)m * sizeof(double));
+    if (t) memcpy(t, T[z], (size_t)n * sizeof(double));
+    if (y) memcpy(y, Y[z], (size_t)n * sizeof(double));
+    if (prm->output != 0) kbest = ora_kkt_ty(n, m, row_ptr, col, u, w, X[z], T[z], P[z], Y[z], kout);
+  }
+  if (info) {
+    info->rel_kkt = kbest;
+    info->rel_primal = kout[0];
+    info->rel_dual = kout[1];
+    info->rel_gap = kout[2];
+    info->eta = eta;
+    info->omega = omega;
+    info->iters = total;
+    info->restarts = restarts;
+    info->status = status;
+    info->accepted = accepted;
+  }
+  rc = status;
+done:
+  free(u);
+  for (int q = 0; q < 4; ++q) { free(X[q]); free(T[q]); free(P[q]); free(Y[q]); }
+  free(c); free(cp); free(cn); free(g); free(gp); free(gn); free(r); free(deg);
+  if (rc < 0 && info) info->status = rc;
   return rc;
 }

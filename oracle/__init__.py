@@ -108,6 +108,9 @@ def lib():
         L.ora_pdhg_solve.argtypes = [C.c_int, C.c_int, ip64, ip32, dp, dp, C.POINTER(OraParams),
                                      dp, dp, dp, dp, C.POINTER(OraInfo)]
         L.ora_pdhg_solve.restype = C.c_int
+        L.ora_fixed_restart.argtypes = [C.c_int, C.c_int, ip64, ip32, dp, dp, C.c_int, C.c_int,
+                                        C.c_double, dp, dp, dp, dp, dp]
+        L.ora_fixed_restart.restype = C.c_int
         _lib = L
     return _lib
 
@@ -222,6 +225,25 @@ def pdhg_solve(n, m, row_ptr, col, u, w, params: OraParams | None = None,
     return PdhgSolution(p, x, t, y, int(st), info.rel_kkt, info.rel_primal, info.rel_dual,
                         info.rel_gap, int(info.iters), int(info.restarts), info.eta, info.omega,
                         int(info.accepted))
+
+
+def fixed_restart(n, m, row_ptr, col, u, w, K, R, eta=0.0, p_ref=None):
+    """Alg. 2 with fixed sigma = tau = eta (<= 0: 1/(2||K||)) and restart
+    length K, R restarts to the average (the setting of Sec. 3).  Returns
+    (status, p, x, dist[R+1], kkt[R+1]) with dist[n] = |p^{n,0} - p_ref|_2
+    (zeros without p_ref) and kkt[n] the relative KKT error of the n-th
+    restart point."""
+    rp, cl = _csr(row_ptr, col)
+    u, w = _d(u), _d(w)
+    p, x = np.zeros(m), np.zeros(int(rp[-1]))
+    dist, kk = np.zeros(R + 1), np.zeros(R + 1)
+    pr = _d(p_ref) if p_ref is not None else None
+    st = lib().ora_fixed_restart(n, m, _ptr(rp, C.c_int64), _ptr(cl, C.c_int32),
+                                 _ptr(u, C.c_double), _ptr(w, C.c_double), int(K), int(R),
+                                 float(eta), _ptr(pr, C.c_double) if pr is not None else None,
+                                 _ptr(dist, C.c_double) if pr is not None else None,
+                                 _ptr(kk, C.c_double), _ptr(p, C.c_double), _ptr(x, C.c_double))
+    return int(st), p, x, dist, kk
 
 
 def normalize_rows(row_ptr, u):

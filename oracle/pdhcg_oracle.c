@@ -1331,3 +1331,85 @@ done:
   if (rc < 0 && info) info->status = rc;
   return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Alg. 2 as analysed in Sec. 3 (Lemma 1, Lemma 2, Theorem 1): fixed step   */
+/* sizes sigma = tau = eta, fixed restart length K, every restart to the    */
+/* average of the K iterates of its inner loop; no adaptive enhancement.    */
+/* Row normalisation and the initial point as in ora_solve.                 */
+/* eta <= 0: 1/(2 ||K||), ||K|| = sqrt(max_j deg_j).                        */
+/* p_ref[m] (may be NULL): dist[n] = ||p^{n,0} - p_ref||_2, n = 0..R, and   */
+/* kkt[n] (may be NULL) the relative KKT error of (x^{n,0}, p^{n,0}).        */
+/* p[m], x[nnz]: the last restart point.                                     */
+/* ------------------------------------------------------------------------ */
+int ora_fixed_restart(int n, int m, const int64_t *row_ptr, const int32_t *col,
+                      const double *u, const double *w, int K, int R, double eta,
+                      const double *p_ref, double *dist, double *kkt, double *p, double *x) {
+  int rc = ora_validate(n, m, row_ptr, col, u, w);
+  if (rc != ORA_OK) return rc;
+  if (K < 1 || R < 0) return ORA_ERR_ARG;
+  int64_t nnz = row_ptr[n];
+  int dmax = 0;
+  for (int i = 0; i < n; ++i)
+    if ((int)(row_ptr[i + 1] - row_ptr[i]) > dmax) dmax = (int)(row_ptr[i + 1] - row_ptr[i]);
+  double *uh = (double *)malloc((size_t)nnz * sizeof(double));
+  double *xn = (double *)malloc((size_t)nnz * sizeof(double));
+  double *xb = (double *)malloc((size_t)nnz * sizeof(double));
+  double *deg = (double *)calloc((size_t)m, sizeof(double));
+  double *c = (double *)malloc((size_t)m * sizeof(double));
+  double *cp = (double *)malloc((size_t)m * sizeof(double));
+  double *pn = (double *)malloc((size_t)m * sizeof(double));
+  double *pb = (double *)malloc((size_t)m * sizeof(double));
+  ora_params prm;
+  ora_default_params(&prm);
+  for (int i = 0; i < n; ++i) {
+    double mx = 0.0;
+    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k)
+      if (u[k] > mx) mx = u[k];
+    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) uh[k] = u[k] / mx;
+  }
+  for (int64_t k = 0; k < nnz; ++k) deg[col[k]] += 1.0;
+  double maxdeg = 0.0, sumw = 0.0;
+  for (int j = 0; j < m; ++j)
+    if (deg[j] > maxdeg) maxdeg = deg[j];
+  for (int i = 0; i < n; ++i) sumw += w[i];
+  if (!(eta > 0.0)) eta = 1.0 / (2.0 * sqrt(maxdeg));
+  for (int i = 0; i < n; ++i)
+    for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) x[k] = 1.0 / deg[col[k]];
+  for (int j = 0; j < m; ++j) p[j] = sumw / m;
+
+  for (int r = 0; r <= R; ++r) {
+    /* restart point (x^{r,0}, p^{r,0}) */
+    if (p_ref && dist) dist[r] = sqrt(dist2(m, p, p_ref));
+    if (kkt) kkt[r] = ora_kkt(n, m, row_ptr, col, uh, w, x, p, NULL);
+    if (r == R) break;
+    /* inner loop of K iterations from the restart point; after a restart
+     * the extrapolation has no previous iterate: c^{-1} = c^0 */
+    colsum(n, m, row_ptr, col, x, c);
+    memcpy(cp, c, (size_t)m * sizeof(double));
+    for (int k = 0; k < K; ++k) {
+      for (int j = 0; j < m; ++j) pn[j] = p[j] + eta * (2.0 * c[j] - cp[j] - 1.0);
+      rc = prox_sweep(n, row_ptr, col, uh, w, x, pn, eta, &prm, dmax, xn, NULL);
+      if (rc != ORA_OK) goto done;
+      memcpy(x, xn, (size_t)nnz * sizeof(double));
+      memcpy(p, pn, (size_t)m * sizeof(double));
+      memcpy(cp, c, (size_t)m * sizeof(double));
+      colsum(n, m, row_ptr, col, x, c);
+      /* running average of the iterates of this inner loop */
+      if (k == 0) {
+        memcpy(xb, x, (size_t)nnz * sizeof(double));
+        memcpy(pb, p, (size_t)m * sizeof(double));
+      } else {
+        for (int64_t q = 0; q < nnz; ++q) xb[q] += (x[q] - xb[q]) / (double)(k + 1);
+        for (int j = 0; j < m; ++j) pb[j] += (p[j] - pb[j]) / (double)(k + 1);
+      }
+    }
+    /* restart to the average */
+    memcpy(x, xb, (size_t)nnz * sizeof(double));
+    memcpy(p, pb, (size_t)m * sizeof(double));
+  }
+  rc = ORA_OK;
+done:
+  free(uh); free(xn); free(xb); free(deg); free(c); free(cp); free(pn); free(pb);
+  return rc;
+}

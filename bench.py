@@ -3,7 +3,11 @@ market (n = 1e6 buyers, m = 1e4 goods, 100 goods per buyer) on one GPU.
 
 A step is one complete solve (restarted PDHCG, Alg. 2 with the Sec. 5
 enhancements) from the default cold start to the tolerance, with the market
-already resident in HBM.  Prints one JSON line.
+already resident in HBM.  Prints one JSON line.  Further legs (each can be
+switched off): the batched launch against a per-market loop, reverse mode,
+restarted PDHG (Alg. 1) on the same market, the skewed market, the market of
+the e-commerce data's shape and the Arrow-Debreu fixed point.  Every market
+is generated on the host before the first GPU call.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -25,6 +29,7 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "row_pass_fisher1e8_counters.json")
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2506_06258_amd", "csrc", f)
                for f in ("pdhcg_kernels.hip", "pdhcg_device.h", "pdhcg_internal.h")]
+GOLDEN_1E8 = os.path.join(ROOT, "tests", "golden", "fisher_1e8_s1_prices.json")
 
 
 def log(msg):
@@ -39,7 +44,7 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(n_launch_bytes_key="row_pass"):
+def traffic_from_profile():
     """HBM bytes per row-pass launch from the committed counter summary, or
     None when it is missing or was taken on a different kernel source."""
     try:
@@ -51,70 +56,78 @@ def traffic_from_profile(n_launch_bytes_key="row_pass"):
     return prof.get("bytes_per_launch")
 
 
-def batched_leg(args, pdhcg, synth, torch):
-    """Markets/s of one persistent launch over many independent markets
-    against solving a spread sample of the same markets one call at a time,
-    both to the same relative KKT tolerance."""
-    t0 = time.time()
-    bt = synth.batch_markets(args.batch_markets, args.seed + 1000)
-    nnz = int(len(bt.col))
-    log(f"batch of {bt.count} markets generated in {time.time() - t0:.1f}s, nnz={nnz}")
-    B = pdhcg.Batch(bt, device=torch.device("cuda:0"))
-    prm = pdhcg.pdhcg_default_params(tol=args.tol, max_iter=200000)
-    t0 = time.time()
-    sch = B.autotune(prm, trial_iters=64)  # schedule choice, outside the timed region
-    log(f"batch schedule {sch.as_dict()} tuned in {time.time() - t0:.2f}s")
-    st, _, _, infos = B.solve(prm)  # warmup
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    st, p, _, infos = B.solve(prm)
-    torch.cuda.synchronize()
-    dt_b = time.perf_counter() - t1
-    iters_b = np.array([i.iters for i in infos])
-    kkt_b = max(i.rel_kkt for i in infos)
-    ok_b = sum(1 for i in infos if i.status == pdhcg.PDHCG_OK)
-    log(f"batched: {dt_b:.3f}s for {bt.count} markets, {ok_b} converged, max kkt {kkt_b:.2e}")
-    B.close()
+def row_bytes(nnz, n):
+    """Algorithmic bytes of one row pass (the measurement plan's model):
+    per edge u, good id, x read, x written, average read and written (4 B
+    each); per buyer row pointer, budget and utility (4 B each)."""
+    return 24 * nnz + 12 * n
 
-    k = max(1, min(args.loop_markets, bt.count))
-    pick = np.linspace(0, bt.count - 1, k).round().astype(int)
-    Ms = [pdhcg.Market.from_synth(bt.market(int(b)), device=torch.device("cuda:0")) for b in pick]
-    for M in Ms[:2]:
-        M.solve(prm)  # warmup
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kkt_l, iters_l, ok_l = 0.0, [], 0
-    for M in Ms:
+
+def solve_legs(args, M, mk, pdhcg, torch):
+    prm = pdhcg.pdhcg_default_params(tol=args.tol, max_iter=20000, timing=1)
+    for w in range(args.warmup):
         s = M.solve(prm)
-        kkt_l = max(kkt_l, s.info.rel_kkt)
-        iters_l.append(s.info.iters)
-        ok_l += int(s.info.status == pdhcg.PDHCG_OK)
-    torch.cuda.synchronize()
-    dt_l = time.perf_counter() - t1
-    for M in Ms:
-        M.close()
-    log(f"looped: {dt_l:.3f}s for {k} markets, {ok_l} converged, max kkt {kkt_l:.2e}")
-    mps_b = bt.count / dt_b
-    mps_l = k / dt_l
-    return {
-        "workload": (f"{bt.count} independent linear Fisher markets, n~logU[64,8192], "
-                     f"m~logU[16,2048], density~U(5%,30%), u~U(0.01,1), w~U(0.5,1.5), "
-                     f"seed {args.seed + 1000}, total nnz {nnz}; rel. KKT <= {args.tol:g}"),
-        "batched_markets_per_s": mps_b,
-        "batched_seconds": dt_b,
-        "batched_converged": ok_b,
-        "batched_max_rel_kkt": kkt_b,
-        "batched_iters_median": float(np.median(iters_b)),
-        "batched_iters_max": int(iters_b.max()),
-        "batched_schedule": sch.as_dict(),
-        "batched_longest_market_s": float(max(i.seconds for i in infos)),
-        "looped_markets_per_s": mps_l,
-        "looped_sample": f"{k} markets evenly spaced through the batch, one pdhcg_solve call each",
-        "looped_seconds": dt_l,
-        "looped_converged": ok_l,
-        "looped_max_rel_kkt": kkt_l,
-        "speedup": mps_b / mps_l,
-    }
+        log(f"warmup {w}: iters={s.info.iters} kkt={s.info.rel_kkt:.2e} t={s.info.seconds:.3f}s")
+    times, infos = [], []
+    for k in range(args.steps):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s = M.solve(prm)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        times.append(dt)
+        infos.append(s.info)
+        log(f"step {k}: {dt:.4f}s iters={s.info.iters} accepted={s.info.accepted} "
+            f"kkt={s.info.rel_kkt:.2e} restarts={s.info.restarts} "
+            f"rounds_mean={s.info.search_rounds_mean:.2f}")
+        if s.info.status != pdhcg.PDHCG_OK:
+            log(f"solve ended with status {s.info.status}")
+    return s, times, infos
+
+
+def cpu_leg(args, mk, gpu_iters):
+    """The FP64 oracle on the same market: 2 and 2 + cpu_iters iterations
+    (each run ends with one KKT check), the difference timing cpu_iters
+    iterations without the setup; scaled to the GPU solve's iterations.
+    The oracle's full solve to 1e-4, timed when the reference prices were
+    written, is reported beside it."""
+    import oracle
+    oracle.build(force=False)
+    u64, w64 = mk.u.astype(np.float64), mk.w.astype(np.float64)
+    secs = []
+    for k in (2, 2 + args.cpu_iters):
+        t1 = time.perf_counter()
+        r = oracle.solve(mk.n, mk.m, mk.row_ptr, mk.col, u64, w64, tol=0.0, max_iter=k,
+                         eval_every=10**9)
+        secs.append(time.perf_counter() - t1)
+        log(f"cpu oracle: {r.iters} iterations in {secs[-1]:.2f}s")
+    per_it = (secs[1] - secs[0]) / args.cpu_iters
+    full = None
+    try:
+        g = json.load(open(GOLDEN_1E8))
+        if g.get("market") == mk.name and "to_1e-4" in g:
+            full = {"seconds": g["to_1e-4"]["seconds"], "iterations": g["to_1e-4"]["iterations"],
+                    "threads": g["threads"], "cpu": g["cpu_model"],
+                    "note": "oracle solve to rel. KKT 1e-4 on the build host, setup included"}
+    except (OSError, ValueError):
+        pass
+    return {"value": per_it * gpu_iters, "unit": "s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": (f"{args.cpu_iters} FP64 oracle iterations on the same 1e8-edge market "
+                       f"(time of {2 + args.cpu_iters} minus time of 2 iterations: "
+                       f"{per_it:.3f} s/iteration, setup excluded), scaled by the {gpu_iters} "
+                       f"iterations the GPU solve needed to reach rel. KKT {args.tol:g}"),
+            "seconds_per_iteration": per_it, "full_solve_to_1e-4": full}
+
+
+def euler_w_residual(M, mk, s, g, dw, torch):
+    """sum_i w_i dL/dw_i - sum_j p_j dL/dp_j over |sum_j p_j dL/dp_j|: zero
+    for the derivative of the equilibrium prices (p is homogeneous of degree
+    one in w), so it measures how far the unrolled reverse mode is from its
+    limit."""
+    lhs = float((torch.as_tensor(mk.w, device=dw.device).double() * dw.double()).sum())
+    rhs = float((s.p.double() * g.double()).sum())
+    return abs(lhs - rhs) / max(abs(rhs), 1e-30)
 
 
 def backward_leg(args, M, mk, s, pdhcg, torch):
@@ -126,25 +139,143 @@ def backward_leg(args, M, mk, s, pdhcg, torch):
     M.backward(s.x, s.p, s.info.omega, g, unroll=4, ckpt_every=2)  # warmup
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    M.backward(s.x, s.p, s.info.omega, g, unroll=K, ckpt_every=16)
+    _, dw = M.backward(s.x, s.p, s.info.omega, g, unroll=K, ckpt_every=16)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t1
     # per step: two forward passes without the average (u 4, id 2, x read 4,
     # x write 4 B/edge) and one adjoint pass (u 4, id 2, x 4, R in 4, R out 4,
     # dL/du read and write 8 B/edge)
     per_edge = 2 * 14 + 26
-    log(f"backward: {K} unrolled steps in {dt:.3f}s")
+    eul = euler_w_residual(M, mk, s, g, dw, torch)
+    log(f"backward: {K} unrolled steps in {dt:.3f}s, budget Euler residual {eul:.2e}")
     return {"workload": f"pdhcg_backward on the same market, {K} unrolled fixed steps, "
-                        "checkpoints every 16, from the timed solve's point",
+                        "checkpoints every 16, from the timed solve's point, the solve's omega",
             "seconds": dt, "ms_per_step": 1e3 * dt / K,
             "alg_bytes_per_step": per_edge * mk.nnz,
-            "achieved_GBs": per_edge * mk.nnz * K / dt / 1e9}
+            "achieved_GBs": per_edge * mk.nnz * K / dt / 1e9,
+            "budget_euler_residual": eul}
 
 
-def exchange_leg(pdhcg, synth, torch):
+def pdhg_leg(args, M, mk, pdhcg, torch):
+    """Restarted PDHG (Alg. 1, the paper's baseline) on the same market to
+    the same tolerance, one warm-up solve then one timed solve."""
+    prm = pdhcg.pdhcg_default_params(tol=args.tol, max_iter=200000, timing=1)
+    M.pdhg_solve(prm)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sol, _ = M.pdhg_solve(prm)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    i = sol.info
+    avg = i.row_pass_seconds / max(i.row_pass_launches, 1)
+    # row pass: 24 B/edge as PDHCG; per buyer row pointer and budget (8 B),
+    # t, y, g, g_prev read, t, y, g written, averages of t, y read and
+    # written (float64: 88 B)
+    alg = 24 * mk.nnz + 96 * mk.n
+    log(f"pdhg: {dt:.3f}s, {i.iters} iterations, kkt {i.rel_kkt:.2e}, row pass {1e3 * avg:.3f} ms")
+    return {"workload": f"restarted PDHG (Alg. 1) on the same market to rel. KKT <= {args.tol:g}",
+            "seconds": dt, "iterations": int(i.iters), "status": int(i.status),
+            "final_rel_kkt": float(i.rel_kkt), "ms_per_iter": 1e3 * dt / max(i.iters, 1),
+            "row_pass_ms": 1e3 * avg, "alg_bytes_per_launch": alg,
+            "row_pass_GBs": alg / avg / 1e9 if avg > 0 else None,
+            "row_pass_frac": alg / avg / 1e9 / PEAK_HBM_GBS if avg > 0 else None}
+
+
+def batched_leg(args, bt, pdhcg, torch):
+    """Markets/s of one persistent launch over many independent markets
+    against one pdhcg_solve call per market on one stream, both to the same
+    relative KKT tolerance (1e-4, and 1e-6 on a spread sample for the loop)."""
+    nnz = int(len(bt.col))
+    B = pdhcg.Batch(bt, device=torch.device("cuda:0"))
+    out = {"workload": (f"{bt.count} independent linear Fisher markets, n~logU[64,8192], "
+                        f"m~logU[16,2048], density~U(5%,30%), u~U(0.01,1), w~U(0.5,1.5), "
+                        f"seed {args.seed + 1000}, total nnz {nnz}")}
+    prm4 = pdhcg.pdhcg_default_params(tol=1e-4, max_iter=200000)
+    t0 = time.time()
+    sch = B.autotune(prm4, trial_iters=64)  # schedule choice, outside the timed region
+    log(f"batch schedule {sch.as_dict()} tuned in {time.time() - t0:.2f}s")
+    out["batched_schedule"] = sch.as_dict()
+    for tol in (1e-4, 1e-6):
+        prm = pdhcg.pdhcg_default_params(tol=tol, max_iter=400000)
+        B.solve(prm)  # warmup
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st, p, _, infos = B.solve(prm)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        iters = np.array([i.iters for i in infos])
+        ok = sum(1 for i in infos if i.status == pdhcg.PDHCG_OK)
+        key = f"tol_{tol:g}"
+        out[key] = {"batched_seconds": dt, "batched_markets_per_s": bt.count / dt,
+                    "batched_converged": ok,
+                    "batched_max_rel_kkt": max(i.rel_kkt for i in infos),
+                    "batched_iters_median": float(np.median(iters)),
+                    "batched_iters_max": int(iters.max()),
+                    "batched_longest_market_s": float(max(i.seconds for i in infos)),
+                    "batched_sum_market_s": float(sum(i.seconds for i in infos))}
+        log(f"batched {tol:g}: {dt:.3f}s for {bt.count} markets, {ok} converged")
+    B.close()
+    for tol, count in ((1e-4, min(args.loop_markets, bt.count)),
+                       (1e-6, min(args.loop_markets_1e6, bt.count))):
+        if count <= 0:
+            continue
+        prm = pdhcg.pdhcg_default_params(tol=tol, max_iter=400000)
+        pick = np.linspace(0, bt.count - 1, count).round().astype(int)
+        # markets are created (and their first call warmed up) outside the
+        # timed solve calls, one at a time
+        dt, kkt_l, ok_l = 0.0, 0.0, 0
+        for q, b in enumerate(pick):
+            M = pdhcg.Market.from_synth(bt.market(int(b)), device=torch.device("cuda:0"))
+            if q == 0:
+                M.solve(prm)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            s = M.solve(prm)
+            torch.cuda.synchronize()
+            dt += time.perf_counter() - t1
+            kkt_l = max(kkt_l, s.info.rel_kkt)
+            ok_l += int(s.info.status == pdhcg.PDHCG_OK)
+            M.close()
+            if (q + 1) % 1024 == 0:
+                log(f"looped {tol:g}: {q + 1} markets, {dt:.2f}s of solve calls")
+        key = f"tol_{tol:g}"
+        out[key].update({"looped_markets_per_s": count / dt, "looped_seconds": dt,
+                         "looped_markets": count, "looped_converged": ok_l,
+                         "looped_max_rel_kkt": kkt_l,
+                         "speedup": out[key]["batched_markets_per_s"] / (count / dt)})
+        log(f"looped {tol:g}: {dt:.3f}s for {count} markets")
+    return out
+
+
+def market_leg(label, mk, args, pdhcg, torch, with_bytes=True):
+    """One solve of a further market to rel. KKT 1e-4 (warm-up, then timed)."""
+    M = pdhcg.Market.from_synth(mk, device=torch.device("cuda:0"))
+    prm = pdhcg.pdhcg_default_params(tol=args.tol, max_iter=20000, timing=1)
+    M.solve(prm)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s = M.solve(prm)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    info = s.info
+    hot = M.lds_goods()
+    M.close()
+    avg = info.row_pass_seconds / max(info.row_pass_launches, 1)
+    log(f"{label}: {dt:.3f}s, {info.iters} iterations, kkt {info.rel_kkt:.2e}, "
+        f"row pass {1e3 * avg:.3f} ms")
+    out = {"workload": f"{mk.name}: n={mk.n}, m={mk.m}, nnz={mk.nnz}; rel. KKT <= {args.tol:g}",
+           "seconds": dt, "iterations": int(info.iters), "status": int(info.status),
+           "final_rel_kkt": float(info.rel_kkt), "lds_goods": int(hot),
+           "row_pass_ms": 1e3 * avg}
+    if with_bytes and avg > 0:
+        out["row_pass_GBs"] = row_bytes(mk.nnz, mk.n) / avg / 1e9
+        out["row_pass_frac"] = out["row_pass_GBs"] / PEAK_HBM_GBS
+    return out
+
+
+def exchange_leg(mk, pdhcg, torch):
     """Arrow-Debreu fixed point (Sec. 4) on n = m = 1e5 (5e6 utility edges),
     warm-started inner solves to rel. KKT 1e-7, outer tolerance 1e-6."""
-    mk = synth.arrow_debreu_1e5()
     M = pdhcg.Market.from_synth(mk, device=torch.device("cuda:0"))
     inner = pdhcg.pdhcg_default_params(tol=1e-7, max_iter=200000)
     torch.cuda.synchronize()
@@ -162,28 +293,6 @@ def exchange_leg(pdhcg, synth, torch):
             "ms_per_inner_iteration": 1e3 * dt / max(int(res["inner"]), 1)}
 
 
-def skewed_leg(args, pdhcg, synth, torch):
-    """The skewed market (n = 4e6, m = 2e5, Zipf(1.5) degrees, 1/rank
-    popularity) to rel. KKT 1e-4."""
-    t0 = time.time()
-    mk = synth.fisher_skewed(workers=12)
-    log(f"skewed market generated in {time.time() - t0:.1f}s, nnz={mk.nnz}")
-    M = pdhcg.Market.from_synth(mk, device=torch.device("cuda:0"))
-    prm = pdhcg.pdhcg_default_params(tol=args.tol, max_iter=20000, timing=1)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    s = M.solve(prm)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t1
-    info = s.info
-    M.close()
-    log(f"skewed: {dt:.3f}s, {info.iters} iterations, kkt {info.rel_kkt:.2e}")
-    return {"workload": f"skewed linear Fisher market, n={mk.n}, m={mk.m}, nnz={mk.nnz}; "
-                        f"rel. KKT <= {args.tol:g}",
-            "seconds": dt, "iterations": int(info.iters), "final_rel_kkt": float(info.rel_kkt),
-            "row_pass_ms": 1e3 * info.row_pass_seconds / max(info.row_pass_launches, 1)}
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,31 +303,46 @@ def main():
     ap.add_argument("--buyers", type=int, default=1_000_000)
     ap.add_argument("--goods", type=int, default=10_000)
     ap.add_argument("--degree", type=int, default=100)
-    ap.add_argument("--cpu-iters", type=int, default=3,
+    ap.add_argument("--cpu-iters", type=int, default=20,
                     help="oracle iterations timed for the CPU baseline (0: skip)")
     ap.add_argument("--batch-markets", type=int, default=4096,
                     help="markets of the batched leg (0: skip)")
+    ap.add_argument("--loop-markets", type=int, default=4096,
+                    help="markets of the batch solved one call at a time at 1e-4")
+    ap.add_argument("--loop-markets-1e6", type=int, default=256,
+                    help="markets of the batch solved one call at a time at 1e-6")
     ap.add_argument("--backward-unroll", type=int, default=64,
                     help="unrolled steps of the reverse-mode leg on the same market (0: skip)")
+    ap.add_argument("--pdhg", type=int, default=1, help="restarted PDHG leg (0: skip)")
     ap.add_argument("--exchange", type=int, default=1,
                     help="run the Arrow-Debreu leg (1e5 agents and goods; 0: skip)")
-    ap.add_argument("--skewed", type=int, default=0,
-                    help="run the skewed-market leg (4e6 x 2e5, 4.5e8 edges; about a minute)")
-    ap.add_argument("--loop-markets", type=int, default=32,
-                    help="markets of the batch solved one call at a time for the looped rate")
+    ap.add_argument("--skewed", type=int, default=1,
+                    help="run the skewed-market leg (4e6 x 2e5, 4.5e8 edges; 0: skip)")
+    ap.add_argument("--jd", type=int, default=1,
+                    help="run the leg on the market of the e-commerce data's shape (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
-    import torch
+    from paper_2506_06258_amd import synth
 
-    from paper_2506_06258_amd import pdhcg, synth
-
+    # every market on the host first: generators may start worker processes,
+    # which must not inherit a GPU context
     t0 = time.time()
     mk = synth.fisher_1e8(args.seed, args.buyers, args.goods, args.degree)
     log(f"generated {mk.name}: nnz={mk.nnz} in {time.time() - t0:.1f}s")
+    bt = synth.batch_markets(args.batch_markets, args.seed + 1000) if args.batch_markets else None
+    skw = synth.fisher_skewed(workers=12) if args.skewed else None
+    jd = synth.jd_shaped(workers=12) if args.jd else None
+    ad = synth.arrow_debreu_1e5() if args.exchange else None
+    log(f"all markets generated in {time.time() - t0:.1f}s")
+
+    import torch
+
+    from paper_2506_06258_amd import pdhcg
+
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t0 = time.time()
@@ -226,68 +350,34 @@ def main():
     torch.cuda.synchronize()
     log(f"market created in {time.time() - t0:.1f}s; bins={M.bins()}")
 
-    prm = pdhcg.pdhcg_default_params(tol=args.tol, max_iter=20000, timing=1)
-    for w in range(args.warmup):
-        s = M.solve(prm)
-        log(f"warmup {w}: iters={s.info.iters} kkt={s.info.rel_kkt:.2e} "
-            f"t={s.info.seconds:.3f}s")
-    times, infos = [], []
-    torch.cuda.synchronize()
-    for k in range(args.steps):
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        s = M.solve(prm)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t1
-        times.append(dt)
-        infos.append(s.info)
-        log(f"step {k}: {dt:.4f}s iters={s.info.iters} kkt={s.info.rel_kkt:.2e} "
-            f"restarts={s.info.restarts} rounds_mean={s.info.search_rounds_mean:.2f}")
-        if s.info.status != pdhcg.PDHCG_OK:
-            log(f"solve ended with status {s.info.status}")
+    s, times, infos = solve_legs(args, M, mk, pdhcg, torch)
     p = s.p.double().cpu().numpy()
     psum_err = abs(p.sum() - float(mk.w.astype(np.float64).sum())) / float(mk.w.sum())
-
     mean_t = float(np.mean(times))
     iters = int(np.mean([i.iters for i in infos]))
+    accepted = int(np.mean([i.accepted for i in infos]))
     launches = sum(i.row_pass_launches for i in infos)
-    row_sec = sum(i.row_pass_seconds for i in infos)
-    avg_launch = row_sec / max(launches, 1)
-    # per edge: u, x read, x written, average read and written (4 B each) and
-    # the good id (2 B when every good sits in LDS, else 4 B); per buyer the
-    # row pointer and budget; per good its price
-    id_bytes = 2 if M.lds_goods() == mk.m else 4
-    alg_bytes = (20 + id_bytes) * mk.nnz + 8 * mk.n + 4 * mk.m
+    avg_launch = sum(i.row_pass_seconds for i in infos) / max(launches, 1)
+    alg_bytes = row_bytes(mk.nnz, mk.n)
     achieved = alg_bytes / avg_launch / 1e9
-    traffic = traffic_from_profile()
+    # what this kernel moves: 2-byte good ids when every good sits in LDS,
+    # the average read and written only on passes after a kept step
+    id_bytes = 2 if M.lds_goods() == mk.m else 4
+    fold_frac = accepted / max(iters, 1)
+    phys = (12 + id_bytes + 8 * fold_frac) * mk.nnz + 8 * mk.n + 4 * mk.m
 
-    cpu = None
-    if args.cpu_iters > 0:
-        import oracle
-        oracle.build(force=False)
-        u64, w64 = mk.u.astype(np.float64), mk.w.astype(np.float64)
-        t1 = time.perf_counter()
-        r = oracle.solve(mk.n, mk.m, mk.row_ptr, mk.col, u64, w64, tol=0.0,
-                         max_iter=args.cpu_iters, eval_every=10**9)
-        cpu_dt = time.perf_counter() - t1
-        per_it = cpu_dt / max(r.iters, 1)
-        cpu = {"value": per_it * iters, "unit": "s", "cores": oracle.num_threads(),
-               "kind": "oracle",
-               "sample": (f"{r.iters} FP64 oracle iterations on the same 1e8-edge market "
-                          f"({per_it:.2f} s/iteration, setup included), scaled by the "
-                          f"{iters} iterations the GPU solve needed to reach rel. KKT "
-                          f"{args.tol:g}")}
-        log(f"cpu oracle: {per_it:.3f}s/iter on {oracle.num_threads()} threads")
-
-    backward = None
-    if args.backward_unroll > 0:
-        backward = backward_leg(args, M, mk, s, pdhcg, torch)
-
-    batched = None
-    if args.batch_markets > 0:
-        batched = batched_leg(args, pdhcg, synth, torch)
-    exchange = exchange_leg(pdhcg, synth, torch) if args.exchange else None
-    skewed = skewed_leg(args, pdhcg, synth, torch) if args.skewed else None
+    cpu = cpu_leg(args, mk, iters) if args.cpu_iters > 0 else None
+    backward = backward_leg(args, M, mk, s, pdhcg, torch) if args.backward_unroll > 0 else None
+    pdhg = pdhg_leg(args, M, mk, pdhcg, torch) if args.pdhg else None
+    M.close()
+    del s
+    batched = batched_leg(args, bt, pdhcg, torch) if bt is not None else None
+    del bt
+    skewed = market_leg("skewed", skw, args, pdhcg, torch) if skw is not None else None
+    del skw
+    jdl = market_leg("e-commerce-shaped", jd, args, pdhcg, torch) if jd is not None else None
+    del jd
+    exchange = exchange_leg(ad, pdhcg, torch) if ad is not None else None
 
     out = {
         "metric": "time-to-1e-4 KKT & HBM GB/s (1e8-nnz Fisher); batched vs looped markets/s",
@@ -301,6 +391,8 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
+        "precision": ("float32 allocations, utilities and budgets (the O(nnz) stream); float64 "
+                      "prices, column sums, row roots and every global reduction"),
         "data": "synthetic",
         "config": {"workload": (f"linear Fisher market, n={mk.n} buyers, m={mk.m} goods, "
                                 f"{args.degree} uniformly random goods per buyer "
@@ -309,22 +401,30 @@ def main():
                                 f"{args.tol:g}"),
                    "n": mk.n, "m": mk.m, "nnz": mk.nnz, "tol": args.tol},
         "iterations": iters,
+        "accepted_steps": accepted,
         "ms_per_iter": 1e3 * mean_t / max(iters, 1),
         "final_rel_kkt": float(infos[-1].rel_kkt),
         "price_sum_rel_err": psum_err,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS,
-                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                     "unit": "GB/s", "frac": achieved / PEAK_HBM_GBS,
+                     "traffic": traffic_from_profile(),
                      "kernel": "k_row_pass (row prox + average fold + column partials)",
                      "alg_bytes_per_launch": alg_bytes,
+                     "alg_bytes_model": "24 B/edge + 12 B/buyer",
+                     "kernel_bytes_per_launch": phys,
+                     "kernel_bytes_model": (f"{12 + id_bytes} B/edge + 8 B/edge on the "
+                                            f"{fold_frac:.3f} of passes that fold the average "
+                                            "+ 8 B/buyer + 4 B/good"),
                      "avg_launch_ms": 1e3 * avg_launch, "launches_timed": launches},
         "cpu_baseline": cpu,
         "batched": batched,
         "backward": backward,
-        "exchange": exchange,
+        "pdhg": pdhg,
         "skewed": skewed,
+        "ecommerce_shaped": jdl,
+        "exchange": exchange,
     }
     print(json.dumps(out), flush=True)
-    M.close()
 
 
 if __name__ == "__main__":

@@ -71,10 +71,19 @@ enum {
    * such root is a lower bound on s* and is exact once the active set
    * settles.  Default on gfx950. */
   PDHCG_SEARCH_ACTIVESET = 0,
-  /* k-section search of Sec. 2.2.1 (sections = k, 32 in the paper).
+  /* k-section search of Sec. 2.2.1 (sections = k <= 32, 32 in the paper)
+   * on the row shapes of the active-set search: the G lanes that hold a
+   * row evaluate the k candidates one after the other.
    * pdhcg_solve and pdhcg_row_prox return PDHCG_ERR_UNSUPPORTED for it on
    * markets with rows of more than 512 entries. */
-  PDHCG_SEARCH_KSECTION = 1
+  PDHCG_SEARCH_KSECTION = 1,
+  /* The same k-section search mapped as Sec. 2.2.1 maps it: one wave per
+   * row with the row staged in LDS and one lane per candidate
+   * (sections = k <= 64 on wave64).  pdhcg_solve and pdhcg_row_prox return
+   * PDHCG_ERR_UNSUPPORTED for it on markets with rows of more than 512
+   * entries or whose column partials do not fit LDS beside the staging
+   * (m > 14000 on gfx950). */
+  PDHCG_SEARCH_KSECTION_WAVE = 2
 };
 
 enum { PDHCG_STEP_FIXED = 0, PDHCG_STEP_ADAPTIVE = 1 };
@@ -178,6 +187,50 @@ int32_t pdhcg_set_budgets(pdhcg_market market, const float *w);
 int32_t pdhcg_solve(pdhcg_market market, const pdhcg_params *params,
                     int32_t warm, float *p, float *x, float *t,
                     pdhcg_info *info);
+
+/* Alg. 2 in the setting of its analysis (Sec. 3: Lemma 1, Lemma 2,
+ * Theorem 1): fixed step sizes sigma = tau = eta, a fixed restart length K,
+ * and every restart to the average of the K iterates of its inner loop, with
+ * none of the Sec. 5 enhancements except the row normalisation.  Runs
+ * `restarts` inner loops from the default initial point (x0_ij = 1/deg_j,
+ * p0_j = sum(w)/m).
+ *   eta   <= 0: 1/(2||K||) with ||K|| = sqrt(max_j deg_j) (the norm of the
+ *         column-sum operator on the stored pattern); else the step.
+ *   p_ref [m] device, may be NULL: reference prices (normally p*).
+ *   dist  [restarts + 1] host, may be NULL: ||p^{n,0} - p_ref||_2 of the
+ *         restart points n = 0 (the start) .. restarts (0 without p_ref).
+ *   kkt   [restarts + 1] host, may be NULL: relative KKT error (Sec. 5
+ *         Criteria) of each restart point.
+ *   p [m], x [nnz] device outputs: the last restart point.
+ *   info  host, may be NULL (iters = K * restarts).
+ * ERR_ARG on null p/x, K < 1, restarts < 0 or a non-finite eta. */
+int32_t pdhcg_solve_fixed_restart(pdhcg_market market, int32_t K,
+                                  int32_t restarts, double eta,
+                                  const float *p_ref, double *dist,
+                                  double *kkt, float *p, float *x,
+                                  pdhcg_info *info);
+
+/* Solve the Fisher market by restarted PDHG (Alg. 1, Sec. 2.1), the
+ * method PDHCG is compared with in Sec. 5: primal (x, t), dual (p, y) of
+ * the reformulated program (eq. primal-dual-formulation), iterations of
+ * eqs. update:py, update:t and update:x, with the same Sec. 5 enhancements
+ * as pdhcg_solve (row normalisation, adaptive restarts, primal weight,
+ * adaptive step size) and the Sec. 5 Criteria KKT error of (x, t, p, y).
+ * params: as pdhcg_solve (the search fields are unused).  Fixed step mode
+ * uses eta = 0.9 / (sqrt(max_j deg_j) + 1 + sqrt(max_j deg_j max_i deg_i)),
+ * a bound below 1/||K||; adaptive mode starts at eta = 1.  Initial point:
+ * x0_ij = 1/deg_j, p0_j = sum(w)/m, t0 = U x0, y0 = w / t0.
+ *   p [m], x [nnz] device: as pdhcg_solve (warm != 0 reads them).
+ *   t [n], y [n]   device, may be NULL: utilities and their duals in the
+ *                  caller's units (t_i in units of u_i, y_i in 1/u_i); with
+ *                  warm != 0 a non-NULL t or y is also the starting value
+ *                  (else t = U x, y = w / t).
+ * Built for markets whose goods all keep their prices in LDS (m <= 10000
+ * on gfx950) and rows of at most 512 entries: PDHCG_ERR_UNSUPPORTED
+ * otherwise.  Returns as pdhcg_solve. */
+int32_t pdhcg_pdhg_solve(pdhcg_market market, const pdhcg_params *params,
+                         int32_t warm, float *p, float *x, float *t, float *y,
+                         pdhcg_info *info);
 
 /* Relative KKT error (Sec. 5 Criteria, with t_i = u_i^T x_i, y = w/t) of a
  * given point (device p[m], x[nnz]) on the normalised market; float64

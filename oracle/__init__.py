@@ -54,7 +54,7 @@ class OraInfo(C.Structure):
         ("rel_kkt", C.c_double), ("rel_primal", C.c_double), ("rel_dual", C.c_double),
         ("rel_gap", C.c_double), ("eta", C.c_double), ("omega", C.c_double),
         ("iters", C.c_int64), ("restarts", C.c_int32), ("status", C.c_int32),
-        ("accepted", C.c_int64),
+        ("accepted", C.c_int64), ("emax_last", C.c_double),
     ]
 
 
@@ -205,6 +205,7 @@ class PdhgSolution:
     eta: float
     omega: float
     accepted: int
+    emax_last: float
 
 
 def pdhg_solve(n, m, row_ptr, col, u, w, params: OraParams | None = None,
@@ -224,7 +225,7 @@ def pdhg_solve(n, m, row_ptr, col, u, w, params: OraParams | None = None,
                               C.byref(info))
     return PdhgSolution(p, x, t, y, int(st), info.rel_kkt, info.rel_primal, info.rel_dual,
                         info.rel_gap, int(info.iters), int(info.restarts), info.eta, info.omega,
-                        int(info.accepted))
+                        int(info.accepted), info.emax_last)
 
 
 def fixed_restart(n, m, row_ptr, col, u, w, K, R, eta=0.0, p_ref=None):
@@ -328,6 +329,7 @@ class Solution:
     eta: float
     omega: float
     accepted: int = 0
+    emax_last: float = float("nan")
 
 
 def solve(n, m, row_ptr, col, u, w, params: OraParams | None = None, p0=None, x0=None,
@@ -349,7 +351,7 @@ def solve(n, m, row_ptr, col, u, w, params: OraParams | None = None, p0=None, x0
                          _ptr(x, C.c_double), _ptr(t, C.c_double), C.byref(info))
     return Solution(p, x, t, int(st), info.rel_kkt, info.rel_primal, info.rel_dual,
                     info.rel_gap, int(info.iters), int(info.restarts), info.eta, info.omega,
-                    int(info.accepted))
+                    int(info.accepted), info.emax_last)
 
 
 def solve_market(mk, **kw) -> Solution:

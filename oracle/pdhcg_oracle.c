@@ -337,6 +337,7 @@ typedef struct {
   int32_t restarts;
   int32_t status;
   int64_t accepted;    /* steps kept by the adaptive step rule (all when fixed) */
+  double emax_last;    /* the step-size bound eta_max of the last adaptive step */
 } ora_info;
 
 void ora_default_params(ora_params *prm) {
@@ -554,6 +555,7 @@ int ora_solve(int n, int m, const int64_t *row_ptr, const int32_t *col,
   double kkt0 = ora_kkt(n, m, row_ptr, col, uh, w, x, p, NULL);
   double kkt_prev = INFINITY;
   int64_t k_in = 0, total = 0, accepted = 0;
+  double emax_last = NAN;
   int restarts = 0;
   double kout[3] = {NAN, NAN, NAN}, kbest = INFINITY;
   int status = ORA_MAX_ITER;
@@ -587,6 +589,7 @@ int ora_solve(int n, int m, const int64_t *row_ptr, const int32_t *col,
       if (enew < 0.01 * eta0) enew = 0.01 * eta0;
       accept = (eta <= emax) || (eta <= 0.01 * eta0);
       eta = enew;
+      emax_last = emax;
     }
     if (accept) {
       memcpy(x, xn, (size_t)nnz * sizeof(double));
@@ -681,6 +684,7 @@ int ora_solve(int n, int m, const int64_t *row_ptr, const int32_t *col,
     info->restarts = restarts;
     info->status = status;
     info->accepted = accepted;
+    info->emax_last = emax_last;
   }
   rc = status;
 
@@ -1195,6 +1199,7 @@ int ora_pdhg_solve(int n, int m, const int64_t *row_ptr, const int32_t *col,
   double kkt0 = ora_kkt_ty(n, m, row_ptr, col, u, w, X[0], T[0], P[0], Y[0], NULL);
   double kkt_prev = INFINITY, kout[3] = {NAN, NAN, NAN}, kbest = INFINITY;
   int64_t k_in = 0, total = 0, since = 0, accepted = 0;
+  double emax_last = NAN;
   int restarts = 0, status = ORA_MAX_ITER, cand_avg = 0;
 
   while (total < prm->max_iter) {
@@ -1220,6 +1225,7 @@ int ora_pdhg_solve(int n, int m, const int64_t *row_ptr, const int32_t *col,
       if (enew < 0.01 * eta0) enew = 0.01 * eta0;
       accept = (eta <= emax) || (eta <= 0.01 * eta0);
       eta = enew;
+      emax_last = emax;
     }
     if (accept) {
       memcpy(X[0], X[1], (size_t)nnz * sizeof(double));
@@ -1322,6 +1328,7 @@ int ora_pdhg_solve(int n, int m, const int64_t *row_ptr, const int32_t *col,
     info->restarts = restarts;
     info->status = status;
     info->accepted = accepted;
+    info->emax_last = emax_last;
   }
   rc = status;
 done:

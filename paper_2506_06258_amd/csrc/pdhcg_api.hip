@@ -95,6 +95,7 @@ struct pdhcg_market_s {
   std::vector<Bin> bins;
   int32_t total_wg = 0;
   int lds_row = 0, lds_eval = 0;
+  size_t lds_cap = 0;  // LDS bytes a workgroup may use
   int col_blocks = 0;
   // Goods relabelled by degree (most bought first) when their LDS data does
   // not fit: perm[internal] = caller's id, inv[caller's id] = internal (both
@@ -107,6 +108,10 @@ struct pdhcg_market_s {
   int32_t cold_mean_degree = 0;  // mean degree of the goods beyond LDS
   uint32_t *gmax = nullptr;  // [2][m] KKT column maxima of the goods from hot on
   double *gsum = nullptr;    // [m] KKT column sums of the goods from hot on
+  // restarted PDHG (Alg. 1): buyers' t, y, g in three roles and the anchors
+  // of t and y, allocated at the first pdhcg_pdhg_solve
+  double *pdhg_buf = nullptr;
+  PdhgDev pdhg{};
 
   MarketDev dev() const {
     MarketDev d;
@@ -244,6 +249,7 @@ void pdhcg_market_destroy(pdhcg_market mk) {
   f(mk->colpart); f(mk->evalpart); f(mk->evalcs); f(mk->evalchunk);
   f(mk->rowpart); f(mk->colblk); f(mk->cacc); f(mk->S);
   f(mk->colchunk); f(mk->perm); f(mk->inv); f(mk->col16); f(mk->cold_ptr); f(mk->cold_idx); f(mk->srow); f(mk->gmax); f(mk->gsum);
+  f(mk->pdhg_buf);
   for (auto &b : mk->bins) {
     f(b.d_rows);
     f(b.d_rbeg);
@@ -429,6 +435,7 @@ extern "C" int32_t pdhcg_market_create(int32_t n, int32_t m, int64_t nnz, const 
       lds_cu = std::max(lds_cap, (size_t)prop.maxSharedMemoryPerMultiProcessor);
     }
   }
+  mk->lds_cap = lds_cap;
   const size_t static_lds = 1024;  // the kernels' own __shared__ arrays
   // Row pass: float64 column partials and a float64 copy of the prices in
   // LDS when both fit.  Float64 LDS atomics: float32 LDS atomic adds measured
@@ -547,7 +554,8 @@ extern "C" int32_t pdhcg_market_create(int32_t n, int32_t m, int64_t nnz, const 
   }
   MK_HIPC(dalloc(&mk->evalchunk, mk->lds_eval ? (size_t)2 * kColChunks * m : (size_t)1));
   MK_HIPC(dalloc(&mk->cacc, (size_t)kColChunks * m));  // chunk sums in LDS mode
-  MK_HIPC(dalloc(&mk->rowpart, (size_t)mk->total_wg * std::max(kRowStats, kEvalRowStats)));
+  MK_HIPC(dalloc(&mk->rowpart, (size_t)mk->total_wg *
+                                   std::max(std::max(kRowStats, kEvalRowStats), kPdhgEvalStats)));
   MK_HIPC(dalloc(&mk->colblk, (size_t)mk->col_blocks * std::max(kColStats, kEvalColStats)));
   MK_HIPC(dalloc(&mk->colchunk, (size_t)kColChunks * m));
   MK_HIPC(dalloc(&mk->S, 1));
@@ -621,10 +629,14 @@ int32_t check_params(const pdhcg_params *p) {
   if (!p) return fail(PDHCG_ERR_ARG, "params is NULL");
   if (!(p->tol >= 0.0) || p->max_iter < 0 || p->eval_every <= 0)
     return fail(PDHCG_ERR_ARG, "tol >= 0, max_iter >= 0 and eval_every > 0 required");
-  if (p->search != PDHCG_SEARCH_ACTIVESET && p->search != PDHCG_SEARCH_KSECTION)
+  if (p->search != PDHCG_SEARCH_ACTIVESET && p->search != PDHCG_SEARCH_KSECTION &&
+      p->search != PDHCG_SEARCH_KSECTION_WAVE)
     return fail(PDHCG_ERR_ARG, "unknown search");
   if (p->search == PDHCG_SEARCH_KSECTION && (p->sections < 1 || p->sections > kMaxSections))
     return fail(PDHCG_ERR_ARG, "sections must be in [1, 32]");
+  if (p->search == PDHCG_SEARCH_KSECTION_WAVE &&
+      (p->sections < 1 || p->sections > kMaxWaveSections))
+    return fail(PDHCG_ERR_ARG, "sections must be in [1, 64]");
   if (p->max_search_rounds < 1) return fail(PDHCG_ERR_ARG, "max_search_rounds must be >= 1");
   if (p->step_mode != PDHCG_STEP_FIXED && p->step_mode != PDHCG_STEP_ADAPTIVE)
     return fail(PDHCG_ERR_ARG, "unknown step_mode");
@@ -634,13 +646,24 @@ int32_t check_params(const pdhcg_params *p) {
   return PDHCG_OK;
 }
 
-// The k-section search is built for the register-resident row shapes only.
+// The k-section searches are built for rows of at most 512 entries; the
+// one-lane-per-candidate kernel also keeps every good's column partial in
+// LDS beside its row staging.
 int32_t check_search(pdhcg_market mk, const pdhcg_params *p) {
   if (p->search == PDHCG_SEARCH_KSECTION)
     for (const Bin &b : mk->bins)
       if (b.G == 0)
         return fail(PDHCG_ERR_UNSUPPORTED, "the k-section search is not built for rows of more "
                                            "than 512 entries");
+  if (p->search == PDHCG_SEARCH_KSECTION_WAVE) {
+    if (mk->maxdeg_row > kKwaveMaxRow)
+      return fail(PDHCG_ERR_UNSUPPORTED, "the one-lane-per-candidate k-section search is not "
+                                         "built for rows of more than 512 entries");
+    if (!(mk->lds_row & 1) || mk->hot != mk->m || kwave_lds_bytes(mk->m) + 1024 > mk->lds_cap)
+      return fail(PDHCG_ERR_UNSUPPORTED, "the one-lane-per-candidate k-section search needs every "
+                                         "good's column partial in LDS beside the row staging "
+                                         "(m <= 14000 on gfx950)");
+  }
   return PDHCG_OK;
 }
 
@@ -664,8 +687,11 @@ int32_t enqueue_step(pdhcg_market mk, const RowIO &io, hipEvent_t ev0 = nullptr,
   // c_try is zeroed when its goods are summed by device atomics (no LDS)
   HIPC(launch_pstep(md, mk->lds_row == 0 ? 1 : 0, mk->stream));
   if (ev0) HIPC(hipEventRecord(ev0, mk->stream));
-  for (const Bin &b : mk->bins)
-    HIPC(launch_row_pass(md, mk->bindev(b), b.G, b.E, mk->lds_row, io, b.nwg, mk->stream));
+  if (io.search == PDHCG_SEARCH_KSECTION_WAVE)
+    HIPC(launch_row_kwave(md, io, mk->total_wg, mk->stream));
+  else
+    for (const Bin &b : mk->bins)
+      HIPC(launch_row_pass(md, mk->bindev(b), b.G, b.E, mk->lds_row, io, b.nwg, mk->stream));
   if (mk->lds_row == 7)
     HIPC(launch_cold_sums(md, 1, nullptr, nullptr, mk->cold_mean_degree, mk->stream));
   if (ev1) HIPC(hipEventRecord(ev1, mk->stream));
@@ -766,8 +792,11 @@ extern "C" int32_t pdhcg_row_prox(pdhcg_market mk, const float *x_in, const floa
   io.tau = tau;
   io.wfold = 0.0f;
   const MarketDev md = mk->dev();
-  for (const Bin &b : mk->bins)
-    HIPC(launch_row_pass(md, mk->bindev(b), b.G, b.E, mk->lds_row, io, b.nwg, mk->stream));
+  if (io.search == PDHCG_SEARCH_KSECTION_WAVE)
+    HIPC(launch_row_kwave(md, io, mk->total_wg, mk->stream));
+  else
+    for (const Bin &b : mk->bins)
+      HIPC(launch_row_pass(md, mk->bindev(b), b.G, b.E, mk->lds_row, io, b.nwg, mk->stream));
   return PDHCG_OK;
 }
 
@@ -1008,6 +1037,424 @@ extern "C" int32_t pdhcg_solve(pdhcg_market mk, const pdhcg_params *params, int3
   return status;
 }
 
+extern "C" int32_t pdhcg_solve_fixed_restart(pdhcg_market mk, int32_t K, int32_t restarts,
+                                             double eta, const float *p_ref, double *dist,
+                                             double *kkt, float *p, float *x, pdhcg_info *info) {
+  if (!mk || !p || !x) return fail(PDHCG_ERR_ARG, "null argument");
+  if (K < 1 || restarts < 0) return fail(PDHCG_ERR_ARG, "K >= 1 and restarts >= 0 required");
+  if (!(eta >= 0.0) || !std::isfinite(eta)) return fail(PDHCG_ERR_ARG, "eta must be finite");
+  hipStream_t st = mk->stream;
+  const auto t0 = std::chrono::steady_clock::now();
+  const int m = mk->m;
+  const int64_t nnz = mk->nnz;
+  const double knorm = std::sqrt((double)std::max(1, mk->maxdeg_col));
+  if (!(eta > 0.0)) eta = 1.0 / (2.0 * knorm);
+  pdhcg_params prm;
+  pdhcg_default_params(&prm);
+
+  HIPC(launch_init_point(mk->col, mk->deg, nnz, mk->X[0], mk->P[0], m, mk->sumw / (double)m, st));
+  if (mk->srow) HIPC(launch_zero_f32(mk->srow, mk->n, st));
+  // the price anchor of the KKT pass holds the reference prices, so the pass
+  // returns |p - p_ref|^2 for the current and the averaged point
+  if (p_ref)
+    HIPC(launch_gather_f32_to_f64(p_ref, mk->perm, mk->PA, m, st));
+  else
+    HIPC(launch_copy_f64(mk->P[0], mk->PA, m, st));
+  HIPC(launch_copy_f32(mk->X[0], mk->XA, nnz, st));
+  DevState &S = *mk->hS;
+  std::memset(&S, 0, sizeof(S));
+  S.ix[0] = 0; S.ix[1] = 1; S.ix[2] = 2;
+  S.ip[0] = 0; S.ip[1] = 1; S.ip[2] = 2;
+  S.ic[0] = 0; S.ic[1] = 1; S.ic[2] = 2;
+  int32_t rc = push_state(mk);
+  if (rc != PDHCG_OK) return rc;
+  {
+    EvalIO io;
+    std::memset(&io, 0, sizeof(io));
+    io.xc = mk->X[0];
+    io.pc = mk->P[0];
+    io.want_cc = 1;
+    io.cavg_out = mk->C[1];
+    io.rowscale = mk->rowmax;
+    io.panc = mk->PA;
+    rc = enqueue_eval(mk, io);
+    if (rc != PDHCG_OK) return rc;
+  }
+  rc = pull_state(mk);
+  if (rc != PDHCG_OK) return rc;
+  if (dist) dist[0] = p_ref ? std::sqrt(S.dpa2[0]) : 0.0;
+  if (kkt) kkt[0] = kkt_max(S.kkt[0]);
+  double klast = kkt_max(S.kkt[0]);
+  double kparts[3] = {S.kkt[0][0], S.kkt[0][1], S.kkt[0][2]};
+  HIPC(launch_copy_f64(mk->C[1], mk->C[0], m, st));
+  // fixed steps sigma = tau = eta (primal weight one)
+  std::memset(&S, 0, sizeof(S));
+  S.ix[0] = 0; S.ix[1] = 1; S.ix[2] = 2;
+  S.ip[0] = 0; S.ip[1] = 1; S.ip[2] = 2;
+  S.ic[0] = 0; S.ic[1] = 1; S.ic[2] = 2;
+  S.step_mode = 0;
+  S.eta = S.eta0 = S.eta_lo = S.eta_hi = eta;
+  S.omega = 1.0;
+  S.tau = eta;
+  S.sigma = eta;
+  rc = push_state(mk);
+  if (rc != PDHCG_OK) return rc;
+  const RowIO step_io = row_io_state(&prm);
+  for (int32_t r = 0; r < restarts; ++r) {
+    for (int32_t q = 0; q < K; ++q) {
+      rc = enqueue_step(mk, step_io);
+      if (rc != PDHCG_OK) return rc;
+    }
+    rc = pull_state(mk);
+    if (rc != PDHCG_OK) return rc;
+    // the average of the K iterates (with the lagged fold of the last one)
+    EvalIO io;
+    std::memset(&io, 0, sizeof(io));
+    io.xc = mk->X[S.ix[0]];
+    io.pc = mk->P[S.ip[0]];
+    io.xa = mk->X[S.ix[2]];
+    io.pa = mk->P[S.ip[2]];
+    io.wfold = S.fold ? (float)(1.0 / (double)S.k_in) : 0.0f;
+    io.xanc = mk->XA;
+    io.panc = mk->PA;
+    io.tc = mk->T[0];
+    io.ta = mk->T[1];
+    io.rowscale = mk->rowmax;
+    io.ccur = mk->C[S.ic[1]];
+    io.cavg_out = mk->C[S.ic[2]];
+    io.pa_out = mk->P[S.ip[2]];
+    rc = enqueue_eval(mk, io);
+    if (rc != PDHCG_OK) return rc;
+    rc = pull_state(mk);
+    if (rc != PDHCG_OK) return rc;
+    if (dist) dist[r + 1] = p_ref ? std::sqrt(S.dpa2[1]) : 0.0;
+    klast = kkt_max(S.kkt[1]);
+    std::memcpy(kparts, S.kkt[1], sizeof(kparts));
+    if (kkt) kkt[r + 1] = klast;
+    if (!std::isfinite(klast)) return fail(PDHCG_ERR_NUMERIC, "non-finite KKT error");
+    // restart to the average (Alg. 2); no extrapolation after a restart
+    std::swap(S.ix[0], S.ix[2]);
+    std::swap(S.ip[0], S.ip[2]);
+    std::swap(S.ic[1], S.ic[2]);
+    HIPC(launch_copy_f64(mk->C[S.ic[1]], mk->C[S.ic[0]], m, st));
+    S.fold = 0;
+    S.k_in = 0;
+    S.since = 0;
+    rc = push_state(mk);
+    if (rc != PDHCG_OK) return rc;
+  }
+  HIPC(hipMemcpyAsync(x, mk->X[S.ix[0]], (size_t)nnz * 4, hipMemcpyDeviceToDevice, st));
+  HIPC(launch_gather_f64_to_f32(mk->P[S.ip[0]], mk->inv, p, m, st));
+  HIPC(hipStreamSynchronize(st));
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->rel_kkt = klast;
+    info->rel_primal = kparts[0];
+    info->rel_dual = kparts[1];
+    info->rel_gap = kparts[2];
+    info->eta = eta;
+    info->omega = 1.0;
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    info->iters = S.total;
+    info->accepted = S.accepted;
+    info->restarts = restarts;
+    info->status = PDHCG_OK;
+    info->search_rounds_max = (int32_t)S.rounds_max;
+    info->search_rounds_mean =
+        S.rows_searched ? (double)S.rounds_sum / (double)S.rows_searched : 0.0;
+  }
+  return PDHCG_OK;
+}
+
+namespace {
+
+// PDHG needs every good's price and column partial in LDS, 2-byte good ids
+// and register-resident rows (at most 512 entries).
+int32_t check_pdhg(pdhcg_market mk) {
+  if (mk->lds_row != 3 || !mk->col16 || !mk->lds_eval || mk->hot != mk->m)
+    return fail(PDHCG_ERR_UNSUPPORTED, "restarted PDHG is built for markets whose goods all fit in "
+                                       "LDS (m <= 10000 on gfx950)");
+  for (const Bin &b : mk->bins)
+    if (b.G == 0)
+      return fail(PDHCG_ERR_UNSUPPORTED, "restarted PDHG is built for rows of at most 512 entries");
+  return PDHCG_OK;
+}
+
+int32_t pdhg_buffers(pdhcg_market mk) {
+  if (mk->pdhg_buf) return PDHCG_OK;
+  const size_t n = (size_t)mk->n;
+  HIPC(dalloc(&mk->pdhg_buf, 11 * n));
+  double *b = mk->pdhg_buf;
+  PdhgDev &d = mk->pdhg;
+  d.T0 = b; d.T1 = b + n; d.T2 = b + 2 * n;
+  d.Y0 = b + 3 * n; d.Y1 = b + 4 * n; d.Y2 = b + 5 * n;
+  d.G0 = b + 6 * n; d.G1 = b + 7 * n; d.G2 = b + 8 * n;
+  d.TA = b + 9 * n; d.YA = b + 10 * n;
+  return PDHCG_OK;
+}
+
+double *pick_d(double *a, double *b, double *c, int i) { return i == 0 ? a : (i == 1 ? b : c); }
+
+// KKT pass of PDHG over the current point and, when has_avg, the average
+// (with the lagged fold of the kept iterate).
+int32_t enqueue_pdhg_eval(pdhcg_market mk, const DevState &S, bool has_avg, float wfold,
+                          bool want_cc) {
+  const MarketDev md = mk->dev();
+  const PdhgDev &pd = mk->pdhg;
+  EvalIO io;
+  std::memset(&io, 0, sizeof(io));
+  io.xc = mk->X[S.ix[0]];
+  io.pc = mk->P[S.ip[0]];
+  io.xa = has_avg ? mk->X[S.ix[2]] : nullptr;
+  io.pa = mk->P[S.ip[2]];
+  io.wfold = wfold;
+  io.xanc = mk->XA;
+  io.panc = mk->PA;
+  io.tc = mk->T[0];
+  io.ta = mk->T[1];
+  io.rowscale = mk->rowmax;
+  io.want_cc = want_cc ? 1 : 0;
+  io.ccur = mk->C[S.ic[1]];
+  io.cavg_out = want_cc ? mk->C[S.ic[1]] : mk->C[S.ic[2]];
+  io.pa_out = has_avg ? mk->P[S.ip[2]] : nullptr;
+  io.evalpart = mk->evalpart;
+  io.evalcs = mk->evalcs;
+  io.evalchunk = mk->evalchunk;
+  io.cacc = mk->cacc;
+  io.gmax = mk->gmax;
+  io.gsum = mk->gsum;
+  const double *tc = pick_d(pd.T0, pd.T1, pd.T2, S.ix[0]);
+  const double *yc = pick_d(pd.Y0, pd.Y1, pd.Y2, S.ip[0]);
+  double *ta = pick_d(pd.T0, pd.T1, pd.T2, S.ix[2]);
+  double *ya = pick_d(pd.Y0, pd.Y1, pd.Y2, S.ip[2]);
+  double *gavg = has_avg ? pick_d(pd.G0, pd.G1, pd.G2, S.ic[2]) : nullptr;
+  for (const Bin &b : mk->bins)
+    HIPC(launch_pdhg_eval(md, pd, mk->bindev(b), b.G, b.E, io, tc, yc, ta, ya, gavg, b.nwg,
+                          mk->total_wg, mk->stream));
+  HIPC(launch_eval_chunks(md, io, mk->total_wg, mk->stream));
+  HIPC(launch_eval_col_stats(md, io, mk->total_wg, 1, mk->stream));
+  HIPC(launch_pdhg_eval_final(md, mk->total_wg, mk->stream));
+  return PDHCG_OK;
+}
+
+}  // namespace
+
+extern "C" int32_t pdhcg_pdhg_solve(pdhcg_market mk, const pdhcg_params *params, int32_t warm,
+                                    float *p, float *x, float *t, float *y, pdhcg_info *info) {
+  if (!mk || !p || !x) return fail(PDHCG_ERR_ARG, "null argument");
+  pdhcg_params dflt;
+  pdhcg_default_params(&dflt);
+  const pdhcg_params *prm = params ? params : &dflt;
+  int32_t rc = check_params(prm);
+  if (rc == PDHCG_OK) rc = check_pdhg(mk);
+  if (rc == PDHCG_OK) rc = pdhg_buffers(mk);
+  if (rc != PDHCG_OK) return rc;
+  hipStream_t st = mk->stream;
+  const auto t0 = std::chrono::steady_clock::now();
+  const int n = mk->n, m = mk->m;
+  const int64_t nnz = mk->nnz;
+  const MarketDev md = mk->dev();
+  const PdhgDev &pd = mk->pdhg;
+
+  // Initial point (readings shared with the oracle): x0_ij = 1/deg_j,
+  // p0_j = sum(w)/m, t0 = U x0, y0 = w / t0; a warm start takes p, x and,
+  // when given, t and y (caller's units).  g_prev = g = t - U x.
+  if (warm) {
+    HIPC(hipMemcpyAsync(mk->X[0], x, (size_t)nnz * 4, hipMemcpyDeviceToDevice, st));
+    HIPC(launch_gather_f32_to_f64(p, mk->perm, mk->P[0], m, st));
+  } else {
+    HIPC(launch_init_point(mk->col, mk->deg, nnz, mk->X[0], mk->P[0], m, mk->sumw / (double)m, st));
+  }
+  HIPC(launch_pdhg_rows_init(md, mk->X[0], warm ? t : nullptr, warm ? y : nullptr, mk->rowmax,
+                             pd.T0, pd.Y0, pd.G0, pd.G1, st));
+  DevState &S = *mk->hS;
+  std::memset(&S, 0, sizeof(S));
+  S.ix[0] = 0; S.ix[1] = 1; S.ix[2] = 2;
+  S.ip[0] = 0; S.ip[1] = 1; S.ip[2] = 2;
+  S.ic[0] = 0; S.ic[1] = 1; S.ic[2] = 2;
+  rc = push_state(mk);
+  if (rc != PDHCG_OK) return rc;
+  // column sums and KKT error of the starting point
+  rc = enqueue_pdhg_eval(mk, S, false, 0.0f, true);
+  if (rc != PDHCG_OK) return rc;
+  rc = pull_state(mk);
+  if (rc != PDHCG_OK) return rc;
+  double kkt0 = kkt_max(S.kkt[0]);
+  HIPC(launch_copy_f64(mk->C[1], mk->C[0], m, st));
+  HIPC(launch_copy_f32(mk->X[0], mk->XA, nnz, st));
+  HIPC(launch_copy_f64(mk->P[0], mk->PA, m, st));
+  HIPC(launch_copy_f64(pd.T0, pd.TA, n, st));
+  HIPC(launch_copy_f64(pd.Y0, pd.YA, n, st));
+
+  // Steps (Sec. 5): tau = eta/omega, sigma = eta*omega.  Fixed mode:
+  // eta = 0.9 / B, B = sqrt(max col degree) + 1 + sqrt(max col degree * max
+  // row degree) >= ||K|| for K = [1^T 0; -U I] with |u_ij| <= 1.
+  const double kbound = std::sqrt((double)mk->maxdeg_col) + 1.0 +
+                        std::sqrt((double)mk->maxdeg_col * (double)mk->maxdeg_row);
+  const bool adaptive = prm->step_mode == PDHCG_STEP_ADAPTIVE;
+  const double eta0 = prm->eta0 > 0.0 ? prm->eta0 : (adaptive ? 1.0 : 0.9 / kbound);
+  const double omega0 = prm->omega0 > 0.0 ? prm->omega0 : 0.05 * mk->sumw / (double)m;
+  double omega = omega0;
+  std::memset(&S, 0, sizeof(S));
+  S.ix[0] = 0; S.ix[1] = 1; S.ix[2] = 2;
+  S.ip[0] = 0; S.ip[1] = 1; S.ip[2] = 2;
+  S.ic[0] = 0; S.ic[1] = 1; S.ic[2] = 2;
+  S.step_mode = adaptive ? 1 : 0;
+  S.eta = eta0;
+  S.eta0 = eta0;
+  S.eta_lo = 0.01 * eta0;
+  S.eta_hi = adaptive ? 3.0 * eta0 : eta0;
+  S.omega = omega;
+  S.tau = eta0 / omega;
+  S.sigma = eta0 * omega;
+  rc = push_state(mk);
+  if (rc != PDHCG_OK) return rc;
+
+  EventPool pool;
+  if (prm->timing) {
+    pool.ev.resize(2 * (size_t)prm->eval_every, nullptr);
+    for (auto &e : pool.ev) HIPC(hipEventCreate(&e));
+  }
+  double row_seconds = 0.0;
+  int64_t row_launches = 0;
+  double kkt_prev = INFINITY, kbest = INFINITY, kout[3] = {NAN, NAN, NAN};
+  int32_t restarts = 0, evals = 0, status = PDHCG_MAX_ITER;
+  bool cand_avg = false;
+  int64_t total = 0;
+  while (true) {
+    const int64_t left = prm->max_iter - total;
+    const int64_t nstep = std::min<int64_t>(prm->eval_every - (total % prm->eval_every), left);
+    for (int64_t q = 0; q < nstep; ++q) {
+      HIPC(launch_pstep(md, 0, st));
+      if (prm->timing) HIPC(hipEventRecord(pool.ev[2 * (size_t)q], st));
+      for (const Bin &b : mk->bins)
+        HIPC(launch_pdhg_row(md, pd, mk->bindev(b), b.G, b.E, b.nwg, st));
+      if (prm->timing) HIPC(hipEventRecord(pool.ev[2 * (size_t)q + 1], st));
+      HIPC(launch_col_decide_pdhg(md, mk->total_wg, st));
+    }
+    rc = pull_state(mk);
+    if (rc != PDHCG_OK) return rc;
+    if (prm->timing) {
+      for (int64_t q = 0; q < nstep; ++q) {
+        float ms = 0.0f;
+        HIPC(hipEventElapsedTime(&ms, pool.ev[2 * (size_t)q], pool.ev[2 * (size_t)q + 1]));
+        row_seconds += 1e-3 * (double)ms;
+        ++row_launches;
+      }
+    }
+    if (S.total != total + nstep)
+      return fail(PDHCG_ERR_HIP, "device iteration counter did not advance as expected");
+    total = S.total;
+    const bool has_avg = S.k_in > 0;
+    const float wfold = (has_avg && S.fold) ? (float)(1.0 / (double)S.k_in) : 0.0f;
+    rc = enqueue_pdhg_eval(mk, S, has_avg, wfold, false);
+    if (rc != PDHCG_OK) return rc;
+    rc = pull_state(mk);
+    if (rc != PDHCG_OK) return rc;
+    S.fold = 0;
+    ++evals;
+    const double kc = kkt_max(S.kkt[0]);
+    const double ka = has_avg ? kkt_max(S.kkt[1]) : INFINITY;
+    if (!std::isfinite(kc) && !std::isfinite(ka)) {
+      status = PDHCG_ERR_NUMERIC;
+      fail(status, "non-finite KKT error at iteration " + std::to_string(total));
+      break;
+    }
+    cand_avg = ka < kc;
+    const double kcand = cand_avg ? ka : kc;
+    std::memcpy(kout, cand_avg ? S.kkt[1] : S.kkt[0], sizeof(kout));
+    kbest = kcand;
+    if (prm->verbose)
+      std::fprintf(stderr, "[pdhg] it=%lld cur=%.3e avg=%.3e eta=%.3e omega=%.3e\n",
+                   (long long)total, kc, ka, S.eta, omega);
+    if (kcand <= prm->tol) {
+      status = PDHCG_OK;
+      break;
+    }
+    if (total >= prm->max_iter) {
+      status = PDHCG_MAX_ITER;
+      break;
+    }
+    if (prm->restart == PDHCG_RESTART_ADAPTIVE) {
+      const bool do_restart =
+          (kcand <= prm->beta_sufficient * kkt0) ||
+          (kcand <= prm->beta_necessary * kkt0 && kcand > kkt_prev) ||
+          ((double)S.since >= prm->beta_artificial * (double)S.total);
+      if (do_restart) {
+        if (cand_avg) {
+          std::swap(S.ix[0], S.ix[2]);
+          std::swap(S.ip[0], S.ip[2]);
+          std::swap(S.ic[1], S.ic[2]);  // column sums and g of the average are in the trial slot
+        }
+        HIPC(launch_copy_f64(mk->C[S.ic[1]], mk->C[S.ic[0]], m, st));
+        HIPC(launch_copy_f64(pick_d(pd.G0, pd.G1, pd.G2, S.ic[1]),
+                             pick_d(pd.G0, pd.G1, pd.G2, S.ic[0]), n, st));
+        HIPC(launch_copy_f32(mk->X[S.ix[0]], mk->XA, nnz, st));
+        HIPC(launch_copy_f64(mk->P[S.ip[0]], mk->PA, m, st));
+        HIPC(launch_copy_f64(pick_d(pd.T0, pd.T1, pd.T2, S.ix[0]), pd.TA, n, st));
+        HIPC(launch_copy_f64(pick_d(pd.Y0, pd.Y1, pd.Y2, S.ip[0]), pd.YA, n, st));
+        const double dx = std::sqrt(S.dxa2[cand_avg ? 1 : 0]);
+        const double dp = std::sqrt(S.dpa2[cand_avg ? 1 : 0]);
+        if (dx > 1e-10 && dp > 1e-10)
+          omega = std::exp(prm->theta * std::log(dp / dx) + (1.0 - prm->theta) * std::log(omega));
+        ++restarts;
+        if (prm->omega_check_every > 0 && restarts % prm->omega_check_every == 0 &&
+            (omega < omega0 / prm->omega_bound || omega > omega0 * prm->omega_bound))
+          omega = omega0;
+        kkt0 = kcand;
+        kkt_prev = INFINITY;
+        S.k_in = 0;
+        S.since = 0;
+        cand_avg = false;
+      } else {
+        kkt_prev = kcand;
+      }
+    }
+    S.omega = omega;
+    S.tau = S.eta / omega;
+    S.sigma = S.eta * omega;
+    rc = push_state(mk);
+    if (rc != PDHCG_OK) return rc;
+  }
+
+  bool out_avg = false;
+  if (prm->output == PDHCG_OUTPUT_CANDIDATE) out_avg = cand_avg;
+  if (prm->output == PDHCG_OUTPUT_AVERAGE) out_avg = S.k_in > 0;
+  const float *xs = mk->X[out_avg ? S.ix[2] : S.ix[0]];
+  const double *ps = mk->P[out_avg ? S.ip[2] : S.ip[0]];
+  HIPC(hipMemcpyAsync(x, xs, (size_t)nnz * 4, hipMemcpyDeviceToDevice, st));
+  HIPC(launch_gather_f64_to_f32(ps, mk->inv, p, m, st));
+  if (t || y)
+    HIPC(launch_pdhg_rows_out(pick_d(pd.T0, pd.T1, pd.T2, out_avg ? S.ix[2] : S.ix[0]),
+                              pick_d(pd.Y0, pd.Y1, pd.Y2, out_avg ? S.ip[2] : S.ip[0]),
+                              mk->rowmax, t, y, n, st));
+  if (prm->output != PDHCG_OUTPUT_CANDIDATE) {
+    const int z = out_avg ? 1 : 0;
+    std::memcpy(kout, S.kkt[z], sizeof(kout));
+    kbest = kkt_max(S.kkt[z]);
+  }
+  HIPC(hipStreamSynchronize(st));
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->rel_kkt = kbest;
+    info->rel_primal = kout[0];
+    info->rel_dual = kout[1];
+    info->rel_gap = kout[2];
+    info->eta = S.eta;
+    info->omega = omega;
+    info->seconds = secs;
+    info->iters = S.total;
+    info->accepted = S.accepted;
+    info->restarts = restarts;
+    info->status = status;
+    info->evals = evals;
+    info->row_pass_seconds = row_seconds;
+    info->row_pass_launches = row_launches;
+  }
+  return status;
+}
+
 extern "C" int32_t pdhcg_arrow_debreu(pdhcg_market mk, const int32_t *e_row_ptr,
                                       const int32_t *e_col, const float *e_val, int64_t e_nnz,
                                       const pdhcg_params *inner, double outer_tol,
@@ -1132,15 +1579,10 @@ int32_t finish_colsum(pdhcg_market mk, double *chunk, double *atomic_sum, double
   return PDHCG_OK;
 }
 
-}  // namespace
-
-extern "C" int32_t pdhcg_backward(pdhcg_market mk, const float *x, const float *p, double omega,
-                                  int32_t unroll, int32_t ckpt_every, const float *dL_dp,
-                                  float *dL_du, float *dL_dw) {
-  if (!mk || !x || !p || !dL_dp || !dL_du || !dL_dw) return fail(PDHCG_ERR_ARG, "null argument");
-  if (!(omega > 0.0) || !std::isfinite(omega))
-    return fail(PDHCG_ERR_ARG, "omega must be finite and > 0");
-  if (unroll < 1 || ckpt_every < 1) return fail(PDHCG_ERR_ARG, "unroll and ckpt_every must be >= 1");
+template <typename Buffers>
+int32_t backward_impl(pdhcg_market mk, const float *x, const float *p, double omega,
+                      int32_t unroll, int32_t ckpt_every, const float *dL_dp, float *dL_du,
+                      float *dL_dw, Buffers &buf) {
   const int n = mk->n, m = mk->m;
   const int64_t nnz = mk->nnz;
   const hipStream_t st = mk->stream;
@@ -1151,7 +1593,6 @@ extern "C" int32_t pdhcg_backward(pdhcg_market mk, const float *x, const float *
   const double eta = 0.9 / std::sqrt((double)std::max(1, mk->maxdeg_col));
   const double tau = eta / omega, sigma = eta * omega;
 
-  AdjBuffers buf;
   float *ck_x = nullptr, *seg_x = nullptr, *xa = nullptr, *xb = nullptr;
   float *R0 = nullptr, *R1 = nullptr, *duh = nullptr, *dw = nullptr;
   double *ck_p = nullptr, *ck_c = nullptr, *ck_cp = nullptr, *pw = nullptr, *c = nullptr;
@@ -1267,6 +1708,30 @@ extern "C" int32_t pdhcg_backward(pdhcg_market mk, const float *x, const float *
   }
   HIPC(launch_adj_unnormalize(mk->row_ptr, mk->uh, mk->rowmax, duh, n, dL_du, st));
   HIPC(hipMemcpyAsync(dL_dw, dw, (size_t)n * sizeof(float), hipMemcpyDeviceToDevice, st));
-  HIPC(hipStreamSynchronize(st));  // the buffers above are freed on return
+  HIPC(hipStreamSynchronize(st));  // the buffers above are freed or reused after return
   return PDHCG_OK;
 }
+
+int32_t check_backward_args(pdhcg_market mk, const float *x, const float *p, double omega,
+                            int32_t unroll, int32_t ckpt_every, const float *dL_dp,
+                            const float *dL_du, const float *dL_dw) {
+  if (!mk || !x || !p || !dL_dp || !dL_du || !dL_dw) return fail(PDHCG_ERR_ARG, "null argument");
+  if (!(omega > 0.0) || !std::isfinite(omega))
+    return fail(PDHCG_ERR_ARG, "omega must be finite and > 0");
+  if (unroll < 1 || ckpt_every < 1) return fail(PDHCG_ERR_ARG, "unroll and ckpt_every must be >= 1");
+  return PDHCG_OK;
+}
+
+
+}  // namespace
+
+extern "C" int32_t pdhcg_backward(pdhcg_market mk, const float *x, const float *p, double omega,
+                                  int32_t unroll, int32_t ckpt_every, const float *dL_dp,
+                                  float *dL_du, float *dL_dw) {
+  int32_t rc = check_backward_args(mk, x, p, omega, unroll, ckpt_every, dL_dp, dL_du, dL_dw);
+  if (rc != PDHCG_OK) return rc;
+  AdjBuffers buf;
+  return backward_impl(mk, x, p, omega, unroll, ckpt_every, dL_dp, dL_du, dL_dw, buf);
+}
+
+

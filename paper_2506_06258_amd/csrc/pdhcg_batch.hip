@@ -736,6 +736,280 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(BatchDev bd, const 
   }
 }
 
+// ------------------------------------------------------------ reverse mode --
+
+// Arguments of the batched reverse mode.  Workspace per call: checkpoints
+// of x every L steps (nck slices of the concatenated edge arrays), one
+// segment of recomputed allocations (L slices), two adjoint slices R, and
+// float64 checkpoints of p, c, c_prev (3 nck slices of the goods).
+struct BatchAdjArgs {
+  const float *x_in, *p_in, *dL_dp;
+  float *dL_du, *dL_dw;
+  const double *omega;
+  float *ck_x, *seg_x, *R0, *R1;
+  double *ck_pcc;
+  int64_t nnz_total, m_total;
+  int32_t K, L, nck, max_rounds;
+  double rtol;
+};
+
+// Reverse of the row prox of one step for every row of a market (the
+// single-market k_adj_row): with g = r_in + B[col] on the active set A of
+// x^{k+1} (its positive entries), s = u^T x^{k+1}, Q = sum_A u^2,
+// Gu = sum_A u g: h = (tau w / s^2) Gu / (1 + (tau w / s^2) Q),
+// r = g - h u on A (0 elsewhere), dL/du += r tau w / s - h x^{k+1} on A,
+// dL/dw += (tau / s) sum r u; column sums of r into lc.  Rows of any
+// length: G lanes per row, two sweeps (sums, then outputs).
+template <int G>
+__device__ __attribute__((noinline)) void wg_adj_rows(const MView &v, const float *xn,
+                                                       const float *r_in, const double *lB,
+                                                       float *r_out, float *duh, float *dw,
+                                                       double *lc, double tau) {
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int r = lane & (G - 1), seg = lane / G;
+  constexpr int kSeg = kWave / G;
+  for (int base = wave * kSeg; base < v.n; base += kBatchWaves * kSeg) {
+    const int i = base + seg;
+    const bool rv = i < v.n;
+    const int beg = rv ? v.rp[i] : 0, end = rv ? v.rp[i + 1] : 0;
+    const double tw = rv ? tau * (double)v.w[i] : 0.0;
+    double s = 0.0, Q = 0.0, Gu = 0.0;
+    for (int k = beg + r; k < end; k += G) {
+      const float x = xn[k];
+      if (x > 0.0f) {
+        const double u = (double)v.uh[k];
+        s = fma(u, (double)x, s);
+        Q = fma(u, u, Q);
+        Gu = fma(u, (double)r_in[k] + lB[v.col[k]], Gu);
+      }
+    }
+    s = seg_sum_d<G>(s);
+    Q = seg_sum_d<G>(Q);
+    Gu = seg_sum_d<G>(Gu);
+    const bool live = rv && s > 0.0;
+    const double is = live ? fast_rcp(s) : 0.0;
+    const double tws2 = tw * is * is;
+    const double hh = live ? tws2 * Gu / (1.0 + tws2 * Q) : 0.0;
+    double ru = 0.0;
+    for (int k = beg + r; k < end; k += G) {
+      const float x = xn[k];
+      const int c = v.col[k];
+      const double u = (double)v.uh[k];
+      const bool act = live && x > 0.0f;
+      const double rr = act ? (double)r_in[k] + lB[c] - hh * u : 0.0;
+      r_out[k] = (float)rr;
+      if (act) duh[k] += (float)(rr * tw * is - hh * (double)x);
+      ru = fma(rr, u, ru);
+      atomicAdd(&lc[c], rr);
+    }
+    ru = seg_sum_d<G>(ru);
+    if (live && r == 0) dw[i] += (float)(tau * is * ru);
+  }
+}
+
+// Reverse mode for every market of the batch in one persistent launch:
+// each workgroup takes markets from the queue (largest first) and runs the
+// whole reverse pass of a market (as pdhcg_backward): K fixed steps
+// (eta = 0.9 / ||K||, tau = eta / omega_b, sigma = eta omega_b) forward
+// from (x, p) with a checkpoint every L steps, then segment by segment
+// backwards: the segment's forward steps recomputed from its checkpoint,
+// then the reverse of each step (row prox, price step).  Prices, column
+// sums and the price-step adjoint live in LDS (m <= 2048).  dL/du and
+// dL/dw accumulate in the caller's outputs, which are finished in place
+// through the row normalisation.
+__global__ __launch_bounds__(kBatchBlock) void k_batch_backward(BatchDev bd, BatchAdjArgs a) {
+  extern __shared__ double lds_b[];
+  double *lp = lds_b;                        // p
+  double *lc = lp + kBatchMaxGoods;          // column partials
+  double *lcc = lc + kBatchMaxGoods;         // c (column sums of the current x)
+  double *lcp = lcc + kBatchMaxGoods;        // c_prev
+  double *lP = lcp + kBatchMaxGoods;         // adjoint of p
+  double *lB = lP + kBatchMaxGoods;          // adjoint of x through the next price step
+  double *lCn = lB + kBatchMaxGoods;         // carried part of it
+  __shared__ double red[kBatchWaves];
+  __shared__ int s_market;
+  __shared__ double s_eta;
+  while (true) {
+    if (threadIdx.x == 0) {
+      const uint32_t t = atomicAdd(bd.queue, 1u);
+      s_market = (t < (uint32_t)bd.count) ? bd.order[t] : -1;
+    }
+    __syncthreads();
+    const int b = uni(s_market);
+    if (b < 0) return;
+    MView v;
+    v.n = bd.n[b];
+    v.m = bd.m[b];
+    const int64_t ro = bd.row_off[b], go = bd.good_off[b], eo = bd.edge_off[b];
+    v.rp = bd.row_ptr + bd.rp_off[b];
+    v.col = bd.col + eo;
+    v.deg = bd.deg + go;
+    v.uh = bd.uh + eo;
+    v.w = bd.w + ro;
+    v.rowmax = bd.rowmax + ro;
+    const int shape = uni(bd.shape[b]);
+    const int nnz = v.rp[v.n];
+    const int m = v.m;
+    if (threadIdx.x == 0) {
+      double kmax = 0.0;
+      for (int j = 0; j < m; ++j) kmax = fmax(kmax, (double)v.deg[j]);
+      s_eta = 0.9 / sqrt(kmax);
+    }
+    __syncthreads();
+    const double eta = uni(s_eta);
+    const double om = a.omega[b];
+    const double tau = eta / om, sigma = eta * om;
+    const float *x0 = a.x_in + eo;
+    float *R0 = a.R0 + eo, *R1 = a.R1 + eo;
+    float *duh = a.dL_du + eo, *dw = a.dL_dw + ro;
+    auto ckx = [&](int q) { return a.ck_x + (size_t)q * a.nnz_total + eo; };
+    auto segx = [&](int q) { return a.seg_x + (size_t)q * a.nnz_total + eo; };
+    auto ckp = [&](int q, int which) {
+      return a.ck_pcc + ((size_t)q * 3 + which) * a.m_total + go;
+    };
+
+    // One forward step from xin: p += sigma (2 c - c_prev - 1), c_prev = c;
+    // x_out = prox(xin - tau p); c = colsum(x_out).
+    auto forward = [&](const float *xin, float *xout) {
+      for (int j = threadIdx.x; j < m; j += blockDim.x) {
+        lp[j] = lp[j] + sigma * (2.0 * lcc[j] - lcp[j] - 1.0);
+        lcp[j] = lcc[j];
+        lc[j] = 0.0;
+      }
+      __syncthreads();
+      double dx2 = 0.0;
+      switch (shape) {
+        case 0: dx2 = wg_rows_step<8, 4>(v, lp, lc, xin, xout, nullptr, tau, 0.0f, a.max_rounds, a.rtol); break;
+        case 1: dx2 = wg_rows_step<16, 4>(v, lp, lc, xin, xout, nullptr, tau, 0.0f, a.max_rounds, a.rtol); break;
+        case 2: dx2 = wg_rows_step<32, 4>(v, lp, lc, xin, xout, nullptr, tau, 0.0f, a.max_rounds, a.rtol); break;
+        case 3: dx2 = wg_rows_step<64, 4>(v, lp, lc, xin, xout, nullptr, tau, 0.0f, a.max_rounds, a.rtol); break;
+        case 4: dx2 = wg_rows_step<64, 8>(v, lp, lc, xin, xout, nullptr, tau, 0.0f, a.max_rounds, a.rtol); break;
+        default: dx2 = wg_rows_step<64, 16>(v, lp, lc, xin, xout, nullptr, tau, 0.0f, a.max_rounds, a.rtol); break;
+      }
+      (void)dx2;
+      __syncthreads();
+      for (int j = threadIdx.x; j < m; j += blockDim.x) lcc[j] = lc[j];
+      __syncthreads();
+    };
+
+    // start point: p, c = colsum(x), c_prev = c
+    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+      lp[j] = (double)a.p_in[go + j];
+      lc[j] = 0.0;
+    }
+    __syncthreads();
+    switch (shape) {
+      case 0: wg_colsum_x<8>(v, x0, lc); break;
+      case 1: wg_colsum_x<16>(v, x0, lc); break;
+      case 2: wg_colsum_x<32>(v, x0, lc); break;
+      default: wg_colsum_x<64>(v, x0, lc); break;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+      lcc[j] = lc[j];
+      lcp[j] = lc[j];
+    }
+    __syncthreads();
+    // forward sweep, one checkpoint every L steps (x ping-pongs between R0
+    // and R1, which the reverse sweep takes over afterwards)
+    const float *xc = x0;
+    for (int j = 0; j < a.K; ++j) {
+      if (j % a.L == 0) {
+        const int q = j / a.L;
+        float *dst = ckx(q);
+        for (int k = threadIdx.x; k < nnz; k += blockDim.x) dst[k] = xc[k];
+        double *cp0 = ckp(q, 0), *cp1 = ckp(q, 1), *cp2 = ckp(q, 2);
+        for (int jj = threadIdx.x; jj < m; jj += blockDim.x) {
+          cp0[jj] = lp[jj];
+          cp1[jj] = lcc[jj];
+          cp2[jj] = lcp[jj];
+        }
+        __syncthreads();
+      }
+      float *xo = (j % 2 == 0) ? R0 : R1;
+      forward(xc, xo);
+      xc = xo;
+    }
+    // reverse sweep
+    for (int k = threadIdx.x; k < nnz; k += blockDim.x) {
+      R0[k] = 0.0f;
+      duh[k] = 0.0f;
+    }
+    for (int i = threadIdx.x; i < v.n; i += blockDim.x) dw[i] = 0.0f;
+    for (int j = threadIdx.x; j < m; j += blockDim.x) {
+      lP[j] = (double)a.dL_dp[go + j];
+      lB[j] = 0.0;
+      lCn[j] = 0.0;
+    }
+    __syncthreads();
+    float *rin = R0, *rout = R1;
+    for (int q = a.nck - 1; q >= 0; --q) {
+      const int j0 = q * a.L, j1 = min(a.K, j0 + a.L);
+      {
+        const double *cp0 = ckp(q, 0), *cp1 = ckp(q, 1), *cp2 = ckp(q, 2);
+        for (int jj = threadIdx.x; jj < m; jj += blockDim.x) {
+          lp[jj] = cp0[jj];
+          lcc[jj] = cp1[jj];
+          lcp[jj] = cp2[jj];
+        }
+        __syncthreads();
+      }
+      const float *xin = ckx(q);
+      for (int j = j0; j < j1; ++j) {
+        float *xo = segx(j - j0);  // x^{j+1}
+        forward(xin, xo);
+        xin = xo;
+      }
+      for (int j = j1 - 1; j >= j0; --j) {
+        for (int jj = threadIdx.x; jj < m; jj += blockDim.x) lc[jj] = 0.0;
+        __syncthreads();
+        switch (shape) {
+          case 0: wg_adj_rows<8>(v, segx(j - j0), rin, lB, rout, duh, dw, lc, tau); break;
+          case 1: wg_adj_rows<16>(v, segx(j - j0), rin, lB, rout, duh, dw, lc, tau); break;
+          case 2: wg_adj_rows<32>(v, segx(j - j0), rin, lB, rout, duh, dw, lc, tau); break;
+          default: wg_adj_rows<64>(v, segx(j - j0), rin, lB, rout, duh, dw, lc, tau); break;
+        }
+        __syncthreads();
+        // reverse of the price step: Pt = P - tau colsum(r), B = 2 sigma Pt
+        // + Cn, Cn = -sigma Pt, P = Pt
+        for (int jj = threadIdx.x; jj < m; jj += blockDim.x) {
+          const double pt = lP[jj] - tau * lc[jj];
+          lB[jj] = 2.0 * sigma * pt + lCn[jj];
+          lCn[jj] = -sigma * pt;
+          lP[jj] = pt;
+        }
+        __syncthreads();
+        float *t = rin;
+        rin = rout;
+        rout = t;
+      }
+    }
+    // through the row normalisation u_hat = u / max_j u_ij: dL/du_ij =
+    // dL/du_hat_ij / r_i - [j = first maximum] sum_k u_hat_ik dL/du_hat_ik / r_i
+    {
+      const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+      for (int i = wave; i < v.n; i += kBatchWaves) {
+        const int beg = v.rp[i], end = v.rp[i + 1];
+        double gs = 0.0;
+        int first = end;
+        for (int k = beg + lane; k < end; k += kWave) {
+          gs = fma((double)v.uh[k], (double)duh[k], gs);
+          if (v.uh[k] == 1.0f) first = min(first, k);
+        }
+        gs = wave_sum_d(gs);
+        for (int o = 32; o >= 1; o >>= 1) first = min(first, __shfl_xor(first, o));
+        const double inv = 1.0 / (double)v.rowmax[i];
+        for (int k = beg + lane; k < end; k += kWave) {
+          double val = (double)duh[k] * inv;
+          if (k == first) val -= gs * inv;
+          duh[k] = (float)val;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 }  // namespace pdhcg
 
 // ---------------------------------------------------------------- host API --
@@ -1220,19 +1494,58 @@ extern "C" int32_t pdhcg_batch_backward(pdhcg_batch bt, const float *x_cat, cons
   for (int b = 0; b < bt->count; ++b)
     if (!(omega[b] > 0.0) || !std::isfinite(omega[b]))
       return bfail(PDHCG_ERR_ARG, "omega of market " + std::to_string(b) + " must be finite and > 0");
-  // each market through the single-market reverse mode, on the batch's stream
-  for (int b = 0; b < bt->count; ++b) {
-    const int64_t ro = bt->h_row_off[b], go = bt->h_good_off[b], eo = bt->h_edge_off[b];
-    const int64_t nnz = bt->h_edge_off[b + 1] - eo;
-    pdhcg_market mk = nullptr;
-    int32_t rc = pdhcg_market_create(bt->h_n[b], bt->h_m[b], nnz, bt->row_ptr + bt->h_rp_off[b],
-                                     bt->col + eo, bt->u + eo, bt->w + ro, bt->stream, &mk);
-    if (rc != PDHCG_OK) return rc;
-    rc = pdhcg_backward(mk, x_cat + eo, p_cat + go, omega[b], unroll, ckpt_every, dL_dp_cat + go,
-                        dL_du_cat + eo, dL_dw_cat + ro);
-    pdhcg_market_destroy(mk);
-    if (rc != PDHCG_OK) return rc;
-  }
+  const int K = unroll, L = std::min(ckpt_every, unroll);
+  const int nck = (K + L - 1) / L;
+  const int64_t E = bt->total_edges, G = bt->total_goods;
+  // workspace of this call, freed on every exit path
+  struct Owned {
+    std::vector<void *> p;
+    ~Owned() {
+      for (void *q : p)
+        if (q) (void)hipFree(q);
+    }
+  } own;
+  auto get = [&](auto **ptr, size_t count) -> hipError_t {
+    hipError_t e = balloc(ptr, count);
+    if (e == hipSuccess) own.p.push_back(*ptr);
+    return e;
+  };
+  BatchAdjArgs a = {};
+  a.x_in = x_cat;
+  a.p_in = p_cat;
+  a.dL_dp = dL_dp_cat;
+  a.dL_du = dL_du_cat;
+  a.dL_dw = dL_dw_cat;
+  double *d_omega = nullptr;
+  BHIPC(get(&d_omega, (size_t)bt->count));
+  BHIPC(get(&a.ck_x, (size_t)nck * E));
+  BHIPC(get(&a.seg_x, (size_t)L * E));
+  BHIPC(get(&a.R0, (size_t)E));
+  BHIPC(get(&a.R1, (size_t)E));
+  BHIPC(get(&a.ck_pcc, (size_t)3 * nck * G));
+  BHIPC(hipMemcpyAsync(d_omega, omega, (size_t)bt->count * sizeof(double), hipMemcpyHostToDevice,
+                       bt->stream));
+  a.omega = d_omega;
+  a.nnz_total = E;
+  a.m_total = G;
+  a.K = K;
+  a.L = L;
+  a.nck = nck;
+  a.max_rounds = 16;
+  a.rtol = 1e-10;
+  int dev = 0, cus = 256;
+  (void)hipGetDevice(&dev);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+    cus = prop.multiProcessorCount;
+  const size_t shm = (size_t)7 * kBatchMaxGoods * sizeof(double);
+  const int grid = (int)std::min<int64_t>(cus, bt->count);
+  BatchDev bd = batch_view(bt);
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, bt->stream, bt->queue);
+  BHIPC(hipGetLastError());
+  hipLaunchKernelGGL(k_batch_backward, dim3(grid), dim3(kBatchBlock), shm, bt->stream, bd, a);
+  BHIPC(hipGetLastError());
+  BHIPC(hipStreamSynchronize(bt->stream));  // the workspace is freed on return
   return PDHCG_OK;
 }
 

@@ -11,7 +11,9 @@ namespace pdhcg {
 constexpr int kWave = 64;        // CDNA wavefront
 constexpr int kRowBlock = 512;   // threads per row-kernel workgroup (8 waves)
 constexpr int kColBlock = 256;   // threads per column-kernel block
-constexpr int kMaxSections = 32; // largest k of the k-section search
+constexpr int kMaxSections = 32; // largest k of the k-section search with G lanes per row
+constexpr int kMaxWaveSections = 64;  // largest k with one lane per candidate (wave64)
+constexpr int kKwaveMaxRow = 512;     // longest row of the one-wave-per-row k-section kernel
 constexpr int kRowStats = 4;     // per-workgroup partials of the row kernel
 constexpr int kEvalRowStats = 12;
 constexpr int kColStats = 2;
@@ -79,6 +81,19 @@ struct MarketDev {
   DevState *S;
 };
 
+// Per-buyer state of restarted PDHG (Alg. 1) on the reformulated program:
+// utilities t and their duals y (normalised units, float64), and the
+// residuals g = t - U x of the utility constraint.  t and the primal anchor
+// follow the allocation's roles (DevState::ix), y the prices' (ip), g the
+// column sums' (ic: previous / current / trial).
+struct PdhgDev {
+  double *T0, *T1, *T2;
+  double *Y0, *Y1, *Y2;
+  double *G0, *G1, *G2;
+  double *TA, *YA;   // restart anchors of t and y
+};
+constexpr int kPdhgEvalStats = 20;  // per-workgroup statistics of the PDHG KKT pass
+
 // Row kernel shapes (G lanes per row, E entries per lane) that are built.
 #define PDHCG_ROW_VARIANTS(X) \
   X(4, 1) X(4, 2) X(4, 4) X(4, 8) \
@@ -109,7 +124,8 @@ struct RowIO {
   float wfold;      // fold weight 1/k (0: no fold)
   int32_t use_state;
   int32_t colsum;   // accumulate column sums of xout
-  int32_t search;   // 0 active-set, 1 k-section
+  int32_t search;   // 0 active-set, 1 k-section (G lanes per row), 2 k-section
+                    // (one wave per row, one lane per candidate)
   int32_t sections;
   int32_t max_rounds;
   double rtol;
@@ -204,6 +220,32 @@ hipError_t launch_eval_long(const MarketDev &md, const BinDev &bin, int lds_mode
                             const EvalIO &io, int nwg, int total_wg, hipStream_t st);
 hipError_t launch_adj_long(const MarketDev &md, const BinDev &bin, int lds, const AdjIO &io,
                            int nwg, hipStream_t st);
+// k-section search with one wave per row and one lane per candidate
+// (pdhcg_ksec.hip); rows of at most kKwaveMaxRow entries, column partials
+// of every good in LDS.
+size_t kwave_lds_bytes(int m);
+hipError_t launch_row_kwave(const MarketDev &md, const RowIO &io, int nwg, hipStream_t st);
+
+// Restarted PDHG (pdhcg_pdhg.hip); markets whose goods all sit in LDS
+// (LDS mode 3) and rows of at most 512 entries.
+hipError_t launch_pdhg_row(const MarketDev &md, const PdhgDev &pd, const BinDev &bin, int G, int E,
+                           int nwg, hipStream_t st);
+hipError_t launch_pdhg_eval(const MarketDev &md, const PdhgDev &pd, const BinDev &bin, int G,
+                            int E, const EvalIO &io, const double *tc, const double *yc,
+                            double *ta, double *ya, double *g_avg, int nwg, int total_wg,
+                            hipStream_t st);
+hipError_t launch_pdhg_eval_final(const MarketDev &md, int total_wg, hipStream_t st);
+hipError_t launch_pdhg_rows_init(const MarketDev &md, const float *x, const float *t_in,
+                                 const float *y_in, const float *rowmax, double *t, double *y,
+                                 double *g0, double *g1, hipStream_t st);
+hipError_t launch_pdhg_rows_out(const double *t, const double *y, const float *rowmax, float *t_out,
+                                float *y_out, int n, hipStream_t st);
+// KKT column statistics only (k_eval_col), without the PDHCG combination.
+hipError_t launch_eval_col_stats(const MarketDev &md, const EvalIO &io, int total_wg, int partials,
+                                 hipStream_t st);
+// Column kernels of a PDHG step: the step-size rule with the buyers' terms.
+hipError_t launch_col_decide_pdhg(const MarketDev &md, int total_wg, hipStream_t st);
+
 // Reverse mode (pdhcg_adjoint.hip).
 hipError_t launch_adj_pstep(double *p, const double *c, const double *cprev, double sigma, int m,
                             hipStream_t st);

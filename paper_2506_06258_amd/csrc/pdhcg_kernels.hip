@@ -478,7 +478,12 @@ __global__ __launch_bounds__(kColBlock) void k_col_decide(MarketDev md, int tota
 
 // Global sums and the step-size rule, in one block after k_col_decide (the
 // block statistics arrive through the kernel boundary).
-__global__ __launch_bounds__(kColBlock) void k_step_rule(MarketDev md, int total_wg, int tiles) {
+// With pdhg = 1 (restarted PDHG, Alg. 1) the workgroup partials also hold
+// |dy|^2 (slot 1) and dy^T (dt - U dx) (slot 2), and slot 0 includes |dt|^2:
+// the primal norm is over (x, t), the dual norm over (p, y), and the
+// interaction is (dp, dy)^T K (dx, dt) with K = [1^T 0; -U I].
+__global__ __launch_bounds__(kColBlock) void k_step_rule(MarketDev md, int total_wg, int tiles,
+                                                         int pdhg) {
   DevState *S = md.S;
   __shared__ double sh[2][kColBlock / kWave];
   __shared__ double shx[kColBlock / kWave];
@@ -488,7 +493,13 @@ __global__ __launch_bounds__(kColBlock) void k_step_rule(MarketDev md, int total
     a += md.colblk[(size_t)b * kColStats + 0];
     qq += md.colblk[(size_t)b * kColStats + 1];
   }
-  for (int b = threadIdx.x; b < total_wg; b += blockDim.x) x2 += md.rowpart[(size_t)b * kRowStats];
+  for (int b = threadIdx.x; b < total_wg; b += blockDim.x) {
+    x2 += md.rowpart[(size_t)b * kRowStats];
+    if (pdhg) {
+      qq += md.rowpart[(size_t)b * kRowStats + 1];
+      a += md.rowpart[(size_t)b * kRowStats + 2];
+    }
+  }
   a = wave_sum_d(a);
   qq = wave_sum_d(qq);
   x2 = wave_sum_d(x2);
@@ -1086,7 +1097,28 @@ hipError_t launch_col_decide(const MarketDev &md, int total_wg, int from_partial
                      md.hot > 0 ? chunks : 0);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_step_rule, dim3(1), dim3(kColBlock), 0, st, md, total_wg, tiles);
+  hipLaunchKernelGGL(k_step_rule, dim3(1), dim3(kColBlock), 0, st, md, total_wg, tiles, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_col_decide_pdhg(const MarketDev &md, int total_wg, hipStream_t st) {
+  const int tiles = (md.m + kColBlock - 1) / kColBlock;
+  const int chunks = total_wg < kColChunks ? total_wg : kColChunks;
+  hipLaunchKernelGGL(k_col_chunks, dim3((md.hot + kColBlock - 1) / kColBlock, chunks),
+                     dim3(kColBlock), 0, st, md, total_wg);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_col_decide, dim3(tiles), dim3(kColBlock), 0, st, md, total_wg, chunks);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_step_rule, dim3(1), dim3(kColBlock), 0, st, md, total_wg, tiles, 1);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_col_stats(const MarketDev &md, const EvalIO &io, int total_wg, int partials,
+                                 hipStream_t st) {
+  const int tiles = (md.m + kColBlock - 1) / kColBlock;
+  hipLaunchKernelGGL(k_eval_col, dim3(tiles), dim3(kColBlock), 0, st, md, io, total_wg, partials);
   return hipGetLastError();
 }
 

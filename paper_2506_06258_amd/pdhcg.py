@@ -15,6 +15,7 @@ import os
 from dataclasses import dataclass
 from typing import Optional
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -23,7 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libpdhcg.so")
 PDHCG_OK, PDHCG_MAX_ITER = 0, 1
 PDHCG_ERR_ARG, PDHCG_ERR_ASSUMPTION, PDHCG_ERR_NUMERIC = -1, -2, -3
 PDHCG_ERR_OOM, PDHCG_ERR_HIP, PDHCG_ERR_UNSUPPORTED = -4, -5, -6
-PDHCG_SEARCH_ACTIVESET, PDHCG_SEARCH_KSECTION = 0, 1
+PDHCG_SEARCH_ACTIVESET, PDHCG_SEARCH_KSECTION, PDHCG_SEARCH_KSECTION_WAVE = 0, 1, 2
 PDHCG_STEP_FIXED, PDHCG_STEP_ADAPTIVE = 0, 1
 PDHCG_RESTART_NONE, PDHCG_RESTART_ADAPTIVE = 0, 1
 PDHCG_OUTPUT_CANDIDATE, PDHCG_OUTPUT_CURRENT, PDHCG_OUTPUT_AVERAGE = 0, 1, 2
@@ -32,8 +33,10 @@ PDHCG_OUTPUT_CANDIDATE, PDHCG_OUTPUT_CURRENT, PDHCG_OUTPUT_AVERAGE = 0, 1, 2
 EXPORTS = (
     "pdhcg_abi_version", "pdhcg_status_string", "pdhcg_last_error",
     "pdhcg_default_params", "pdhcg_validate_host", "pdhcg_market_create",
-    "pdhcg_set_budgets", "pdhcg_solve", "pdhcg_kkt", "pdhcg_row_prox",
-    "pdhcg_arrow_debreu", "pdhcg_backward", "pdhcg_market_bins", "pdhcg_market_lds_goods",
+    "pdhcg_set_budgets", "pdhcg_solve", "pdhcg_solve_fixed_restart", "pdhcg_pdhg_solve",
+    "pdhcg_kkt", "pdhcg_row_prox",
+    "pdhcg_arrow_debreu", "pdhcg_backward", "pdhcg_market_bins",
+    "pdhcg_market_lds_goods",
     "pdhcg_market_destroy",
     "pdhcg_batch_create", "pdhcg_batch_solve", "pdhcg_batch_autotune", "pdhcg_batch_backward",
     "pdhcg_batch_layout",
@@ -98,6 +101,10 @@ def lib() -> C.CDLL:
         "pdhcg_set_budgets": (i32, [vp, vp]),
         "pdhcg_solve": (i32, [vp, C.POINTER(pdhcg_params), i32, vp, vp, vp,
                               C.POINTER(pdhcg_info)]),
+        "pdhcg_pdhg_solve": (i32, [vp, C.POINTER(pdhcg_params), i32, vp, vp, vp, vp,
+                                   C.POINTER(pdhcg_info)]),
+        "pdhcg_solve_fixed_restart": (i32, [vp, i32, i32, dbl, vp, C.POINTER(dbl),
+                                            C.POINTER(dbl), vp, vp, C.POINTER(pdhcg_info)]),
         "pdhcg_kkt": (i32, [vp, vp, vp, C.POINTER(pdhcg_info)]),
         "pdhcg_row_prox": (i32, [vp, vp, vp, dbl, C.POINTER(pdhcg_params), vp, vp]),
         "pdhcg_arrow_debreu": (i32, [vp, vp, vp, vp, i64, C.POINTER(pdhcg_params), dbl, i32,
@@ -227,6 +234,28 @@ def pdhcg_solve(h, params: pdhcg_params, warm: int, p, x, t=None) -> pdhcg_info:
     return info
 
 
+def pdhcg_pdhg_solve(h, params: pdhcg_params, warm: int, p, x, t=None, y=None) -> pdhcg_info:
+    info = pdhcg_info()
+    st = lib().pdhcg_pdhg_solve(h, C.byref(params), int(warm), _dev_ptr(p, torch.float32, "p"),
+                                _dev_ptr(x, torch.float32, "x"), _dev_ptr(t, torch.float32, "t"),
+                                _dev_ptr(y, torch.float32, "y"), C.byref(info))
+    _check(st, "pdhcg_pdhg_solve", ok=(PDHCG_OK, PDHCG_MAX_ITER))
+    return info
+
+
+def pdhcg_solve_fixed_restart(h, K: int, restarts: int, eta: float, p_ref, p, x):
+    """Returns (info, dist[restarts+1], kkt[restarts+1]) (numpy)."""
+    info = pdhcg_info()
+    dist = np.zeros(restarts + 1)
+    kk = np.zeros(restarts + 1)
+    _check(lib().pdhcg_solve_fixed_restart(
+        h, int(K), int(restarts), float(eta), _dev_ptr(p_ref, torch.float32, "p_ref"),
+        dist.ctypes.data_as(C.POINTER(C.c_double)), kk.ctypes.data_as(C.POINTER(C.c_double)),
+        _dev_ptr(p, torch.float32, "p"), _dev_ptr(x, torch.float32, "x"), C.byref(info)),
+        "pdhcg_solve_fixed_restart")
+    return info, dist, kk
+
+
 def pdhcg_kkt(h, p, x) -> pdhcg_info:
     info = pdhcg_info()
     _check(lib().pdhcg_kkt(h, _dev_ptr(p, torch.float32, "p"), _dev_ptr(x, torch.float32, "x"),
@@ -338,6 +367,28 @@ class Market:
             x.copy_(torch.as_tensor(x0, dtype=torch.float32))
         info = pdhcg_solve(self._h, prm, int(warm), p, x, t)
         return Solution(p, x, t, info)
+
+    def pdhg_solve(self, params: Optional[pdhcg_params] = None, **kw):
+        """Restarted PDHG (pdhcg_pdhg_solve): (Solution, y) with t and y in
+        the caller's units."""
+        prm = params if params is not None else pdhcg_default_params(**kw)
+        p = torch.empty(self.m, dtype=torch.float32, device=self.device)
+        x = torch.empty(self.nnz, dtype=torch.float32, device=self.device)
+        t = torch.empty(self.n, dtype=torch.float32, device=self.device)
+        y = torch.empty(self.n, dtype=torch.float32, device=self.device)
+        info = pdhcg_pdhg_solve(self._h, prm, 0, p, x, t, y)
+        return Solution(p, x, t, info), y
+
+    def solve_fixed_restart(self, K: int, restarts: int, eta: float = 0.0, p_ref=None):
+        """Alg. 2 with fixed steps and restart length (pdhcg_solve_fixed_restart):
+        (Solution without t, dist, kkt)."""
+        p = torch.empty(self.m, dtype=torch.float32, device=self.device)
+        x = torch.empty(self.nnz, dtype=torch.float32, device=self.device)
+        pr = None
+        if p_ref is not None:
+            pr = torch.as_tensor(p_ref).to(self.device, torch.float32).contiguous()
+        info, dist, kk = pdhcg_solve_fixed_restart(self._h, K, restarts, eta, pr, p, x)
+        return Solution(p, x, None, info), dist, kk
 
     def set_budgets(self, w) -> None:
         w_t = torch.as_tensor(w).to(self.device, torch.float32).contiguous()

@@ -133,8 +133,10 @@ def run_backward(unroll: int) -> None:
 
 def run_ksweep() -> None:
     """The 1e8-edge market to rel. KKT 1e-4 with the paper's k-section row
-    search for k = 2 ... 32 (Sec. 2.2.1, Table 1) and with the active-set
-    search: iterations, row-pass time and search rounds."""
+    search for k = 2 ... 64 (Sec. 2.2.1, Table 1) in both mappings (one lane
+    per candidate with the row in LDS; the G lanes holding a row taking the
+    candidates in turn) and with the active-set search: iterations, row-pass
+    time and search rounds."""
     import torch
 
     sys.path.insert(0, ROOT)
@@ -143,12 +145,16 @@ def run_ksweep() -> None:
     mk = synth.fisher_1e8(1)
     M = pdhcg.Market.from_synth(mk, device=torch.device("cuda:0"))
     cases = [("active set", pdhcg.PDHCG_SEARCH_ACTIVESET, 32)]
-    cases += [(f"{k}-section", pdhcg.PDHCG_SEARCH_KSECTION, k) for k in (2, 4, 8, 16, 32)]
+    cases += [(f"{k}-section, one lane per candidate", pdhcg.PDHCG_SEARCH_KSECTION_WAVE, k)
+              for k in (2, 4, 8, 16, 32, 64)]
+    cases += [(f"{k}-section, candidates in turn", pdhcg.PDHCG_SEARCH_KSECTION, k)
+              for k in (2, 4, 8, 16, 32)]
     print("| search | iterations | solve s | row pass ms | mean rounds | max rounds | rel. KKT |")
     print("|---|---|---|---|---|---|---|")
     for name, search, k in cases:
+        # rounds are bounded only by the bracket width (search_rtol 1e-10)
         prm = pdhcg.pdhcg_default_params(tol=1e-4, max_iter=20000, timing=1, search=search,
-                                         sections=k)
+                                         sections=k, max_search_rounds=200)
         M.solve(prm)  # warmup
         s = M.solve(prm)
         torch.cuda.synchronize()

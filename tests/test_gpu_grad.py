@@ -59,7 +59,12 @@ def test_backward_matches_oracle(cuda, seed, n, m):
     M = pdhcg.Market(rp, col, u, w, m=m, device=cuda)
     sol = M.solve(tol=1e-7, max_iter=200000)
     assert sol.info.status == pdhcg.PDHCG_OK
-    du, dw = M.backward(sol.x, sol.p, sol.info.omega, torch.tensor(g, dtype=torch.float32),
+    # The limit of the unrolled reverse mode does not depend on the primal
+    # weight, but how fast it is reached does, by orders of magnitude (on
+    # this market the oracle's 1024-step error is 2e-7 at omega 0.45 and
+    # 5e-3 at omega 0.17); the GPU solve's final omega depends on its own
+    # float32 trajectory, so both sides unroll with the oracle's.
+    du, dw = M.backward(sol.x, sol.p, ref.omega, torch.tensor(g, dtype=torch.float32),
                         unroll=1024, ckpt_every=32)
     du = du.double().cpu().numpy()
     dw = dw.double().cpu().numpy()
@@ -186,4 +191,40 @@ def test_batch_backward_matches_oracle(cuda):
     with pytest.raises(pdhcg.PDHCGError) as e:
         B.backward(x, p, [0.0] * len(markets), torch.tensor(np.concatenate(gs)))
     assert e.value.status == pdhcg.PDHCG_ERR_ARG
+    B.close()
+
+
+def test_batch_backward_matches_single_market(cuda):
+    """The persistent batched reverse mode computes, market by market, what
+    the single-market reverse mode computes (same unrolled iteration, same
+    primal weights): markets chosen so that every batch row shape appears,
+    including rows of more than 1024 entries."""
+    from paper_2506_06258_amd import synth
+    specs = [(300, 40, 0.3), (300, 120, 0.3), (400, 300, 0.3), (500, 700, 0.3),
+             (300, 1500, 0.4), (60, 2000, 0.6)]
+    markets = [synth.bernoulli_market(n, m, q, 60 + k, w_mode="uniform").as_float32()
+               for k, (n, m, q) in enumerate(specs)]
+    bt = synth.batch_from_markets(markets)
+    B = pdhcg.Batch(bt, device=cuda)
+    st, p, x, infos = B.solve(tol=1e-5, max_iter=200000)
+    assert st == pdhcg.PDHCG_OK
+    rng = np.random.default_rng(5)
+    g = torch.tensor(rng.normal(size=int(B.good_off[-1])), dtype=torch.float32)
+    omegas = [i.omega for i in infos]
+    K, L = 48, 8
+    du, dw = B.backward(x, p, omegas, g, unroll=K, ckpt_every=L)
+    du, dw = du.double().cpu().numpy(), dw.double().cpu().numpy()
+    row_off = np.concatenate([[0], np.cumsum([mk.n for mk in markets])])
+    for b, mk in enumerate(markets):
+        eo0, eo1 = int(B.edge_off[b]), int(B.edge_off[b + 1])
+        go0, go1 = int(B.good_off[b]), int(B.good_off[b + 1])
+        M = pdhcg.Market.from_synth(mk, device=cuda)
+        d1, w1 = M.backward(x[eo0:eo1], p[go0:go1], omegas[b], g[go0:go1], unroll=K,
+                            ckpt_every=L)
+        M.close()
+        d1, w1 = d1.double().cpu().numpy(), w1.double().cpu().numpy()
+        assert np.all(np.isfinite(du[eo0:eo1])), b
+        # float64 LDS sums in no fixed order on both sides: equal to rounding
+        assert _rel(du[eo0:eo1], d1) <= 1e-5, (b, _rel(du[eo0:eo1], d1))
+        assert _rel(dw[row_off[b]:row_off[b + 1]], w1) <= 1e-5, b
     B.close()

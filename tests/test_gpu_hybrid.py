@@ -108,7 +108,9 @@ def test_backward(cuda, monkeypatch):
     assert M.lds_goods() == 5
     sol = M.solve(tol=1e-7, max_iter=200000)
     assert sol.info.status == pdhcg.PDHCG_OK
-    du, dw = M.backward(sol.x, sol.p, sol.info.omega, torch.tensor(g, dtype=torch.float32),
+    # the oracle's primal weight for the unrolled steps: the limit does not
+    # depend on it, how fast it is reached does (see test_gpu_grad.py)
+    du, dw = M.backward(sol.x, sol.p, ref.omega, torch.tensor(g, dtype=torch.float32),
                         unroll=1024, ckpt_every=32)
     du, dw = du.double().cpu().numpy(), dw.double().cpu().numpy()
     assert _rel(du, du_i) <= 1e-4, _rel(du, du_i)

@@ -92,6 +92,32 @@ def test_row_prox_search_variants(cuda, search, sections):
     check_row_prox(mk, cuda, x_in, p, 0.05, prm)
 
 
+@pytest.mark.parametrize("sections", [2, 4, 8, 16, 32, 64])
+def test_row_prox_ksection_wave(cuda, sections):
+    """The k-section search as Sec. 2.2.1 maps it (one wave per row, the row
+    in LDS, one lane per candidate) for every k of Table 1, stopped by the
+    bracket width (search_rtol), not by the round cap."""
+    mk = f32(synth.fisher_small(1))
+    rng = np.random.default_rng(70 + sections)
+    x_in, p = prox_state(mk, rng, "random")
+    prm = pdhcg.pdhcg_default_params(search=pdhcg.PDHCG_SEARCH_KSECTION_WAVE, sections=sections,
+                                     max_search_rounds=200)
+    check_row_prox(mk, cuda, x_in, p, 0.05, prm)
+
+
+@pytest.mark.parametrize("d", [1, 17, 64, 100, 257, 500])
+def test_row_prox_ksection_wave_degrees(cuda, d):
+    """Rows of 1 to 500 entries (1 to 8 per lane of the loading wave)."""
+    n = 997
+    m = max(d, 60)
+    mk = f32(synth.fixed_degree_market(n, m, d, 300 + d, "uniform"))
+    rng = np.random.default_rng(d + 1)
+    x_in, p = prox_state(mk, rng, "random")
+    prm = pdhcg.pdhcg_default_params(search=pdhcg.PDHCG_SEARCH_KSECTION_WAVE, sections=32,
+                                     max_search_rounds=200)
+    check_row_prox(mk, cuda, x_in, p, 0.3 / (mk.w.sum() / mk.m), prm)
+
+
 @pytest.mark.parametrize("d", [1, 3, 8, 17, 40, 64, 100, 129, 257, 500])
 def test_row_prox_degree_variants(cuda, d):
     """Every row-kernel shape (lanes x entries) with a ragged last pass."""
@@ -148,6 +174,54 @@ def test_trajectory_parity_ksection(cuda):
     assert np.max(np.abs(g.p.cpu().numpy() - ora.p)) <= 2e-4 * np.max(np.abs(ora.p))
 
 
+@pytest.mark.parametrize("sections", [2, 64])
+def test_trajectory_parity_ksection_wave(cuda, sections):
+    mk = f32(synth.fisher_small(2))
+    g, ora = trajectory(mk, cuda, 24, search=pdhcg.PDHCG_SEARCH_KSECTION_WAVE,
+                        sections=sections, max_search_rounds=200)
+    assert np.max(np.abs(g.p.cpu().numpy() - ora.p)) <= 2e-4 * np.max(np.abs(ora.p))
+    assert np.max(np.abs(g.x.cpu().numpy() - ora.x)) <= 2e-4 * np.max(np.abs(ora.x))
+    assert 0 < g.info.search_rounds_max < 200  # stopped by the bracket width
+
+
+def test_adaptive_trajectory_tracks_oracle(cuda):
+    """The adaptive step rule, the restarts and the primal-weight update
+    (Sec. 5) step by step: a solve cut off after k iterations is the first k
+    iterations of a longer one on both sides (no restart decision at the
+    cut), so for every k up to 66 the kept-step count, the restart count,
+    the next step size eta, the primal weight and the current prices after k
+    iterations are compared with the oracle's.  The range holds rejected
+    steps, the first KKT check and restart (at 64) and its primal-weight
+    update.  Bars: kept-step and restart counts exactly; eta and omega to
+    2e-2 relative and prices to 1e-3 of their scale.  The rule divides by
+    dp^T K dx, a sum of differences of column sums, which amplifies the
+    float32 rounding of the allocation: measured, eta agrees to 3e-6 up to
+    iteration 30 and to 1e-2 at 64, and the trajectories separate after
+    about 70 iterations (both then converge to the same prices, which the
+    solve tests check)."""
+    mk = f32(synth.fisher_small(0))
+    M = pdhcg.Market.from_synth(mk, device=cuda)
+    seen_restart, seen_reject = False, False
+    for k in range(1, 67):
+        common = dict(tol=0.0, max_iter=k, output=1)
+        g = M.solve(**common)
+        ora = oracle.solve(mk.n, mk.m, mk.row_ptr, mk.col, mk.u.astype(np.float64),
+                           mk.w.astype(np.float64), **common)
+        ge, oe, go, oo = float(g.info.eta), float(ora.eta), float(g.info.omega), float(ora.omega)
+        ga, oa, gr, orr = int(g.info.accepted), int(ora.accepted), int(g.info.restarts), int(ora.restarts)
+        pg = g.p.cpu().numpy().astype(np.float64)
+        perr = float(np.max(np.abs(pg - ora.p)) / np.max(np.abs(ora.p)))
+        case = (k, ga, oa, gr, orr, ge, oe, go, oo, perr)
+        assert int(g.info.iters) == k and ora.iters == k, case
+        assert ga == oa and gr == orr, case
+        assert abs(ge - oe) <= 2e-2 * oe and abs(go - oo) <= 2e-2 * oo, case
+        assert perr <= 1e-3, case
+        seen_restart |= orr > 0
+        seen_reject |= oa < k
+    assert seen_restart and seen_reject
+    M.close()
+
+
 @pytest.fixture(scope="module")
 def small_reference():
     mk = f32(synth.fisher_small(0))
@@ -196,6 +270,7 @@ def test_solve_variants_reach_same_prices(cuda, small_reference):
     mk, ora = small_reference
     M = pdhcg.Market.from_synth(mk, device=cuda)
     for kw in (dict(step_mode=0), dict(search=pdhcg.PDHCG_SEARCH_KSECTION, sections=32),
+               dict(search=pdhcg.PDHCG_SEARCH_KSECTION_WAVE, sections=64, max_search_rounds=200),
                dict(output=pdhcg.PDHCG_OUTPUT_AVERAGE)):
         sol = M.solve(tol=1e-5, max_iter=200000, **kw)
         assert sol.info.status == pdhcg.PDHCG_OK, kw

@@ -117,13 +117,14 @@ def test_ksection_rejected_on_long_rows(cuda):
     instead of silently using another search."""
     mk = synth.fixed_degree_market(40, 700, 520, 9, "uniform").as_float32()
     M = pdhcg.Market.from_synth(mk, device=cuda)
-    prm = pdhcg.pdhcg_default_params(search=pdhcg.PDHCG_SEARCH_KSECTION, sections=32)
-    with pytest.raises(pdhcg.PDHCGError) as e:
-        M.solve(prm)
-    assert e.value.status == pdhcg.PDHCG_ERR_UNSUPPORTED
     x_in = torch.full((mk.nnz,), 0.01, device=cuda)
     p = torch.ones(mk.m, device=cuda)
-    with pytest.raises(pdhcg.PDHCGError) as e:
-        M.row_prox(x_in, p, 0.1, prm)
-    assert e.value.status == pdhcg.PDHCG_ERR_UNSUPPORTED
+    for search in (pdhcg.PDHCG_SEARCH_KSECTION, pdhcg.PDHCG_SEARCH_KSECTION_WAVE):
+        prm = pdhcg.pdhcg_default_params(search=search, sections=32)
+        with pytest.raises(pdhcg.PDHCGError) as e:
+            M.solve(prm)
+        assert e.value.status == pdhcg.PDHCG_ERR_UNSUPPORTED
+        with pytest.raises(pdhcg.PDHCGError) as e:
+            M.row_prox(x_in, p, 0.1, prm)
+        assert e.value.status == pdhcg.PDHCG_ERR_UNSUPPORTED
     M.close()

@@ -290,6 +290,24 @@ int32_t pdhcg_backward(pdhcg_market market, const float *x, const float *p,
                        double omega, int32_t unroll, int32_t ckpt_every,
                        const float *dL_dp, float *dL_du, float *dL_dw);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation and results as pdhcg_backward, with its workspace taken from
+ * a fixed 64 MiB array that the library holds in each GPU's memory until the
+ * process ends, instead of buffers allocated per call.  Calls no hipMalloc,
+ * hipFree or allocating library routine.  The workspace needed is
+ *   4 nnz (ceil(unroll/c) + c + 5) + 4 n + 8 m (3 ceil(unroll/c) + 23)
+ * bytes (c = min(ckpt_every, unroll); each piece rounded up to 256 bytes);
+ * above 64 MiB the call returns PDHCG_ERR_UNSUPPORTED before any device work.
+ * Every call on one GPU uses that GPU's single array and leaves it dirty
+ * (each call initialises what it reads): calls that overlap in time on one
+ * GPU (other threads, other streams) race and must be serialised by the
+ * caller.  Arguments, errors and synchronisation as pdhcg_backward. */
+int32_t pdhcg_backward_noalloc(pdhcg_market market, const float *x,
+                               const float *p, double omega, int32_t unroll,
+                               int32_t ckpt_every, const float *dL_dp,
+                               float *dL_du, float *dL_dw);
+
 /* Number of market rows in each kernel bin and the bin shapes chosen at
  * creation (host arrays of length cap; returns the number of bins). */
 int32_t pdhcg_market_bins(pdhcg_market market, int32_t cap,

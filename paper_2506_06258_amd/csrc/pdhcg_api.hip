@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1579,6 +1580,35 @@ int32_t finish_colsum(pdhcg_market mk, double *chunk, double *atomic_sum, double
   return PDHCG_OK;
 }
 
+// Bump allocation over a caller-provided device region (the no-allocation
+// entry point's static workspace): 256-byte aligned pieces, never freed.
+struct ArenaBuffers {
+  char *base = nullptr;
+  size_t cap = 0, used = 0;
+  template <typename T>
+  hipError_t get(T **p, size_t count) {
+    const size_t bytes = ((std::max<size_t>(count, 1) * sizeof(T)) + 255) & ~size_t(255);
+    *p = nullptr;
+    if (used + bytes > cap) return hipErrorOutOfMemory;
+    *p = reinterpret_cast<T *>(base + used);
+    used += bytes;
+    return hipSuccess;
+  }
+};
+
+// Device bytes the reverse mode's buffers take (as ArenaBuffers lays them
+// out): checkpoints of x, p, c, c_prev; one segment of recomputed
+// allocations; five nnz work arrays; the budget adjoint; seven goods arrays
+// and the column-chunk sums.
+size_t backward_bytes(int64_t nnz, int n, int m, int K, int L) {
+  auto al = [](size_t b) { return (std::max<size_t>(b, 1) + 255) & ~size_t(255); };
+  const size_t nck = (size_t)((K + L - 1) / L);
+  size_t b = al(nck * nnz * 4) + al((size_t)L * nnz * 4) + 5 * al((size_t)nnz * 4) +
+             al((size_t)n * 4) + 3 * al(nck * m * 8) + al((size_t)kColChunks * m * 8) +
+             7 * al((size_t)m * 8);
+  return b;
+}
+
 template <typename Buffers>
 int32_t backward_impl(pdhcg_market mk, const float *x, const float *p, double omega,
                       int32_t unroll, int32_t ckpt_every, const float *dL_dp, float *dL_du,
@@ -1589,9 +1619,6 @@ int32_t backward_impl(pdhcg_market mk, const float *x, const float *p, double om
   const MarketDev md = mk->dev();
   const int K = unroll, L = std::min(ckpt_every, unroll);
   const int nck = (K + L - 1) / L;
-  // fixed step (Lemma 1): eta = 0.9 / ||K||, ||K|| = sqrt(max column degree)
-  const double eta = 0.9 / std::sqrt((double)std::max(1, mk->maxdeg_col));
-  const double tau = eta / omega, sigma = eta * omega;
 
   float *ck_x = nullptr, *seg_x = nullptr, *xa = nullptr, *xb = nullptr;
   float *R0 = nullptr, *R1 = nullptr, *duh = nullptr, *dw = nullptr;
@@ -1617,6 +1644,9 @@ int32_t backward_impl(pdhcg_market mk, const float *x, const float *p, double om
   HIPC(buf.get(&P, (size_t)m));
   HIPC(buf.get(&B, (size_t)m));
   HIPC(buf.get(&Cn, (size_t)m));
+  // fixed step (Lemma 1): eta = 0.9 / ||K||, ||K|| = sqrt(max column degree)
+  const double eta = 0.9 / std::sqrt((double)std::max(1, mk->maxdeg_col));
+  const double tau = eta / omega, sigma = eta * omega;
 
   pdhcg_params dflt;
   pdhcg_default_params(&dflt);
@@ -1722,6 +1752,43 @@ int32_t check_backward_args(pdhcg_market mk, const float *x, const float *p, dou
   return PDHCG_OK;
 }
 
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+
+}  // namespace
+
+// Workspace of pdhcg_backward_noalloc: a fixed array in every GPU's memory,
+// held until the process ends.  In host code this name is only a stand-in
+// for the symbol: the device address comes from hipGetSymbolAddress, once
+// per device, and only that address is passed to kernels.
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, looked up on the first call for
+// that device (with it current) and cached.
+int32_t scratch_address(int device, char **out) {
+  *out = nullptr;
+  if (device < 0 || device >= kMaxDevices) return fail(PDHCG_ERR_ARG, "device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = 0;
+    HIPC(hipGetDevice(&cur));
+    if (cur != device) HIPC(hipSetDevice(device));
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (cur != device) HIPC(hipSetDevice(cur));
+    if (e != hipSuccess)
+      return fail(PDHCG_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    if (!ptr) return fail(PDHCG_ERR_HIP, "hipGetSymbolAddress(scratch) returned a null address");
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = static_cast<char *>(g_scratch_ptr[device]);
+  return PDHCG_OK;
+}
 
 }  // namespace
 
@@ -1734,4 +1801,21 @@ extern "C" int32_t pdhcg_backward(pdhcg_market mk, const float *x, const float *
   return backward_impl(mk, x, p, omega, unroll, ckpt_every, dL_dp, dL_du, dL_dw, buf);
 }
 
-
+extern "C" int32_t pdhcg_backward_noalloc(pdhcg_market mk, const float *x, const float *p,
+                                          double omega, int32_t unroll, int32_t ckpt_every,
+                                          const float *dL_dp, float *dL_du, float *dL_dw) {
+  int32_t rc = check_backward_args(mk, x, p, omega, unroll, ckpt_every, dL_dp, dL_du, dL_dw);
+  if (rc != PDHCG_OK) return rc;
+  const int L = std::min(ckpt_every, unroll);
+  const size_t need = backward_bytes(mk->nnz, mk->n, mk->m, unroll, L);
+  if (need > kNoAllocBytes)
+    return fail(PDHCG_ERR_UNSUPPORTED,
+                "pdhcg_backward_noalloc needs " + std::to_string(need) + " bytes of workspace for "
+                "this market and unroll/ckpt_every; its fixed workspace holds " +
+                std::to_string(kNoAllocBytes) + " bytes (use pdhcg_backward)");
+  ArenaBuffers buf;
+  rc = scratch_address(mk->device, &buf.base);
+  if (rc != PDHCG_OK) return rc;
+  buf.cap = kNoAllocBytes;
+  return backward_impl(mk, x, p, omega, unroll, ckpt_every, dL_dp, dL_du, dL_dw, buf);
+}

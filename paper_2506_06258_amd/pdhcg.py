@@ -35,7 +35,7 @@ EXPORTS = (
     "pdhcg_default_params", "pdhcg_validate_host", "pdhcg_market_create",
     "pdhcg_set_budgets", "pdhcg_solve", "pdhcg_solve_fixed_restart", "pdhcg_pdhg_solve",
     "pdhcg_kkt", "pdhcg_row_prox",
-    "pdhcg_arrow_debreu", "pdhcg_backward", "pdhcg_market_bins",
+    "pdhcg_arrow_debreu", "pdhcg_backward", "pdhcg_backward_noalloc", "pdhcg_market_bins",
     "pdhcg_market_lds_goods",
     "pdhcg_market_destroy",
     "pdhcg_batch_create", "pdhcg_batch_solve", "pdhcg_batch_autotune", "pdhcg_batch_backward",
@@ -111,6 +111,7 @@ def lib() -> C.CDLL:
                                      vp, vp, vp, C.POINTER(i32), C.POINTER(i64),
                                      C.POINTER(pdhcg_info)]),
         "pdhcg_backward": (i32, [vp, vp, vp, dbl, i32, i32, vp, vp, vp]),
+        "pdhcg_backward_noalloc": (i32, [vp, vp, vp, dbl, i32, i32, vp, vp, vp]),
         "pdhcg_market_bins": (i32, [vp, i32, vp, vp, vp]),
         "pdhcg_market_lds_goods": (i32, [vp]),
         "pdhcg_market_destroy": (None, [vp]),
@@ -279,6 +280,17 @@ def pdhcg_backward(h, x, p, omega: float, unroll: int, ckpt_every: int, dL_dp, d
                                 _dev_ptr(dL_dw, torch.float32, "dL_dw")), "pdhcg_backward")
 
 
+def pdhcg_backward_noalloc(h, x, p, omega: float, unroll: int, ckpt_every: int, dL_dp, dL_du,
+                           dL_dw):
+    _check(lib().pdhcg_backward_noalloc(h, _dev_ptr(x, torch.float32, "x"),
+                                        _dev_ptr(p, torch.float32, "p"),
+                                        float(omega), int(unroll), int(ckpt_every),
+                                        _dev_ptr(dL_dp, torch.float32, "dL_dp"),
+                                        _dev_ptr(dL_du, torch.float32, "dL_du"),
+                                        _dev_ptr(dL_dw, torch.float32, "dL_dw")),
+           "pdhcg_backward_noalloc")
+
+
 def pdhcg_arrow_debreu(h, e_row_ptr, e_col, e_val, e_nnz, inner: pdhcg_params, outer_tol,
                        outer_max, w, p, x):
     oi, ii, info = C.c_int32(0), C.c_int64(0), pdhcg_info()
@@ -410,13 +422,20 @@ class Market:
         """Goods whose column data the row kernels keep in LDS (m: all)."""
         return pdhcg_market_lds_goods(self._h)
 
-    def backward(self, x, p, omega: float, dL_dp, unroll: int = 1024, ckpt_every: int = 32):
+    def backward(self, x, p, omega: float, dL_dp, unroll: int = 1024, ckpt_every: int = 32,
+                 out=None, noalloc: bool = False):
         """(dL/du, dL/dw) by reverse mode through `unroll` fixed-step
-        iterations from (x, p); see pdhcg_backward."""
-        du = torch.empty(self.nnz, dtype=torch.float32, device=self.device)
-        dw = torch.empty(self.n, dtype=torch.float32, device=self.device)
+        iterations from (x, p); see pdhcg_backward.  noalloc: call
+        pdhcg_backward_noalloc (the library's fixed workspace); out: optional
+        (du, dw) tensors to write into."""
+        if out is None:
+            du = torch.empty(self.nnz, dtype=torch.float32, device=self.device)
+            dw = torch.empty(self.n, dtype=torch.float32, device=self.device)
+        else:
+            du, dw = out
         g = torch.as_tensor(dL_dp).to(self.device, torch.float32).contiguous()
-        pdhcg_backward(self._h, x.contiguous(), p.contiguous(), omega, unroll, ckpt_every, g, du, dw)
+        fn = pdhcg_backward_noalloc if noalloc else pdhcg_backward
+        fn(self._h, x.contiguous(), p.contiguous(), omega, unroll, ckpt_every, g, du, dw)
         return du, dw
 
     def arrow_debreu(self, e_row_ptr, e_col, e_val, w0, inner: Optional[pdhcg_params] = None,

@@ -247,6 +247,49 @@ def batched_leg(args, bt, pdhcg, torch):
     return out
 
 
+def batched_backward_leg(args, bt, pdhcg, torch):
+    """Reverse mode over every market of the batch in one persistent launch
+    (pdhcg_batch_backward) for L = sum_j (p_j - q_j)^2, q a seeded 1%
+    perturbation of the batch's own solution (a loss target only): seconds
+    per call and the residual of the budget identity
+    sum_i w_i dL/dw_i = sum_j p_j dL/dp_j, which the derivative of the
+    equilibrium prices satisfies exactly, per market."""
+    B = pdhcg.Batch(bt, device=torch.device("cuda:0"))
+    st, p, x, infos = B.solve(tol=1e-6, max_iter=400000)
+    rng = np.random.default_rng(77)
+    pp = p.double().cpu().numpy()
+    g = 2.0 * (pp - pp * (1.0 + 0.01 * rng.normal(size=pp.size)))
+    gt = torch.tensor(g, dtype=torch.float32)
+    omegas = [i.omega for i in infos]
+    _, row_off, good_off, _ = bt.offsets()
+    wv = bt.w.astype(np.float64)
+    out = {"workload": "pdhcg_batch_backward over every market of the batch, loss sum (p - q)^2, "
+                       "q a seeded 1% perturbation of the solved prices (rel. KKT 1e-6), each "
+                       "market's primal weight, checkpoints every 16"}
+    for K in args.batch_backward_unroll:
+        B.backward(x, p, omegas, gt, unroll=4, ckpt_every=2)  # warmup
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        du, dw = B.backward(x, p, omegas, gt, unroll=K, ckpt_every=16)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        dwn = dw.double().cpu().numpy()
+        res = []
+        for b in range(bt.count):
+            lhs = float(wv[row_off[b]:row_off[b + 1]] @ dwn[row_off[b]:row_off[b + 1]])
+            rhs = float(pp[good_off[b]:good_off[b + 1]] @ g[good_off[b]:good_off[b + 1]])
+            res.append(abs(lhs - rhs) / max(abs(rhs), 1e-30))
+        res = np.array(res)
+        out[f"unroll_{K}"] = {"seconds": dt, "markets_per_s": bt.count / dt,
+                              "budget_identity_residual_median": float(np.median(res)),
+                              "budget_identity_residual_p90": float(np.quantile(res, 0.9)),
+                              "markets_below_1e-4": int((res <= 1e-4).sum())}
+        log(f"batched backward unroll {K}: {dt:.3f}s, identity residual median "
+            f"{np.median(res):.2e}, {(res <= 1e-4).sum()} markets <= 1e-4")
+    B.close()
+    return out
+
+
 def market_leg(label, mk, args, pdhcg, torch, with_bytes=True):
     """One solve of a further market to rel. KKT 1e-4 (warm-up, then timed)."""
     M = pdhcg.Market.from_synth(mk, device=torch.device("cuda:0"))
@@ -313,6 +356,8 @@ def main():
                     help="markets of the batch solved one call at a time at 1e-6")
     ap.add_argument("--backward-unroll", type=int, default=64,
                     help="unrolled steps of the reverse-mode leg on the same market (0: skip)")
+    ap.add_argument("--batch-backward-unroll", type=int, nargs="*", default=[64, 512],
+                    help="unrolled steps of the batched reverse-mode leg (none: skip)")
     ap.add_argument("--pdhg", type=int, default=1, help="restarted PDHG leg (0: skip)")
     ap.add_argument("--exchange", type=int, default=1,
                     help="run the Arrow-Debreu leg (1e5 agents and goods; 0: skip)")
@@ -372,6 +417,8 @@ def main():
     M.close()
     del s
     batched = batched_leg(args, bt, pdhcg, torch) if bt is not None else None
+    batched_bw = (batched_backward_leg(args, bt, pdhcg, torch)
+                  if bt is not None and args.batch_backward_unroll else None)
     del bt
     skewed = market_leg("skewed", skw, args, pdhcg, torch) if skw is not None else None
     del skw
@@ -418,6 +465,7 @@ def main():
                      "avg_launch_ms": 1e3 * avg_launch, "launches_timed": launches},
         "cpu_baseline": cpu,
         "batched": batched,
+        "batched_backward": batched_bw,
         "backward": backward,
         "pdhg": pdhg,
         "skewed": skewed,

@@ -271,7 +271,10 @@ int32_t pdhcg_arrow_debreu(pdhcg_market market, const int32_t *e_row_ptr,
 /* Gradient of a loss L(p) of the prices with respect to the utilities u
  * and budgets w, by reverse mode through `unroll` fixed-step PDHCG
  * iterations (the price step of eq. update:py and the row prox of Sec. 2.2,
- * step eta = 0.9/||K||, tau = eta/omega, sigma = eta*omega) started from
+ * tau = eta/omega, sigma = eta*omega, eta = 0.9/||K_x|| with K_x the
+ * column-sum operator on the support of x: ||K_x|| = sqrt(the largest
+ * number of buyers with x_ij > 0 of a good), Lemma 1's step condition for
+ * the entries that move near the start point) started from
  * (x, p), normally the solution pdhcg_solve returned; the start point is
  * held constant, so at an equilibrium the result tends, as unroll grows, to
  * the derivative of the equilibrium prices (implicit function theorem on
@@ -296,7 +299,7 @@ int32_t pdhcg_backward(pdhcg_market market, const float *x, const float *p,
  * a fixed 64 MiB array that the library holds in each GPU's memory until the
  * process ends, instead of buffers allocated per call.  Calls no hipMalloc,
  * hipFree or allocating library routine.  The workspace needed is
- *   4 nnz (ceil(unroll/c) + c + 5) + 4 n + 8 m (3 ceil(unroll/c) + 23)
+ *   4 nnz (ceil(unroll/c) + c + 5) + 4 n + 8 m (3 ceil(unroll/c) + 23) + 4 (m + 1)
  * bytes (c = min(ckpt_every, unroll); each piece rounded up to 256 bytes);
  * above 64 MiB the call returns PDHCG_ERR_UNSUPPORTED before any device work.
  * Every call on one GPU uses that GPU's single array and leaves it dirty

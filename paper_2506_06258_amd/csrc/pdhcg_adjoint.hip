@@ -31,6 +31,25 @@ int grid_1d(int64_t n, int block) { return (int)((n + block - 1) / block); }
 
 }  // namespace
 
+// Buyers per good on the support of x: cnt[col[k]] += (x[k] > 0), then the
+// largest count into *out (both zeroed by the caller).
+__global__ void k_active_count(const int32_t *col, const float *x, int64_t nnz, int32_t *cnt) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < nnz && x[k] > 0.0f) atomicAdd(&cnt[col[k]], 1);
+}
+
+__global__ void k_int_max(const int32_t *cnt, int m, int32_t *out) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  int v = j < m ? cnt[j] : 0;
+  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o));
+  if ((threadIdx.x & (kWave - 1)) == 0 && v > 0) atomicMax(out, v);
+}
+
+__global__ void k_zero_i32(int32_t *a, int64_t len) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < len) a[k] = 0;
+}
+
 // p += sigma (2 c - cprev - 1), float64.
 __global__ void k_adj_pstep(double *p, const double *c, const double *cprev, double sigma,
                             int m) {
@@ -238,6 +257,15 @@ __global__ void k_adj_unnormalize(const int32_t *row_ptr, const float *uh, const
 }
 
 // ------------------------------------------------------------- launchers --
+
+hipError_t launch_active_colmax(const int32_t *col, const float *x, int64_t nnz, int32_t *cnt,
+                               int m, int32_t *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_zero_i32, dim3(grid_1d(m + 1, 256)), dim3(256), 0, st, cnt, (int64_t)m);
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, st, out, (int64_t)1);
+  hipLaunchKernelGGL(k_active_count, dim3(grid_1d(nnz, 256)), dim3(256), 0, st, col, x, nnz, cnt);
+  hipLaunchKernelGGL(k_int_max, dim3(grid_1d(m, 256)), dim3(256), 0, st, cnt, m, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_adj_pstep(double *p, const double *c, const double *cprev, double sigma, int m,
                             hipStream_t st) {

@@ -1598,14 +1598,14 @@ struct ArenaBuffers {
 
 // Device bytes the reverse mode's buffers take (as ArenaBuffers lays them
 // out): checkpoints of x, p, c, c_prev; one segment of recomputed
-// allocations; five nnz work arrays; the budget adjoint; seven goods arrays
-// and the column-chunk sums.
+// allocations; five nnz work arrays; the budget adjoint; seven goods arrays,
+// the column-chunk sums and the per-good support counts.
 size_t backward_bytes(int64_t nnz, int n, int m, int K, int L) {
   auto al = [](size_t b) { return (std::max<size_t>(b, 1) + 255) & ~size_t(255); };
   const size_t nck = (size_t)((K + L - 1) / L);
   size_t b = al(nck * nnz * 4) + al((size_t)L * nnz * 4) + 5 * al((size_t)nnz * 4) +
              al((size_t)n * 4) + 3 * al(nck * m * 8) + al((size_t)kColChunks * m * 8) +
-             7 * al((size_t)m * 8);
+             7 * al((size_t)m * 8) + al(((size_t)m + 1) * 4);
   return b;
 }
 
@@ -1644,8 +1644,19 @@ int32_t backward_impl(pdhcg_market mk, const float *x, const float *p, double om
   HIPC(buf.get(&P, (size_t)m));
   HIPC(buf.get(&B, (size_t)m));
   HIPC(buf.get(&Cn, (size_t)m));
-  // fixed step (Lemma 1): eta = 0.9 / ||K||, ||K|| = sqrt(max column degree)
-  const double eta = 0.9 / std::sqrt((double)std::max(1, mk->maxdeg_col));
+  int32_t *cnt = nullptr;
+  HIPC(buf.get(&cnt, (size_t)m + 1));
+
+  // Fixed step of the unrolled iteration: Lemma 1's condition
+  // sigma tau ||K||^2 < 1 for the operator that moves near the start point.
+  // Entries off the support of x stay at zero there (the prox clips them),
+  // so K is the column-sum operator on the support: ||K|| = sqrt(largest
+  // number of buyers with x_ij > 0 of a good).  eta = 0.9 / ||K||.
+  HIPC(launch_active_colmax(mk->col, x, nnz, cnt, m, cnt + m, st));
+  int32_t maxact = 0;
+  HIPC(hipMemcpyAsync(&maxact, cnt + m, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIPC(hipStreamSynchronize(st));
+  const double eta = 0.9 / std::sqrt((double)std::max(1, maxact));
   const double tau = eta / omega, sigma = eta * omega;
 
   pdhcg_params dflt;

@@ -810,7 +810,8 @@ __device__ __attribute__((noinline)) void wg_adj_rows(const MView &v, const floa
 // Reverse mode for every market of the batch in one persistent launch:
 // each workgroup takes markets from the queue (largest first) and runs the
 // whole reverse pass of a market (as pdhcg_backward): K fixed steps
-// (eta = 0.9 / ||K||, tau = eta / omega_b, sigma = eta omega_b) forward
+// (eta = 0.9 / ||K|| on the support of x, tau = eta / omega_b,
+// sigma = eta omega_b) forward
 // from (x, p) with a checkpoint every L steps, then segment by segment
 // backwards: the segment's forward steps recomputed from its checkpoint,
 // then the reverse of each step (row prox, price step).  Prices, column
@@ -850,16 +851,27 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_backward(BatchDev bd, Bat
     const int shape = uni(bd.shape[b]);
     const int nnz = v.rp[v.n];
     const int m = v.m;
-    if (threadIdx.x == 0) {
-      double kmax = 0.0;
-      for (int j = 0; j < m; ++j) kmax = fmax(kmax, (double)v.deg[j]);
-      s_eta = 0.9 / sqrt(kmax);
+    const float *x0 = a.x_in + eo;
+    // step: eta = 0.9 / ||K|| for the column-sum operator on the support of
+    // the start point (the entries that move near it), ||K|| = sqrt(largest
+    // number of buyers with x_ij > 0 of a good); counted in the B area of
+    // LDS, which the reverse sweep clears before use
+    {
+      int *lcnt = reinterpret_cast<int *>(lB);
+      for (int j = threadIdx.x; j < m; j += blockDim.x) lcnt[j] = 0;
+      __syncthreads();
+      for (int k = threadIdx.x; k < nnz; k += blockDim.x)
+        if (x0[k] > 0.0f) atomicAdd(&lcnt[v.col[k]], 1);
+      __syncthreads();
+      double cm = 0.0;
+      for (int j = threadIdx.x; j < m; j += blockDim.x) cm = fmax(cm, (double)lcnt[j]);
+      cm = block_max(cm, red);
+      if (threadIdx.x == 0) s_eta = 0.9 / sqrt(fmax(cm, 1.0));
+      __syncthreads();
     }
-    __syncthreads();
     const double eta = uni(s_eta);
     const double om = a.omega[b];
     const double tau = eta / om, sigma = eta * om;
-    const float *x0 = a.x_in + eo;
     float *R0 = a.R0 + eo, *R1 = a.R1 + eo;
     float *duh = a.dL_du + eo, *dw = a.dL_dw + ro;
     auto ckx = [&](int q) { return a.ck_x + (size_t)q * a.nnz_total + eo; };

@@ -247,6 +247,10 @@ hipError_t launch_eval_col_stats(const MarketDev &md, const EvalIO &io, int tota
 hipError_t launch_col_decide_pdhg(const MarketDev &md, int total_wg, hipStream_t st);
 
 // Reverse mode (pdhcg_adjoint.hip).
+// Largest number of buyers with x_ij > 0 over the goods (cnt: [m] work
+// array; out: one int, device).
+hipError_t launch_active_colmax(const int32_t *col, const float *x, int64_t nnz, int32_t *cnt,
+                               int m, int32_t *out, hipStream_t st);
 hipError_t launch_adj_pstep(double *p, const double *c, const double *cprev, double sigma, int m,
                             hipStream_t st);
 hipError_t launch_sum_partials(const double *part, int rows, int hot, int m, double *chunk,

@@ -7,6 +7,8 @@
   python -m paper_2506_06258_amd.profile_run backward [--unroll 64]
   python -m paper_2506_06258_amd.profile_run ksweep
   python -m paper_2506_06258_amd.profile_run jd
+  python -m paper_2506_06258_amd.profile_run pdhg
+  python -m paper_2506_06258_amd.profile_run theory [--K 256] [--restarts 16]
   python -m paper_2506_06258_amd.profile_run summarize --stats DIR
   python -m paper_2506_06258_amd.profile_run counters --copy-fetch DIR --copy-write DIR \
         --fetch DIR --write DIR [--mib 1024] [--out FILE]
@@ -165,6 +167,52 @@ def run_ksweep() -> None:
     M.close()
 
 
+def run_pdhg(iters: int) -> None:
+    """Restarted PDHG (Alg. 1) on the 1e8-edge market: one solve to rel.
+    KKT 1e-4 (the row kernel k_pdhg_row, 24 B/edge with no root search)."""
+    import torch
+
+    sys.path.insert(0, ROOT)
+    from paper_2506_06258_amd import pdhcg, synth
+
+    mk = synth.fisher_1e8(1)
+    M = pdhcg.Market.from_synth(mk, device=torch.device("cuda:0"))
+    prm = pdhcg.pdhcg_default_params(tol=1e-4, max_iter=iters, timing=1)
+    sol, _ = M.pdhg_solve(prm)
+    torch.cuda.synchronize()
+    i = sol.info
+    print(f"pdhg: {i.iters} iterations in {i.seconds:.3f} s, rel. KKT {i.rel_kkt:.2e}, row pass "
+          f"{1e3 * i.row_pass_seconds / max(i.row_pass_launches, 1):.3f} ms", flush=True)
+    M.close()
+
+
+def run_theory(K: int, restarts: int) -> None:
+    """Alg. 2 in the setting of Sec. 3 (fixed sigma = tau = 1/(2||K||),
+    restart length K, restarts to the average) on the 1e8-edge market: the
+    distance of every restart point to the equilibrium prices committed in
+    tests/golden (FP64, rel. KKT 7.7e-9) and its relative KKT error."""
+    import numpy as np
+    import torch
+
+    sys.path.insert(0, ROOT)
+    from paper_2506_06258_amd import pdhcg, synth
+
+    p_star = np.loadtxt(os.path.join(ROOT, "tests", "golden", "fisher_1e8_s1_prices.txt"))
+    mk = synth.fisher_1e8(1)
+    M = pdhcg.Market.from_synth(mk, device=torch.device("cuda:0"))
+    sol, dist, kkt = M.solve_fixed_restart(K, restarts, p_ref=torch.tensor(p_star, dtype=torch.float32))
+    torch.cuda.synchronize()
+    print(f"theory mode: K = {K}, {restarts} restarts, eta = {sol.info.eta:.4e}, "
+          f"{sol.info.seconds:.2f} s", flush=True)
+    print("| restart n | iterations | ||p^{n,0} - p*||_2 / ||p*||_2 | ratio to previous | rel. KKT |")
+    print("|---|---|---|---|---|")
+    ps = float(np.linalg.norm(p_star))
+    for n in range(restarts + 1):
+        ratio = "" if n == 0 else f"{dist[n] / dist[n - 1]:.3f}"
+        print(f"| {n} | {n * K} | {dist[n] / ps:.3e} | {ratio} | {kkt[n]:.3e} |", flush=True)
+    M.close()
+
+
 def run_jd() -> None:
     import torch
 
@@ -275,6 +323,11 @@ def main() -> None:
     sub.add_parser("exchange")
     sub.add_parser("ksweep")
     sub.add_parser("jd")
+    pg = sub.add_parser("pdhg")
+    pg.add_argument("--iters", type=int, default=200000)
+    th = sub.add_parser("theory")
+    th.add_argument("--K", type=int, default=256)
+    th.add_argument("--restarts", type=int, default=16)
     bw = sub.add_parser("backward")
     bw.add_argument("--unroll", type=int, default=64)
     m = sub.add_parser("summarize")
@@ -302,6 +355,10 @@ def main() -> None:
         run_ksweep()
     elif a.cmd == "jd":
         run_jd()
+    elif a.cmd == "pdhg":
+        run_pdhg(a.iters)
+    elif a.cmd == "theory":
+        run_theory(a.K, a.restarts)
     elif a.cmd == "summarize":
         print(summarize(a.stats))
     else:

@@ -1,7 +1,8 @@
 """The reverse mode (pdhcg_backward) against the oracle's FP64 reverse mode
 through the same unrolled iteration (oracle.unrolled_grad: the same K
-fixed steps, tau = eta/omega, sigma = eta*omega with eta = 0.9/||K||, from
-the same start point), on every row-kernel shape the solver picks: the
+fixed steps, tau = eta/omega, sigma = eta*omega with eta = 0.9/||K_x||, K_x
+the column-sum operator on the support of the start point, from the same
+start point), on every row-kernel shape the solver picks: the
 short shapes with 2-byte good ids, 16 lanes x 7 entries (the 1e8-edge
 market's rows of 100), 64 x 8 (rows of up to 512), rows of more than 512
 entries (one wave per row), goods beyond LDS (relabelled market), and a
@@ -31,7 +32,10 @@ def _check(mk, cuda, K=64, expect=None, hot=None, monkeypatch=None):
     bins = M.bins()
     if expect is not None:
         assert any((g, e) == expect for g, e, _ in bins), bins
-    sol = M.solve(tol=1e-5, max_iter=200000)
+    # a tight start point: the unrolled map is piecewise smooth (entries
+    # cross zero), and from a loose start the trajectory moves enough for
+    # float32 and float64 iterates to take different pieces
+    sol = M.solve(tol=1e-7, max_iter=400000)
     assert sol.info.status == pdhcg.PDHCG_OK
     rng = np.random.default_rng(mk.nnz % 1000)
     g = rng.normal(size=mk.m)
@@ -40,9 +44,10 @@ def _check(mk, cuda, K=64, expect=None, hot=None, monkeypatch=None):
                         ckpt_every=16)
     du, dw = du.double().cpu().numpy(), dw.double().cpu().numpy()
     M.close()
-    deg = np.bincount(mk.col, minlength=mk.m)
-    eta = 0.9 / np.sqrt(deg.max())
     x0 = sol.x.double().cpu().numpy()
+    # pdhcg_backward's step: 0.9 / sqrt(largest number of buyers with x > 0)
+    act = np.bincount(mk.col[x0 > 0], minlength=mk.m)
+    eta = 0.9 / np.sqrt(max(act.max(), 1))
     p0 = sol.p.double().cpu().numpy()
     st, du_o, dw_o, _ = oracle.unrolled_grad(mk.n, mk.m, mk.row_ptr, mk.col, mk.u, mk.w, x0, p0,
                                              eta / omega, eta * omega, K, g)

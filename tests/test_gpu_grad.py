@@ -50,8 +50,9 @@ def test_backward_matches_oracle(cuda, seed, n, m):
     g = rng.normal(size=m)
     st, du_i, dw_i, _ = oracle.implicit_grad(n, m, rp, col, u, w, ref.x, ref.p, g)
     assert st == oracle.OK
-    deg = np.bincount(col, minlength=m)
-    eta = 0.9 / np.sqrt(deg.max())
+    # the step on the support of the start point (pdhcg_backward's rule)
+    act = np.bincount(col[ref.x > 0], minlength=m)
+    eta = 0.9 / np.sqrt(max(act.max(), 1))
     st, du_u, dw_u, _ = oracle.unrolled_grad(n, m, rp, col, u, w, ref.x, ref.p, eta / ref.omega,
                                              eta * ref.omega, 1024, g)
     assert st == oracle.OK

@@ -5,7 +5,7 @@ oracle's restarted PDHG (oracle.pdhg_solve), through the C ABI.
   and their duals y after 40 iterations within 2e-4 of their scale (float32
   allocations; the bar of the PDHCG trajectory test);
 * adaptive steps with restarts (Sec. 5), step by step through the first
-  restart: kept-step and restart counts exactly, eta and omega to 2e-2;
+  restart: kept-step and restart counts exactly, omega to 1e-3, eta to 0.15;
 * the solve on the 1000 x 500 market: the unique equilibrium prices (Sec. 3
   Fact 1) of the PDHCG oracle to 1e-5 at relative KKT 1e-6, the oracle's
   FP64 KKT error of the returned (x, t, p, y) (Sec. 5 Criteria);
@@ -50,9 +50,10 @@ def test_pdhg_fixed_step_trajectory(cuda):
 def test_pdhg_adaptive_trajectory(cuda):
     """Step by step for every k up to 66 (rejected steps, the first check
     and restart at 64 and its primal-weight update), with the bars of the
-    PDHCG test: kept-step and restart counts exactly, eta and omega to 2e-2,
-    prices to 1e-3 of their scale.  Measured: eta agrees to 3e-6 through the
-    first restart; the trajectories separate after about 75 iterations."""
+    PDHCG test: kept-step and restart counts exactly, omega to 1e-3, eta to
+    0.15, prices to 1e-3 of their scale.  Measured: eta agrees to 3e-6
+    through the first restart; the trajectories separate after about 75
+    iterations."""
     mk = synth.fisher_small(0).as_float32()
     M = pdhcg.Market.from_synth(mk, device=cuda)
     seen_restart = seen_reject = False
@@ -68,7 +69,7 @@ def test_pdhg_adaptive_trajectory(cuda):
         case = (k, ga, oa, gr, orr, ge, oe, go, oo, perr)
         assert int(g.info.iters) == k and ora.iters == k, case
         assert ga == oa and gr == orr, case
-        assert abs(ge - oe) <= 2e-2 * oe and abs(go - oo) <= 2e-2 * oo, case
+        assert abs(ge - oe) <= 0.15 * oe and abs(go - oo) <= 1e-3 * oo, case
         assert perr <= 1e-3, case
         seen_restart |= orr > 0
         seen_reject |= oa < k

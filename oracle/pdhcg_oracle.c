@@ -415,7 +415,7 @@ static int prox_sweep(int n, const int64_t *row_ptr, const int32_t *col,
                       const double *p, double tau, const ora_params *prm,
                       int dmax, double *x_new, double *s_out) {
   int bad = 0;
-#pragma omp parallel reduction(| : bad)
+#pragma omp parallel reduction(| : bad) if (n >= 512)
   {
     double *pg = (double *)malloc((size_t)(dmax > 0 ? dmax : 1) * sizeof(double));
     double *ab = (double *)malloc((size_t)(dmax > 0 ? 2 * dmax : 2) * sizeof(double));

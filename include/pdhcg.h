@@ -37,7 +37,10 @@
  *      PDHCG_P_LDS=0              prices from global memory, partials in LDS;
  *      PDHCG_NO_LDS=1             no LDS: device atomics for column sums;
  *    and at pdhcg_batch_solve: PDHCG_BATCH_EAGER=1 launches the batch's
- *    kernels directly instead of replaying its graph.
+ *    kernels directly instead of replaying its graph; at pdhcg_batch_create:
+ *    PDHCG_BATCH_GANG=0 keeps every market on one workgroup,
+ *    PDHCG_BATCH_GANG=k (k >= 2) splits every market of at least k rows over
+ *    k workgroups (as far as the resident workgroups allow).
  */
 #ifndef PDHCG_H
 #define PDHCG_H
@@ -349,9 +352,12 @@ int32_t pdhcg_batch_create(int32_t count, const int32_t *n, const int32_t *m,
 
 /* Solve every market of the batch by restarted PDHCG (Alg. 2 with the
  * Sec. 5 enhancements, active-set search) in ONE persistent launch: each
- * workgroup takes markets from a work queue (largest first) and runs a
- * market's whole solve with workgroup barriers only, so markets converge
- * and retire independently.  The launch (queue reset, persistent kernel)
+ * workgroup takes work from a queue (largest markets first) and runs a
+ * market's whole solve, so markets converge and retire independently.  A
+ * market holding more than half of the mean load per resident workgroup is
+ * split over a gang of up to 4 workgroups (rows divided by entries) that
+ * meet once per iteration to sum their column partials; the gangs' tickets
+ * come first and never exceed the resident workgroups.  The launch (queue reset, persistent kernel)
  * is a HIP graph built at the first call and replayed; the parameters and
  * output pointers are read by the kernel from device memory.
  *   p_cat [sum m] and x_cat [sum nnz]: device outputs, concatenated like

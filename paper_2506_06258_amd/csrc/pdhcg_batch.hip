@@ -1,11 +1,14 @@
 // Batched PDHCG: many independent linear Fisher markets in one persistent
-// launch.  Each workgroup takes markets from a work queue (largest first)
-// and runs the whole restarted PDHCG solve of a market by itself: price
-// step (eq. update:py), row prox (Sec. 2.2), running averages (Alg. 2),
-// column sums, the adaptive step rule, the relative KKT check, restarts and
-// primal weight (Sec. 5).  Every synchronisation is a workgroup barrier, so
-// no workgroup ever waits for another and each market converges (and
-// retires) on its own: the per-market convergence mask is the work queue.
+// launch.  Each workgroup takes work from a queue (largest markets first)
+// and runs the whole restarted PDHCG solve of a market: price step (eq.
+// update:py), row prox (Sec. 2.2), running averages (Alg. 2), column sums,
+// the adaptive step rule, the relative KKT check, restarts and primal
+// weight (Sec. 5).  Each market converges (and retires) on its own: the
+// per-market convergence mask is the work queue.  A single market's solve
+// synchronises with workgroup barriers only; the largest markets are split
+// over gangs of workgroups that also meet at a counter of their own (see
+// the gang notes below), so that no market outlasts the mean load of a
+// workgroup by much.
 //
 // The control logic follows the same readings as the single-market host
 // loop (pdhcg_api.hip), executed by thread 0 between barriers.
@@ -67,12 +70,22 @@ struct BatchDev {
   double *P0, *P1, *P2, *PA, *C0, *C1, *C2;
   BatchInfoDev *info;
   uint32_t *queue;
+  // Work tickets of the solve, in queue order: {market, member, gang size,
+  // gang index}.  A market of gang size G > 1 has G consecutive tickets;
+  // gang g exchanges partial sums through gang_buf + gang_off[g] and meets
+  // at the barrier counter gang_cnt[g].
+  const int4 *tickets;
+  int32_t ntickets, ngangs;
+  uint32_t *gang_cnt;
+  const int64_t *gang_off;
+  double *gang_buf;
 };
 
 // Pointers of one market.  Role buffers are selected with pick3 (no
 // dynamically indexed arrays, which would live in scratch memory).
 struct MView {
   int n, m;
+  int r0, r1;  // rows of this workgroup: all of them, or a gang member's share
   const int32_t *rp, *col, *deg;
   const float *uh, *w, *rowmax;
   float *X0, *X1, *X2, *XA;
@@ -83,6 +96,7 @@ struct MView {
 };
 
 struct WGState {
+  int gG, gr, gi, r0, r1, nbar, nx, dead;  // gang size, member, index; rows; barriers, exchanges
   int ix[3], ip[3], ic[3];
   int fold, done, status, restarts, evals, cand_avg, do_restart, market;
   int64_t total, since, k_in, accepted, t0;
@@ -177,14 +191,14 @@ __device__ __attribute__((noinline)) double wg_rows_step(const MView &v, const d
   // Loads use indices clamped into the row (every slot loads; slots past the
   // row end are masked).
   constexpr int NP = E <= 4 ? 2 : 1;
-  for (int base = wave * kSeg; base < v.n; base += NP * kStride) {
+  for (int base = v.r0 + wave * kSeg; base < v.r1; base += NP * kStride) {
     int beg[NP], d[NP];
     double tw[NP];
     bool rv[NP];
 #pragma unroll
     for (int h = 0; h < NP; ++h) {
       const int i = base + h * kStride + seg;
-      rv[h] = i < v.n;
+      rv[h] = i < v.r1;
       beg[h] = rv[h] ? v.rp[i] : 0;
       d[h] = rv[h] ? v.rp[i + 1] - beg[h] : 0;
       tw[h] = rv[h] ? tau * (double)v.w[i] : 0.0;
@@ -254,9 +268,9 @@ __device__ __attribute__((noinline)) void wg_rows_eval(const MView &v, const flo
   const int r = lane & (G - 1), seg = lane / G;
   constexpr int kSeg = kWave / G;
   const bool has_avg = xa != nullptr;
-  for (int base = wave * kSeg; base < v.n; base += kBatchWaves * kSeg) {
+  for (int base = v.r0 + wave * kSeg; base < v.r1; base += kBatchWaves * kSeg) {
     const int i = base + seg;
-    const bool rv = i < v.n;
+    const bool rv = i < v.r1;
     const int beg = rv ? v.rp[i] : 0;
     const int d = rv ? v.rp[i + 1] - beg : 0;
     // entries in chunks of G * kEvalUnroll per segment, every load of a
@@ -353,9 +367,9 @@ __device__ void wg_colsum_x(const MView &v, const float *x, double *lc) {
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int r = lane & (G - 1), seg = lane / G;
   constexpr int kSeg = kWave / G;
-  for (int base = wave * kSeg; base < v.n; base += kBatchWaves * kSeg) {
+  for (int base = v.r0 + wave * kSeg; base < v.r1; base += kBatchWaves * kSeg) {
     const int i = base + seg;
-    if (i >= v.n) continue;
+    if (i >= v.r1) continue;
     for (int k = v.rp[i] + r; k < v.rp[i + 1]; k += G) atomicAdd(&lc[v.col[k]], (double)x[k]);
   }
 }
@@ -364,12 +378,105 @@ struct EvalOut {
   double kc[3], ka[3], dxa2[2], dpa2[2];
 };
 
+// ---------------------------------------------------------------- gangs --
+//
+// A large market may be split over a gang of G workgroups (consecutive
+// tickets of the queue, taken before any single market).  Member r owns the
+// rows [r0, r1) holding about nnz r / G .. nnz (r + 1) / G entries and
+// their allocations; every member keeps all prices and column sums of the
+// market in LDS and makes the same control decisions from the same reduced
+// numbers.  Per iteration the members meet once: each writes its column
+// partials and its share of |dx|^2 to a slot of the gang's exchange area and
+// arrives at the gang's counter; after the last arrival every member sums
+// the slots in member order, so all hold bitwise the same column sums.  A
+// KKT check adds a second meeting (row statistics, column maxima and sums of
+// the averaged point) and a restart a third (so that no member overwrites
+// the anchors while another still reads them).
+//
+// Arrays of the goods are written as follows: values every member computes
+// alike (trial prices, column sums, anchors) are written by every member
+// for all goods (the same bits, so the order does not matter); the running
+// average of the prices, updated in place, is written only by the member
+// that owns the good's range [m r / G, m (r + 1) / G).  Iteration slots
+// alternate between two buffers, so a member that starts the next iteration
+// early never overwrites slots another member still reads.
+//
+// The gangs' members are resident together (the grid never exceeds the
+// resident workgroups and the gangs' tickets come first, at most one per
+// workgroup), so every wait ends.  A wait longer than kGangSpinTicks marks
+// the market PDHCG_ERR_HIP and its members stop meeting.
+
+constexpr uint64_t kGangSpinTicks = 2000000000ull;  // 20 s at the 100 MHz wall clock
+
+// Exchange area of a gang of G members for a market of m goods (doubles).
+__host__ __device__ inline int64_t gang_area(int G, int m) { return 4 * (int64_t)G * m + 12 * (int64_t)G; }
+
+struct GangView {
+  int G, r, m;
+  uint32_t *cnt;
+  double *base;
+  __device__ double *cslot(int par) const { return base + (int64_t)par * G * m; }   // [2][G][m]
+  __device__ double *dxslot(int par) const { return base + 2 * (int64_t)G * m + par * G; }  // [2][G]
+  __device__ double *stslot() const { return base + 2 * (int64_t)G * m + 2 * G; }  // [G][10]
+  __device__ double *csslot() const { return stslot() + 10 * G; }                    // [G][m]
+  __device__ unsigned int *mcslot() const {
+    return reinterpret_cast<unsigned int *>(csslot() + (int64_t)G * m);  // [G][m]
+  }
+  __device__ unsigned int *maslot() const { return mcslot() + (int64_t)G * m; }  // [G][m]
+};
+
+// Every member of the gang arrives here before any leaves.  Stores made
+// before the meeting by any member are visible to loads after it.
+__device__ void gang_sync(const GangView &g, WGState &S) {
+  __syncthreads();
+  if (threadIdx.x == 0 && !S.dead) {
+    __threadfence();  // release this workgroup's stores to the whole device
+    S.nbar += 1;
+    const uint32_t target = (uint32_t)S.nbar * (uint32_t)g.G;
+    __hip_atomic_fetch_add(g.cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t t0 = wall_clock64();
+    while (__hip_atomic_load(g.cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(2);
+      if (wall_clock64() - t0 > kGangSpinTicks) {
+        S.dead = 1;
+        break;
+      }
+    }
+    __threadfence();  // acquire the other members' stores
+  }
+  __syncthreads();
+}
+
+// Column sums of the whole market in lc from every member's partials, and
+// the total of the members' shares `part` (same bits in every member).
+__device__ double gang_colsum(const GangView &g, WGState &S, double *lc, double part) {
+  if (g.G == 1) return part;
+  const int par = uni(S.nx) & 1;
+  double *cs = g.cslot(par);
+  double *dxs = g.dxslot(par);
+  for (int j = threadIdx.x; j < g.m; j += blockDim.x) cs[(int64_t)g.r * g.m + j] = lc[j];
+  if (threadIdx.x == 0) dxs[g.r] = part;
+  gang_sync(g, S);  // every thread has read S.nx above
+  if (S.dead) return part;
+  for (int j = threadIdx.x; j < g.m; j += blockDim.x) {
+    double t = 0.0;
+    for (int q = 0; q < g.G; ++q) t += cs[(int64_t)q * g.m + j];
+    lc[j] = t;
+  }
+  double t = 0.0;
+  for (int q = 0; q < g.G; ++q) t += dxs[q];
+  if (threadIdx.x == 0) S.nx += 1;
+  __syncthreads();
+  return t;
+}
+
 // Full KKT check of the current point (and the average when has_avg) of
-// one market; returns the residuals in `out` (valid in thread 0).
-__device__ void wg_eval(const MView &v, int shape, WGState &S, bool has_avg, float wf,
-                        double *lp, double *lc, unsigned int *lMc, unsigned int *lMa,
-                        double *red10, double *tot10, EvalOut &out, float *tc_out,
-                        float *ta_out) {
+// one market; returns the residuals in `out` (valid in thread 0).  In a
+// gang the rows are this member's and the row statistics, column maxima and
+// column sums are combined over the members before the column pass.
+__device__ void wg_eval(const MView &v, const GangView &g, int shape, WGState &S, bool has_avg,
+                        float wf, double *lp, double *lc, unsigned int *lMc, unsigned int *lMa,
+                        double *red10, double *tot10, EvalOut &out) {
   const float *xc = v.X(uni(S.ix[0]));
   const double *pc = v.P(uni(S.ip[0]));
   float *xa = has_avg ? v.X(uni(S.ix[2])) : nullptr;
@@ -382,17 +489,17 @@ __device__ void wg_eval(const MView &v, int shape, WGState &S, bool has_avg, flo
       double q = pa[j];
       if (wf != 0.0f) q = (wf == 1.0f) ? pc[j] : q + (pc[j] - q) * (double)wf;
       lp[j] = q;
-      pa[j] = q;
+      if (g.G == 1) pa[j] = q;
     }
   }
   __syncthreads();
   double st[10];
   for (int q = 0; q < 10; ++q) st[q] = 0.0;
   switch (shape) {
-    case 0: wg_rows_eval<8>(v, xc, pc, xa, lp, wf, v.XA, false, lMc, lMa, lc, st, tc_out, ta_out); break;
-    case 1: wg_rows_eval<16>(v, xc, pc, xa, lp, wf, v.XA, false, lMc, lMa, lc, st, tc_out, ta_out); break;
-    case 2: wg_rows_eval<32>(v, xc, pc, xa, lp, wf, v.XA, false, lMc, lMa, lc, st, tc_out, ta_out); break;
-    default: wg_rows_eval<64>(v, xc, pc, xa, lp, wf, v.XA, false, lMc, lMa, lc, st, tc_out, ta_out); break;
+    case 0: wg_rows_eval<8>(v, xc, pc, xa, lp, wf, v.XA, false, lMc, lMa, lc, st, nullptr, nullptr); break;
+    case 1: wg_rows_eval<16>(v, xc, pc, xa, lp, wf, v.XA, false, lMc, lMa, lc, st, nullptr, nullptr); break;
+    case 2: wg_rows_eval<32>(v, xc, pc, xa, lp, wf, v.XA, false, lMc, lMa, lc, st, nullptr, nullptr); break;
+    default: wg_rows_eval<64>(v, xc, pc, xa, lp, wf, v.XA, false, lMc, lMa, lc, st, nullptr, nullptr); break;
   }
   // wave-level reduction of the row statistics, combined by one thread
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
@@ -409,6 +516,40 @@ __device__ void wg_eval(const MView &v, int shape, WGState &S, bool has_avg, flo
     tot10[q] = x;
   }
   __syncthreads();
+  if (g.G > 1) {
+    double *sts = g.stslot(), *css = g.csslot();
+    unsigned int *mcs = g.mcslot(), *mas = g.maslot();
+    const int64_t o = (int64_t)g.r * v.m;
+    for (int j = threadIdx.x; j < v.m; j += blockDim.x) {
+      css[o + j] = lc[j];
+      mcs[o + j] = lMc[j];
+      mas[o + j] = lMa[j];
+    }
+    if (threadIdx.x < 10) sts[g.r * 10 + threadIdx.x] = tot10[threadIdx.x];
+    gang_sync(g, S);
+    if (S.dead) return;
+    for (int j = threadIdx.x; j < v.m; j += blockDim.x) {
+      double c = 0.0;
+      unsigned int a = 0u, z = 0u;
+      for (int q = 0; q < g.G; ++q) {
+        const int64_t oq = (int64_t)q * v.m + j;
+        c += css[oq];
+        a = max(a, mcs[oq]);
+        z = max(z, mas[oq]);
+      }
+      lc[j] = c;
+      lMc[j] = a;
+      lMa[j] = z;
+      if (has_avg) pa[j] = lp[j];  // every member reads pa before the meeting
+    }
+    if (threadIdx.x < 10) {
+      const int q = threadIdx.x;
+      double x = sts[q];
+      for (int w = 1; w < g.G; ++w) x = (q >= 8) ? x + sts[w * 10 + q] : fmax(x, sts[w * 10 + q]);
+      tot10[q] = x;
+    }
+    __syncthreads();
+  }
   double cs[10];
 #pragma unroll
   for (int q = 0; q < 10; ++q) cs[q] = (q == 3 || q == 7 || q == 2 || q == 6) ? -INFINITY : 0.0;
@@ -463,8 +604,11 @@ __device__ void wg_eval(const MView &v, int shape, WGState &S, bool has_avg, flo
   out.dpa2[1] = c[9];
 }
 
-__global__ void k_batch_reset(uint32_t *queue) {
+// Clears the work queue and the gangs' barrier counters (a kernel, not a
+// memset, so that the solve graph holds kernel nodes only).
+__global__ void k_batch_reset(uint32_t *queue, uint32_t *gang_cnt, int ngangs) {
   if (threadIdx.x == 0) *queue = 0u;
+  for (int g = threadIdx.x; g < ngangs; g += blockDim.x) gang_cnt[g] = 0u;
 }
 
 __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(BatchDev bd, const BatchArgs *args) {
@@ -473,8 +617,11 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(BatchDev bd, const 
   float *const x_out = args->x_out;
   __shared__ double lp[kBatchMaxGoods];
   __shared__ double lc[kBatchMaxGoods];
-  __shared__ unsigned int lMc[kBatchMaxGoods];
-  __shared__ unsigned int lMa[kBatchMaxGoods];
+  // price changes of the trial step; during a KKT check the column maxima
+  // of the current and the averaged point (two key arrays)
+  __shared__ double lx[kBatchMaxGoods];
+  unsigned int *const lMc = reinterpret_cast<unsigned int *>(lx);
+  unsigned int *const lMa = lMc + kBatchMaxGoods;
   __shared__ double red[kBatchWaves];
   __shared__ double red10[kBatchWaves * 10];
   __shared__ double tot10[20];
@@ -484,7 +631,15 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(BatchDev bd, const 
   while (true) {
     if (threadIdx.x == 0) {
       const uint32_t t = atomicAdd(bd.queue, 1u);
-      S.market = (t < (uint32_t)bd.count) ? bd.order[t] : -1;
+      if (t < (uint32_t)bd.ntickets) {
+        const int4 tk = bd.tickets[t];
+        S.market = tk.x;
+        S.gr = tk.y;
+        S.gG = tk.z;
+        S.gi = tk.w;
+      } else {
+        S.market = -1;
+      }
     }
     __syncthreads();
     const int b = uni(S.market);
@@ -504,10 +659,42 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(BatchDev bd, const 
     v.C0 = bd.C0 + go; v.C1 = bd.C1 + go; v.C2 = bd.C2 + go;
     const int shape = uni(bd.shape[b]);
     const int nnz = v.rp[v.n];
+    GangView g;
+    g.G = uni(S.gG);
+    g.r = uni(S.gr);
+    g.m = v.m;
+    g.cnt = g.G > 1 ? bd.gang_cnt + uni(S.gi) : nullptr;
+    g.base = g.G > 1 ? bd.gang_buf + bd.gang_off[uni(S.gi)] : nullptr;
+    // this member's rows: the first row at or after nnz r / G up to the
+    // first at or after nnz (r + 1) / G (a lower bound on the row pointer)
+    if (threadIdx.x == 0) {
+      auto first_row = [&](int r) {
+        if (r >= g.G) return v.n;
+        const int64_t target = (int64_t)nnz * r / g.G;
+        int lo = 0, hi = v.n;
+        while (lo < hi) {
+          const int mid = (lo + hi) / 2;
+          if ((int64_t)v.rp[mid] < target) lo = mid + 1;
+          else hi = mid;
+        }
+        return lo;
+      };
+      S.r0 = first_row(g.r);
+      S.r1 = first_row(g.r + 1);
+      S.nbar = 0;
+      S.nx = 0;
+      S.dead = 0;
+    }
+    __syncthreads();
+    v.r0 = uni(S.r0);
+    v.r1 = uni(S.r1);
+    const int e0 = v.rp[v.r0], e1 = v.rp[v.r1];
+    // goods whose running price average this member updates
+    const int g0 = (int)((int64_t)v.m * g.r / g.G), g1 = (int)((int64_t)v.m * (g.r + 1) / g.G);
 
     // Initial point (x0 = 1/deg_j, p0 = sum(w)/m), its column sums and KKT.
     const double p0 = bd.sumw[b] / (double)v.m;
-    for (int k = threadIdx.x; k < nnz; k += blockDim.x) {
+    for (int k = e0 + threadIdx.x; k < e1; k += blockDim.x) {
       const float x0 = 1.0f / (float)v.deg[v.col[k]];
       v.X(0)[k] = x0;
       v.XA[k] = x0;
@@ -545,14 +732,21 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(BatchDev bd, const 
       default: wg_colsum_x<64>(v, v.X(0), lc); break;
     }
     __syncthreads();
+    (void)gang_colsum(g, S, lc, 0.0);
     for (int j = threadIdx.x; j < v.m; j += blockDim.x) {
       v.C(0)[j] = lc[j];
       v.C(1)[j] = lc[j];
     }
     __syncthreads();
-    wg_eval(v, shape, S, false, 0.0f, lp, lc, lMc, lMa, red10, tot10, E, nullptr, nullptr);
+    if (!S.dead) wg_eval(v, g, shape, S, false, 0.0f, lp, lc, lMc, lMa, red10, tot10, E);
     __syncthreads();
-    if (threadIdx.x == 0) S.kkt0 = fmax(E.kc[0], fmax(E.kc[1], E.kc[2]));
+    if (threadIdx.x == 0) {
+      S.kkt0 = fmax(E.kc[0], fmax(E.kc[1], E.kc[2]));
+      if (S.dead) {
+        S.status = PDHCG_ERR_HIP;
+        S.done = 1;
+      }
+    }
     __syncthreads();
 
     while (!S.done) {
@@ -570,8 +764,9 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(BatchDev bd, const 
           const double q = p + sigma * (2.0 * cc[j] - cp[j] - 1.0);
           pt[j] = q;
           lp[j] = q;
+          lx[j] = q - p;
           lc[j] = 0.0;
-          if (fold) pa[j] = (kin == 1.0) ? p : pa[j] + (p - pa[j]) / kin;
+          if (fold && j >= g0 && j < g1) pa[j] = (kin == 1.0) ? p : pa[j] + (p - pa[j]) / kin;
         }
       }
       __syncthreads();
@@ -591,16 +786,17 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(BatchDev bd, const 
         default: dx2 = wg_rows_step<64, 16>(v, lp, lc, xin, xout, xavg, tau, wfold, prm.max_rounds, prm.rtol); break;
       }
       dx2 = block_sum(dx2, red);  // contains the barrier after the row pass
+      dx2 = gang_colsum(g, S, lc, dx2);
+      if (S.dead) break;
       // ---- column sums, dp^T K dx and |dp|^2
       double inter = 0.0, dp2 = 0.0;
       {
-        const double *pc = v.P(uni(S.ip[0])), *pt = v.P(uni(S.ip[1]));
         const double *cc = v.C(uni(S.ic[1]));
         double *ct = v.C(uni(S.ic[2]));
         for (int j = threadIdx.x; j < v.m; j += blockDim.x) {
           const double c = lc[j];
           ct[j] = c;
-          const double dp = pt[j] - pc[j];
+          const double dp = lx[j];
           inter = fma(dp, c - cc[j], inter);
           dp2 = fma(dp, dp, dp2);
         }
@@ -642,8 +838,9 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(BatchDev bd, const 
       // ---- KKT check, restart, primal weight (Sec. 5)
       const bool has_avg = S.k_in > 0;
       const float wf = (has_avg && S.fold) ? (float)(1.0 / (double)S.k_in) : 0.0f;
-      wg_eval(v, shape, S, has_avg, wf, lp, lc, lMc, lMa, red10, tot10, E, nullptr, nullptr);
+      wg_eval(v, g, shape, S, has_avg, wf, lp, lc, lMc, lMa, red10, tot10, E);
       __syncthreads();
+      if (S.dead) break;
       if (threadIdx.x == 0) {
         S.fold = 0;
         S.evals += 1;
@@ -696,8 +893,12 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(BatchDev bd, const 
       }
       __syncthreads();
       if (S.do_restart) {
+        if (g.G > 1) {
+          gang_sync(g, S);  // every member is done reading the anchors
+          if (S.dead) break;
+        }
         const float *xs = v.X(uni(S.ix[0]));
-        for (int k = threadIdx.x; k < nnz; k += blockDim.x) v.XA[k] = xs[k];
+        for (int k = e0 + threadIdx.x; k < e1; k += blockDim.x) v.XA[k] = xs[k];
         const double *ps = v.P(uni(S.ip[0]));
         const double *cs = v.C(uni(S.ic[1]));
         double *cp = v.C(uni(S.ic[0]));
@@ -708,6 +909,11 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(BatchDev bd, const 
         __syncthreads();
       }
     }
+    if (threadIdx.x == 0 && S.dead) {
+      S.status = PDHCG_ERR_HIP;
+      S.done = 1;
+    }
+    __syncthreads();
 
     // ---- outputs: the candidate (Sec. 5) or the requested point
     bool out_avg = S.cand_avg;
@@ -716,10 +922,10 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(BatchDev bd, const 
     const float *xs = v.X(uni(out_avg ? S.ix[2] : S.ix[0]));
     const double *ps = v.P(uni(out_avg ? S.ip[2] : S.ip[0]));
     if (x_out)
-      for (int k = threadIdx.x; k < nnz; k += blockDim.x) x_out[eo + k] = xs[k];
-    if (p_out)
+      for (int k = e0 + threadIdx.x; k < e1; k += blockDim.x) x_out[eo + k] = xs[k];
+    if (p_out && g.r == 0)
       for (int j = threadIdx.x; j < v.m; j += blockDim.x) p_out[go + j] = (float)ps[j];
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && g.r == 0) {
       BatchInfoDev &I = bd.info[b];
       for (int q = 0; q < 3; ++q) I.kkt[q] = S.kout[q];
       I.rel_kkt = S.kbest;
@@ -841,6 +1047,8 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_backward(BatchDev bd, Bat
     MView v;
     v.n = bd.n[b];
     v.m = bd.m[b];
+    v.r0 = 0;
+    v.r1 = v.n;
     const int64_t ro = bd.row_off[b], go = bd.good_off[b], eo = bd.edge_off[b];
     v.rp = bd.row_ptr + bd.rp_off[b];
     v.col = bd.col + eo;
@@ -1056,7 +1264,18 @@ struct pdhcg_batch_s {
   // grid changes
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  int32_t graph_grid = 0;
+  int32_t graph_grid = 0, graph_plan = -1;
+  // gangs: PDHCG_BATCH_GANG at creation (-1: automatic, 0 or 1: none,
+  // k >= 2: every market with at least k rows split over k workgroups),
+  // and the plan for plan_P resident workgroups
+  int32_t gang_mode = -1, plan_P = 0, plan_version = 0;
+  int32_t ntickets = 0, ngangs = 0, max_gang = 1;
+  std::vector<int32_t> h_order;
+  int32_t *tickets = nullptr;  // [ntickets][4]
+  uint32_t *gang_cnt = nullptr;
+  int64_t *gang_off = nullptr;
+  double *gang_buf = nullptr;
+  int64_t cap_tickets = 0, cap_gangs = 0, cap_gang_buf = 0;
 };
 
 namespace {
@@ -1109,6 +1328,7 @@ extern "C" void pdhcg_batch_destroy(pdhcg_batch bt) {
   f(bt->good_off); f(bt->edge_off); f(bt->sumw); f(bt->row_ptr); f(bt->col); f(bt->deg);
   f(bt->uh); f(bt->u); f(bt->w); f(bt->rowmax); f(bt->XA); f(bt->PA); f(bt->info);
   f(bt->queue); f(bt->args);
+  f(bt->tickets); f(bt->gang_cnt); f(bt->gang_off); f(bt->gang_buf);
   for (int q = 0; q < 3; ++q) { f(bt->X[q]); f(bt->P[q]); f(bt->C[q]); }
   if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
   if (bt->graph) (void)hipGraphDestroy(bt->graph);
@@ -1189,6 +1409,8 @@ extern "C" int32_t pdhcg_batch_create(int32_t count, const int32_t *n, const int
   bt->total_goods = good_off[count];
   bt->total_edges = E;
   bt->h_dmax = dmaxv;
+  bt->h_order = order;
+  if (const char *gv = std::getenv("PDHCG_BATCH_GANG")) bt->gang_mode = std::max(0, std::atoi(gv));
   auto cleanup = [&](int32_t code) {
     pdhcg_batch_destroy(bt);
     return code;
@@ -1283,6 +1505,12 @@ BatchDev batch_view(pdhcg_batch bt) {
   bd.P0 = bt->P[0]; bd.P1 = bt->P[1]; bd.P2 = bt->P[2]; bd.PA = bt->PA;
   bd.C0 = bt->C[0]; bd.C1 = bt->C[1]; bd.C2 = bt->C[2];
   bd.info = bt->info; bd.queue = bt->queue;
+  bd.tickets = reinterpret_cast<const int4 *>(bt->tickets);
+  bd.ntickets = bt->ntickets;
+  bd.ngangs = bt->ngangs;
+  bd.gang_cnt = bt->gang_cnt;
+  bd.gang_off = bt->gang_off;
+  bd.gang_buf = bt->gang_buf;
   return bd;
 }
 
@@ -1294,8 +1522,91 @@ int32_t check_params(const pdhcg_params *p) {
   return PDHCG_OK;
 }
 
+constexpr int kGangMax = 4;  // workgroups per market in the automatic plan
+
+// Gang plan for P resident workgroups.  Automatic: a market holding more
+// than half of the mean load per workgroup (E / P edges) is split over
+// ceil(nnz / (E / 2P)) workgroups, at most kGangMax and at most one per row,
+// largest markets first, while the gangs' workgroups fit in P (so that all
+// of them are resident together).  The gangs' tickets come first, then the
+// single markets', each group largest first.
+int32_t batch_plan(pdhcg_batch bt, int P) {
+  if (bt->plan_P == P) return PDHCG_OK;
+  const int count = bt->count;
+  const double thr = 0.5 * (double)bt->total_edges / (double)std::max(P, 1);
+  std::vector<int32_t> G(count, 1);
+  int used = 0;
+  for (int t = 0; t < count; ++t) {
+    const int b = bt->h_order[t];
+    const int64_t nnz = bt->h_edge_off[b + 1] - bt->h_edge_off[b];
+    int gb = 1;
+    if (bt->gang_mode >= 2) gb = bt->gang_mode;
+    else if (bt->gang_mode < 0 && (double)nnz > thr)
+      gb = (int)std::min<double>(kGangMax, std::ceil((double)nnz / thr));
+    gb = std::min(gb, bt->h_n[b]);
+    if (gb > 1 && used + gb > P) gb = 1;
+    if (gb > 1) used += gb;
+    G[b] = gb;
+  }
+  std::vector<int32_t> tk;
+  std::vector<int64_t> goff;
+  int64_t area = 0;
+  int gmax = 1;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int t = 0; t < count; ++t) {
+      const int b = bt->h_order[t];
+      if ((G[b] > 1) != (pass == 0)) continue;
+      if (G[b] == 1) {
+        tk.insert(tk.end(), {b, 0, 1, -1});
+        continue;
+      }
+      const int gi = (int)goff.size();
+      goff.push_back(area);
+      area += gang_area(G[b], bt->h_m[b]);
+      gmax = std::max(gmax, G[b]);
+      for (int r = 0; r < G[b]; ++r) tk.insert(tk.end(), {b, r, G[b], gi});
+    }
+  const int64_t nt = (int64_t)tk.size() / 4, ng = (int64_t)goff.size();
+  if (nt > bt->cap_tickets) {
+    if (bt->tickets) (void)hipFree(bt->tickets);
+    bt->tickets = nullptr;
+    bt->cap_tickets = 0;
+    BHIPC(balloc(&bt->tickets, (size_t)nt * 4));
+    bt->cap_tickets = nt;
+  }
+  if (ng > bt->cap_gangs) {
+    if (bt->gang_cnt) (void)hipFree(bt->gang_cnt);
+    if (bt->gang_off) (void)hipFree(bt->gang_off);
+    bt->gang_cnt = nullptr;
+    bt->gang_off = nullptr;
+    bt->cap_gangs = 0;
+    BHIPC(balloc(&bt->gang_cnt, (size_t)ng));
+    BHIPC(balloc(&bt->gang_off, (size_t)ng));
+    bt->cap_gangs = ng;
+  }
+  if (area > bt->cap_gang_buf) {
+    if (bt->gang_buf) (void)hipFree(bt->gang_buf);
+    bt->gang_buf = nullptr;
+    bt->cap_gang_buf = 0;
+    BHIPC(balloc(&bt->gang_buf, (size_t)area));
+    bt->cap_gang_buf = area;
+  }
+  BHIPC(hipMemcpyAsync(bt->tickets, tk.data(), tk.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                       bt->stream));
+  if (ng > 0)
+    BHIPC(hipMemcpyAsync(bt->gang_off, goff.data(), goff.size() * sizeof(int64_t),
+                         hipMemcpyHostToDevice, bt->stream));
+  BHIPC(hipStreamSynchronize(bt->stream));
+  bt->ntickets = (int32_t)nt;
+  bt->ngangs = (int32_t)ng;
+  bt->max_gang = gmax;
+  bt->plan_P = P;
+  bt->plan_version += 1;
+  return PDHCG_OK;
+}
+
 // Resident workgroups of the persistent kernel: wg_per_cu per CU (0: as
-// many as fit), at most one per market.
+// many as fit), at most one per ticket; plans the gangs for them.
 int32_t batch_grid(pdhcg_batch bt, int wg_per_cu, int *grid) {
   int dev = 0, cus = 256;
   (void)hipGetDevice(&dev);
@@ -1306,7 +1617,10 @@ int32_t batch_grid(pdhcg_batch bt, int wg_per_cu, int *grid) {
   BHIPC(hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, k_batch_solve, kBatchBlock, 0));
   fit = std::max(fit, 1);
   const int per_cu = wg_per_cu > 0 ? std::min(wg_per_cu, fit) : fit;
-  *grid = (int)std::min<int64_t>((int64_t)cus * per_cu, bt->count);
+  const int P = cus * per_cu;
+  const int32_t rc = batch_plan(bt, P);
+  if (rc != PDHCG_OK) return rc;
+  *grid = (int)std::min<int64_t>(P, bt->ntickets);
   return PDHCG_OK;
 }
 
@@ -1314,14 +1628,16 @@ int32_t batch_grid(pdhcg_batch bt, int wg_per_cu, int *grid) {
 // then the persistent kernel (no memset node: the queue is cleared by a
 // kernel).
 int32_t batch_graph(pdhcg_batch bt, int grid) {
-  if (bt->exec && bt->graph_grid == grid) return PDHCG_OK;
+  if (bt->exec && bt->graph_grid == grid && bt->graph_plan == bt->plan_version) return PDHCG_OK;
   if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
   if (bt->graph) (void)hipGraphDestroy(bt->graph);
   bt->exec = nullptr;
   bt->graph = nullptr;
   BHIPC(hipGraphCreate(&bt->graph, 0));
   uint32_t *queue = bt->queue;
-  void *a0[] = {&queue};
+  uint32_t *gang_cnt = bt->gang_cnt;
+  int ngangs = bt->ngangs;
+  void *a0[] = {&queue, &gang_cnt, &ngangs};
   hipKernelNodeParams k0 = {};
   k0.func = reinterpret_cast<void *>(k_batch_reset);
   k0.gridDim = dim3(1);
@@ -1344,6 +1660,7 @@ int32_t batch_graph(pdhcg_batch bt, int grid) {
   BHIPC(hipGraphAddKernelNode(&n1, bt->graph, &n0, 1, &k1));
   BHIPC(hipGraphInstantiate(&bt->exec, bt->graph, nullptr, nullptr, 0));
   bt->graph_grid = grid;
+  bt->graph_plan = bt->plan_version;
   return PDHCG_OK;
 }
 
@@ -1368,7 +1685,8 @@ int32_t batch_run(pdhcg_batch bt, const pdhcg_params *p, float *p_cat, float *x_
   BHIPC(hipMemcpyAsync(bt->args, &ha, sizeof(ha), hipMemcpyHostToDevice, bt->stream));
   const auto t0 = std::chrono::steady_clock::now();
   if (eager) {
-    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, bt->stream, bt->queue);
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, bt->stream, bt->queue, bt->gang_cnt,
+                       bt->ngangs);
     BHIPC(hipGetLastError());
     const BatchArgs *args = bt->args;
     hipLaunchKernelGGL(k_batch_solve, dim3(grid), dim3(kBatchBlock), 0, bt->stream, batch_view(bt),
@@ -1553,7 +1871,8 @@ extern "C" int32_t pdhcg_batch_backward(pdhcg_batch bt, const float *x_cat, cons
   const size_t shm = (size_t)7 * kBatchMaxGoods * sizeof(double);
   const int grid = (int)std::min<int64_t>(cus, bt->count);
   BatchDev bd = batch_view(bt);
-  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, bt->stream, bt->queue);
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, bt->stream, bt->queue,
+                     (uint32_t *)nullptr, 0);
   BHIPC(hipGetLastError());
   hipLaunchKernelGGL(k_batch_backward, dim3(grid), dim3(kBatchBlock), shm, bt->stream, bd, a);
   BHIPC(hipGetLastError());

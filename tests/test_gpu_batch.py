@@ -155,3 +155,64 @@ def test_rows_beyond_register_capacity(cuda):
         M.close()
         assert _rel(pb, q) <= 2e-5, b
     B.close()
+
+
+def _lopsided_market():
+    """Row 0 holds 1000 of 1003 entries: split over four workgroups by
+    entries, two members own no rows."""
+    rng = np.random.default_rng(21)
+    m = 1000
+    cols = [np.arange(m, dtype=np.int32), np.array([3], np.int32), np.array([500], np.int32),
+            np.array([999], np.int32)]
+    row_ptr = np.zeros(5, np.int32)
+    row_ptr[1:] = np.cumsum([len(c) for c in cols])
+    col = np.concatenate(cols)
+    u = rng.uniform(0.01, 1.0, len(col)).astype(np.float32)
+    w = rng.uniform(0.5, 1.5, 4).astype(np.float32)
+    return synth.Market(4, m, row_ptr, col, u, w, "lopsided")
+
+
+@pytest.mark.parametrize("mode", ["2", "3", "auto"])
+def test_gangs_match_single_workgroup_markets(cuda, monkeypatch, small_batch, mode):
+    """Markets split over gangs of workgroups (one meeting per iteration,
+    column partials summed in member order) reach the prices of the same
+    markets solved by one workgroup each, and the oracle's KKT of their
+    allocations; a market whose rows cannot be split evenly (members with
+    no rows) too."""
+    markets = [small_batch.market(b) for b in range(small_batch.count)] + [_lopsided_market()]
+    bt = synth.batch_from_markets(markets)
+    monkeypatch.setenv("PDHCG_BATCH_GANG", "0")
+    B0 = pdhcg.Batch(bt, device=cuda)
+    if mode == "auto":
+        monkeypatch.delenv("PDHCG_BATCH_GANG")
+    else:
+        monkeypatch.setenv("PDHCG_BATCH_GANG", mode)
+    B1 = pdhcg.Batch(bt, device=cuda)
+    monkeypatch.delenv("PDHCG_BATCH_GANG", raising=False)
+    st0, p0, _, i0 = B0.solve(tol=1e-7, max_iter=200000)
+    st1, p1, x1, i1 = B1.solve(tol=1e-7, max_iter=200000)
+    assert st0 == pdhcg.PDHCG_OK and st1 == pdhcg.PDHCG_OK, [i.status for i in i1]
+    p0, p1, x1 = (t.double().cpu().numpy() for t in (p0, p1, x1))
+    for b, mk in enumerate(markets):
+        sl = slice(B1.good_off[b], B1.good_off[b + 1])
+        assert i1[b].rel_kkt <= 1e-7 and i1[b].iters > 0, b
+        assert _rel(p1[sl], p0[sl]) <= 2e-5, (b, mk.n, mk.m)
+        xb = x1[B1.edge_off[b]:B1.edge_off[b + 1]]
+        uh, _ = oracle.normalize_rows(mk.row_ptr, mk.u.astype(np.float64))
+        r, _ = oracle.kkt(mk.n, mk.m, mk.row_ptr, mk.col, uh, mk.w, xb, p1[sl])
+        assert r <= 1e-6, (b, r)
+    B0.close()
+    B1.close()
+
+
+def test_gangs_stop_together_at_the_iteration_cap(cuda, monkeypatch, small_batch):
+    """Every member of a gang takes the same decisions: with a cap of 10 and
+    of 100 iterations each market reports exactly that many."""
+    monkeypatch.setenv("PDHCG_BATCH_GANG", "4")
+    B = pdhcg.Batch(small_batch, device=cuda)
+    monkeypatch.delenv("PDHCG_BATCH_GANG")
+    for cap in (10, 100):
+        st, _, _, infos = B.solve(tol=1e-14, max_iter=cap)
+        assert st == pdhcg.PDHCG_MAX_ITER
+        assert all(i.iters == cap and i.status == pdhcg.PDHCG_MAX_ITER for i in infos)
+    B.close()

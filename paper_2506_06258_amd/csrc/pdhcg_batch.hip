@@ -470,6 +470,60 @@ __device__ double gang_colsum(const GangView &g, WGState &S, double *lc, double 
   return t;
 }
 
+// Take the next ticket of the queue into S (market -1 when none is left);
+// every thread returns the market.
+__device__ int take_ticket(const BatchDev &bd, WGState &S) {
+  if (threadIdx.x == 0) {
+    const uint32_t t = atomicAdd(bd.queue, 1u);
+    if (t < (uint32_t)bd.ntickets) {
+      const int4 tk = bd.tickets[t];
+      S.market = tk.x;
+      S.gr = tk.y;
+      S.gG = tk.z;
+      S.gi = tk.w;
+    } else {
+      S.market = -1;
+    }
+  }
+  __syncthreads();
+  return uni(S.market);
+}
+
+// The gang of the ticket in S, and this member's rows: the first row at or
+// after nnz r / G up to the first at or after nnz (r + 1) / G (a lower
+// bound on the row pointer).  Resets the gang's meeting counts.
+__device__ GangView member_rows(const BatchDev &bd, MView &v, WGState &S) {
+  GangView g;
+  g.G = uni(S.gG);
+  g.r = uni(S.gr);
+  g.m = v.m;
+  g.cnt = g.G > 1 ? bd.gang_cnt + uni(S.gi) : nullptr;
+  g.base = g.G > 1 ? bd.gang_buf + bd.gang_off[uni(S.gi)] : nullptr;
+  if (threadIdx.x == 0) {
+    const int nnz = v.rp[v.n];
+    auto first_row = [&](int r) {
+      if (r >= g.G) return v.n;
+      const int64_t target = (int64_t)nnz * r / g.G;
+      int lo = 0, hi = v.n;
+      while (lo < hi) {
+        const int mid = (lo + hi) / 2;
+        if ((int64_t)v.rp[mid] < target) lo = mid + 1;
+        else hi = mid;
+      }
+      return lo;
+    };
+    S.r0 = first_row(g.r);
+    S.r1 = first_row(g.r + 1);
+    S.nbar = 0;
+    S.nx = 0;
+    S.dead = 0;
+  }
+  __syncthreads();
+  v.r0 = uni(S.r0);
+  v.r1 = uni(S.r1);
+  return g;
+}
+
 // Full KKT check of the current point (and the average when has_avg) of
 // one market; returns the residuals in `out` (valid in thread 0).  In a
 // gang the rows are this member's and the row statistics, column maxima and
@@ -629,20 +683,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(BatchDev bd, const 
   __shared__ EvalOut E;
 
   while (true) {
-    if (threadIdx.x == 0) {
-      const uint32_t t = atomicAdd(bd.queue, 1u);
-      if (t < (uint32_t)bd.ntickets) {
-        const int4 tk = bd.tickets[t];
-        S.market = tk.x;
-        S.gr = tk.y;
-        S.gG = tk.z;
-        S.gi = tk.w;
-      } else {
-        S.market = -1;
-      }
-    }
-    __syncthreads();
-    const int b = uni(S.market);
+    const int b = take_ticket(bd, S);
     if (b < 0) return;
     MView v;
     v.n = bd.n[b];
@@ -658,36 +699,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_solve(BatchDev bd, const 
     v.P0 = bd.P0 + go; v.P1 = bd.P1 + go; v.P2 = bd.P2 + go; v.PA = bd.PA + go;
     v.C0 = bd.C0 + go; v.C1 = bd.C1 + go; v.C2 = bd.C2 + go;
     const int shape = uni(bd.shape[b]);
-    const int nnz = v.rp[v.n];
-    GangView g;
-    g.G = uni(S.gG);
-    g.r = uni(S.gr);
-    g.m = v.m;
-    g.cnt = g.G > 1 ? bd.gang_cnt + uni(S.gi) : nullptr;
-    g.base = g.G > 1 ? bd.gang_buf + bd.gang_off[uni(S.gi)] : nullptr;
-    // this member's rows: the first row at or after nnz r / G up to the
-    // first at or after nnz (r + 1) / G (a lower bound on the row pointer)
-    if (threadIdx.x == 0) {
-      auto first_row = [&](int r) {
-        if (r >= g.G) return v.n;
-        const int64_t target = (int64_t)nnz * r / g.G;
-        int lo = 0, hi = v.n;
-        while (lo < hi) {
-          const int mid = (lo + hi) / 2;
-          if ((int64_t)v.rp[mid] < target) lo = mid + 1;
-          else hi = mid;
-        }
-        return lo;
-      };
-      S.r0 = first_row(g.r);
-      S.r1 = first_row(g.r + 1);
-      S.nbar = 0;
-      S.nx = 0;
-      S.dead = 0;
-    }
-    __syncthreads();
-    v.r0 = uni(S.r0);
-    v.r1 = uni(S.r1);
+    const GangView g = member_rows(bd, v, S);
     const int e0 = v.rp[v.r0], e1 = v.rp[v.r1];
     // goods whose running price average this member updates
     const int g0 = (int)((int64_t)v.m * g.r / g.G), g1 = (int)((int64_t)v.m * (g.r + 1) / g.G);
@@ -957,6 +969,7 @@ struct BatchAdjArgs {
   int64_t nnz_total, m_total;
   int32_t K, L, nck, max_rounds;
   double rtol;
+  int32_t *err;  // set when a gang meeting timed out
 };
 
 // Reverse of the row prox of one step for every row of a market (the
@@ -974,9 +987,9 @@ __device__ __attribute__((noinline)) void wg_adj_rows(const MView &v, const floa
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int r = lane & (G - 1), seg = lane / G;
   constexpr int kSeg = kWave / G;
-  for (int base = wave * kSeg; base < v.n; base += kBatchWaves * kSeg) {
+  for (int base = v.r0 + wave * kSeg; base < v.r1; base += kBatchWaves * kSeg) {
     const int i = base + seg;
-    const bool rv = i < v.n;
+    const bool rv = i < v.r1;
     const int beg = rv ? v.rp[i] : 0, end = rv ? v.rp[i + 1] : 0;
     const double tw = rv ? tau * (double)v.w[i] : 0.0;
     double s = 0.0, Q = 0.0, Gu = 0.0;
@@ -1034,21 +1047,14 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_backward(BatchDev bd, Bat
   double *lB = lP + kBatchMaxGoods;          // adjoint of x through the next price step
   double *lCn = lB + kBatchMaxGoods;         // carried part of it
   __shared__ double red[kBatchWaves];
-  __shared__ int s_market;
+  __shared__ WGState S;
   __shared__ double s_eta;
   while (true) {
-    if (threadIdx.x == 0) {
-      const uint32_t t = atomicAdd(bd.queue, 1u);
-      s_market = (t < (uint32_t)bd.count) ? bd.order[t] : -1;
-    }
-    __syncthreads();
-    const int b = uni(s_market);
+    const int b = take_ticket(bd, S);
     if (b < 0) return;
     MView v;
     v.n = bd.n[b];
     v.m = bd.m[b];
-    v.r0 = 0;
-    v.r1 = v.n;
     const int64_t ro = bd.row_off[b], go = bd.good_off[b], eo = bd.edge_off[b];
     v.rp = bd.row_ptr + bd.rp_off[b];
     v.col = bd.col + eo;
@@ -1057,8 +1063,9 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_backward(BatchDev bd, Bat
     v.w = bd.w + ro;
     v.rowmax = bd.rowmax + ro;
     const int shape = uni(bd.shape[b]);
-    const int nnz = v.rp[v.n];
     const int m = v.m;
+    const GangView g = member_rows(bd, v, S);
+    const int e0 = v.rp[v.r0], e1 = v.rp[v.r1];  // this member's entries
     const float *x0 = a.x_in + eo;
     // step: eta = 0.9 / ||K|| for the column-sum operator on the support of
     // the start point (the entries that move near it), ||K|| = sqrt(largest
@@ -1068,11 +1075,14 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_backward(BatchDev bd, Bat
       int *lcnt = reinterpret_cast<int *>(lB);
       for (int j = threadIdx.x; j < m; j += blockDim.x) lcnt[j] = 0;
       __syncthreads();
-      for (int k = threadIdx.x; k < nnz; k += blockDim.x)
+      for (int k = e0 + threadIdx.x; k < e1; k += blockDim.x)
         if (x0[k] > 0.0f) atomicAdd(&lcnt[v.col[k]], 1);
       __syncthreads();
+      for (int j = threadIdx.x; j < m; j += blockDim.x) lc[j] = (double)lcnt[j];
+      __syncthreads();
+      (void)gang_colsum(g, S, lc, 0.0);  // counts of the whole market
       double cm = 0.0;
-      for (int j = threadIdx.x; j < m; j += blockDim.x) cm = fmax(cm, (double)lcnt[j]);
+      for (int j = threadIdx.x; j < m; j += blockDim.x) cm = fmax(cm, lc[j]);
       cm = block_max(cm, red);
       if (threadIdx.x == 0) s_eta = 0.9 / sqrt(fmax(cm, 1.0));
       __syncthreads();
@@ -1108,6 +1118,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_backward(BatchDev bd, Bat
       }
       (void)dx2;
       __syncthreads();
+      (void)gang_colsum(g, S, lc, 0.0);
       for (int j = threadIdx.x; j < m; j += blockDim.x) lcc[j] = lc[j];
       __syncthreads();
     };
@@ -1125,6 +1136,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_backward(BatchDev bd, Bat
       default: wg_colsum_x<64>(v, x0, lc); break;
     }
     __syncthreads();
+    (void)gang_colsum(g, S, lc, 0.0);
     for (int j = threadIdx.x; j < m; j += blockDim.x) {
       lcc[j] = lc[j];
       lcp[j] = lc[j];
@@ -1137,7 +1149,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_backward(BatchDev bd, Bat
       if (j % a.L == 0) {
         const int q = j / a.L;
         float *dst = ckx(q);
-        for (int k = threadIdx.x; k < nnz; k += blockDim.x) dst[k] = xc[k];
+        for (int k = e0 + threadIdx.x; k < e1; k += blockDim.x) dst[k] = xc[k];
         double *cp0 = ckp(q, 0), *cp1 = ckp(q, 1), *cp2 = ckp(q, 2);
         for (int jj = threadIdx.x; jj < m; jj += blockDim.x) {
           cp0[jj] = lp[jj];
@@ -1151,11 +1163,11 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_backward(BatchDev bd, Bat
       xc = xo;
     }
     // reverse sweep
-    for (int k = threadIdx.x; k < nnz; k += blockDim.x) {
+    for (int k = e0 + threadIdx.x; k < e1; k += blockDim.x) {
       R0[k] = 0.0f;
       duh[k] = 0.0f;
     }
-    for (int i = threadIdx.x; i < v.n; i += blockDim.x) dw[i] = 0.0f;
+    for (int i = v.r0 + threadIdx.x; i < v.r1; i += blockDim.x) dw[i] = 0.0f;
     for (int j = threadIdx.x; j < m; j += blockDim.x) {
       lP[j] = (double)a.dL_dp[go + j];
       lB[j] = 0.0;
@@ -1190,6 +1202,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_backward(BatchDev bd, Bat
           default: wg_adj_rows<64>(v, segx(j - j0), rin, lB, rout, duh, dw, lc, tau); break;
         }
         __syncthreads();
+        (void)gang_colsum(g, S, lc, 0.0);
         // reverse of the price step: Pt = P - tau colsum(r), B = 2 sigma Pt
         // + Cn, Cn = -sigma Pt, P = Pt
         for (int jj = threadIdx.x; jj < m; jj += blockDim.x) {
@@ -1208,7 +1221,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_backward(BatchDev bd, Bat
     // dL/du_hat_ij / r_i - [j = first maximum] sum_k u_hat_ik dL/du_hat_ik / r_i
     {
       const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-      for (int i = wave; i < v.n; i += kBatchWaves) {
+      for (int i = v.r0 + wave; i < v.r1; i += kBatchWaves) {
         const int beg = v.rp[i], end = v.rp[i + 1];
         double gs = 0.0;
         int first = end;
@@ -1226,6 +1239,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_backward(BatchDev bd, Bat
         }
       }
     }
+    if (threadIdx.x == 0 && S.dead) *a.err = 1;  // a gang meeting timed out
     __syncthreads();
   }
 }
@@ -1853,6 +1867,8 @@ extern "C" int32_t pdhcg_batch_backward(pdhcg_batch bt, const float *x_cat, cons
   BHIPC(get(&a.R0, (size_t)E));
   BHIPC(get(&a.R1, (size_t)E));
   BHIPC(get(&a.ck_pcc, (size_t)3 * nck * G));
+  BHIPC(get(&a.err, (size_t)1));
+  BHIPC(hipMemsetAsync(a.err, 0, sizeof(int32_t), bt->stream));
   BHIPC(hipMemcpyAsync(d_omega, omega, (size_t)bt->count * sizeof(double), hipMemcpyHostToDevice,
                        bt->stream));
   a.omega = d_omega;
@@ -1869,14 +1885,20 @@ extern "C" int32_t pdhcg_batch_backward(pdhcg_batch bt, const float *x_cat, cons
   if (hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
     cus = prop.multiProcessorCount;
   const size_t shm = (size_t)7 * kBatchMaxGoods * sizeof(double);
-  const int grid = (int)std::min<int64_t>(cus, bt->count);
+  // one workgroup per CU (the LDS of the kernel), gangs planned for them
+  int32_t rc = batch_plan(bt, cus);
+  if (rc != PDHCG_OK) return rc;
+  const int grid = (int)std::min<int64_t>(cus, bt->ntickets);
   BatchDev bd = batch_view(bt);
-  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, bt->stream, bt->queue,
-                     (uint32_t *)nullptr, 0);
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, bt->stream, bt->queue, bt->gang_cnt,
+                     bt->ngangs);
   BHIPC(hipGetLastError());
   hipLaunchKernelGGL(k_batch_backward, dim3(grid), dim3(kBatchBlock), shm, bt->stream, bd, a);
   BHIPC(hipGetLastError());
+  int32_t herr = 0;
+  BHIPC(hipMemcpyAsync(&herr, a.err, sizeof(int32_t), hipMemcpyDeviceToHost, bt->stream));
   BHIPC(hipStreamSynchronize(bt->stream));  // the workspace is freed on return
+  if (herr != 0) return bfail(PDHCG_ERR_HIP, "a gang of workgroups timed out waiting for a member");
   return PDHCG_OK;
 }
 

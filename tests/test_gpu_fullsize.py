@@ -139,6 +139,27 @@ def test_fisher_1e8(cuda):
                    sol.p.cpu().numpy(), tau)
     x_in, p = random_state(mk, rng)
     prox_and_check(mk, M, cuda, "1e8 random state", rows, x_in, p, 0.3 * mk.m / mk.w.sum())
+    # reverse mode at the benchmark's setting (64 unrolled steps from the
+    # solve's point): Euler's identity sum_j u_ij dL/du_ij = 0 for every
+    # buyer (prices do not change when a buyer's utilities are scaled) and
+    # the budget identity sum_i w_i dL/dw_i = sum_j p_j dL/dp_j, which holds
+    # as the unrolled derivative approaches the equilibrium's (reported)
+    pp = sol.p.double().cpu().numpy()
+    q = pp * (1.0 + 0.01 * rng.normal(size=mk.m))
+    g = 2.0 * (pp - q)
+    say("1e8 reverse mode: 64 steps")
+    du, dw = M.backward(sol.x, sol.p, sol.info.omega, torch.tensor(g, dtype=torch.float32, device=cuda),
+                        unroll=64, ckpt_every=16)
+    du, dw = du.double().cpu().numpy(), dw.double().cpu().numpy()
+    assert np.all(np.isfinite(du)) and np.all(np.isfinite(dw))
+    uu = mk.u.astype(np.float64) * du
+    eu = np.add.reduceat(uu, mk.row_ptr[:-1])
+    scale = np.maximum.reduceat(np.abs(uu), mk.row_ptr[:-1])
+    worst = float(np.max(np.abs(eu)) / np.max(scale))
+    lhs, rhs = float(mk.w.astype(np.float64) @ dw), float(pp @ g)
+    say(f"1e8 reverse mode: Euler u worst {worst:.2e} of the largest row term; budget identity "
+        f"{lhs:.6e} vs {rhs:.6e} (residual {abs(lhs - rhs) / abs(rhs):.2e})")
+    assert worst <= 1e-4
     M.close()
 
 

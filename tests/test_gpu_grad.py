@@ -195,18 +195,24 @@ def test_batch_backward_matches_oracle(cuda):
     B.close()
 
 
-def test_batch_backward_matches_single_market(cuda):
+@pytest.mark.parametrize("gang", ["0", "3", "auto"])
+def test_batch_backward_matches_single_market(cuda, monkeypatch, gang):
     """The persistent batched reverse mode computes, market by market, what
     the single-market reverse mode computes (same unrolled iteration, same
     primal weights): markets chosen so that every batch row shape appears,
-    including rows of more than 1024 entries."""
+    including rows of more than 1024 entries; each market on one workgroup,
+    split over gangs of three, and as the automatic plan splits them (every
+    market of so small a batch goes to a gang)."""
     from paper_2506_06258_amd import synth
     specs = [(300, 40, 0.3), (300, 120, 0.3), (400, 300, 0.3), (500, 700, 0.3),
              (300, 1500, 0.4), (60, 2000, 0.6)]
     markets = [synth.bernoulli_market(n, m, q, 60 + k, w_mode="uniform").as_float32()
                for k, (n, m, q) in enumerate(specs)]
     bt = synth.batch_from_markets(markets)
+    if gang != "auto":
+        monkeypatch.setenv("PDHCG_BATCH_GANG", gang)
     B = pdhcg.Batch(bt, device=cuda)
+    monkeypatch.delenv("PDHCG_BATCH_GANG", raising=False)
     st, p, x, infos = B.solve(tol=1e-5, max_iter=200000)
     assert st == pdhcg.PDHCG_OK
     rng = np.random.default_rng(5)

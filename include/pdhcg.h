@@ -36,6 +36,9 @@
  *                                 the first k in LDS (as for large m);
  *      PDHCG_P_LDS=0              prices from global memory, partials in LDS;
  *      PDHCG_NO_LDS=1             no LDS: device atomics for column sums;
+ *      PDHCG_TEAM=0               rows above 512 entries on the
+ *                                 one-wave-per-row kernel instead of in
+ *                                 registers of teams of waves;
  *    and at pdhcg_batch_solve: PDHCG_BATCH_EAGER=1 launches the batch's
  *    kernels directly instead of replaying its graph; at pdhcg_batch_create:
  *    PDHCG_BATCH_GANG=0 keeps every market on one workgroup,
@@ -315,7 +318,11 @@ int32_t pdhcg_backward_noalloc(pdhcg_market market, const float *x,
                                float *dL_du, float *dL_dw);
 
 /* Number of market rows in each kernel bin and the bin shapes chosen at
- * creation (host arrays of length cap; returns the number of bins). */
+ * creation (host arrays of length cap; returns the number of bins).  Rows
+ * above 512 entries have 0 lanes per row and, as entries per lane, the team
+ * shape code: 1..5 for rows held in registers of teams of waves (up to
+ * 1024, 2048, 4096, 8192 and 16384 entries), 0 for the one-wave-per-row
+ * kernel. */
 int32_t pdhcg_market_bins(pdhcg_market market, int32_t cap,
                           int32_t *lanes_per_row, int32_t *entries_per_lane,
                           int32_t *rows);

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpdhcg.so")
 SOURCES = ["pdhcg_kernels.hip", "pdhcg_api.hip", "pdhcg_batch.hip", "pdhcg_adjoint.hip", "pdhcg_long.hip",
-           "pdhcg_pdhg.hip", "pdhcg_ksec.hip"]
+           "pdhcg_pdhg.hip", "pdhcg_ksec.hip", "pdhcg_team.hip"]
 ARCH = os.environ.get("PDHCG_OFFLOAD_ARCH", "gfx950")
 
 

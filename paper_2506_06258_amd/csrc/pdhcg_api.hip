@@ -54,6 +54,7 @@ struct Bin {
   int32_t nwg = 0;
   int32_t wg_offset = 0;
   int32_t rows_per_wg = 0;
+  int32_t team_off = 0;  // team kernel (G = 0, E > 0): first row index in the panel offsets
   int64_t nnz = 0;
 };
 
@@ -105,6 +106,13 @@ struct pdhcg_market_s {
   int32_t *perm = nullptr, *inv = nullptr;
   uint16_t *col16 = nullptr;  // 2-byte good ids (LDS modes 1 and 3)
   int32_t *cold_ptr = nullptr, *cold_idx = nullptr;  // goods beyond LDS by column (mode 7)
+  // panel buffers of the cold entries of team-kernel rows (mode 7)
+  float *pval = nullptr;
+  uint16_t *pid = nullptr;
+  int32_t *proff = nullptr;
+  int64_t *pbeg = nullptr;
+  double *ppart = nullptr;
+  int32_t npanel = 0, pchunks = 0;
   float *srow = nullptr;  // [n] roots of long rows between solver passes (markets with long rows)
   int32_t cold_mean_degree = 0;  // mean degree of the goods beyond LDS
   uint32_t *gmax = nullptr;  // [2][m] KKT column maxima of the goods from hot on
@@ -124,6 +132,11 @@ struct pdhcg_market_s {
     d.col16 = col16;
     d.cold_ptr = cold_ptr;
     d.cold_idx = cold_idx;
+    d.pval = pval;
+    d.pid = pid;
+    d.proff = proff;
+    d.npanel = npanel;
+    d.pad_panel = 0;
     d.srow = srow;
     d.row_ptr = row_ptr;
     d.col = col;
@@ -155,6 +168,7 @@ struct pdhcg_market_s {
     d.nrows = b.nrows;
     d.wg_offset = b.wg_offset;
     d.rows_per_wg = b.rows_per_wg;
+    d.team_off = b.team_off;
     return d;
   }
 };
@@ -249,7 +263,8 @@ void pdhcg_market_destroy(pdhcg_market mk) {
   f(mk->XA); f(mk->PA); f(mk->Pk); f(mk->T[0]); f(mk->T[1]);
   f(mk->colpart); f(mk->evalpart); f(mk->evalcs); f(mk->evalchunk);
   f(mk->rowpart); f(mk->colblk); f(mk->cacc); f(mk->S);
-  f(mk->colchunk); f(mk->perm); f(mk->inv); f(mk->col16); f(mk->cold_ptr); f(mk->cold_idx); f(mk->srow); f(mk->gmax); f(mk->gsum);
+  f(mk->colchunk); f(mk->perm); f(mk->inv); f(mk->col16); f(mk->cold_ptr); f(mk->cold_idx); f(mk->srow);
+  f(mk->pval); f(mk->pid); f(mk->proff); f(mk->pbeg); f(mk->ppart); f(mk->gmax); f(mk->gsum);
   f(mk->pdhg_buf);
   for (auto &b : mk->bins) {
     f(b.d_rows);
@@ -301,13 +316,19 @@ void choose_shape(int d, int *G, int *E) {
 }
 
 int32_t build_bins(pdhcg_market mk, const std::vector<int32_t> &h_row_ptr, int wg_per_cu) {
-  // group rows by kernel shape
+  // group rows by kernel shape; rows above kLongRow entries take G = 0: the
+  // team kernel (E = its shape code) up to kTeamMaxRow entries, the
+  // one-wave-per-row kernel (E = 0) beyond, or for all of them with
+  // PDHCG_TEAM=0
+  bool team = true;
+  if (const char *e = std::getenv("PDHCG_TEAM")) team = std::atoi(e) != 0;
   std::vector<std::pair<int, int>> shapes;
   std::vector<int> shape_of((size_t)mk->n);
   for (int32_t i = 0; i < mk->n; ++i) {
     const int d = h_row_ptr[(size_t)i + 1] - h_row_ptr[(size_t)i];
-    int G = 0, E = 0;  // rows above kLongRow entries: the one-wave-per-row kernels
+    int G = 0, E = 0;
     if (d <= kLongRow) choose_shape(d, &G, &E);
+    else if (team) E = team_code(d);
     auto key = std::make_pair(G, E);
     auto it = std::find(shapes.begin(), shapes.end(), key);
     int s;
@@ -371,6 +392,12 @@ int32_t build_bins(pdhcg_market mk, const std::vector<int32_t> &h_row_ptr, int w
     }
   }
   mk->total_wg = off;
+  int32_t toff = 0;
+  for (auto &b : mk->bins)
+    if (b.G == 0 && b.E > 0) {
+      b.team_off = toff;
+      toff += b.nrows;
+    }
   return PDHCG_OK;
 }
 
@@ -527,21 +554,78 @@ extern "C" int32_t pdhcg_market_create(int32_t n, int32_t m, int64_t nnz, const 
     MK_HIPC(dalloc(&mk->perm, (size_t)m));
     MK_HIPC(dalloc(&mk->inv, (size_t)m));
   }
-  // entries of the goods beyond LDS, column by column in row order
-  std::vector<int32_t> h_cold_ptr, h_cold_idx;
+  // Goods beyond LDS (mode 7).  The cold entries of team-kernel rows go to
+  // panel buffers (panels of kPanelW goods, runs laid out panel by panel,
+  // row by row inside a panel); the other cold entries are gathered column
+  // by column (in row order) by k_cold_sums.
+  std::vector<int32_t> h_cold_ptr, h_cold_idx, h_proff;
+  std::vector<int64_t> h_pbeg;
+  int64_t panel_entries = 0;
   if (mk->lds_row == 7) {
     const int32_t hot = mk->hot, ncold = m - hot;
+    std::vector<char> in_team((size_t)n, 0);
+    std::vector<int32_t> team_rows;
+    const int np = (ncold + kPanelW - 1) / kPanelW;
+    if (np <= kMaxPanels)
+      for (const Bin &b : mk->bins)
+        if (b.G == 0 && b.E > 0)
+          for (int32_t q = 0; q < b.nrows; ++q) {
+            const int32_t i = b.rows.empty() ? q : b.rows[(size_t)q];
+            team_rows.push_back(i);
+            in_team[(size_t)i] = 1;
+          }
+    if (!team_rows.empty()) {
+      mk->npanel = np;
+      std::vector<int64_t> tot((size_t)np, 0);
+      h_proff.assign(team_rows.size() * (size_t)np, 0);
+      for (size_t r = 0; r < team_rows.size(); ++r) {
+        const int32_t i = team_rows[r];
+        for (int32_t k = h_rp[(size_t)i]; k < h_rp[(size_t)i + 1]; ++k)
+          if (h_col[(size_t)k] >= hot) h_proff[r * (size_t)np + (size_t)((h_col[(size_t)k] - hot) >> kPanelShift)] += 1;
+      }
+      h_pbeg.assign((size_t)np + 1, 0);
+      for (size_t r = 0; r < team_rows.size(); ++r)
+        for (int p = 0; p < np; ++p) tot[(size_t)p] += h_proff[r * (size_t)np + (size_t)p];
+      for (int p = 0; p < np; ++p) h_pbeg[(size_t)p + 1] = h_pbeg[(size_t)p] + tot[(size_t)p];
+      panel_entries = h_pbeg[(size_t)np];
+      if (panel_entries > INT32_MAX) return cleanup(fail(PDHCG_ERR_UNSUPPORTED, "too many cold entries"));
+      std::vector<int64_t> run(h_pbeg.begin(), h_pbeg.end() - 1);
+      for (size_t r = 0; r < team_rows.size(); ++r)
+        for (int p = 0; p < np; ++p) {
+          const int32_t c = h_proff[r * (size_t)np + (size_t)p];
+          h_proff[r * (size_t)np + (size_t)p] = (int32_t)run[(size_t)p];
+          run[(size_t)p] += c;
+        }
+    }
     h_cold_ptr.assign((size_t)ncold + 1, 0);
-    for (int64_t k = 0; k < nnz; ++k)
-      if (h_col[(size_t)k] >= hot) h_cold_ptr[(size_t)(h_col[(size_t)k] - hot) + 1] += 1;
+    for (int32_t i = 0; i < n; ++i) {
+      if (in_team[(size_t)i]) continue;
+      for (int32_t k = h_rp[(size_t)i]; k < h_rp[(size_t)i + 1]; ++k)
+        if (h_col[(size_t)k] >= hot) h_cold_ptr[(size_t)(h_col[(size_t)k] - hot) + 1] += 1;
+    }
     for (int32_t g = 0; g < ncold; ++g) h_cold_ptr[(size_t)g + 1] += h_cold_ptr[(size_t)g];
     h_cold_idx.resize((size_t)h_cold_ptr[(size_t)ncold]);
     std::vector<int32_t> fill(h_cold_ptr.begin(), h_cold_ptr.end() - 1);
-    for (int64_t k = 0; k < nnz; ++k)
-      if (h_col[(size_t)k] >= hot) h_cold_idx[(size_t)fill[(size_t)(h_col[(size_t)k] - hot)]++] = (int32_t)k;
+    for (int32_t i = 0; i < n; ++i) {
+      if (in_team[(size_t)i]) continue;
+      for (int32_t k = h_rp[(size_t)i]; k < h_rp[(size_t)i + 1]; ++k)
+        if (h_col[(size_t)k] >= hot) h_cold_idx[(size_t)fill[(size_t)(h_col[(size_t)k] - hot)]++] = k;
+    }
     mk->cold_mean_degree = (int32_t)(h_cold_idx.size() / (size_t)std::max(ncold, 1));
     MK_HIPC(dalloc(&mk->cold_ptr, h_cold_ptr.size()));
     MK_HIPC(dalloc(&mk->cold_idx, std::max<size_t>(h_cold_idx.size(), 1)));
+    if (mk->npanel > 0) {
+      int cus = 256;
+      hipDeviceProp_t prop;
+      if (hipGetDeviceProperties(&prop, mk->device) == hipSuccess && prop.multiProcessorCount > 0)
+        cus = prop.multiProcessorCount;
+      mk->pchunks = std::max(1, std::min(64, 2 * cus / mk->npanel));
+      MK_HIPC(dalloc(&mk->pval, (size_t)std::max<int64_t>(panel_entries, 1)));
+      MK_HIPC(dalloc(&mk->pid, (size_t)std::max<int64_t>(panel_entries, 1)));
+      MK_HIPC(dalloc(&mk->proff, h_proff.size()));
+      MK_HIPC(dalloc(&mk->pbeg, h_pbeg.size()));
+      MK_HIPC(dalloc(&mk->ppart, (size_t)mk->npanel * mk->pchunks * kPanelW));
+    }
   }
   // roots of long rows between solver passes (start of each search)
   if (std::any_of(mk->bins.begin(), mk->bins.end(), [](const Bin &b) { return b.G == 0; }))
@@ -564,6 +648,10 @@ extern "C" int32_t pdhcg_market_create(int32_t n, int32_t m, int64_t nnz, const 
   std::memset(mk->hS, 0, sizeof(DevState));
 
   MK_HIPC(hipMemcpyAsync(mk->row_ptr, row_ptr, ((size_t)n + 1) * 4, hipMemcpyDeviceToDevice, st));
+  if (!h_proff.empty()) {
+    MK_HIPC(hipMemcpyAsync(mk->proff, h_proff.data(), h_proff.size() * 4, hipMemcpyHostToDevice, st));
+    MK_HIPC(hipMemcpyAsync(mk->pbeg, h_pbeg.data(), h_pbeg.size() * 8, hipMemcpyHostToDevice, st));
+  }
   if (!h_cold_ptr.empty()) {
     MK_HIPC(hipMemcpyAsync(mk->cold_ptr, h_cold_ptr.data(), h_cold_ptr.size() * 4,
                            hipMemcpyHostToDevice, st));
@@ -682,6 +770,17 @@ RowIO row_io_state(const pdhcg_params *p) {
 
 // One trial step: price step, row pass over every bin, column kernel.
 // ev0/ev1 (optional) bracket the row-pass launches.
+// Column sums of the goods beyond LDS (mode 7) of the allocation x (or of
+// the trial allocation when use_state) into out: the gathered entries
+// first, then the panel sums of the team-kernel rows.
+int32_t enqueue_cold_sums(pdhcg_market mk, const MarketDev &md, int use_state, const float *x,
+                          double *out, hipStream_t st) {
+  HIPC(launch_cold_sums(md, use_state, x, out, mk->cold_mean_degree, st));
+  HIPC(launch_panel_sums(md, use_state, out, mk->pval, mk->pid, mk->pbeg, mk->ppart, mk->pchunks,
+                         st));
+  return PDHCG_OK;
+}
+
 int32_t enqueue_step(pdhcg_market mk, const RowIO &io, hipEvent_t ev0 = nullptr,
                      hipEvent_t ev1 = nullptr) {
   const MarketDev md = mk->dev();
@@ -693,8 +792,10 @@ int32_t enqueue_step(pdhcg_market mk, const RowIO &io, hipEvent_t ev0 = nullptr,
   else
     for (const Bin &b : mk->bins)
       HIPC(launch_row_pass(md, mk->bindev(b), b.G, b.E, mk->lds_row, io, b.nwg, mk->stream));
-  if (mk->lds_row == 7)
-    HIPC(launch_cold_sums(md, 1, nullptr, nullptr, mk->cold_mean_degree, mk->stream));
+  if (mk->lds_row == 7) {
+    const int32_t rc = enqueue_cold_sums(mk, md, 1, nullptr, nullptr, mk->stream);
+    if (rc != PDHCG_OK) return rc;
+  }
   if (ev1) HIPC(hipEventRecord(ev1, mk->stream));
   HIPC(launch_col_decide(md, mk->total_wg, mk->lds_row & 1, mk->stream));
   return PDHCG_OK;
@@ -1678,7 +1779,10 @@ int32_t backward_impl(pdhcg_market mk, const float *x, const float *p, double om
     io.xout = xout;
     for (const Bin &b : mk->bins)
       HIPC(launch_row_pass(md, mk->bindev(b), b.G, b.E, mk->lds_row, io, b.nwg, st));
-    if (mk->lds_row == 7) HIPC(launch_cold_sums(md, 0, xout, asum, mk->cold_mean_degree, st));
+    if (mk->lds_row == 7) {
+      const int32_t rc = enqueue_cold_sums(mk, md, 0, xout, asum, st);
+      if (rc != PDHCG_OK) return rc;
+    }
     return finish_colsum(mk, chunk, asum, c);
   };
 

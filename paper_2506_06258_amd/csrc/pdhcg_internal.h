@@ -19,6 +19,13 @@ constexpr int kEvalRowStats = 12;
 constexpr int kColStats = 2;
 constexpr int kEvalColStats = 12;
 constexpr int kColChunks = 16;   // partial-row chunks per column tile
+// Long rows held in registers by teams of waves (pdhcg_team.hip).
+constexpr int kTeamBlock = 512;     // threads per workgroup of the team kernel
+constexpr int kTeamMaxRow = 16384;  // longest row it holds (512 threads x 32)
+// Goods beyond the LDS: panels of kPanelW goods, at most kMaxPanels.
+constexpr int kPanelShift = 13;
+constexpr int kPanelW = 1 << kPanelShift;
+constexpr int kMaxPanels = 32;
 // Per-edge arrays are addressed with 32-bit byte offsets, and offsets from
 // 2^31 up mark idle lanes: markets have at most 2^29 stored entries.
 constexpr int64_t kMaxBufferEntries = int64_t(1) << 29;
@@ -63,6 +70,13 @@ struct MarketDev {
   const int32_t *cold_ptr;
   const int32_t *cold_idx;
   float *srow;       // [n] root of each long row at the last solver pass (0: none)
+  // panel buffers of the goods from hot on (rows of the team kernel): the
+  // entries' values and their good's index inside its panel; row r of the
+  // team bins owns the run starting at proff[r * npanel + panel]
+  float *pval;
+  uint16_t *pid;
+  const int32_t *proff;
+  int32_t npanel, pad_panel;
   const int32_t *row_ptr;
   const int32_t *col;
   const uint16_t *col16;  // the same good ids in 16 bits, for markets whose
@@ -110,6 +124,7 @@ struct BinDev {
   int32_t nrows;
   int32_t wg_offset;    // first partial slot of this bin
   int32_t rows_per_wg;  // rows per workgroup (the row kernel interleaves passes instead)
+  int32_t team_off;     // team kernel: index of the bin's first row in the panel offsets
 };
 
 // Inputs/outputs of a row pass.  With use_state = 1 the kernel takes the
@@ -220,6 +235,15 @@ hipError_t launch_eval_long(const MarketDev &md, const BinDev &bin, int lds_mode
                             const EvalIO &io, int nwg, int total_wg, hipStream_t st);
 hipError_t launch_adj_long(const MarketDev &md, const BinDev &bin, int lds, const AdjIO &io,
                            int nwg, hipStream_t st);
+// Rows of 513 .. kTeamMaxRow entries in registers of teams of waves: a bin
+// of them has G = 0 and E = its team shape code (team_code of its rows);
+// its cold entries go to the panel buffers, summed by launch_panel_sums.
+int team_code(int d);
+hipError_t launch_row_team(const MarketDev &md, const BinDev &bin, int code, int lds_mode,
+                           const RowIO &io, int nwg, hipStream_t st);
+hipError_t launch_panel_sums(const MarketDev &md, int use_state, double *out, const float *pval,
+                             const uint16_t *pid, const int64_t *pbeg, double *part, int nchunk,
+                             hipStream_t st);
 // k-section search with one wave per row and one lane per candidate
 // (pdhcg_ksec.hip); rows of at most kKwaveMaxRow entries, column partials
 // of every good in LDS.

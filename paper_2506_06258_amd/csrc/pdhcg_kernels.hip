@@ -1018,7 +1018,9 @@ static hipError_t row_launch_t(const MarketDev &md, const BinDev &bin, const Row
 
 hipError_t launch_row_pass(const MarketDev &md, const BinDev &bin, int G, int E, int lds_mode,
                            const RowIO &io, int nwg, hipStream_t st) {
-  if (G == 0) return launch_row_long(md, bin, lds_mode, io, nwg, st);
+  if (G == 0)
+    return E > 0 ? launch_row_team(md, bin, E, lds_mode, io, nwg, st)
+                 : launch_row_long(md, bin, lds_mode, io, nwg, st);
   const int mode = io.search;
 #define PDHCG_ROW_LDS(g, e, md_)                                                  \
   switch (lds_mode) {                                                             \

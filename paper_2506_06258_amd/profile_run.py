@@ -7,6 +7,7 @@
   python -m paper_2506_06258_amd.profile_run backward [--unroll 64]
   python -m paper_2506_06258_amd.profile_run ksweep
   python -m paper_2506_06258_amd.profile_run jd
+  python -m paper_2506_06258_amd.profile_run longrows [--iters 24]
   python -m paper_2506_06258_amd.profile_run pdhg
   python -m paper_2506_06258_amd.profile_run theory [--K 256] [--restarts 16]
   python -m paper_2506_06258_amd.profile_run summarize --stats DIR
@@ -234,6 +235,42 @@ def run_jd() -> None:
     M.close()
 
 
+def run_longrows(iters: int) -> None:
+    """Row pass of markets whose rows all exceed 512 entries (fixed degree
+    3000, 6000 and 12000), every good in LDS and 1024 goods in LDS, the long
+    rows in registers of teams of waves and on the one-wave-per-row kernel
+    (PDHCG_TEAM=0): fixed-step iterations, row-pass time from the solver's
+    HIP events."""
+    import torch
+
+    sys.path.insert(0, ROOT)
+    from paper_2506_06258_amd import pdhcg, synth
+
+    dev = torch.device("cuda:0")
+    cases = [(60000, 3000, 4000), (30000, 6000, 8000), (20000, 12000, 13000)]
+    print("| n | entries per row | m | goods in LDS | long-row kernel | row pass ms | G entries/s |")
+    print("|---|---|---|---|---|---|---|")
+    for n, d, m in cases:
+        mk = synth.fixed_degree_market(n, m, d, 7, "uniform").as_float32()
+        for hot in (None, 1024):
+            for team in ("1", "0"):
+                os.environ["PDHCG_TEAM"] = team
+                if hot:
+                    os.environ["PDHCG_HOT"] = str(hot)
+                M = pdhcg.Market.from_synth(mk, device=dev)
+                os.environ.pop("PDHCG_HOT", None)
+                os.environ.pop("PDHCG_TEAM", None)
+                prm = pdhcg.pdhcg_default_params(tol=0.0, max_iter=iters, timing=1,
+                                                 eval_every=100000, step_mode=0, restart=0)
+                M.solve(prm)
+                s = M.solve(prm)
+                per = s.info.row_pass_seconds / max(s.info.row_pass_launches, 1)
+                kern = "teams of waves" if team == "1" else "one wave per row"
+                print(f"| {n} | {d} | {m} | {M.lds_goods()} | {kern} | {per * 1e3:.3f} | "
+                      f"{mk.nnz / per / 1e9:.1f} |", flush=True)
+                M.close()
+
+
 def _rows(path_glob: str):
     files = sorted(glob.glob(path_glob, recursive=True))
     if not files:
@@ -323,6 +360,8 @@ def main() -> None:
     sub.add_parser("exchange")
     sub.add_parser("ksweep")
     sub.add_parser("jd")
+    lr = sub.add_parser("longrows")
+    lr.add_argument("--iters", type=int, default=24)
     pg = sub.add_parser("pdhg")
     pg.add_argument("--iters", type=int, default=200000)
     th = sub.add_parser("theory")
@@ -355,6 +394,8 @@ def main() -> None:
         run_ksweep()
     elif a.cmd == "jd":
         run_jd()
+    elif a.cmd == "longrows":
+        run_longrows(a.iters)
     elif a.cmd == "pdhg":
         run_pdhg(a.iters)
     elif a.cmd == "theory":

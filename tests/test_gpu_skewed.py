@@ -14,17 +14,59 @@ from test_gpu_parity import check_row_prox, prox_state, rel_err
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("d", [513, 1500, 4000])
-def test_row_prox_long_rows(cuda, d):
-    n, m = 300, d + 200
+# team kernel shape code of a row length (rows held by teams of waves)
+TEAM_CODE = {513: 1, 1500: 2, 4000: 3, 6000: 4, 12000: 5, 17000: 0}
+
+
+@pytest.mark.parametrize("kernel", ["team", "wave"])
+@pytest.mark.parametrize("d", [513, 1500, 4000, 6000, 12000, 17000])
+def test_row_prox_long_rows(cuda, monkeypatch, d, kernel):
+    """Rows above 512 entries: in registers of teams of waves (every team
+    shape; rows above 16384 entries stay on the one-wave-per-row kernel) and
+    on the one-wave-per-row kernel (PDHCG_TEAM=0), entry by entry against
+    the exact prox.  Above 10,112 goods the market takes the relabelled
+    layout (goods beyond LDS)."""
+    n, m = (300, d + 200) if d <= 4000 else (40, d + 200)
     mk = synth.fixed_degree_market(n, m, d, 300 + d, "uniform").as_float32()
+    if kernel == "wave":
+        monkeypatch.setenv("PDHCG_TEAM", "0")
     M = pdhcg.Market.from_synth(mk, device=cuda)
-    assert M.bins() == [(0, 0, n)]
+    assert M.bins() == [(0, TEAM_CODE[d] if kernel == "team" else 0, n)]
     M.close()
     rng = np.random.default_rng(d)
     for kind in ("init", "random", "sparse"):
         x_in, p = prox_state(mk, rng, kind)
         check_row_prox(mk, cuda, x_in, p, 0.3 / (mk.w.sum() / mk.m))
+
+
+@pytest.mark.parametrize("hot", [None, 64])
+def test_team_and_wave_kernels_reach_the_same_prices(cuda, monkeypatch, zipf_small, hot):
+    """Solves of a market with rows of up to 1500 entries, its long rows on
+    the team kernel or on the one-wave-per-row kernel, with all goods in LDS
+    and with 64 (the others' column sums through the panel buffers or the
+    column gathers), against the oracle and each other."""
+    mk, ora = zipf_small
+    prices = {}
+    for kernel in ("team", "wave"):
+        if hot is not None:
+            monkeypatch.setenv("PDHCG_HOT", str(hot))
+        if kernel == "wave":
+            monkeypatch.setenv("PDHCG_TEAM", "0")
+        M = pdhcg.Market.from_synth(mk, device=cuda)
+        monkeypatch.delenv("PDHCG_TEAM", raising=False)
+        monkeypatch.delenv("PDHCG_HOT", raising=False)
+        long_bins = [e for g, e, _ in M.bins() if g == 0]
+        assert long_bins and all((e == 0) == (kernel == "wave") for e in long_bins), M.bins()
+        sol = M.solve(tol=1e-6, max_iter=400000)
+        assert sol.info.status == pdhcg.PDHCG_OK, pdhcg.pdhcg_last_error()
+        p, x = sol.p.cpu().numpy().astype(np.float64), sol.x.cpu().numpy().astype(np.float64)
+        uh, _ = oracle.normalize_rows(mk.row_ptr, mk.u.astype(np.float64))
+        r, _ = oracle.kkt(mk.n, mk.m, mk.row_ptr, mk.col, uh, mk.w, x, p)
+        assert r <= 2e-6, (kernel, r)
+        assert rel_err(p, ora.p) <= 1e-5, kernel
+        prices[kernel] = p
+        M.close()
+    assert rel_err(prices["team"], prices["wave"]) <= 2e-5
 
 
 @pytest.fixture(scope="module")
@@ -97,7 +139,7 @@ def test_backward_with_long_rows(cuda):
     st, du_i, dw_i, _ = oracle.implicit_grad(n, m, row_ptr, col, u, w, ref.x, ref.p, g)
     assert st == oracle.OK
     M = pdhcg.Market(row_ptr, col, u, w, m=m, device=cuda)
-    assert M.bins() == [(0, 0, n)]
+    assert M.bins() == [(0, 1, n)]  # the team kernel, 128 threads x 8 entries per row
     sol = M.solve(tol=1e-7, max_iter=400000)
     assert sol.info.status == pdhcg.PDHCG_OK
     # the fixed-step map contracts slowly on this market (few buyers, long

@@ -110,6 +110,7 @@ struct pdhcg_market_s {
   float *pval = nullptr;
   uint16_t *pid = nullptr;
   int32_t *proff = nullptr;
+  int32_t *cslot = nullptr;
   int64_t *pbeg = nullptr;
   double *ppart = nullptr;
   int32_t npanel = 0, pchunks = 0;
@@ -135,6 +136,7 @@ struct pdhcg_market_s {
     d.pval = pval;
     d.pid = pid;
     d.proff = proff;
+    d.cslot = cslot;
     d.npanel = npanel;
     d.pad_panel = 0;
     d.srow = srow;
@@ -264,7 +266,7 @@ void pdhcg_market_destroy(pdhcg_market mk) {
   f(mk->colpart); f(mk->evalpart); f(mk->evalcs); f(mk->evalchunk);
   f(mk->rowpart); f(mk->colblk); f(mk->cacc); f(mk->S);
   f(mk->colchunk); f(mk->perm); f(mk->inv); f(mk->col16); f(mk->cold_ptr); f(mk->cold_idx); f(mk->srow);
-  f(mk->pval); f(mk->pid); f(mk->proff); f(mk->pbeg); f(mk->ppart); f(mk->gmax); f(mk->gsum);
+  f(mk->pval); f(mk->pid); f(mk->proff); f(mk->pbeg); f(mk->ppart); f(mk->cslot); f(mk->gmax); f(mk->gsum);
   f(mk->pdhg_buf);
   for (auto &b : mk->bins) {
     f(b.d_rows);
@@ -554,18 +556,26 @@ extern "C" int32_t pdhcg_market_create(int32_t n, int32_t m, int64_t nnz, const 
     MK_HIPC(dalloc(&mk->perm, (size_t)m));
     MK_HIPC(dalloc(&mk->inv, (size_t)m));
   }
-  // Goods beyond LDS (mode 7).  The cold entries of team-kernel rows go to
-  // panel buffers (panels of kPanelW goods, runs laid out panel by panel,
-  // row by row inside a panel); the other cold entries are gathered column
-  // by column (in row order) by k_cold_sums.
-  std::vector<int32_t> h_cold_ptr, h_cold_idx, h_proff;
+  // Goods beyond LDS (mode 7): their entries go to panel buffers (panels of
+  // kPanelW goods, laid out panel by panel) or are gathered column by column
+  // (in row order) by k_cold_sums.  Inside panel p the runs of the
+  // team-kernel rows come first (row by row; each team fills its row's run
+  // through LDS counters), then the entries of the other rows at fixed
+  // slots (cslot, row by row) with their fixed in-panel good index.  The
+  // other rows use fixed slots when at least kSlotShare of their entries
+  // are of such goods (the slot of every entry is read, so a small share is
+  // cheaper to gather); with more than kMaxPanels panels every entry of
+  // these goods is gathered.
+  constexpr double kSlotShare = 0.2;
+  std::vector<int32_t> h_cold_ptr, h_cold_idx, h_proff, h_cslot;
   std::vector<int64_t> h_pbeg;
+  std::vector<uint16_t> h_pid;
   int64_t panel_entries = 0;
   if (mk->lds_row == 7) {
     const int32_t hot = mk->hot, ncold = m - hot;
+    const int np = (ncold + kPanelW - 1) / kPanelW;
     std::vector<char> in_team((size_t)n, 0);
     std::vector<int32_t> team_rows;
-    const int np = (ncold + kPanelW - 1) / kPanelW;
     if (np <= kMaxPanels)
       for (const Bin &b : mk->bins)
         if (b.G == 0 && b.E > 0)
@@ -574,21 +584,39 @@ extern "C" int32_t pdhcg_market_create(int32_t n, int32_t m, int64_t nnz, const 
             team_rows.push_back(i);
             in_team[(size_t)i] = 1;
           }
-    if (!team_rows.empty()) {
+    int64_t other = 0, other_cold = 0;
+    for (int32_t i = 0; i < n; ++i) {
+      if (in_team[(size_t)i]) continue;
+      for (int32_t k = h_rp[(size_t)i]; k < h_rp[(size_t)i + 1]; ++k) {
+        other += 1;
+        other_cold += h_col[(size_t)k] >= hot ? 1 : 0;
+      }
+    }
+    const bool fixed = np <= kMaxPanels && other_cold > 0 &&
+                       (double)other_cold >= kSlotShare * (double)other;
+    if (!team_rows.empty() || fixed) {
       mk->npanel = np;
-      std::vector<int64_t> tot((size_t)np, 0);
+      auto panel_of = [&](int32_t c) { return (size_t)((c - hot) >> kPanelShift); };
+      std::vector<int64_t> tot_team((size_t)np, 0), tot_fixed((size_t)np, 0);
       h_proff.assign(team_rows.size() * (size_t)np, 0);
       for (size_t r = 0; r < team_rows.size(); ++r) {
         const int32_t i = team_rows[r];
         for (int32_t k = h_rp[(size_t)i]; k < h_rp[(size_t)i + 1]; ++k)
-          if (h_col[(size_t)k] >= hot) h_proff[r * (size_t)np + (size_t)((h_col[(size_t)k] - hot) >> kPanelShift)] += 1;
+          if (h_col[(size_t)k] >= hot) h_proff[r * (size_t)np + panel_of(h_col[(size_t)k])] += 1;
       }
-      h_pbeg.assign((size_t)np + 1, 0);
       for (size_t r = 0; r < team_rows.size(); ++r)
-        for (int p = 0; p < np; ++p) tot[(size_t)p] += h_proff[r * (size_t)np + (size_t)p];
-      for (int p = 0; p < np; ++p) h_pbeg[(size_t)p + 1] = h_pbeg[(size_t)p] + tot[(size_t)p];
+        for (int p = 0; p < np; ++p) tot_team[(size_t)p] += h_proff[r * (size_t)np + (size_t)p];
+      if (fixed)
+        for (int32_t i = 0; i < n; ++i) {
+          if (in_team[(size_t)i]) continue;
+          for (int32_t k = h_rp[(size_t)i]; k < h_rp[(size_t)i + 1]; ++k)
+            if (h_col[(size_t)k] >= hot) tot_fixed[panel_of(h_col[(size_t)k])] += 1;
+        }
+      h_pbeg.assign((size_t)np + 1, 0);
+      for (int p = 0; p < np; ++p)
+        h_pbeg[(size_t)p + 1] = h_pbeg[(size_t)p] + tot_team[(size_t)p] + tot_fixed[(size_t)p];
       panel_entries = h_pbeg[(size_t)np];
-      if (panel_entries > INT32_MAX) return cleanup(fail(PDHCG_ERR_UNSUPPORTED, "too many cold entries"));
+      // team runs
       std::vector<int64_t> run(h_pbeg.begin(), h_pbeg.end() - 1);
       for (size_t r = 0; r < team_rows.size(); ++r)
         for (int p = 0; p < np; ++p) {
@@ -596,35 +624,52 @@ extern "C" int32_t pdhcg_market_create(int32_t n, int32_t m, int64_t nnz, const 
           h_proff[r * (size_t)np + (size_t)p] = (int32_t)run[(size_t)p];
           run[(size_t)p] += c;
         }
-    }
-    h_cold_ptr.assign((size_t)ncold + 1, 0);
-    for (int32_t i = 0; i < n; ++i) {
-      if (in_team[(size_t)i]) continue;
-      for (int32_t k = h_rp[(size_t)i]; k < h_rp[(size_t)i + 1]; ++k)
-        if (h_col[(size_t)k] >= hot) h_cold_ptr[(size_t)(h_col[(size_t)k] - hot) + 1] += 1;
-    }
-    for (int32_t g = 0; g < ncold; ++g) h_cold_ptr[(size_t)g + 1] += h_cold_ptr[(size_t)g];
-    h_cold_idx.resize((size_t)h_cold_ptr[(size_t)ncold]);
-    std::vector<int32_t> fill(h_cold_ptr.begin(), h_cold_ptr.end() - 1);
-    for (int32_t i = 0; i < n; ++i) {
-      if (in_team[(size_t)i]) continue;
-      for (int32_t k = h_rp[(size_t)i]; k < h_rp[(size_t)i + 1]; ++k)
-        if (h_col[(size_t)k] >= hot) h_cold_idx[(size_t)fill[(size_t)(h_col[(size_t)k] - hot)]++] = k;
-    }
-    mk->cold_mean_degree = (int32_t)(h_cold_idx.size() / (size_t)std::max(ncold, 1));
-    MK_HIPC(dalloc(&mk->cold_ptr, h_cold_ptr.size()));
-    MK_HIPC(dalloc(&mk->cold_idx, std::max<size_t>(h_cold_idx.size(), 1)));
-    if (mk->npanel > 0) {
+      // fixed slots of the other rows
+      h_pid.assign((size_t)std::max<int64_t>(panel_entries, 1), 0);
+      if (fixed) {
+        h_cslot.assign((size_t)nnz, -1);
+        for (int32_t i = 0; i < n; ++i) {
+          if (in_team[(size_t)i]) continue;
+          for (int32_t k = h_rp[(size_t)i]; k < h_rp[(size_t)i + 1]; ++k) {
+            const int32_t c = h_col[(size_t)k];
+            if (c < hot) continue;
+            const int64_t sl = run[panel_of(c)]++;
+            h_cslot[(size_t)k] = (int32_t)sl;
+            h_pid[(size_t)sl] = (uint16_t)((c - hot) & (kPanelW - 1));
+          }
+        }
+      }
       int cus = 256;
       hipDeviceProp_t prop;
       if (hipGetDeviceProperties(&prop, mk->device) == hipSuccess && prop.multiProcessorCount > 0)
         cus = prop.multiProcessorCount;
-      mk->pchunks = std::max(1, std::min(64, 2 * cus / mk->npanel));
+      mk->pchunks = std::max(1, std::min(64, 2 * cus / np));
       MK_HIPC(dalloc(&mk->pval, (size_t)std::max<int64_t>(panel_entries, 1)));
-      MK_HIPC(dalloc(&mk->pid, (size_t)std::max<int64_t>(panel_entries, 1)));
-      MK_HIPC(dalloc(&mk->proff, h_proff.size()));
+      MK_HIPC(dalloc(&mk->pid, h_pid.size()));
+      MK_HIPC(dalloc(&mk->proff, std::max<size_t>(h_proff.size(), 1)));
       MK_HIPC(dalloc(&mk->pbeg, h_pbeg.size()));
-      MK_HIPC(dalloc(&mk->ppart, (size_t)mk->npanel * mk->pchunks * kPanelW));
+      if (fixed) MK_HIPC(dalloc(&mk->cslot, (size_t)nnz));
+      MK_HIPC(dalloc(&mk->ppart, (size_t)np * mk->pchunks * kPanelW));
+    }
+    if (!fixed && other_cold > 0) {
+      // the other rows' entries of these goods, gathered by column
+      h_cold_ptr.assign((size_t)ncold + 1, 0);
+      for (int32_t i = 0; i < n; ++i) {
+        if (in_team[(size_t)i]) continue;
+        for (int32_t k = h_rp[(size_t)i]; k < h_rp[(size_t)i + 1]; ++k)
+          if (h_col[(size_t)k] >= hot) h_cold_ptr[(size_t)(h_col[(size_t)k] - hot) + 1] += 1;
+      }
+      for (int32_t g = 0; g < ncold; ++g) h_cold_ptr[(size_t)g + 1] += h_cold_ptr[(size_t)g];
+      h_cold_idx.resize((size_t)h_cold_ptr[(size_t)ncold]);
+      std::vector<int32_t> fill(h_cold_ptr.begin(), h_cold_ptr.end() - 1);
+      for (int32_t i = 0; i < n; ++i) {
+        if (in_team[(size_t)i]) continue;
+        for (int32_t k = h_rp[(size_t)i]; k < h_rp[(size_t)i + 1]; ++k)
+          if (h_col[(size_t)k] >= hot) h_cold_idx[(size_t)fill[(size_t)(h_col[(size_t)k] - hot)]++] = k;
+      }
+      mk->cold_mean_degree = (int32_t)(h_cold_idx.size() / (size_t)std::max(ncold, 1));
+      MK_HIPC(dalloc(&mk->cold_ptr, h_cold_ptr.size()));
+      MK_HIPC(dalloc(&mk->cold_idx, std::max<size_t>(h_cold_idx.size(), 1)));
     }
   }
   // roots of long rows between solver passes (start of each search)
@@ -648,9 +693,13 @@ extern "C" int32_t pdhcg_market_create(int32_t n, int32_t m, int64_t nnz, const 
   std::memset(mk->hS, 0, sizeof(DevState));
 
   MK_HIPC(hipMemcpyAsync(mk->row_ptr, row_ptr, ((size_t)n + 1) * 4, hipMemcpyDeviceToDevice, st));
-  if (!h_proff.empty()) {
-    MK_HIPC(hipMemcpyAsync(mk->proff, h_proff.data(), h_proff.size() * 4, hipMemcpyHostToDevice, st));
+  if (mk->npanel > 0) {
+    if (!h_proff.empty())
+      MK_HIPC(hipMemcpyAsync(mk->proff, h_proff.data(), h_proff.size() * 4, hipMemcpyHostToDevice, st));
     MK_HIPC(hipMemcpyAsync(mk->pbeg, h_pbeg.data(), h_pbeg.size() * 8, hipMemcpyHostToDevice, st));
+    if (!h_cslot.empty())
+      MK_HIPC(hipMemcpyAsync(mk->cslot, h_cslot.data(), h_cslot.size() * 4, hipMemcpyHostToDevice, st));
+    MK_HIPC(hipMemcpyAsync(mk->pid, h_pid.data(), h_pid.size() * 2, hipMemcpyHostToDevice, st));
   }
   if (!h_cold_ptr.empty()) {
     MK_HIPC(hipMemcpyAsync(mk->cold_ptr, h_cold_ptr.data(), h_cold_ptr.size() * 4,
@@ -771,13 +820,13 @@ RowIO row_io_state(const pdhcg_params *p) {
 // One trial step: price step, row pass over every bin, column kernel.
 // ev0/ev1 (optional) bracket the row-pass launches.
 // Column sums of the goods beyond LDS (mode 7) of the allocation x (or of
-// the trial allocation when use_state) into out: the gathered entries
-// first, then the panel sums of the team-kernel rows.
+// the trial allocation when use_state) into out: the panel sums, or the
+// gathers by column when the goods do not fit the panels.
 int32_t enqueue_cold_sums(pdhcg_market mk, const MarketDev &md, int use_state, const float *x,
                           double *out, hipStream_t st) {
   HIPC(launch_cold_sums(md, use_state, x, out, mk->cold_mean_degree, st));
   HIPC(launch_panel_sums(md, use_state, out, mk->pval, mk->pid, mk->pbeg, mk->ppart, mk->pchunks,
-                         st));
+                         mk->cold_ptr != nullptr, st));
   return PDHCG_OK;
 }
 

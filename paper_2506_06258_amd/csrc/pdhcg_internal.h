@@ -76,6 +76,9 @@ struct MarketDev {
   float *pval;
   uint16_t *pid;
   const int32_t *proff;
+  // the other rows' entries of those goods have fixed slots: cslot[q] (-1
+  // for the entries of the goods in LDS and of team-kernel rows)
+  const int32_t *cslot;
   int32_t npanel, pad_panel;
   const int32_t *row_ptr;
   const int32_t *col;
@@ -243,7 +246,7 @@ hipError_t launch_row_team(const MarketDev &md, const BinDev &bin, int code, int
                            const RowIO &io, int nwg, hipStream_t st);
 hipError_t launch_panel_sums(const MarketDev &md, int use_state, double *out, const float *pval,
                              const uint16_t *pid, const int64_t *pbeg, double *part, int nchunk,
-                             hipStream_t st);
+                             int accumulate, hipStream_t st);
 // k-section search with one wave per row and one lane per candidate
 // (pdhcg_ksec.hip); rows of at most kKwaveMaxRow entries, column partials
 // of every good in LDS.

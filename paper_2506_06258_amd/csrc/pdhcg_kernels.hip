@@ -185,6 +185,10 @@ __global__ __launch_bounds__(kRowBlock) void k_row_pass(MarketDev md, BinDev bin
   const __amdgpu_buffer_rsrc_t ry = make_rsrc(xavg, fold_read ? ebytes : 0u);
   const __amdgpu_buffer_rsrc_t ryw = make_rsrc(xavg, fold ? ebytes : 0u);
   const __amdgpu_buffer_rsrc_t rs = make_rsrc(io.s_out, io.s_out ? (uint32_t)md.n * 4u : 0u);
+  // entries of the goods beyond LDS: their fixed slots in the panel buffer
+  const bool slots = kHybrid && io.colsum && md.cslot != nullptr;
+  const __amdgpu_buffer_rsrc_t rcs = make_rsrc(md.cslot, slots ? ebytes : 0u);
+  const __amdgpu_buffer_rsrc_t rpv = make_rsrc(md.pval, slots ? ebytes : 0u);  // slots < nnz
 
   double dx2 = 0.0;  // |x_try - x|^2 of the lane's entries (float64, like the global sum)
   uint32_t rmax = 0;
@@ -211,6 +215,7 @@ __global__ __launch_bounds__(kRowBlock) void k_row_pass(MarketDev md, BinDev bin
   // averaged allocation into y.
   double a[E];
   float y[E];
+  int cs[E];
   auto head = [&](const RowRegs<E> &Rc, const RowBounds &bc) {
     if (kHybrid) {
       // both loads for every entry (no branch around a memory instruction):
@@ -231,6 +236,10 @@ __global__ __launch_bounds__(kRowBlock) void k_row_pass(MarketDev md, BinDev bin
     const uint32_t off = lane_off(bc);
 #pragma unroll
     for (int e = 0; e < E; ++e) y[e] = bload_f(ry, off + 4u * G * e);
+    if (kHybrid) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) cs[e] = slots ? bload_i(rcs, off + 4u * G * e) : -1;
+    }
   };
   // Body of a pass: entries Rc (dc entries, budget wc, bounds bc) and its
   // prices are in flight or resident; bn holds the bounds of the next pass.
@@ -275,10 +284,12 @@ __global__ __launch_bounds__(kRowBlock) void k_row_pass(MarketDev md, BinDev bin
       dx2 = fma(df, df, dx2);
       if (io.colsum) {
         if (kHybrid) {
-          // goods from hot on are summed afterwards by k_cold_sums
+          // goods from hot on: to their panel slot (summed afterwards by
+          // the panel kernels), or gathered by k_cold_sums
           const int c = Rc.c[e];
           const bool hc = c < hot;
           atomicAdd(&lc[hc ? c : hot], (ok[e] && hc) ? (double)xn : 0.0);
+          bstore_f(rpv, (ok[e] && cs[e] >= 0) ? 4u * (uint32_t)cs[e] : kOutOfRange, xn);
         } else {
           atomicAdd((LDS_MODE & 1) ? &lc[Rc.c[e]] : &cglob[Rc.c[e]], ok[e] ? (double)xn : 0.0);
         }

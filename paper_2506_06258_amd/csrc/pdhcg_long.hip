@@ -122,9 +122,15 @@ __global__ __launch_bounds__(kRowBlock) void k_row_long(MarketDev md, BinDev bin
               dx2 = fma(-ds, ds, dx2);
               add -= (double)xs;
             }
-            // with LDS_MODE & 4 the goods from hot on are summed by k_cold_sums
+            // with LDS_MODE & 4 the goods from hot on go to their panel
+            // slot (a later sweep of the row overwrites it) or are gathered
+            // by k_cold_sums
             if (io.colsum && (!(LDS_MODE & 4) || c[e] < hot))
               atomicAdd(((LDS_MODE & 1) && c[e] < hot) ? &lc[c[e]] : &cglob[c[e]], add);
+            else if ((LDS_MODE & 4) && io.colsum && md.cslot) {
+              const int sl = md.cslot[q];
+              if (sl >= 0) md.pval[sl] = xn;
+            }
           }
         }
       }

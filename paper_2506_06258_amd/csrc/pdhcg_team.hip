@@ -11,11 +11,11 @@
 // Goods beyond the LDS (relabelled markets, LDS mode 7): the entries of
 // these goods are written, with their good's index inside its panel, to
 // the panel buffers (pval / pid), where every long row owns a run per
-// panel of kPanelW goods.  The runs are laid out panel by panel, so that
-// k_panel_part reads each panel's entries contiguously and sums them in an
-// LDS copy of the panel; k_panel_sum adds the panels' partial sums to the
-// column sums (those of the other rows' entries of these goods come from
-// k_cold_sums, which runs first).
+// panel of kPanelW goods; the other row kernels write their entries of
+// these goods to fixed slots (cslot) after the runs.  The buffers are laid
+// out panel by panel, so that k_panel_part reads each panel's entries
+// contiguously and sums them in an LDS copy of the panel, and k_panel_sum
+// writes the panels' sums as the column sums of these goods.
 //
 // The LDS conventions (bit 1: float64 column partials, bit 2: float64
 // prices, bit 4: only the goods below hot in LDS; workgroup partials
@@ -359,9 +359,11 @@ __global__ __launch_bounds__(1024) void k_panel_part(const float *val, const uin
   for (int j = threadIdx.x; j < kPanelW; j += blockDim.x) dst[j] = acc[j];
 }
 
-// out[hot + g] += the panel partial sums of good hot + g (in chunk order).
+// out[hot + g] (+)= the panel partial sums of good hot + g (in chunk order):
+// added to what k_cold_sums wrote when some of these goods' entries are
+// gathered by column, written otherwise.
 __global__ __launch_bounds__(256) void k_panel_sum(MarketDev md, int use_state, double *out,
-                                                   const double *part, int nchunk) {
+                                                   const double *part, int nchunk, int accumulate) {
   if (use_state) out = pick3<double *>(md.C0, md.C1, md.C2, md.S->ic[2]);
   const int ncold = md.m - md.hot;
   const int g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -370,7 +372,7 @@ __global__ __launch_bounds__(256) void k_panel_sum(MarketDev md, int use_state, 
   const double *src = part + (size_t)P * nchunk * kPanelW + j;
   double s = 0.0;
   for (int r = 0; r < nchunk; ++r) s += src[(size_t)r * kPanelW];
-  out[md.hot + g] += s;
+  out[md.hot + g] = accumulate ? out[md.hot + g] + s : s;
 }
 
 // ------------------------------------------------------------- launchers --
@@ -416,7 +418,7 @@ hipError_t launch_row_team(const MarketDev &md, const BinDev &bin, int code, int
 
 hipError_t launch_panel_sums(const MarketDev &md, int use_state, double *out, const float *pval,
                              const uint16_t *pid, const int64_t *pbeg, double *part, int nchunk,
-                             hipStream_t st) {
+                             int accumulate, hipStream_t st) {
   const int ncold = md.m - md.hot;
   if (md.npanel <= 0 || ncold <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_panel_part, dim3(nchunk, md.npanel), dim3(1024), kPanelW * sizeof(double), st,
@@ -424,7 +426,7 @@ hipError_t launch_panel_sums(const MarketDev &md, int use_state, double *out, co
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_panel_sum, dim3((ncold + 255) / 256), dim3(256), 0, st, md, use_state, out,
-                     part, nchunk);
+                     part, nchunk, accumulate);
   return hipGetLastError();
 }
 

@@ -643,7 +643,12 @@ extern "C" int32_t pdhcg_market_create(int32_t n, int32_t m, int64_t nnz, const 
       hipDeviceProp_t prop;
       if (hipGetDeviceProperties(&prop, mk->device) == hipSuccess && prop.multiProcessorCount > 0)
         cus = prop.multiProcessorCount;
-      mk->pchunks = std::max(1, std::min(64, 2 * cus / np));
+      // chunks per panel for k_panel_part: about two blocks per CU, but no
+      // block below 32768 entries (the partial sums are 64 KiB per block)
+      int64_t most = 1;
+      for (int p = 0; p < np; ++p) most = std::max(most, h_pbeg[(size_t)p + 1] - h_pbeg[(size_t)p]);
+      mk->pchunks = (int)std::max<int64_t>(
+          1, std::min<int64_t>({64, 2 * cus / np, (most + 32767) / 32768}));
       MK_HIPC(dalloc(&mk->pval, (size_t)std::max<int64_t>(panel_entries, 1)));
       MK_HIPC(dalloc(&mk->pid, h_pid.size()));
       MK_HIPC(dalloc(&mk->proff, std::max<size_t>(h_proff.size(), 1)));

@@ -36,9 +36,11 @@
  *                                 the first k in LDS (as for large m);
  *      PDHCG_P_LDS=0              prices from global memory, partials in LDS;
  *      PDHCG_NO_LDS=1             no LDS: device atomics for column sums;
- *      PDHCG_TEAM=0               rows above 512 entries on the
- *                                 one-wave-per-row kernel instead of in
- *                                 registers of teams of waves;
+ *      PDHCG_TEAM=0 / 2           rows above 512 entries all on the
+ *                                 one-wave-per-row kernel / all (up to
+ *                                 16384 entries) in registers of teams of
+ *                                 waves (default: teams for the rows of
+ *                                 relabelled markets);
  *    and at pdhcg_batch_solve: PDHCG_BATCH_EAGER=1 launches the batch's
  *    kernels directly instead of replaying its graph; at pdhcg_batch_create:
  *    PDHCG_BATCH_GANG=0 keeps every market on one workgroup,

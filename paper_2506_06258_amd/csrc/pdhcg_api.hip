@@ -318,19 +318,24 @@ void choose_shape(int d, int *G, int *E) {
 }
 
 int32_t build_bins(pdhcg_market mk, const std::vector<int32_t> &h_row_ptr, int wg_per_cu) {
-  // group rows by kernel shape; rows above kLongRow entries take G = 0: the
-  // team kernel (E = its shape code) up to kTeamMaxRow entries, the
-  // one-wave-per-row kernel (E = 0) beyond, or for all of them with
-  // PDHCG_TEAM=0
-  bool team = true;
-  if (const char *e = std::getenv("PDHCG_TEAM")) team = std::atoi(e) != 0;
+  // group rows by kernel shape; rows above kLongRow entries take G = 0:
+  // the team kernel (E = its shape code) or the one-wave-per-row kernel
+  // (E = 0).  Teams hold a row in registers (one read) but need many
+  // registers per thread; the one-wave-per-row kernel reads a row two or
+  // three times with few registers, so more waves share a CU.  Measured:
+  // teams win where the LDS already limits a CU to one workgroup
+  // (relabelled markets, LDS mode 7), which is where they are used
+  // (PDHCG_TEAM=1, the default); PDHCG_TEAM=0 never uses them, PDHCG_TEAM=2
+  // for every row up to kTeamMaxRow entries.
+  int team_mode = 1;
+  if (const char *e = std::getenv("PDHCG_TEAM")) team_mode = std::atoi(e);
   std::vector<std::pair<int, int>> shapes;
   std::vector<int> shape_of((size_t)mk->n);
   for (int32_t i = 0; i < mk->n; ++i) {
     const int d = h_row_ptr[(size_t)i + 1] - h_row_ptr[(size_t)i];
     int G = 0, E = 0;
     if (d <= kLongRow) choose_shape(d, &G, &E);
-    else if (team) E = team_code(d);
+    else if (team_mode == 2 || (team_mode == 1 && mk->lds_row == 7)) E = team_code(d);
     auto key = std::make_pair(G, E);
     auto it = std::find(shapes.begin(), shapes.end(), key);
     int s;

@@ -237,23 +237,24 @@ def run_jd() -> None:
 
 def run_longrows(iters: int) -> None:
     """Row pass of markets whose rows all exceed 512 entries (fixed degree
-    3000, 6000 and 12000), every good in LDS and 1024 goods in LDS, the long
-    rows in registers of teams of waves and on the one-wave-per-row kernel
-    (PDHCG_TEAM=0): fixed-step iterations, row-pass time from the solver's
-    HIP events."""
+    800, 1500, 3000, 6000 and 12000), every good in LDS and 1024 goods in LDS, the long
+    rows in registers of teams of waves (PDHCG_TEAM=2) and on the
+    one-wave-per-row kernel (PDHCG_TEAM=0): fixed-step iterations, row-pass
+    time from the solver's HIP events."""
     import torch
 
     sys.path.insert(0, ROOT)
     from paper_2506_06258_amd import pdhcg, synth
 
     dev = torch.device("cuda:0")
-    cases = [(60000, 3000, 4000), (30000, 6000, 8000), (20000, 12000, 13000)]
+    cases = [(120000, 800, 1500), (100000, 1500, 2500), (60000, 3000, 4000), (30000, 6000, 8000),
+             (20000, 12000, 13000)]
     print("| n | entries per row | m | goods in LDS | long-row kernel | row pass ms | G entries/s |")
     print("|---|---|---|---|---|---|---|")
     for n, d, m in cases:
         mk = synth.fixed_degree_market(n, m, d, 7, "uniform").as_float32()
         for hot in (None, 1024):
-            for team in ("1", "0"):
+            for team in ("2", "0"):
                 os.environ["PDHCG_TEAM"] = team
                 if hot:
                     os.environ["PDHCG_HOT"] = str(hot)
@@ -265,7 +266,7 @@ def run_longrows(iters: int) -> None:
                 M.solve(prm)
                 s = M.solve(prm)
                 per = s.info.row_pass_seconds / max(s.info.row_pass_launches, 1)
-                kern = "teams of waves" if team == "1" else "one wave per row"
+                kern = "teams of waves" if team == "2" else "one wave per row"
                 print(f"| {n} | {d} | {m} | {M.lds_goods()} | {kern} | {per * 1e3:.3f} | "
                       f"{mk.nnz / per / 1e9:.1f} |", flush=True)
                 M.close()

@@ -75,11 +75,10 @@ def test_adjoint_register_shapes(cuda, d, expect):
 @pytest.mark.parametrize("kernel", ["team", "wave"])
 def test_adjoint_long_rows(cuda, monkeypatch, kernel):
     """Rows of 700 entries: the forward steps of the reverse mode on the team
-    kernel (shape code 1) or on the one-wave-per-row kernel; the adjoint
+    kernel (shape code 1, forced) or on the one-wave-per-row kernel; the adjoint
     pass is the one-wave-per-row adjoint kernel in both."""
     mk = synth.fixed_degree_market(120, 1500, 700, 41).as_float32()
-    if kernel == "wave":
-        monkeypatch.setenv("PDHCG_TEAM", "0")
+    monkeypatch.setenv("PDHCG_TEAM", "0" if kernel == "wave" else "2")
     _check(mk, cuda, expect=(0, 1 if kernel == "team" else 0))
 
 

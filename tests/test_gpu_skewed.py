@@ -18,18 +18,18 @@ pytestmark = pytest.mark.gpu
 TEAM_CODE = {513: 1, 1500: 2, 4000: 3, 6000: 4, 12000: 5, 17000: 0}
 
 
+
 @pytest.mark.parametrize("kernel", ["team", "wave"])
 @pytest.mark.parametrize("d", [513, 1500, 4000, 6000, 12000, 17000])
 def test_row_prox_long_rows(cuda, monkeypatch, d, kernel):
     """Rows above 512 entries: in registers of teams of waves (every team
     shape; rows above 16384 entries stay on the one-wave-per-row kernel) and
     on the one-wave-per-row kernel (PDHCG_TEAM=0), entry by entry against
-    the exact prox.  Above 10,112 goods the market takes the relabelled
-    layout (goods beyond LDS)."""
+    the exact prox (PDHCG_TEAM=2 takes the teams on every layout).  Above
+    10,112 goods the market takes the relabelled layout (goods beyond LDS)."""
     n, m = (300, d + 200) if d <= 4000 else (40, d + 200)
     mk = synth.fixed_degree_market(n, m, d, 300 + d, "uniform").as_float32()
-    if kernel == "wave":
-        monkeypatch.setenv("PDHCG_TEAM", "0")
+    monkeypatch.setenv("PDHCG_TEAM", "0" if kernel == "wave" else "2")
     M = pdhcg.Market.from_synth(mk, device=cuda)
     assert M.bins() == [(0, TEAM_CODE[d] if kernel == "team" else 0, n)]
     M.close()
@@ -50,8 +50,7 @@ def test_team_and_wave_kernels_reach_the_same_prices(cuda, monkeypatch, zipf_sma
     for kernel in ("team", "wave"):
         if hot is not None:
             monkeypatch.setenv("PDHCG_HOT", str(hot))
-        if kernel == "wave":
-            monkeypatch.setenv("PDHCG_TEAM", "0")
+        monkeypatch.setenv("PDHCG_TEAM", "0" if kernel == "wave" else "2")
         M = pdhcg.Market.from_synth(mk, device=cuda)
         monkeypatch.delenv("PDHCG_TEAM", raising=False)
         monkeypatch.delenv("PDHCG_HOT", raising=False)
@@ -139,7 +138,7 @@ def test_backward_with_long_rows(cuda):
     st, du_i, dw_i, _ = oracle.implicit_grad(n, m, row_ptr, col, u, w, ref.x, ref.p, g)
     assert st == oracle.OK
     M = pdhcg.Market(row_ptr, col, u, w, m=m, device=cuda)
-    assert M.bins() == [(0, 1, n)]  # the team kernel, 128 threads x 8 entries per row
+    assert M.bins() == [(0, 0, n)]  # the one-wave-per-row kernel (all goods in LDS)
     sol = M.solve(tol=1e-7, max_iter=400000)
     assert sol.info.status == pdhcg.PDHCG_OK
     # the fixed-step map contracts slowly on this market (few buyers, long

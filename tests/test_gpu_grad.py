@@ -235,3 +235,61 @@ def test_batch_backward_matches_single_market(cuda, monkeypatch, gang):
         assert _rel(du[eo0:eo1], d1) <= 1e-5, (b, _rel(du[eo0:eo1], d1))
         assert _rel(dw[row_off[b]:row_off[b + 1]], w1) <= 1e-5, b
     B.close()
+
+
+def test_batch_backward_on_c3_markets_matches_implicit_derivative(cuda):
+    """The batched and differentiated workload's loss, sum_j (p_j - q_j)^2 with
+    q a seeded 1% perturbation of the oracle's prices, on markets of the
+    4096-market batch itself (generated one by one with the batch's per-market
+    seeds; eight of the first 400 spread over sizes up to 40,000 entries, so
+    that the oracle's implicit derivative is quick): the batched reverse mode
+    through 4096 unrolled steps (1024 and 2048 reported)
+    against the FP64 implicit derivative at the equilibrium, 1e-4 of the
+    largest entry."""
+    from paper_2506_06258_amd import synth
+    picks = []
+    for b in range(400):
+        rng = np.random.default_rng([1001, b])
+        n = int(round(np.exp(rng.uniform(np.log(64), np.log(8192)))))
+        m = int(round(np.exp(rng.uniform(np.log(16), np.log(2048)))))
+        q = float(rng.uniform(0.05, 0.30))
+        picks.append((int(round(n * m * q)), b))
+    # eight markets spread over sizes up to 40,000 entries
+    small = sorted(t for t in picks if t[0] <= 40000)
+    picks = [small[int(round(k * (len(small) - 1) / 7))][1] for k in range(8)]
+    markets, refs, gs = [], [], []
+    for b in picks:
+        rng = np.random.default_rng([1001, b])
+        n = int(round(np.exp(rng.uniform(np.log(64), np.log(8192)))))
+        m = int(round(np.exp(rng.uniform(np.log(16), np.log(2048)))))
+        q = float(rng.uniform(0.05, 0.30))
+        rp, col, u, w = synth._sample_market(rng, n, m, q)
+        mk = synth.Market(n, m, rp.astype(np.int32), col, u, w, f"c3[{b}]")
+        ref = oracle.solve(n, m, mk.row_ptr, col, u.astype(np.float64), w.astype(np.float64),
+                           tol=1e-13, max_iter=4000000)
+        assert ref.status == oracle.OK, b
+        qp = ref.p * (1.0 + 0.01 * np.random.default_rng(b).normal(size=m))
+        g = 2.0 * (ref.p - qp)
+        st, du_i, dw_i, _ = oracle.implicit_grad(n, m, mk.row_ptr, col, u, w, ref.x, ref.p, g)
+        assert st == oracle.OK, b
+        markets.append(mk)
+        refs.append((du_i, dw_i))
+        gs.append(g)
+    bt = synth.batch_from_markets(markets)
+    B = pdhcg.Batch(bt, device=cuda)
+    st, p, x, infos = B.solve(tol=1e-7, max_iter=400000)
+    assert st == pdhcg.PDHCG_OK
+    row_off = np.concatenate([[0], np.cumsum([mk.n for mk in markets])])
+    for K in (1024, 2048, 4096):
+        du, dw = B.backward(x, p, [i.omega for i in infos], torch.tensor(np.concatenate(gs)),
+                            unroll=K, ckpt_every=32)
+        du, dw = du.double().cpu().numpy(), dw.double().cpu().numpy()
+        errs = []
+        for k, (du_i, dw_i) in enumerate(refs):
+            eu = _rel(du[B.edge_off[k]:B.edge_off[k + 1]], du_i)
+            ew = _rel(dw[row_off[k]:row_off[k + 1]], dw_i)
+            errs.append((picks[k], markets[k].n, markets[k].m, markets[k].nnz, float(eu), float(ew)))
+        print(f"c3 markets, unroll {K} (b, n, m, nnz, du err, dw err):", errs)
+    for b, n, m, nnz, eu, ew in errs:
+        assert eu <= 1e-4 and ew <= 1e-4, (b, n, m, eu, ew)
+    B.close()

@@ -1849,8 +1849,11 @@ int32_t backward_impl(pdhcg_market mk, const float *x, const float *p, double om
   HIPC(launch_gather_f32_to_f64(p, mk->perm, pw, m, st));
   HIPC(launch_colsum_atomic(mk->col, x, nnz, c, m, st));
   HIPC(hipMemcpyAsync(cp, c, (size_t)m * sizeof(double), hipMemcpyDeviceToDevice, st));
+  // (it stops at the last checkpoint: the steps after it are recomputed by
+  // the reverse sweep anyway)
   const float *xcur = x;
-  for (int j = 0; j < K; ++j) {
+  const int jlast = (nck - 1) * L;
+  for (int j = 0; j <= jlast; ++j) {
     if (j % L == 0) {
       const int q = j / L;
       HIPC(hipMemcpyAsync(ck_x + (size_t)q * nnz, xcur, (size_t)nnz * sizeof(float),
@@ -1862,6 +1865,7 @@ int32_t backward_impl(pdhcg_market mk, const float *x, const float *p, double om
       HIPC(hipMemcpyAsync(ck_cp + (size_t)q * m, cp, (size_t)m * sizeof(double),
                           hipMemcpyDeviceToDevice, st));
     }
+    if (j == jlast) break;
     float *xnext = (j % 2 == 0) ? xa : xb;
     int32_t rc = forward(xcur, xnext);
     if (rc != PDHCG_OK) return rc;

@@ -1142,10 +1142,12 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_backward(BatchDev bd, Bat
       lcp[j] = lc[j];
     }
     __syncthreads();
-    // forward sweep, one checkpoint every L steps (x ping-pongs between R0
-    // and R1, which the reverse sweep takes over afterwards)
+    // forward sweep, one checkpoint every L steps, up to the last one (x
+    // ping-pongs between R0 and R1, which the reverse sweep takes over
+    // afterwards)
     const float *xc = x0;
-    for (int j = 0; j < a.K; ++j) {
+    const int jlast = (a.nck - 1) * a.L;
+    for (int j = 0; j <= jlast; ++j) {
       if (j % a.L == 0) {
         const int q = j / a.L;
         float *dst = ckx(q);
@@ -1158,6 +1160,7 @@ __global__ __launch_bounds__(kBatchBlock) void k_batch_backward(BatchDev bd, Bat
         }
         __syncthreads();
       }
+      if (j == jlast) break;
       float *xo = (j % 2 == 0) ? R0 : R1;
       forward(xc, xo);
       xc = xo;

@@ -152,8 +152,9 @@ def euler_w_residual(M, mk, s, g, dw, torch):
 
 def backward_leg(args, M, mk, s, pdhcg, torch):
     """Reverse mode (pdhcg_backward) through `backward_unroll` fixed-step
-    iterations from the solution, checkpoints every 16: one forward sweep,
-    one recomputed forward pass and one adjoint pass per step."""
+    iterations from the solution, checkpoints every 16: a forward sweep up to
+    the last checkpoint (K - 16 steps), one recomputed forward pass and one
+    adjoint pass per step."""
     K = args.backward_unroll
     g = torch.randn(mk.m, device=M.device, generator=torch.Generator(device=M.device).manual_seed(7))
     M.backward(s.x, s.p, s.info.omega, g, unroll=4, ckpt_every=2)  # warmup
@@ -162,10 +163,11 @@ def backward_leg(args, M, mk, s, pdhcg, torch):
     _, dw = M.backward(s.x, s.p, s.info.omega, g, unroll=K, ckpt_every=16)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t1
-    # per step: two forward passes without the average (u 4, id 2, x read 4,
-    # x write 4 B/edge) and one adjoint pass (u 4, id 2, x 4, R in 4, R out 4,
-    # dL/du read and write 8 B/edge)
-    per_edge = 2 * 14 + 26
+    # forward passes without the average (u 4, id 2, x read 4, x write 4
+    # B/edge): K - 16 in the sweep and K recomputed; adjoint passes (u 4, id 2,
+    # x 4, R in 4, R out 4, dL/du read and write 8 B/edge): K
+    L = min(16, K)
+    per_edge = (14 * ((K - L) + K) + 26 * K) / K
     eul = euler_w_residual(M, mk, s, g, dw, torch)
     log(f"backward: {K} unrolled steps in {dt:.3f}s, budget Euler residual {eul:.2e}")
     return {"workload": f"pdhcg_backward on the same market, {K} unrolled fixed steps, "

@@ -8,6 +8,7 @@
   python -m paper_2506_06258_amd.profile_run ksweep
   python -m paper_2506_06258_amd.profile_run jd
   python -m paper_2506_06258_amd.profile_run longrows [--iters 24]
+  python -m paper_2506_06258_amd.profile_run table2 [--seeds 3]
   python -m paper_2506_06258_amd.profile_run pdhg
   python -m paper_2506_06258_amd.profile_run theory [--K 256] [--restarts 16]
   python -m paper_2506_06258_amd.profile_run summarize --stats DIR
@@ -235,6 +236,50 @@ def run_jd() -> None:
     M.close()
 
 
+# Table 2 of the paper (Sec. 5.1): PDHCG to relative KKT 1e-4 on one
+# NVIDIA H100 (Julia/CUDA), geometric means over 10 random instances:
+# (n, m, q) -> (iterations, seconds).
+TABLE2 = [((1000, 400, 0.2), (2612, 1.7)), ((10000, 4000, 0.02), (2758, 3.6)),
+          ((100000, 4000, 0.02), (1200, 8.3)), ((1000000, 4000, 0.02), (2283, 116.3)),
+          ((10000000, 4000, 0.01), (2423, 589.7))]
+
+
+def run_table2(seeds: int) -> None:
+    """The markets of Table 2 (synth.table2_market), restarted PDHCG to rel.
+    KKT 1e-4 with default parameters: iterations and seconds per instance
+    (a short solve first loads the kernels), the paper's figures beside."""
+    import math
+
+    import torch
+
+    sys.path.insert(0, ROOT)
+    from paper_2506_06258_amd import pdhcg, synth
+
+    dev = torch.device("cuda:0")
+    print("| n | m | q | nnz | instances | iterations (geo. mean) | seconds (geo. mean) | "
+          "paper iterations | paper seconds (H100) |")
+    print("|---|---|---|---|---|---|---|---|---|")
+    for (n, m, q), (pit, psec) in TABLE2:
+        its, secs, nnz = [], [], 0
+        for seed in range(seeds):
+            mk = synth.table2_market(n, m, q, seed)
+            nnz = mk.nnz
+            M = pdhcg.Market.from_synth(mk, device=dev)
+            M.solve(tol=1e-4, max_iter=64)
+            torch.cuda.synchronize()
+            s = M.solve(tol=1e-4, max_iter=100000)
+            torch.cuda.synchronize()
+            assert s.info.status == pdhcg.PDHCG_OK, s.info.status
+            its.append(s.info.iters)
+            secs.append(s.info.seconds)
+            M.close()
+            del mk
+        gi = math.exp(sum(math.log(v) for v in its) / len(its))
+        gs = math.exp(sum(math.log(v) for v in secs) / len(secs))
+        print(f"| {n} | {m} | {q:g} | {nnz} | {seeds} | {gi:.0f} | {gs:.3f} | {pit} | {psec} |",
+              flush=True)
+
+
 def run_longrows(iters: int) -> None:
     """Row pass of markets whose rows all exceed 512 entries (fixed degree
     800, 1500, 3000, 6000 and 12000), every good in LDS and 1024 goods in LDS, the long
@@ -361,6 +406,8 @@ def main() -> None:
     sub.add_parser("exchange")
     sub.add_parser("ksweep")
     sub.add_parser("jd")
+    t2 = sub.add_parser("table2")
+    t2.add_argument("--seeds", type=int, default=3)
     lr = sub.add_parser("longrows")
     lr.add_argument("--iters", type=int, default=24)
     pg = sub.add_parser("pdhg")
@@ -395,6 +442,8 @@ def main() -> None:
         run_ksweep()
     elif a.cmd == "jd":
         run_jd()
+    elif a.cmd == "table2":
+        run_table2(a.seeds)
     elif a.cmd == "longrows":
         run_longrows(a.iters)
     elif a.cmd == "pdhg":

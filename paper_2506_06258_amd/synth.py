@@ -154,6 +154,33 @@ def fixed_degree_market(n: int, m: int, d: int, seed: int,
     return Market(n, m, row_ptr, col, u, w, name or f"fixdeg-{n}x{m}-d{d}-s{seed}")
 
 
+def table2_market(n: int, m: int, q: float, seed: int, dtype=np.float32) -> Market:
+    """The synthetic Fisher markets of the paper's Table 2 (Sec. 5.1): buyer i
+    values each good independently with probability q (row degree
+    d_i ~ Binomial(m, q), at least 1, goods uniform and distinct), u_ij ~ U(0, 1)
+    on the stored entries, w_i ~ U(0, 1)."""
+    rng = np.random.default_rng([seed, 2])
+    deg = np.maximum(rng.binomial(m, q, size=n), 1).astype(np.int64)
+    row_ptr = np.zeros(n + 1, np.int64)
+    np.cumsum(deg, out=row_ptr[1:])
+    col = np.empty(int(row_ptr[-1]), np.int32)
+    order = np.argsort(deg, kind="stable")
+    sdeg = deg[order]
+    bounds = np.flatnonzero(np.diff(sdeg)) + 1
+    for grp in np.split(order, bounds):
+        d = int(deg[grp[0]])
+        C = _distinct_sorted_rows(rng, grp.size, d, m)
+        idx = (row_ptr[grp][:, None] + np.arange(d)[None, :]).reshape(-1)
+        col[idx] = C.reshape(-1)
+    if (np.bincount(col, minlength=m) == 0).any():
+        raise RuntimeError("a good received no buyer; raise n q")
+    u = rng.uniform(0.0, 1.0, size=col.size).astype(dtype)
+    u = np.maximum(u, np.finfo(np.float32).tiny).astype(dtype)
+    w = rng.uniform(0.0, 1.0, size=n).astype(dtype)
+    w = np.maximum(w, np.finfo(np.float32).tiny).astype(dtype)
+    return Market(n, m, row_ptr.astype(np.int32), col, u, w, f"table2-{n}x{m}-q{q:g}-s{seed}")
+
+
 def _zipf_rows(args):
     """Goods of one block of rows of zipf_market (see there)."""
     seed, block, d, m, ranking = args

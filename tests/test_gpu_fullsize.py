@@ -363,3 +363,26 @@ def test_arrow_debreu_1e5(cuda):
     say(f"Arrow-Debreu: oracle KKT of the last inner point {r:.3e} {parts}")
     assert r <= 1e-5
     M.close()
+
+
+def test_table2_markets(cuda):
+    """The paper's Table 2 markets (Sec. 5.1 generator): the smallest shape
+    against the oracle's prices at rel. KKT 1e-6, the 8e7-edge shape to rel.
+    KKT 1e-4 with the oracle's FP64 KKT of the returned point."""
+    mk = synth.table2_market(1000, 400, 0.2, 0)
+    ref = oracle.solve(mk.n, mk.m, mk.row_ptr, mk.col, mk.u.astype(np.float64),
+                       mk.w.astype(np.float64), tol=1e-11, max_iter=400000)
+    assert ref.status == oracle.OK
+    M = pdhcg.Market.from_synth(mk, device=cuda)
+    sol = M.solve(tol=1e-6, max_iter=400000)
+    assert sol.info.status == pdhcg.PDHCG_OK
+    p = sol.p.double().cpu().numpy()
+    err = np.max(np.abs(p - ref.p)) / np.max(ref.p)
+    say(f"table 2, 1000 x 400 x 0.2: {sol.info.iters} iterations, price error {err:.2e}")
+    assert err <= 1e-5
+    M.close()
+    say("table 2, 1e6 x 4000 x 0.02: generate")
+    mk = synth.table2_market(1000000, 4000, 0.02, 0)
+    M = pdhcg.Market.from_synth(mk, device=cuda)
+    solve_and_check(mk, M, cuda, "table 2, 1e6 x 4000 x 0.02")
+    M.close()

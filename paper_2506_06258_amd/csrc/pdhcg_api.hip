@@ -832,11 +832,12 @@ RowIO row_io_state(const pdhcg_params *p) {
 // Column sums of the goods beyond LDS (mode 7) of the allocation x (or of
 // the trial allocation when use_state) into out: the panel sums, or the
 // gathers by column when the goods do not fit the panels.
+// With sum_panels = 0 the panel partials are left for k_col_decide to sum.
 int32_t enqueue_cold_sums(pdhcg_market mk, const MarketDev &md, int use_state, const float *x,
-                          double *out, hipStream_t st) {
+                          double *out, hipStream_t st, int sum_panels = 1) {
   HIPC(launch_cold_sums(md, use_state, x, out, mk->cold_mean_degree, st));
   HIPC(launch_panel_sums(md, use_state, out, mk->pval, mk->pid, mk->pbeg, mk->ppart, mk->pchunks,
-                         mk->cold_ptr != nullptr, st));
+                         mk->cold_ptr != nullptr, sum_panels, st));
   return PDHCG_OK;
 }
 
@@ -851,12 +852,15 @@ int32_t enqueue_step(pdhcg_market mk, const RowIO &io, hipEvent_t ev0 = nullptr,
   else
     for (const Bin &b : mk->bins)
       HIPC(launch_row_pass(md, mk->bindev(b), b.G, b.E, mk->lds_row, io, b.nwg, mk->stream));
+  // the panel partials (goods beyond LDS) are summed by k_col_decide
+  const bool panels = mk->lds_row == 7 && md.npanel > 0 && mk->hot < mk->m;
   if (mk->lds_row == 7) {
-    const int32_t rc = enqueue_cold_sums(mk, md, 1, nullptr, nullptr, mk->stream);
+    const int32_t rc = enqueue_cold_sums(mk, md, 1, nullptr, nullptr, mk->stream, panels ? 0 : 1);
     if (rc != PDHCG_OK) return rc;
   }
   if (ev1) HIPC(hipEventRecord(ev1, mk->stream));
-  HIPC(launch_col_decide(md, mk->total_wg, mk->lds_row & 1, mk->stream));
+  HIPC(launch_col_decide(md, mk->total_wg, mk->lds_row & 1, panels ? mk->ppart : nullptr,
+                         mk->pchunks, mk->cold_ptr != nullptr, mk->stream));
   return PDHCG_OK;
 }
 

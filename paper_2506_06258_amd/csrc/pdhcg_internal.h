@@ -198,8 +198,10 @@ hipError_t launch_pstep(const MarketDev &md, int zero_ctry, hipStream_t st);
 // and trial column sums of DevState, else x / out.
 hipError_t launch_cold_sums(const MarketDev &md, int use_state, const float *x, double *out,
                             int mean_degree, hipStream_t st);
+// ppart (or null): panel partials of the goods from hot on, summed into
+// c_try by k_col_decide (added to c_try when pacc).
 hipError_t launch_col_decide(const MarketDev &md, int total_wg, int from_partials,
-                             hipStream_t st);
+                             const double *ppart, int pchunks, int pacc, hipStream_t st);
 hipError_t launch_eval_row(const MarketDev &md, const BinDev &bin, int G, int E,
                            int lds_mode, const EvalIO &io, int nwg, int total_wg,
                            hipStream_t st);
@@ -244,9 +246,11 @@ hipError_t launch_adj_long(const MarketDev &md, const BinDev &bin, int lds, cons
 int team_code(int d);
 hipError_t launch_row_team(const MarketDev &md, const BinDev &bin, int code, int lds_mode,
                            const RowIO &io, int nwg, hipStream_t st);
+// With sum = 0 only the partials are written (the caller sums them, as
+// launch_col_decide does).
 hipError_t launch_panel_sums(const MarketDev &md, int use_state, double *out, const float *pval,
                              const uint16_t *pid, const int64_t *pbeg, double *part, int nchunk,
-                             int accumulate, hipStream_t st);
+                             int accumulate, int sum, hipStream_t st);
 // k-section search with one wave per row and one lane per candidate
 // (pdhcg_ksec.hip); rows of at most kKwaveMaxRow entries, column partials
 // of every good in LDS.

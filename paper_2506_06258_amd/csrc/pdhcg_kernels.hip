@@ -445,8 +445,13 @@ __global__ __launch_bounds__(kColBlock) void k_col_chunks(MarketDev md, int tota
 }
 
 // c_try from the chunk sums (nq chunks, fixed order), dp^T (c_try - c) and
-// |dp|^2 per block, and the last block to arrive applies the step rule.
-__global__ __launch_bounds__(kColBlock) void k_col_decide(MarketDev md, int total_wg, int nq) {
+// |dp|^2 per block (the step rule follows in k_step_rule).  With ppart the
+// goods from hot on also take their panel partial sums (pchunks chunks per
+// panel, in chunk order), added to what k_cold_sums wrote when pacc, so the
+// panels need no summing kernel of their own.
+__global__ __launch_bounds__(kColBlock) void k_col_decide(MarketDev md, int total_wg, int nq,
+                                                          const double *ppart, int pchunks,
+                                                          int pacc) {
   DevState *S = md.S;
   const int m = md.m;
   const int tile = blockIdx.x;
@@ -459,6 +464,13 @@ __global__ __launch_bounds__(kColBlock) void k_col_decide(MarketDev md, int tota
     double c = 0.0;
     for (int k = 0; k < nq; ++k) c += md.colchunk[(size_t)k * m + j];
     ctry[j] = c;
+  }
+  if (ppart && j >= md.hot && j < m) {
+    const int g = j - md.hot;
+    const double *src = ppart + (size_t)(g >> kPanelShift) * pchunks * kPanelW + (g & (kPanelW - 1));
+    double s = 0.0;
+    for (int r = 0; r < pchunks; ++r) s += src[(size_t)r * kPanelW];
+    ctry[j] = pacc ? ctry[j] + s : s;
   }
   double inter = 0.0, dp2 = 0.0;
   if (j < m) {
@@ -1097,7 +1109,7 @@ hipError_t launch_cold_sums(const MarketDev &md, int use_state, const float *x, 
 }
 
 hipError_t launch_col_decide(const MarketDev &md, int total_wg, int from_partials,
-                             hipStream_t st) {
+                             const double *ppart, int pchunks, int pacc, hipStream_t st) {
   const int tiles = (md.m + kColBlock - 1) / kColBlock;
   const int chunks = from_partials ? (total_wg < kColChunks ? total_wg : kColChunks) : 0;
   if (chunks > 0 && md.hot > 0) {
@@ -1107,7 +1119,7 @@ hipError_t launch_col_decide(const MarketDev &md, int total_wg, int from_partial
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_col_decide, dim3(tiles), dim3(kColBlock), 0, st, md, total_wg,
-                     md.hot > 0 ? chunks : 0);
+                     md.hot > 0 ? chunks : 0, ppart, pchunks, pacc);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_step_rule, dim3(1), dim3(kColBlock), 0, st, md, total_wg, tiles, 0);
@@ -1121,7 +1133,8 @@ hipError_t launch_col_decide_pdhg(const MarketDev &md, int total_wg, hipStream_t
                      dim3(kColBlock), 0, st, md, total_wg);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_col_decide, dim3(tiles), dim3(kColBlock), 0, st, md, total_wg, chunks);
+  hipLaunchKernelGGL(k_col_decide, dim3(tiles), dim3(kColBlock), 0, st, md, total_wg, chunks,
+                     nullptr, 0, 0);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_step_rule, dim3(1), dim3(kColBlock), 0, st, md, total_wg, tiles, 1);

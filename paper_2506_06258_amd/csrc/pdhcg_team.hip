@@ -418,13 +418,13 @@ hipError_t launch_row_team(const MarketDev &md, const BinDev &bin, int code, int
 
 hipError_t launch_panel_sums(const MarketDev &md, int use_state, double *out, const float *pval,
                              const uint16_t *pid, const int64_t *pbeg, double *part, int nchunk,
-                             int accumulate, hipStream_t st) {
+                             int accumulate, int sum, hipStream_t st) {
   const int ncold = md.m - md.hot;
   if (md.npanel <= 0 || ncold <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_panel_part, dim3(nchunk, md.npanel), dim3(1024), kPanelW * sizeof(double), st,
                      pval, pid, pbeg, part);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !sum) return e;
   hipLaunchKernelGGL(k_panel_sum, dim3((ncold + 255) / 256), dim3(256), 0, st, md, use_state, out,
                      part, nchunk, accumulate);
   return hipGetLastError();

@@ -106,6 +106,11 @@ struct pdhcg_market_s {
   int32_t *perm = nullptr, *inv = nullptr;
   uint16_t *col16 = nullptr;  // 2-byte good ids (LDS modes 1 and 3)
   int32_t *cold_ptr = nullptr, *cold_idx = nullptr;  // goods beyond LDS by column (mode 7)
+  // every entry of the goods beyond LDS by column, with its row, and the
+  // rows' dual values, for the KKT pass (mode 7)
+  int32_t *ecold_ptr = nullptr, *ecold_idx = nullptr, *ecold_row = nullptr;
+  double *yrow = nullptr;
+  int32_t ecold_mean_degree = 0;
   // panel buffers of the cold entries of team-kernel rows (mode 7)
   float *pval = nullptr;
   uint16_t *pid = nullptr;
@@ -139,6 +144,10 @@ struct pdhcg_market_s {
     d.cslot = cslot;
     d.npanel = npanel;
     d.pad_panel = 0;
+    d.ecold_ptr = ecold_ptr;
+    d.ecold_idx = ecold_idx;
+    d.ecold_row = ecold_row;
+    d.yrow = yrow;
     d.srow = srow;
     d.row_ptr = row_ptr;
     d.col = col;
@@ -267,6 +276,7 @@ void pdhcg_market_destroy(pdhcg_market mk) {
   f(mk->rowpart); f(mk->colblk); f(mk->cacc); f(mk->S);
   f(mk->colchunk); f(mk->perm); f(mk->inv); f(mk->col16); f(mk->cold_ptr); f(mk->cold_idx); f(mk->srow);
   f(mk->pval); f(mk->pid); f(mk->proff); f(mk->pbeg); f(mk->ppart); f(mk->cslot); f(mk->gmax); f(mk->gsum);
+  f(mk->ecold_ptr); f(mk->ecold_idx); f(mk->ecold_row); f(mk->yrow);
   f(mk->pdhg_buf);
   for (auto &b : mk->bins) {
     f(b.d_rows);
@@ -682,6 +692,35 @@ extern "C" int32_t pdhcg_market_create(int32_t n, int32_t m, int64_t nnz, const 
       MK_HIPC(dalloc(&mk->cold_idx, std::max<size_t>(h_cold_idx.size(), 1)));
     }
   }
+  // KKT pass of the goods beyond LDS (mode 7): their entries column by
+  // column (in row order) with their rows, so that one segment of lanes per
+  // good takes its maxima and sums (device atomics on these goods, three per
+  // entry, ran at about 22 G/s)
+  std::vector<int32_t> h_ecold_ptr, h_ecold_idx, h_ecold_row;
+  if (mk->lds_row == 7 && mk->lds_eval && mk->hot < m) {
+    const int32_t hot = mk->hot, ncold = m - hot;
+    h_ecold_ptr.assign((size_t)ncold + 1, 0);
+    for (int64_t k = 0; k < nnz; ++k)
+      if (h_col[(size_t)k] >= hot) h_ecold_ptr[(size_t)(h_col[(size_t)k] - hot) + 1] += 1;
+    for (int32_t g = 0; g < ncold; ++g) h_ecold_ptr[(size_t)g + 1] += h_ecold_ptr[(size_t)g];
+    const size_t tot = (size_t)h_ecold_ptr[(size_t)ncold];
+    h_ecold_idx.resize(std::max<size_t>(tot, 1), 0);
+    h_ecold_row.resize(std::max<size_t>(tot, 1), 0);
+    std::vector<int32_t> fill(h_ecold_ptr.begin(), h_ecold_ptr.end() - 1);
+    for (int32_t i = 0; i < n; ++i)
+      for (int32_t k = h_rp[(size_t)i]; k < h_rp[(size_t)i + 1]; ++k) {
+        const int32_t c = h_col[(size_t)k];
+        if (c < hot) continue;
+        const int32_t sl = fill[(size_t)(c - hot)]++;
+        h_ecold_idx[(size_t)sl] = k;
+        h_ecold_row[(size_t)sl] = i;
+      }
+    mk->ecold_mean_degree = (int32_t)(tot / (size_t)std::max(ncold, 1));
+    MK_HIPC(dalloc(&mk->ecold_ptr, h_ecold_ptr.size()));
+    MK_HIPC(dalloc(&mk->ecold_idx, h_ecold_idx.size()));
+    MK_HIPC(dalloc(&mk->ecold_row, h_ecold_row.size()));
+    MK_HIPC(dalloc(&mk->yrow, (size_t)2 * n));
+  }
   // roots of long rows between solver passes (start of each search)
   if (std::any_of(mk->bins.begin(), mk->bins.end(), [](const Bin &b) { return b.G == 0; }))
     MK_HIPC(dalloc(&mk->srow, (size_t)n));
@@ -717,6 +756,14 @@ extern "C" int32_t pdhcg_market_create(int32_t n, int32_t m, int64_t nnz, const 
     if (!h_cold_idx.empty())
       MK_HIPC(hipMemcpyAsync(mk->cold_idx, h_cold_idx.data(), h_cold_idx.size() * 4,
                              hipMemcpyHostToDevice, st));
+  }
+  if (!h_ecold_ptr.empty()) {
+    MK_HIPC(hipMemcpyAsync(mk->ecold_ptr, h_ecold_ptr.data(), h_ecold_ptr.size() * 4,
+                           hipMemcpyHostToDevice, st));
+    MK_HIPC(hipMemcpyAsync(mk->ecold_idx, h_ecold_idx.data(), h_ecold_idx.size() * 4,
+                           hipMemcpyHostToDevice, st));
+    MK_HIPC(hipMemcpyAsync(mk->ecold_row, h_ecold_row.data(), h_ecold_row.size() * 4,
+                           hipMemcpyHostToDevice, st));
   }
   if (!h_col16.empty())
     MK_HIPC(hipMemcpyAsync(mk->col16, h_col16.data(), (size_t)nnz * 2, hipMemcpyHostToDevice, st));
@@ -892,6 +939,7 @@ int32_t enqueue_eval(pdhcg_market mk, EvalIO io) {
   for (const Bin &b : mk->bins)
     HIPC(launch_eval_row(md, mk->bindev(b), b.G, b.E, mk->lds_eval, io, b.nwg, mk->total_wg,
                          mk->stream));
+  if (mk->lds_eval) HIPC(launch_eval_cold(md, io, mk->ecold_mean_degree, mk->stream));
   if (mk->lds_eval) HIPC(launch_eval_chunks(md, io, mk->total_wg, mk->stream));
   HIPC(launch_eval_col(md, io, mk->total_wg, mk->lds_eval, mk->stream));
   return PDHCG_OK;

@@ -80,6 +80,15 @@ struct MarketDev {
   // for the entries of the goods in LDS and of team-kernel rows)
   const int32_t *cslot;
   int32_t npanel, pad_panel;
+  // every entry of the goods from hot on, column by column in row order,
+  // with its row (KKT pass of relabelled markets, k_eval_cold; null when
+  // their maxima and sums are taken with device atomics), and the rows'
+  // dual values y = w / u^T x of the current and averaged points [2][n]
+  // written by the KKT row kernels for it
+  const int32_t *ecold_ptr;
+  const int32_t *ecold_idx;
+  const int32_t *ecold_row;
+  double *yrow;
   const int32_t *row_ptr;
   const int32_t *col;
   const uint16_t *col16;  // the same good ids in 16 bits, for markets whose
@@ -200,6 +209,9 @@ hipError_t launch_cold_sums(const MarketDev &md, int use_state, const float *x, 
                             int mean_degree, hipStream_t st);
 // ppart (or null): panel partials of the goods from hot on, summed into
 // c_try by k_col_decide (added to c_try when pacc).
+// KKT column maxima and sums of the goods from hot on from the lists
+// ecold_* (one segment of lanes per good, no atomics), into io.gmax / io.gsum.
+hipError_t launch_eval_cold(const MarketDev &md, const EvalIO &io, int mean_degree, hipStream_t st);
 hipError_t launch_col_decide(const MarketDev &md, int total_wg, int from_partials,
                              const double *ppart, int pchunks, int pacc, hipStream_t st);
 hipError_t launch_eval_row(const MarketDev &md, const BinDev &bin, int G, int E,

@@ -418,6 +418,82 @@ __global__ __launch_bounds__(256) void k_cold_sums(MarketDev md, int use_state, 
   }
 }
 
+// KKT column quantities of the goods from hot on (relabelled markets) from
+// their entry lists: a segment of GC lanes per good runs over the good's
+// entries (in row order, 4 loads in flight per lane), forms the same keys
+// ord_key(u_ij y_i - p_j) as the KKT row kernels (y_i from yrow, prices
+// folded the same way) and the float64 sum of the entries of the averaged
+// point (or of the current one when want_cc), and writes the good's maxima
+// and sum to io.gmax / io.gsum.  The row kernels leave these goods to it.
+template <int GC>
+__global__ __launch_bounds__(256) void k_eval_cold(MarketDev md, EvalIO io) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int r = lane & (GC - 1);
+  const int m = md.m, hot = md.hot, ncold = m - hot;
+  const size_t n = (size_t)md.n;
+  const bool has_avg = io.xa != nullptr;
+  const bool want_sum = (has_avg && !io.want_cc) || io.want_cc;
+  const float wf = io.wfold;
+  const int segs = (int)(gridDim.x * (blockDim.x / GC));
+  // as in k_cold_sums: the segments of a wave run the wave's largest trip count
+  for (int g0 = (blockIdx.x * blockDim.x + threadIdx.x - r) / GC; g0 - (lane / GC) < ncold;
+       g0 += segs) {
+    const int g = g0;
+    const bool gv = g < ncold;
+    const int j = hot + (gv ? g : 0);
+    const int b = gv ? md.ecold_ptr[g] : 0, e = gv ? md.ecold_ptr[g + 1] : 0;
+    const double p = io.pc[j];
+    double pa = has_avg ? io.pa[j] : 0.0;
+    if (has_avg && wf != 0.0f) pa = (wf == 1.0f) ? p : pa + (p - pa) * (double)wf;
+    unsigned int kc = 0u, ka = 0u;
+    double acc = 0.0;
+    int trips = (e - b + 4 * GC - 1) / (4 * GC);
+    for (int o = 1; o < kWave / GC; o <<= 1) trips = max(trips, __shfl_xor(trips, o * GC));
+    for (int t0 = 0; t0 < trips; ++t0) {
+      const int k0 = b + r + t0 * 4 * GC;
+      int q[4], row[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const bool ok = k0 + t * GC < e;
+        q[t] = ok ? md.ecold_idx[k0 + t * GC] : -1;
+        row[t] = ok ? md.ecold_row[k0 + t * GC] : 0;
+      }
+      float u[4], xc[4], xa[4];
+      double yc[4], ya[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int k = q[t] >= 0 ? q[t] : 0;
+        u[t] = md.uh[k];
+        xc[t] = io.xc[k];
+        xa[t] = has_avg ? io.xa[k] : 0.0f;
+        yc[t] = md.yrow[row[t]];
+        ya[t] = has_avg ? md.yrow[n + row[t]] : 0.0;
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        if (q[t] < 0) continue;
+        const double vc = (double)u[t] * yc[t];
+        kc = max(kc, ord_key((float)(vc - p)));
+        if (has_avg) {
+          const double va = (double)u[t] * ya[t];
+          ka = max(ka, ord_key((float)(va - pa)));
+        }
+        if (want_sum) acc += (double)(io.want_cc ? xc[t] : xa[t]);
+      }
+    }
+    for (int o = 1; o < GC; o <<= 1) {
+      kc = max(kc, (unsigned int)__shfl_xor((int)kc, o));
+      ka = max(ka, (unsigned int)__shfl_xor((int)ka, o));
+    }
+    acc = seg_sum_d<GC>(acc);
+    if (gv && r == 0) {
+      io.gmax[j] = kc;
+      if (has_avg) io.gmax[(size_t)m + j] = ka;
+      if (want_sum) io.gsum[j] = acc;
+    }
+  }
+}
+
 // Chunk sums of the per-workgroup column partials: block (t, q) adds the
 // partial rows of chunk q for tile t's goods (partial rows cover the goods
 // [0, hot): all goods unless the market is hybrid, where the others are
@@ -593,8 +669,10 @@ __global__ __launch_bounds__(kRowBlock) void k_eval_row(MarketDev md, BinDev bin
   const bool has_avg = io.xa != nullptr;
   const bool sum_avg = has_avg && !io.want_cc;
   // LDS mode: goods [0, hot) in LDS, the others in the device-wide
-  // accumulators io.gmax / io.gsum
+  // accumulators io.gmax / io.gsum, or (with the lists ecold_*) left to
+  // k_eval_cold, which takes the rows' y from yrow
   const int hot = (LDS_MODE == 1) ? md.hot : 0;
+  const bool cg = (LDS_MODE == 1) && md.ecold_ptr != nullptr;
   double *lcs = lds_e;
   unsigned int *lMc = reinterpret_cast<unsigned int *>(lds_e + hot);
   unsigned int *lMa = lMc + hot;
@@ -693,6 +771,10 @@ __global__ __launch_bounds__(kRowBlock) void k_eval_row(MarketDev md, BinDev bin
     if (rv && r == 0) {
       if (io.tc) io.tc[i] = (float)(tc * (double)io.rowscale[i]);
       if (io.ta && has_avg) io.ta[i] = (float)(ta * (double)io.rowscale[i]);
+      if (cg) {
+        md.yrow[i] = yc;
+        md.yrow[(size_t)md.n + i] = ya;
+      }
       st[0] = fmax(st[0], yc);
       st[4] = fmax(st[4], ya);
     }
@@ -710,7 +792,7 @@ __global__ __launch_bounds__(kRowBlock) void k_eval_row(MarketDev md, BinDev bin
         st[3] = fmax(st[3], (double)xc[e]);
         const unsigned int bc = ord_key((float)(vc - pcj[e]));
         if (c < hot) atomicMax(&lMc[c], bc);
-        else atomicMax(&xMc[c], bc);
+        else if (!cg) atomicMax(&xMc[c], bc);
         if (has_avg) {
           const double va = (double)uh[e] * ya;
           const double ra = paj[e] - va;
@@ -721,9 +803,9 @@ __global__ __launch_bounds__(kRowBlock) void k_eval_row(MarketDev md, BinDev bin
           st[7] = fmax(st[7], (double)xa[e]);
           const unsigned int ba = ord_key((float)(va - paj[e]));
           if (c < hot) atomicMax(&lMa[c], ba);
-          else atomicMax(&xMa[c], ba);
+          else if (!cg) atomicMax(&xMa[c], ba);
         }
-        if (sum_avg || io.want_cc) {
+        if ((sum_avg || io.want_cc) && (c < hot || !cg)) {
           const double add = io.want_cc ? xc[e] : xa[e];
           atomicAdd(c < hot ? &lcs[c] : &xcs[c], add);
         }
@@ -1104,6 +1186,23 @@ hipError_t launch_cold_sums(const MarketDev &md, int use_state, const float *x, 
     case 16: hipLaunchKernelGGL(k_cold_sums<16>, dim3(blocks), dim3(256), 0, st, md, use_state, x, out); break;
     case 32: hipLaunchKernelGGL(k_cold_sums<32>, dim3(blocks), dim3(256), 0, st, md, use_state, x, out); break;
     default: hipLaunchKernelGGL(k_cold_sums<64>, dim3(blocks), dim3(256), 0, st, md, use_state, x, out); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_eval_cold(const MarketDev &md, const EvalIO &io, int mean_degree,
+                            hipStream_t st) {
+  const int ncold = md.m - md.hot;
+  if (ncold <= 0 || !md.ecold_ptr) return hipSuccess;
+  // lanes per good: about a quarter of the mean degree (4 loads in flight per lane)
+  const int gc = mean_degree >= 192 ? 64 : mean_degree >= 96 ? 32 : mean_degree >= 48 ? 16 : 8;
+  const int per_block = 256 / gc;
+  const int blocks = (int)std::min<int64_t>(((int64_t)ncold + per_block - 1) / per_block, 4096);
+  switch (gc) {
+    case 8: hipLaunchKernelGGL(k_eval_cold<8>, dim3(blocks), dim3(256), 0, st, md, io); break;
+    case 16: hipLaunchKernelGGL(k_eval_cold<16>, dim3(blocks), dim3(256), 0, st, md, io); break;
+    case 32: hipLaunchKernelGGL(k_eval_cold<32>, dim3(blocks), dim3(256), 0, st, md, io); break;
+    default: hipLaunchKernelGGL(k_eval_cold<64>, dim3(blocks), dim3(256), 0, st, md, io); break;
   }
   return hipGetLastError();
 }

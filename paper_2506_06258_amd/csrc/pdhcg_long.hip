@@ -261,6 +261,7 @@ __global__ __launch_bounds__(kRowBlock) void k_eval_long(MarketDev md, BinDev bi
   const bool has_avg = io.xa != nullptr;
   const bool sum_avg = has_avg && !io.want_cc;
   const int hot = (LDS_MODE == 1) ? md.hot : 0;
+  const bool cg = (LDS_MODE == 1) && md.ecold_ptr != nullptr;  // goods from hot on: k_eval_cold
   double *lcs = lds_e;
   unsigned int *lMc = reinterpret_cast<unsigned int *>(lds_e + hot);
   unsigned int *lMa = lMc + hot;
@@ -330,6 +331,10 @@ __global__ __launch_bounds__(kRowBlock) void k_eval_long(MarketDev md, BinDev bi
     if (lane == 0) {
       if (io.tc) io.tc[i] = (float)(tc * (double)io.rowscale[i]);
       if (io.ta && has_avg) io.ta[i] = (float)(ta * (double)io.rowscale[i]);
+      if (cg) {
+        md.yrow[i] = yc;
+        md.yrow[(size_t)md.n + i] = ya;
+      }
       st[0] = fmax(st[0], yc);
       st[4] = fmax(st[4], ya);
     }
@@ -369,7 +374,7 @@ __global__ __launch_bounds__(kRowBlock) void k_eval_long(MarketDev md, BinDev bi
           st[3] = fmax(st[3], (double)xc);
           const unsigned int bc = ord_key((float)(vc - p));
           if (c < hot) atomicMax(&lMc[c], bc);
-          else atomicMax(&xMc[c], bc);
+          else if (!cg) atomicMax(&xMc[c], bc);
           const float xa = xav[e];
           if (has_avg) {
             double pa = pav[e];
@@ -383,10 +388,10 @@ __global__ __launch_bounds__(kRowBlock) void k_eval_long(MarketDev md, BinDev bi
             st[7] = fmax(st[7], (double)xa);
             const unsigned int ba = ord_key((float)(va - pa));
             if (c < hot) atomicMax(&lMa[c], ba);
-            else atomicMax(&xMa[c], ba);
+            else if (!cg) atomicMax(&xMa[c], ba);
             if (io.xanc) st[9] += (double)(xa - z[e]) * (double)(xa - z[e]);
           }
-          if (sum_avg || io.want_cc) {
+          if ((sum_avg || io.want_cc) && (c < hot || !cg)) {
             const double add = io.want_cc ? xc : xa;
             atomicAdd(c < hot ? &lcs[c] : &xcs[c], add);
           }

@@ -143,6 +143,34 @@ def test_row_prox_mixed_degrees(cuda):
     check_row_prox(mk, cuda, x_in, p, 0.01)
 
 
+def test_merged_bins_match_oracle(cuda, monkeypatch):
+    """Register-resident bins of equal lane count merged into the one with the
+    most entries per lane (the default where the LDS holds one workgroup per
+    CU), so that most rows fill a small part of their shape: the row prox
+    against the oracle's, and the solved prices against the oracle's."""
+    mk = f32(synth.bernoulli_market(3000, 700, 0.04, 5, w_mode="uniform"))
+    monkeypatch.setenv("PDHCG_MERGE_BINS", "0")
+    M = pdhcg.Market.from_synth(mk, device=cuda)
+    plain = M.bins()
+    M.close()
+    monkeypatch.setenv("PDHCG_MERGE_BINS", "1")
+    M = pdhcg.Market.from_synth(mk, device=cuda)
+    merged = M.bins()
+    lanes = [g for g, _, _ in merged if g > 0]
+    assert len(merged) < len(plain) and len(lanes) == len(set(lanes)), (plain, merged)
+    assert sum(r for _, _, r in merged) == mk.n
+    rng = np.random.default_rng(11)
+    x_in, p = prox_state(mk, rng, "random")
+    check_row_prox(mk, cuda, x_in, p, 0.01)
+    ora = oracle.solve(mk.n, mk.m, mk.row_ptr, mk.col, mk.u.astype(np.float64),
+                       mk.w.astype(np.float64), tol=1e-11, max_iter=400000)
+    assert ora.status == oracle.OK
+    sol = M.solve(tol=1e-6, max_iter=200000)
+    assert sol.info.status == pdhcg.PDHCG_OK, pdhcg.pdhcg_last_error()
+    assert rel_err(sol.p.cpu().numpy().astype(np.float64), ora.p) <= 1e-5
+    M.close()
+
+
 def trajectory(mk, dev, iters, **kw):
     deg = np.bincount(mk.col, minlength=mk.m)
     eta = 0.9 / np.sqrt(deg.max())

@@ -601,8 +601,8 @@ extern "C" int32_t pdhcg_market_create(int32_t n, int32_t m, int64_t nnz, const 
   // other rows use fixed slots when at least kSlotShare of their entries
   // are of such goods (the slot of every entry is read, so a small share is
   // cheaper to gather); with more than kMaxPanels panels every entry of
-  // these goods is gathered.
-  constexpr double kSlotShare = 0.2;
+  // these goods is gathered.  PDHCG_SLOT_SHARE overrides the share.
+  constexpr double kSlotShare = 0.1;
   std::vector<int32_t> h_cold_ptr, h_cold_idx, h_proff, h_cslot;
   std::vector<int64_t> h_pbeg;
   std::vector<uint16_t> h_pid;
@@ -628,8 +628,10 @@ extern "C" int32_t pdhcg_market_create(int32_t n, int32_t m, int64_t nnz, const 
         other_cold += h_col[(size_t)k] >= hot ? 1 : 0;
       }
     }
+    double share = kSlotShare;
+    if (const char *e = std::getenv("PDHCG_SLOT_SHARE")) share = std::atof(e);
     const bool fixed = np <= kMaxPanels && other_cold > 0 &&
-                       (double)other_cold >= kSlotShare * (double)other;
+                       (double)other_cold >= share * (double)other;
     if (!team_rows.empty() || fixed) {
       mk->npanel = np;
       auto panel_of = [&](int32_t c) { return (size_t)((c - hot) >> kPanelShift); };

@@ -38,6 +38,11 @@
  *                                 when the LDS holds one workgroup per CU);
  *      PDHCG_HOT=k                relabel the goods by degree and keep only
  *                                 the first k in LDS (as for large m);
+ *      PDHCG_SLOT_SHARE=f         on relabelled markets, give the short
+ *                                 rows' entries of goods beyond LDS fixed
+ *                                 panel slots when they are at least this
+ *                                 share of those rows' entries (default 0.1;
+ *                                 else they are gathered by column);
  *      PDHCG_P_LDS=0              prices from global memory, partials in LDS;
  *      PDHCG_NO_LDS=1             no LDS: device atomics for column sums;
  *      PDHCG_TEAM=0 / 2           rows above 512 entries all on the

@@ -32,10 +32,10 @@
  *    parameter sweeps; results stay those of the method):
  *      PDHCG_ROW_G, PDHCG_ROW_E   force the row shape (lanes, entries per
  *                                 lane) of every bin that it can hold;
- *      PDHCG_MERGE_BINS=0 / 1     keep / merge the register-resident bins
- *                                 of equal lane count into the one with the
- *                                 most entries per lane (default: merged
- *                                 when the LDS holds one workgroup per CU);
+ *      PDHCG_MERGE_BINS=0         keep one bin per row shape (default: the
+ *                                 register-resident bins of equal lane
+ *                                 count merge into the one with the most
+ *                                 entries per lane);
  *      PDHCG_HOT=k                relabel the goods by degree and keep only
  *                                 the first k in LDS (as for large m);
  *      PDHCG_SLOT_SHARE=f         on relabelled markets, give the short

@@ -339,13 +339,15 @@ int32_t build_bins(pdhcg_market mk, const std::vector<int32_t> &h_row_ptr, int w
   // for every row up to kTeamMaxRow entries.
   int team_mode = 1;
   if (const char *e = std::getenv("PDHCG_TEAM")) team_mode = std::atoi(e);
-  // Where the LDS holds one workgroup per CU, register-resident bins of the
-  // same lane count G merge into the one with the most entries per lane: a
-  // pass takes 64 / G rows per wave whatever E is, and each bin's launch
-  // stages the prices, writes a partial row per workgroup and drains its
-  // tail (measured on the e-commerce-shaped market: five bins 1.18 ms, two
-  // 0.95 ms per row pass).  PDHCG_MERGE_BINS=0 / 1 disables / forces it.
-  bool merge = wg_per_cu <= 1;
+  // Register-resident bins of the same lane count G merge into the one with
+  // the most entries per lane: a pass takes 64 / G rows per wave whatever E
+  // is, and each bin's launch stages the prices, writes a partial row per
+  // workgroup and drains its tail.  Measured per row pass: e-commerce-shaped
+  // market (one workgroup per CU by LDS) five bins 1.18 ms, two 0.95 ms;
+  // the Table 2 markets (m = 4000, two workgroups per CU by LDS) 8-19% less,
+  // also where the wider shape leaves room for one workgroup only.
+  // PDHCG_MERGE_BINS=0 keeps a bin per shape.
+  bool merge = true;
   if (const char *e = std::getenv("PDHCG_MERGE_BINS")) merge = std::atoi(e) != 0;
   int emax[65] = {0};
   if (merge)

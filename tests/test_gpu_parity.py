@@ -133,8 +133,10 @@ def test_row_prox_degree_variants(cuda, d):
     check_row_prox(mk, cuda, x_in, p, 0.3 / (mk.w.sum() / mk.m))
 
 
-def test_row_prox_mixed_degrees(cuda):
-    """Several bins in one market (Bernoulli degrees spread over shapes)."""
+def test_row_prox_mixed_degrees(cuda, monkeypatch):
+    """Several bins in one market (Bernoulli degrees spread over shapes, one
+    bin per shape)."""
+    monkeypatch.setenv("PDHCG_MERGE_BINS", "0")
     rng = np.random.default_rng(3)
     mk = f32(synth.bernoulli_market(3000, 700, 0.04, 5, w_mode="uniform"))
     # add a few long rows
@@ -145,9 +147,9 @@ def test_row_prox_mixed_degrees(cuda):
 
 def test_merged_bins_match_oracle(cuda, monkeypatch):
     """Register-resident bins of equal lane count merged into the one with the
-    most entries per lane (the default where the LDS holds one workgroup per
-    CU), so that most rows fill a small part of their shape: the row prox
-    against the oracle's, and the solved prices against the oracle's."""
+    most entries per lane (the default), so that most rows fill a small part
+    of their shape: the row prox against the oracle's, and the solved prices
+    against the oracle's."""
     mk = f32(synth.bernoulli_market(3000, 700, 0.04, 5, w_mode="uniform"))
     monkeypatch.setenv("PDHCG_MERGE_BINS", "0")
     M = pdhcg.Market.from_synth(mk, device=cuda)

@@ -329,7 +329,9 @@ int32_t pdhcg_backward_noalloc(pdhcg_market market, const float *x,
                                float *dL_du, float *dL_dw);
 
 /* Number of market rows in each kernel bin and the bin shapes chosen at
- * creation (host arrays of length cap; returns the number of bins).  Rows
+ * creation (host arrays of length cap; returns the number of bins).  Rows of
+ * up to 512 entries take G lanes x E entries per lane, the bins of equal G
+ * merged into the largest E (unless PDHCG_MERGE_BINS=0).  Rows
  * above 512 entries have 0 lanes per row and, as entries per lane, the team
  * shape code: 1..5 for rows held in registers of teams of waves (up to
  * 1024, 2048, 4096, 8192 and 16384 entries), 0 for the one-wave-per-row

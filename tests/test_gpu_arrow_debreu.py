@@ -2,9 +2,11 @@
 against the oracle's fixed point on the same seeded exchange market.
 
 Tolerance: each inner solve stops at relative KKT 1e-7 on the device (float32
-allocations), so prices carry ~1e-6 relative noise; the fixed point is
-compared at 1e-4 relative, and its defining identities (sum of budgets kept,
-E p = w) at float32 rounding."""
+allocations; 1e-8 is below what float32 allocations reach), and the outer
+loop at a relative price change of 1e-5; the fixed point is compared with the
+oracle's at 1e-5 relative (measured 2.0e-6; 2.2e-7 with an outer tolerance of
+1e-6), and its defining identities (sum of budgets kept, E p = w) at float32
+rounding."""
 import numpy as np
 import pytest
 import torch
@@ -35,7 +37,7 @@ def test_arrow_debreu_matches_oracle(cuda):
     rows_e = np.repeat(np.arange(mk.n), np.diff(mk.e_row_ptr))
     Ep = np.bincount(rows_e, weights=mk.e_val.astype(np.float64) * p[mk.e_col], minlength=mk.n)
     assert np.max(np.abs(Ep - w) / w) < 1e-5
-    assert np.max(np.abs(p - ref["p"])) / np.max(ref["p"]) < 1e-4
+    assert np.max(np.abs(p - ref["p"])) / np.max(ref["p"]) < 1e-5
     M.close()
 
 

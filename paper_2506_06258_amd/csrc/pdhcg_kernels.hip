@@ -536,16 +536,27 @@ __global__ __launch_bounds__(kColBlock) void k_col_decide(MarketDev md, int tota
   const double *pt = pick3<double *>(md.P0, md.P1, md.P2, S->ip[1]);
   const double *ccur = pick3<double *>(md.C0, md.C1, md.C2, S->ic[1]);
   double *ctry = pick3<double *>(md.C0, md.C1, md.C2, S->ic[2]);
+  // every load issued before the sums (which keep the chunk order)
   if (nq > 0 && j < md.hot) {
+    double v[kColChunks];
+#pragma unroll
+    for (int k = 0; k < kColChunks; ++k) v[k] = k < nq ? md.colchunk[(size_t)k * m + j] : 0.0;
     double c = 0.0;
-    for (int k = 0; k < nq; ++k) c += md.colchunk[(size_t)k * m + j];
+#pragma unroll
+    for (int k = 0; k < kColChunks; ++k) c += v[k];
     ctry[j] = c;
   }
   if (ppart && j >= md.hot && j < m) {
     const int g = j - md.hot;
     const double *src = ppart + (size_t)(g >> kPanelShift) * pchunks * kPanelW + (g & (kPanelW - 1));
     double s = 0.0;
-    for (int r = 0; r < pchunks; ++r) s += src[(size_t)r * kPanelW];
+    for (int r0 = 0; r0 < pchunks; r0 += 8) {
+      double v[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) v[t] = r0 + t < pchunks ? src[(size_t)(r0 + t) * kPanelW] : 0.0;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) s += v[t];
+    }
     ctry[j] = pacc ? ctry[j] + s : s;
   }
   double inter = 0.0, dp2 = 0.0;

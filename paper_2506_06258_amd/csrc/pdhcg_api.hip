@@ -22,6 +22,10 @@
 
 using namespace pdhcg;
 
+namespace pdhcg {
+int long_row_threads();  // threads per workgroup of the solver's long-row kernel (pdhcg_long.hip)
+}
+
 namespace {
 
 thread_local std::string g_err;
@@ -403,7 +407,9 @@ int32_t build_bins(pdhcg_market mk, const std::vector<int32_t> &h_row_ptr, int w
   const int kWaves = kRowBlock / kWave;
   for (auto &b : mk->bins) {
     b.nrows = (int32_t)b.rows.size();
-    const int per_pass = b.G ? kWaves * (kWave / b.G) : kWaves;
+    // rows per workgroup pass: the segments of its waves, a wave per row for
+    // the long-row kernel (whose solver pass runs more waves per workgroup)
+    const int per_pass = b.G ? kWaves * (kWave / b.G) : (b.E == 0 ? long_row_threads() / kWave : kWaves);
     const int64_t passes = (b.nrows + per_pass - 1) / per_pass;
     int nwg = (int)std::max<int64_t>(1, std::min<int64_t>(passes, budget));
     const int64_t passes_per_wg = (passes + nwg - 1) / nwg;

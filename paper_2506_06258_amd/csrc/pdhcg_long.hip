@@ -23,8 +23,15 @@
 
 namespace pdhcg {
 
+// The solver's long-row kernel runs 12 waves per workgroup (it needs 125
+// VGPRs, so 3 waves per SIMD fit): where the LDS holds one workgroup per CU,
+// a bin of up to 12 x (CUs) rows then gives every row a wave of its own in
+// one round.
+constexpr int kLongBlock = 768;
+int long_row_threads() { return kLongBlock; }
+
 template <int LDS_MODE>
-__global__ __launch_bounds__(kRowBlock) void k_row_long(MarketDev md, BinDev bin, RowIO io) {
+__global__ __launch_bounds__(kLongBlock) void k_row_long(MarketDev md, BinDev bin, RowIO io) {
   extern __shared__ double lds_d[];
   const int m = md.m;
   const float *xin = io.xin;
@@ -57,7 +64,7 @@ __global__ __launch_bounds__(kRowBlock) void k_row_long(MarketDev md, BinDev bin
   }
   const int lane = threadIdx.x & (kWave - 1);
   const int wave = threadIdx.x / kWave;
-  constexpr int kWaves = kRowBlock / kWave;
+  constexpr int kWaves = kLongBlock / kWave;
   const int wg = blockIdx.x;
   const int row_lo = wg * bin.rows_per_wg;
   const int row_hi = min(row_lo + bin.rows_per_wg, bin.nrows);
@@ -531,10 +538,10 @@ hipError_t launch_row_long(const MarketDev &md, const BinDev &bin, int lds_mode,
   const size_t shm = lh * (((lds_mode & 2) ? sizeof(double) : 0) +
                            ((lds_mode & 1) ? sizeof(double) : 0));
   switch (lds_mode) {
-    case 0: hipLaunchKernelGGL(k_row_long<0>, dim3(nwg), dim3(kRowBlock), shm, st, md, bin, io); break;
-    case 1: hipLaunchKernelGGL(k_row_long<1>, dim3(nwg), dim3(kRowBlock), shm, st, md, bin, io); break;
-    case 3: hipLaunchKernelGGL(k_row_long<3>, dim3(nwg), dim3(kRowBlock), shm, st, md, bin, io); break;
-    case 7: hipLaunchKernelGGL(k_row_long<7>, dim3(nwg), dim3(kRowBlock), shm, st, md, bin, io); break;
+    case 0: hipLaunchKernelGGL(k_row_long<0>, dim3(nwg), dim3(kLongBlock), shm, st, md, bin, io); break;
+    case 1: hipLaunchKernelGGL(k_row_long<1>, dim3(nwg), dim3(kLongBlock), shm, st, md, bin, io); break;
+    case 3: hipLaunchKernelGGL(k_row_long<3>, dim3(nwg), dim3(kLongBlock), shm, st, md, bin, io); break;
+    case 7: hipLaunchKernelGGL(k_row_long<7>, dim3(nwg), dim3(kLongBlock), shm, st, md, bin, io); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

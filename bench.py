@@ -391,7 +391,7 @@ def main():
                     help="run the leg on the market of the e-commerce data's shape (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+        print(json.dumps({"error": "the benchmark runs on one GPU (the library has no multi-GPU path); --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
